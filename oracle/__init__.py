@@ -1,0 +1,265 @@
+"""Plain CPU FP64 oracle for the 3D photoacoustic RTO sampler (arXiv 2607.21373).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the GPU library never does, and the
+two share no code.  The arithmetic lives in ``pat_oracle.c`` (plain loops,
+float64, no FMA contraction); this module only marshals NumPy arrays.
+
+Layouts at this interface follow the GPU library's user-facing conventions:
+  p0, p      [R][N]            one row per right-hand side
+  y, yhat    [R][N_T][N_obs]   time-major data of each right-hand side
+  eta        [S][N_T][N_obs],  xi [S][N]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pat_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (float64, -ffp-contract=off, OpenMP)."""
+    cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    lib.orc_create.restype = ctypes.c_void_p
+    lib.orc_create.argtypes = [ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp, ctypes.c_int, ctypes.c_int,
+                               _ip, _dp, ctypes.c_double, ctypes.c_int]
+    lib.orc_destroy.argtypes = [ctypes.c_void_p]
+    lib.orc_nnz.restype = ctypes.c_int64
+    lib.orc_nnz.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.orc_get_csr.argtypes = [ctypes.c_void_p, ctypes.c_int, _lp, _ip, _dp]
+    lib.orc_get_mass.argtypes = [ctypes.c_void_p, _dp]
+    lib.orc_get_sensors.argtypes = [ctypes.c_void_p, _ip, _dp]
+    lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+    lib.orc_step_transpose.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+    lib.orc_forward.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+    lib.orc_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+    lib.orc_prior_apply.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp]
+    lib.orc_prior_apply_transpose.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp]
+    lib.orc_cgls.restype = ctypes.c_int
+    lib.orc_cgls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, _dp, _dp, _dp, _dp]
+    lib.orc_rto.restype = ctypes.c_int
+    lib.orc_rto.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                            ctypes.c_int, _dp, _dp, _dp, _dp]
+    lib.orc_stats.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+    lib.orc_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray], t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+class Problem:
+    """Assembled discrete PAT problem (mesh, wave speed, boundary, sensors, dt, N_T)."""
+
+    def __init__(self, coords, tets, c_tet=None, absorbing=True, dt=0.01, n_steps=100,
+                 sensor_nodes=None, sensor_pos=None):
+        lib = _load()
+        self.coords = _f64(coords)
+        self.tets = np.ascontiguousarray(tets, dtype=np.int32)
+        self.c_tet = None if c_tet is None else _f64(c_tet)
+        self.n_nodes = int(self.coords.shape[0])
+        self.n_steps = int(n_steps)
+        self.dt = float(dt)
+        if (sensor_nodes is None) == (sensor_pos is None):
+            raise ValueError("give exactly one of sensor_nodes and sensor_pos")
+        sn = None if sensor_nodes is None else np.ascontiguousarray(sensor_nodes, dtype=np.int32)
+        sp = None if sensor_pos is None else _f64(sensor_pos)
+        self.n_obs = int(sn.size if sn is not None else sp.shape[0])
+        h = lib.orc_create(self.n_nodes, _ptr(self.coords), int(self.tets.shape[0]), _ptr(self.tets, _ip),
+                           _ptr(self.c_tet), int(bool(absorbing)), self.n_obs, _ptr(sn, _ip), _ptr(sp),
+                           self.dt, self.n_steps)
+        if not h:
+            raise ValueError("oracle problem creation failed (sensor outside the mesh or bad ids)")
+        self._h = ctypes.c_void_p(h)
+
+    @classmethod
+    def from_workload(cls, w, n_steps: Optional[int] = None):
+        return cls(w.coords, w.tets, w.c_tet, w.absorbing, w.dt, w.n_steps if n_steps is None else n_steps,
+                   sensor_nodes=w.sensor_nodes, sensor_pos=w.sensor_pos)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_destroy(h)
+            self._h = None
+
+    # -- assembled operators (for tests) ---------------------------------
+    def csr(self, which: str):
+        """Return (rowptr, col, val) of 'K', 'K1' or 'B'."""
+        w = {"K": 0, "K1": 1, "B": 2}[which]
+        lib = _load()
+        nnz = int(lib.orc_nnz(self._h, w))
+        rp = np.empty(self.n_nodes + 1, dtype=np.int64)
+        col = np.empty(max(nnz, 1), dtype=np.int32)
+        val = np.empty(max(nnz, 1), dtype=np.float64)
+        lib.orc_get_csr(self._h, w, _ptr(rp, _lp), _ptr(col, _ip), _ptr(val))
+        return rp, col[:nnz], val[:nnz]
+
+    def matrix(self, which: str):
+        import scipy.sparse as sp
+        rp, col, val = self.csr(which)
+        return sp.csr_matrix((val, col, rp), shape=(self.n_nodes, self.n_nodes))
+
+    def lumped_mass(self) -> np.ndarray:
+        m = np.empty(self.n_nodes)
+        _load().orc_get_mass(self._h, _ptr(m))
+        return m
+
+    def sensors(self):
+        nodes = np.empty((self.n_obs, 4), dtype=np.int32)
+        w = np.empty((self.n_obs, 4))
+        _load().orc_get_sensors(self._h, _ptr(nodes, _ip), _ptr(w))
+        return nodes, w
+
+    # -- time stepping ----------------------------------------------------
+    def step(self, p: np.ndarray, v: np.ndarray):
+        """One forward step on [R][N] arrays; returns new (p, v)."""
+        p = np.atleast_2d(p); v = np.atleast_2d(v)
+        R = p.shape[0]
+        pn, vn = np.array(p.T, dtype=np.float64, order="C"), np.array(v.T, dtype=np.float64, order="C")
+        work = np.empty(2 * self.n_nodes * R)
+        _load().orc_step(self._h, R, _ptr(pn), _ptr(vn), _ptr(work))
+        return pn.T.copy(), vn.T.copy()
+
+    def step_transpose(self, ph: np.ndarray, vh: np.ndarray):
+        """One transpose step (A_dt^T) on [R][N] arrays; returns new (ph, vh)."""
+        ph = np.atleast_2d(ph); vh = np.atleast_2d(vh)
+        R = ph.shape[0]
+        a, b = np.array(ph.T, dtype=np.float64, order="C"), np.array(vh.T, dtype=np.float64, order="C")
+        work = np.empty(self.n_nodes * R)
+        _load().orc_step_transpose(self._h, R, _ptr(a), _ptr(b), _ptr(work))
+        return a.T.copy(), b.T.copy()
+
+    def forward(self, p0: np.ndarray) -> np.ndarray:
+        """y = G p0 for p0 [R][N] (or [N]); returns [R][N_T][N_obs] (or [N_T][N_obs])."""
+        single = np.ndim(p0) == 1
+        p0 = np.atleast_2d(p0)
+        R = p0.shape[0]
+        x = _f64(p0.T)
+        y = np.empty((self.n_steps, self.n_obs, R))
+        _load().orc_forward(self._h, R, _ptr(x), _ptr(y))
+        out = np.moveaxis(y, 2, 0)
+        return np.ascontiguousarray(out[0] if single else out)
+
+    def adjoint(self, yhat: np.ndarray) -> np.ndarray:
+        """p = G^T yhat for yhat [R][N_T][N_obs] (or [N_T][N_obs]); returns [R][N] (or [N])."""
+        single = np.ndim(yhat) == 2
+        yh = yhat[None] if single else yhat
+        R = yh.shape[0]
+        a = _f64(np.moveaxis(yh, 0, 2))
+        p = np.empty((self.n_nodes, R))
+        _load().orc_adjoint(self._h, R, _ptr(a), _ptr(p))
+        out = p.T
+        return np.ascontiguousarray(out[0] if single else out)
+
+    def prior_apply(self, x: np.ndarray, a: float, transpose: bool = False) -> np.ndarray:
+        """L x (or L^T x) for L = M_L^{-1/2}(M_L + a K1); x [R][N] or [N]."""
+        single = np.ndim(x) == 1
+        x2 = np.atleast_2d(x)
+        R = x2.shape[0]
+        xi = _f64(x2.T)
+        y = np.empty_like(xi)
+        f = _load().orc_prior_apply_transpose if transpose else _load().orc_prior_apply
+        f(self._h, R, float(a), _ptr(xi), _ptr(y))
+        return np.ascontiguousarray(y.T[0] if single else y.T)
+
+    # -- least squares and sampling ----------------------------------------
+    def cgls(self, bd: np.ndarray, bp: np.ndarray, sigma: float, prior_a: float, n_iter: int,
+             reorth: bool = True):
+        """CGLS for min ||G_ext x - b||, b = (bd [R][N_T][N_obs], bp [R][N]).
+
+        Returns (x [R][N], resid [R][n_iter+1])."""
+        R = bp.shape[0]
+        bdi = _f64(np.moveaxis(bd, 0, 2))
+        bpi = _f64(bp.T)
+        x = np.empty((self.n_nodes, R))
+        res = np.empty((R, n_iter + 1))
+        rc = _load().orc_cgls(self._h, R, float(sigma), float(prior_a), int(n_iter), int(bool(reorth)),
+                              _ptr(bdi), _ptr(bpi), _ptr(x), _ptr(res))
+        if rc != 0:
+            raise MemoryError("oracle CGLS could not allocate its workspace")
+        return np.ascontiguousarray(x.T), res
+
+    def rto(self, yobs: np.ndarray, sigma: float, prior_a: float, n_iter: int, eta: np.ndarray, xi: np.ndarray,
+            reorth: bool = True):
+        """RTO samples (Algorithm 1): returns (samples [S][N], resid [S][n_iter+1])."""
+        S = xi.shape[0]
+        ya = _f64(yobs)
+        ea = _f64(np.moveaxis(eta, 0, 2))
+        xa = _f64(xi.T)
+        out = np.empty((self.n_nodes, S))
+        res = np.empty((S, n_iter + 1))
+        rc = _load().orc_rto(self._h, S, _ptr(ya), float(sigma), float(prior_a), int(n_iter), int(bool(reorth)),
+                             _ptr(ea), _ptr(xa), _ptr(out), _ptr(res))
+        if rc != 0:
+            raise MemoryError("oracle RTO could not allocate its workspace")
+        return np.ascontiguousarray(out.T), res
+
+
+def stats(samples: np.ndarray):
+    """Pointwise mean and std (1/(S-1)) of samples [S][N], eq. (ergodic)."""
+    S, N = samples.shape
+    a = _f64(samples.T)
+    mean = np.empty(N); std = np.empty(N)
+    _load().orc_stats(N, S, _ptr(a), _ptr(mean), _ptr(std))
+    return mean, std
+
+
+def noise_sigma(Y: np.ndarray, eta0: np.ndarray, d_noise: float, rule: str) -> float:
+    """Absolute noise level of the synthetic data.
+
+    rule "l2": sigma = d_noise * ||Y|| / ||eta0|| (Sec. 2, eq. (noise-model); the
+    dt weights of the discrete L2(0,T; l2) norms cancel in the ratio).
+    rule "max": sigma = d_noise * max|Y|.
+    """
+    if rule == "l2":
+        return float(d_noise * np.sqrt(np.sum(Y * Y)) / np.sqrt(np.sum(eta0 * eta0)))
+    if rule == "max":
+        return float(d_noise * np.max(np.abs(Y)))
+    raise ValueError(rule)
+
+
+def synthesize(problem: Problem, w, eta0: Optional[np.ndarray] = None):
+    """Noise-free data Y = G p0_true, sigma, and y_obs = Y + sigma * eta0."""
+    import workloads
+    Y = problem.forward(w.p0_true)
+    if eta0 is None:
+        eta0 = workloads.noise_draw(problem.n_steps, problem.n_obs, w.noise_seed)
+    sigma = noise_sigma(Y, eta0, w.d_noise, w.noise_rule)
+    return Y, Y + sigma * eta0, sigma

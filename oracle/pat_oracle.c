@@ -1,0 +1,676 @@
+/*
+ * Plain CPU FP64 oracle for the matrix-free RTO sampler of
+ * "3D Uncertainty Quantification for Photoacoustic Tomography" (arXiv 2607.21373).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct reference
+ * that the GPU library is checked against.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it; the product never does.
+ * It shares no code with the GPU library.
+ *
+ * Everything is float64, built with -ffp-contract=off.  Multi-vectors with R
+ * right-hand sides are stored node-major, RHS fastest: x[i*R + r].  Parallel
+ * loops run over independent rows only, and every reduction is a sequential sum
+ * in index order, so results are bitwise identical for any thread count.
+ *
+ * What each part follows in the paper:
+ *   assembly            Sec. 3, eq. (semi-discrete) and the matrix definitions
+ *                       below it; lumped mass M_L = diag(M 1) (Sec. 3)
+ *   sensor operator Pi  Sec. 3, eq. (lagrange): P1 interpolation at the sensor
+ *                       point (injection when the sensor is a node)
+ *   forward step        Sec. 3, eq. (fully-discrete) with M replaced by M_L
+ *   forward map G       Sec. 3, eq. (discrete-wave-matrix): y^n = Pi z^n, n=1..N_T
+ *   transpose step      Sec. 5.1, eq. (adjoint-verlet); App. B
+ *   transpose map G^T   Sec. 5.1, eqs. (transpose-definition), (backward-recursion)
+ *   G_ext, b            Sec. 5, eq. (extended-matrices); residual and transpose
+ *                       action eqs. (lsqr-residual), (lsqr-transpose-action)
+ *   CGLS                least-squares solve of eq. (normal-equations), with full
+ *                       reorthogonalisation of the normal-equation residuals
+ *   RTO sample          Sec. 5, eq. (optimization); Algorithm 1
+ *   mean / std          Sec. 6.2, eq. (ergodic)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int n;            /* number of rows (= columns) */
+    int64_t nnz;
+    int64_t *rowptr;  /* [n+1] */
+    int *col;         /* [nnz], ascending within a row */
+    double *val;      /* [nnz] */
+} ocsr;
+
+typedef struct {
+    int n_nodes, n_obs, n_steps;
+    double dt;
+    ocsr K;    /* [K]_mn = c^2 int grad phi_m . grad phi_n */
+    ocsr K1;   /* same with c = 1 (used by the prior) */
+    ocsr B;    /* [B]_mn = (1/c) int_{boundary} phi_m phi_n ; all zero when reflecting */
+    double *mL;     /* lumped mass, diag(M 1) */
+    int *snode;     /* [n_obs][4] */
+    double *sw;     /* [n_obs][4] interpolation weights */
+} oproblem;
+
+/* ------------------------------------------------------------------ */
+/* Sparse pattern construction                                         */
+/* ------------------------------------------------------------------ */
+
+static int cmp_int(const void *a, const void *b) {
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* Build a CSR pattern from groups of `k` node ids (every pair in a group couples). */
+static int pattern_from_groups(int n, int64_t ngroups, int k, const int *groups, ocsr *A) {
+    int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
+    if (!cnt) return -1;
+    for (int64_t g = 0; g < ngroups; ++g)
+        for (int a = 0; a < k; ++a) cnt[groups[g * k + a] + 1] += k;
+    for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    int *tmp = malloc(sizeof(int) * (size_t)(cnt[n] > 0 ? cnt[n] : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)n);
+    if (!tmp || !fill) { free(cnt); free(tmp); free(fill); return -1; }
+    for (int i = 0; i < n; ++i) fill[i] = cnt[i];
+    for (int64_t g = 0; g < ngroups; ++g)
+        for (int a = 0; a < k; ++a) {
+            int row = groups[g * k + a];
+            for (int b = 0; b < k; ++b) tmp[fill[row]++] = groups[g * k + b];
+        }
+    A->n = n;
+    A->rowptr = malloc(sizeof(int64_t) * ((size_t)n + 1));
+    A->rowptr[0] = 0;
+    /* sort and deduplicate each row */
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        int64_t s = cnt[i], e = cnt[i + 1];
+        qsort(tmp + s, (size_t)(e - s), sizeof(int), cmp_int);
+        int64_t u = 0;
+        for (int64_t t = s; t < e; ++t)
+            if (u == 0 || tmp[s + u - 1] != tmp[t]) tmp[s + u++] = tmp[t];
+        fill[i] = u;
+        total += u;
+        A->rowptr[i + 1] = total;
+    }
+    A->nnz = total;
+    A->col = malloc(sizeof(int) * (size_t)(total > 0 ? total : 1));
+    A->val = calloc((size_t)(total > 0 ? total : 1), sizeof(double));
+    for (int i = 0; i < n; ++i)
+        memcpy(A->col + A->rowptr[i], tmp + cnt[i], sizeof(int) * (size_t)fill[i]);
+    free(tmp); free(fill); free(cnt);
+    return 0;
+}
+
+/* Location of column j in row i (binary search); -1 if absent. */
+static int64_t csr_find(const ocsr *A, int i, int j) {
+    int64_t lo = A->rowptr[i], hi = A->rowptr[i + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (A->col[mid] == j) return mid;
+        if (A->col[mid] < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+static void csr_free(ocsr *A) { free(A->rowptr); free(A->col); free(A->val); memset(A, 0, sizeof(*A)); }
+
+/* ------------------------------------------------------------------ */
+/* Geometry                                                            */
+/* ------------------------------------------------------------------ */
+
+static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static void cross3(const double *a, const double *b, double *o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Gradients of the four barycentric (P1 nodal basis) functions of a tetrahedron
+ * and its signed 6*volume.  grad lambda_1 = (e2 x e3)/det, etc., with
+ * e_k = x_k - x_0 and det = e1 . (e2 x e3); grad lambda_0 = -sum of the others. */
+static double tet_gradients(const double *X, const int *t, double g[4][3]) {
+    double e1[3], e2[3], e3[3], c23[3], c31[3], c12[3];
+    sub3(X + 3 * t[1], X + 3 * t[0], e1);
+    sub3(X + 3 * t[2], X + 3 * t[0], e2);
+    sub3(X + 3 * t[3], X + 3 * t[0], e3);
+    cross3(e2, e3, c23); cross3(e3, e1, c31); cross3(e1, e2, c12);
+    double det = dot3(e1, c23);
+    for (int d = 0; d < 3; ++d) {
+        g[1][d] = c23[d] / det;
+        g[2][d] = c31[d] / det;
+        g[3][d] = c12[d] / det;
+        g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    }
+    return det;
+}
+
+/* ------------------------------------------------------------------ */
+/* Boundary faces: faces owned by exactly one tetrahedron              */
+/* ------------------------------------------------------------------ */
+
+typedef struct { int a, b, c, tet; } oface;
+
+static int cmp_face(const void *x, const void *y) {
+    const oface *f = x, *g = y;
+    if (f->a != g->a) return (f->a > g->a) - (f->a < g->a);
+    if (f->b != g->b) return (f->b > g->b) - (f->b < g->b);
+    if (f->c != g->c) return (f->c > g->c) - (f->c < g->c);
+    return (f->tet > g->tet) - (f->tet < g->tet);
+}
+
+static void sort3(int *v) {
+    int t;
+    if (v[0] > v[1]) { t = v[0]; v[0] = v[1]; v[1] = t; }
+    if (v[1] > v[2]) { t = v[1]; v[1] = v[2]; v[2] = t; }
+    if (v[0] > v[1]) { t = v[0]; v[0] = v[1]; v[1] = t; }
+}
+
+/* Returns the number of boundary faces; fills faces[nb] (sorted node triples + owner). */
+static int64_t boundary_faces(int64_t E, const int *tets, oface **out) {
+    static const int fl[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    oface *all = malloc(sizeof(oface) * (size_t)(4 * E));
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 4; ++f) {
+            int v[3] = {tets[4 * e + fl[f][0]], tets[4 * e + fl[f][1]], tets[4 * e + fl[f][2]]};
+            sort3(v);
+            all[4 * e + f] = (oface){v[0], v[1], v[2], (int)e};
+        }
+    qsort(all, (size_t)(4 * E), sizeof(oface), cmp_face);
+    int64_t nb = 0;
+    for (int64_t i = 0; i < 4 * E;) {
+        int64_t j = i + 1;
+        while (j < 4 * E && all[j].a == all[i].a && all[j].b == all[i].b && all[j].c == all[i].c) ++j;
+        if (j - i == 1) all[nb++] = all[i];
+        i = j;
+    }
+    *out = all;
+    return nb;
+}
+
+/* ------------------------------------------------------------------ */
+/* Problem construction                                                */
+/* ------------------------------------------------------------------ */
+
+/* Point location: the tetrahedron whose smallest barycentric coordinate of x is
+ * largest (first such tetrahedron on ties).  Returns that smallest coordinate. */
+static double locate(int64_t E, const int *tets, const double *X, const double *x, int *best_tet, double lam_out[4]) {
+    double best = -1e300;
+    *best_tet = -1;
+    for (int64_t e = 0; e < E; ++e) {
+        const int *t = tets + 4 * e;
+        double e1[3], e2[3], e3[3], d[3], c[3], lam[4];
+        sub3(X + 3 * t[1], X + 3 * t[0], e1);
+        sub3(X + 3 * t[2], X + 3 * t[0], e2);
+        sub3(X + 3 * t[3], X + 3 * t[0], e3);
+        sub3(x, X + 3 * t[0], d);
+        cross3(e2, e3, c);
+        double det = dot3(e1, c);
+        lam[1] = dot3(d, c) / det;
+        cross3(e3, e1, c);
+        lam[2] = dot3(d, c) / det;
+        cross3(e1, e2, c);
+        lam[3] = dot3(d, c) / det;
+        lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+        double m = lam[0];
+        for (int k = 1; k < 4; ++k) if (lam[k] < m) m = lam[k];
+        if (m > best) {
+            best = m;
+            *best_tet = (int)e;
+            for (int k = 0; k < 4; ++k) lam_out[k] = lam[k];
+        }
+    }
+    return best;
+}
+
+/* Create the discrete problem.
+ *   coords[N][3], tets[E][4]: P1 mesh.  c_tet[E] wave speed per element or NULL (c = 1).
+ *   absorbing: 1 = first-order absorbing boundary (B assembled), 0 = reflecting (B = 0).
+ *   Sensors: either sensor_nodes[n_obs] (node ids) or sensor_pos[n_obs][3] (points).
+ * Returns NULL on failure (a sensor outside the mesh, bad input). */
+oproblem *orc_create(int N, const double *coords, int64_t E, const int *tets, const double *c_tet,
+                     int absorbing, int n_obs, const int *sensor_nodes, const double *sensor_pos,
+                     double dt, int n_steps) {
+    oproblem *P = calloc(1, sizeof(oproblem));
+    P->n_nodes = N; P->n_obs = n_obs; P->n_steps = n_steps; P->dt = dt;
+    for (int64_t e = 0; e < 4 * E; ++e)
+        if (tets[e] < 0 || tets[e] >= N) { free(P); return NULL; }
+
+    /* stiffness matrices K (c^2) and K1 (c = 1), lumped mass */
+    pattern_from_groups(N, E, 4, tets, &P->K);
+    pattern_from_groups(N, E, 4, tets, &P->K1);
+    P->mL = calloc((size_t)N, sizeof(double));
+    for (int64_t e = 0; e < E; ++e) {
+        const int *t = tets + 4 * e;
+        double g[4][3];
+        double det = tet_gradients(coords, t, g);
+        double vol = fabs(det) / 6.0;
+        double c = c_tet ? c_tet[e] : 1.0;
+        for (int a = 0; a < 4; ++a) {
+            P->mL[t[a]] += vol / 4.0;
+            for (int b = 0; b < 4; ++b) {
+                double kab = vol * dot3(g[a], g[b]);
+                int64_t pos = csr_find(&P->K, t[a], t[b]);
+                P->K.val[pos] += c * c * kab;
+                P->K1.val[pos] += kab;
+            }
+        }
+    }
+
+    /* boundary mass: consistent P1 face mass (area/12)(1 + delta_ab), scaled by 1/c
+     * of the tetrahedron that owns the face */
+    oface *faces = NULL;
+    int64_t nb = absorbing ? boundary_faces(E, tets, &faces) : 0;
+    int *fnodes = malloc(sizeof(int) * (size_t)(3 * (nb > 0 ? nb : 1)));
+    for (int64_t f = 0; f < nb; ++f) {
+        fnodes[3 * f] = faces[f].a; fnodes[3 * f + 1] = faces[f].b; fnodes[3 * f + 2] = faces[f].c;
+    }
+    pattern_from_groups(N, nb, 3, fnodes, &P->B);
+    for (int64_t f = 0; f < nb; ++f) {
+        const int *v = fnodes + 3 * f;
+        double e1[3], e2[3], cr[3];
+        sub3(coords + 3 * v[1], coords + 3 * v[0], e1);
+        sub3(coords + 3 * v[2], coords + 3 * v[0], e2);
+        cross3(e1, e2, cr);
+        double area = 0.5 * sqrt(dot3(cr, cr));
+        double c = c_tet ? c_tet[faces[f].tet] : 1.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                P->B.val[csr_find(&P->B, v[a], v[b])] += (a == b ? 2.0 : 1.0) * area / 12.0 / c;
+    }
+    free(fnodes); free(faces);
+
+    /* sensor interpolation rows */
+    P->snode = malloc(sizeof(int) * 4 * (size_t)(n_obs > 0 ? n_obs : 1));
+    P->sw = malloc(sizeof(double) * 4 * (size_t)(n_obs > 0 ? n_obs : 1));
+    int bad = 0;
+    if (sensor_nodes) {
+        for (int s = 0; s < n_obs; ++s) {
+            if (sensor_nodes[s] < 0 || sensor_nodes[s] >= N) bad = 1;
+            for (int k = 0; k < 4; ++k) { P->snode[4 * s + k] = sensor_nodes[s]; P->sw[4 * s + k] = k == 0 ? 1.0 : 0.0; }
+        }
+    } else {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int s = 0; s < n_obs; ++s) {
+            int te; double lam[4];
+            double m = locate(E, tets, coords, sensor_pos + 3 * s, &te, lam);
+            if (te < 0 || m < -1e-10) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            for (int k = 0; k < 4; ++k) { P->snode[4 * s + k] = tets[4 * te + k]; P->sw[4 * s + k] = lam[k]; }
+        }
+    }
+    if (bad) {
+        csr_free(&P->K); csr_free(&P->K1); csr_free(&P->B);
+        free(P->mL); free(P->snode); free(P->sw); free(P);
+        return NULL;
+    }
+    return P;
+}
+
+void orc_destroy(oproblem *P) {
+    if (!P) return;
+    csr_free(&P->K); csr_free(&P->K1); csr_free(&P->B);
+    free(P->mL); free(P->snode); free(P->sw); free(P);
+}
+
+/* Export sizes and arrays (for tests). which: 0 = K, 1 = K1, 2 = B. */
+int64_t orc_nnz(const oproblem *P, int which) { return which == 0 ? P->K.nnz : which == 1 ? P->K1.nnz : P->B.nnz; }
+void orc_get_csr(const oproblem *P, int which, int64_t *rowptr, int *col, double *val) {
+    const ocsr *A = which == 0 ? &P->K : which == 1 ? &P->K1 : &P->B;
+    memcpy(rowptr, A->rowptr, sizeof(int64_t) * ((size_t)A->n + 1));
+    memcpy(col, A->col, sizeof(int) * (size_t)A->nnz);
+    memcpy(val, A->val, sizeof(double) * (size_t)A->nnz);
+}
+void orc_get_mass(const oproblem *P, double *mL) { memcpy(mL, P->mL, sizeof(double) * (size_t)P->n_nodes); }
+void orc_get_sensors(const oproblem *P, int *snode, double *sw) {
+    memcpy(snode, P->snode, sizeof(int) * 4 * (size_t)P->n_obs);
+    memcpy(sw, P->sw, sizeof(double) * 4 * (size_t)P->n_obs);
+}
+
+/* ------------------------------------------------------------------ */
+/* Sparse products, row by row                                         */
+/* ------------------------------------------------------------------ */
+
+/* acc[r] = sum_k A_ik x[col_k][r] for one row i */
+static inline void row_product(const ocsr *A, int i, int R, const double *restrict x, double *restrict acc) {
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+        const double a = A->val[k];
+        const double *xj = x + (size_t)A->col[k] * R;
+        for (int r = 0; r < R; ++r) acc[r] += a * xj[r];
+    }
+}
+
+/* y = A x for multi-vectors */
+void orc_spmv(const ocsr *A, int R, const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < A->n; ++i) row_product(A, i, R, x, y + (size_t)i * R);
+}
+
+/* ------------------------------------------------------------------ */
+/* Forward Stormer-Verlet step, eq. (fully-discrete) with M -> M_L     */
+/* ------------------------------------------------------------------ */
+
+/* One step z^n = (p, v) -> z^{n+1}; p, v updated in place.
+ * work: 2*N*R doubles (p^{n+1/2} and the new v). */
+void orc_step(const oproblem *P, int R, double *p, double *v, double *work) {
+    const int N = P->n_nodes;
+    const double dt = P->dt;
+    double *ph = work, *vn = work + (size_t)N * R;
+    /* p^{n+1/2} = p^n + (dt/2) v^n */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r) ph[(size_t)i * R + r] = p[(size_t)i * R + r] + 0.5 * dt * v[(size_t)i * R + r];
+    /* M_L v^{n+1} = M_L v^n - dt K p^{n+1/2} - dt B v^n */
+#pragma omp parallel
+    {
+        double *kp = malloc(sizeof(double) * (size_t)R), *bv = malloc(sizeof(double) * (size_t)R);
+#pragma omp for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            row_product(&P->K, i, R, ph, kp);
+            row_product(&P->B, i, R, v, bv);
+            for (int r = 0; r < R; ++r) {
+                double rhs = P->mL[i] * v[(size_t)i * R + r] - dt * kp[r] - dt * bv[r];
+                vn[(size_t)i * R + r] = rhs / P->mL[i];
+            }
+        }
+        free(kp); free(bv);
+    }
+    /* p^{n+1} = p^{n+1/2} + (dt/2) v^{n+1} */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r) {
+            v[(size_t)i * R + r] = vn[(size_t)i * R + r];
+            p[(size_t)i * R + r] = ph[(size_t)i * R + r] + 0.5 * dt * vn[(size_t)i * R + r];
+        }
+}
+
+/* y_s = sum_k w_sk p[node_sk] (Pi applied to the pressure part) */
+static void observe(const oproblem *P, int R, const double *p, double *y) {
+    for (int s = 0; s < P->n_obs; ++s)
+        for (int r = 0; r < R; ++r) {
+            double acc = 0.0;
+            for (int k = 0; k < 4; ++k) acc += P->sw[4 * s + k] * p[(size_t)P->snode[4 * s + k] * R + r];
+            y[(size_t)s * R + r] = acc;
+        }
+}
+
+/* Forward map: y^n = Pi A^n z_0, z_0 = (p0, 0), n = 1..N_T.
+ * p0 [N][R]; y [N_T][n_obs][R]. */
+void orc_forward(const oproblem *P, int R, const double *p0, double *y) {
+    const size_t NR = (size_t)P->n_nodes * R;
+    double *p = malloc(sizeof(double) * NR), *v = calloc(NR, sizeof(double)), *w = malloc(sizeof(double) * 2 * NR);
+    memcpy(p, p0, sizeof(double) * NR);
+    for (int n = 1; n <= P->n_steps; ++n) {
+        orc_step(P, R, p, v, w);
+        observe(P, R, p, y + (size_t)(n - 1) * P->n_obs * R);
+    }
+    free(p); free(v); free(w);
+}
+
+/* ------------------------------------------------------------------ */
+/* Transpose step, eq. (adjoint-verlet): A^T = S1^T S2^T S3^T S4^T      */
+/* ------------------------------------------------------------------ */
+
+/* (ph, vh) <- A_dt^T (ph, vh), in place.  work: N*R doubles (q). */
+void orc_step_transpose(const oproblem *P, int R, double *ph, double *vh, double *work) {
+    const int N = P->n_nodes;
+    const double dt = P->dt;
+    double *q = work;
+    /* vh^{n+1/2} = vh^{n+1} + (dt/2) ph^{n+1};  M_L q = vh^{n+1/2} */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r)
+            q[(size_t)i * R + r] = (vh[(size_t)i * R + r] + 0.5 * dt * ph[(size_t)i * R + r]) / P->mL[i];
+    /* ph^n = ph^{n+1/2} - dt K^T q ;  vh^n = (M_L - dt B^T) q + (dt/2) ph^n   (K, B symmetric) */
+#pragma omp parallel
+    {
+        double *kq = malloc(sizeof(double) * (size_t)R), *bq = malloc(sizeof(double) * (size_t)R);
+#pragma omp for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            row_product(&P->K, i, R, q, kq);
+            row_product(&P->B, i, R, q, bq);
+            for (int r = 0; r < R; ++r) {
+                double pn = ph[(size_t)i * R + r] - dt * kq[r];
+                ph[(size_t)i * R + r] = pn;
+                vh[(size_t)i * R + r] = (P->mL[i] * q[(size_t)i * R + r] - dt * bq[r]) + 0.5 * dt * pn;
+            }
+        }
+        free(kq); free(bq);
+    }
+}
+
+/* ph[node] += Pi^T yhat  (scatter of sensor values to the interpolation nodes) */
+static void inject(const oproblem *P, int R, const double *yh, double *ph) {
+    for (int s = 0; s < P->n_obs; ++s)
+        for (int k = 0; k < 4; ++k)
+            for (int r = 0; r < R; ++r)
+                ph[(size_t)P->snode[4 * s + k] * R + r] += P->sw[4 * s + k] * yh[(size_t)s * R + r];
+}
+
+/* Transpose map: G^T yhat = J^T A^T zhat^1 with zhat^{N_T} = Pi^T yhat^{N_T},
+ * zhat^n = Pi^T yhat^n + A^T zhat^{n+1}.  yhat [N_T][n_obs][R]; p [N][R]. */
+void orc_adjoint(const oproblem *P, int R, const double *yhat, double *p) {
+    const size_t NR = (size_t)P->n_nodes * R;
+    double *vh = calloc(NR, sizeof(double)), *w = malloc(sizeof(double) * NR);
+    memset(p, 0, sizeof(double) * NR);
+    for (int n = P->n_steps; n >= 1; --n) {
+        inject(P, R, yhat + (size_t)(n - 1) * P->n_obs * R, p);
+        orc_step_transpose(P, R, p, vh, w);
+    }
+    free(vh); free(w);
+}
+
+/* ------------------------------------------------------------------ */
+/* Extended operator of eq. (extended-matrices) with prior factor L     */
+/* ------------------------------------------------------------------ */
+
+/* Prior square root L = M_L^{-1/2} (M_L + a K1), so L^T L = (M_L + a K1) M_L^{-1} (M_L + a K1);
+ * a = 0 gives L = M_L^{1/2}, the independent prior of eq. (iid-prior). */
+static void prior_apply(const oproblem *P, int R, double a, const double *x, double *y) {
+    const int N = P->n_nodes;
+    orc_spmv(&P->K1, R, x, y);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r)
+            y[(size_t)i * R + r] = (P->mL[i] * x[(size_t)i * R + r] + a * y[(size_t)i * R + r]) / sqrt(P->mL[i]);
+}
+
+static void prior_apply_transpose(const oproblem *P, int R, double a, const double *x, double *y, double *tmp) {
+    const int N = P->n_nodes;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r) tmp[(size_t)i * R + r] = x[(size_t)i * R + r] / sqrt(P->mL[i]);
+    orc_spmv(&P->K1, R, tmp, y);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r)
+            y[(size_t)i * R + r] = P->mL[i] * tmp[(size_t)i * R + r] + a * y[(size_t)i * R + r];
+}
+
+void orc_prior_apply(const oproblem *P, int R, double a, const double *x, double *y) { prior_apply(P, R, a, x, y); }
+void orc_prior_apply_transpose(const oproblem *P, int R, double a, const double *x, double *y) {
+    double *tmp = malloc(sizeof(double) * (size_t)P->n_nodes * R);
+    prior_apply_transpose(P, R, a, x, y, tmp);
+    free(tmp);
+}
+
+/* per-RHS sum of squares over m rows (sequential, index order) */
+static void sumsq(size_t m, int R, const double *x, double *out) {
+    for (int r = 0; r < R; ++r) out[r] = 0.0;
+    for (size_t i = 0; i < m; ++i)
+        for (int r = 0; r < R; ++r) out[r] += x[i * R + r] * x[i * R + r];
+}
+
+/* per-RHS dot product over m rows (sequential, index order) */
+static void dotr(size_t m, int R, const double *x, const double *y, double *out) {
+    for (int r = 0; r < R; ++r) out[r] = 0.0;
+    for (size_t i = 0; i < m; ++i)
+        for (int r = 0; r < R; ++r) out[r] += x[i * R + r] * y[i * R + r];
+}
+
+/* ------------------------------------------------------------------ */
+/* CGLS with full reorthogonalisation, applied to eq. (normal-equations) */
+/* ------------------------------------------------------------------ */
+
+/* Solves min_x || G_ext x - b ||_2 for R right-hand sides at once, with a fixed
+ * number of iterations, x_0 = 0.  G_ext = [ G / sigma ; L ].
+ *   bd [N_T][n_obs][R], bp [N][R]      right-hand side b = (bd, bp)
+ *   x  [N][R]                          output
+ *   resid [R][n_iter+1] or NULL        ||b - G_ext x_k|| (recursively updated residual)
+ * The normal-equation residuals s_k = G_ext^T r_k are mutually orthogonal in exact
+ * arithmetic; with reorth != 0 each new s_k is orthogonalised against all earlier
+ * normalised ones by classical Gram-Schmidt applied twice.  Returns 0, or -1 if
+ * memory could not be allocated. */
+int orc_cgls(const oproblem *P, int R, double sigma, double prior_a, int n_iter, int reorth,
+             const double *bd, const double *bp, double *x, double *resid) {
+    const int N = P->n_nodes;
+    const size_t NR = (size_t)N * R, MR = (size_t)P->n_steps * P->n_obs * R;
+    const size_t M = (size_t)P->n_steps * P->n_obs;
+    double *rd = malloc(sizeof(double) * MR), *qd = malloc(sizeof(double) * MR);
+    double *rp = malloc(sizeof(double) * NR), *qp = malloc(sizeof(double) * NR);
+    double *s = malloc(sizeof(double) * NR), *d = malloc(sizeof(double) * NR), *tmp = malloc(sizeof(double) * NR);
+    double *Q = reorth ? malloc(sizeof(double) * NR * (size_t)(n_iter + 1)) : NULL;
+    double *gamma = malloc(sizeof(double) * R), *delta = malloc(sizeof(double) * R), *w1 = malloc(sizeof(double) * R),
+           *w2 = malloc(sizeof(double) * R);
+    double *coef = malloc(sizeof(double) * (size_t)R * (size_t)(n_iter + 1));
+    if (!rd || !qd || !rp || !qp || !s || !d || !tmp || (reorth && !Q) || !gamma || !delta || !w1 || !w2 || !coef) {
+        free(rd); free(qd); free(rp); free(qp); free(s); free(d); free(tmp); free(Q);
+        free(gamma); free(delta); free(w1); free(w2); free(coef);
+        return -1;
+    }
+    const double isig = 1.0 / sigma;
+
+    memset(x, 0, sizeof(double) * NR);
+    memcpy(rd, bd, sizeof(double) * MR);
+    memcpy(rp, bp, sizeof(double) * NR);
+
+    /* s_0 = G_ext^T r_0 = sigma^{-1} G^T r_d + L^T r_p */
+#define GEXT_T(dst)                                                                  \
+    do {                                                                             \
+        orc_adjoint(P, R, rd, dst);                                                  \
+        prior_apply_transpose(P, R, prior_a, rp, qp, tmp);                           \
+        for (size_t i_ = 0; i_ < NR; ++i_) dst[i_] = isig * dst[i_] + qp[i_];        \
+    } while (0)
+
+    GEXT_T(s);
+    sumsq((size_t)N, R, s, gamma);
+    if (resid) {
+        sumsq(M, R, rd, w1); sumsq((size_t)N, R, rp, w2);
+        for (int r = 0; r < R; ++r) resid[(size_t)r * (n_iter + 1)] = sqrt(w1[r] + w2[r]);
+    }
+    if (reorth)
+        for (size_t i = 0; i < N; ++i)
+            for (int r = 0; r < R; ++r) Q[i * R + r] = gamma[r] > 0 ? s[i * R + r] / sqrt(gamma[r]) : 0.0;
+    memcpy(d, s, sizeof(double) * NR);
+
+    for (int k = 1; k <= n_iter; ++k) {
+        /* q = G_ext d */
+        orc_forward(P, R, d, qd);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < (int64_t)MR; ++i) qd[i] = isig * qd[i];
+        prior_apply(P, R, prior_a, d, qp);
+        sumsq(M, R, qd, w1);
+        sumsq((size_t)N, R, qp, w2);
+        for (int r = 0; r < R; ++r) delta[r] = w1[r] + w2[r];
+        /* alpha = gamma / ||q||^2 ; x += alpha d ; r -= alpha q */
+        for (int r = 0; r < R; ++r) w1[r] = delta[r] > 0 ? gamma[r] / delta[r] : 0.0;
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < N; ++i)
+            for (int r = 0; r < R; ++r) {
+                x[(size_t)i * R + r] += w1[r] * d[(size_t)i * R + r];
+                rp[(size_t)i * R + r] -= w1[r] * qp[(size_t)i * R + r];
+            }
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < (int64_t)M; ++i)
+            for (int r = 0; r < R; ++r) rd[i * R + r] -= w1[r] * qd[i * R + r];
+        if (resid) {
+            double *a1 = delta, *a2 = w2;
+            sumsq(M, R, rd, a1); sumsq((size_t)N, R, rp, a2);
+            for (int r = 0; r < R; ++r) resid[(size_t)r * (n_iter + 1) + k] = sqrt(a1[r] + a2[r]);
+        }
+        if (k == n_iter) break;
+        /* s = G_ext^T r */
+        GEXT_T(s);
+        if (reorth) {
+            for (int pass = 0; pass < 2; ++pass) {
+                /* coefficients c_j = Q_j^T s, j < k, all from the same s */
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int j = 0; j < k; ++j) dotr(NR / R, R, Q + (size_t)j * NR, s, coef + (size_t)j * R);
+                /* s -= sum_j c_j Q_j */
+#pragma omp parallel for schedule(static)
+                for (int i = 0; i < N; ++i)
+                    for (int j = 0; j < k; ++j)
+                        for (int r = 0; r < R; ++r)
+                            s[(size_t)i * R + r] -= coef[(size_t)j * R + r] * Q[(size_t)j * NR + (size_t)i * R + r];
+            }
+        }
+        sumsq((size_t)N, R, s, w1);
+        if (reorth)
+            for (size_t i = 0; i < N; ++i)
+                for (int r = 0; r < R; ++r)
+                    Q[(size_t)k * NR + i * R + r] = w1[r] > 0 ? s[i * R + r] / sqrt(w1[r]) : 0.0;
+        /* beta = gamma_new / gamma ; d = s + beta d */
+        for (int r = 0; r < R; ++r) {
+            w2[r] = gamma[r] > 0 ? w1[r] / gamma[r] : 0.0;
+            gamma[r] = w1[r];
+        }
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < N; ++i)
+            for (int r = 0; r < R; ++r) d[(size_t)i * R + r] = s[(size_t)i * R + r] + w2[r] * d[(size_t)i * R + r];
+    }
+#undef GEXT_T
+    free(rd); free(qd); free(rp); free(qp); free(s); free(d); free(tmp); free(Q);
+    free(gamma); free(delta); free(w1); free(w2); free(coef);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* RTO samples, Algorithm 1 with the right-hand side of eq. (extended-matrices) */
+/* ------------------------------------------------------------------ */
+
+/* S posterior samples at once.  The perturbed problem is
+ *   min_p sigma^{-2} ||G p - (y + sigma eta)||^2 + ||L (p - p_prior)||^2,
+ * p_prior = L^{-1} xi, so b = ( (y + sigma eta)/sigma ; L p_prior ) = ( y/sigma + eta ; xi ).
+ *   yobs [N_T][n_obs]; eta [N_T][n_obs][S]; xi [N][S]; samples [N][S]. */
+int orc_rto(const oproblem *P, int S, const double *yobs, double sigma, double prior_a, int n_iter, int reorth,
+            const double *eta, const double *xi, double *samples, double *resid) {
+    const size_t M = (size_t)P->n_steps * P->n_obs;
+    double *bd = malloc(sizeof(double) * M * S);
+    if (!bd) return -1;
+    for (size_t i = 0; i < M; ++i)
+        for (int r = 0; r < S; ++r) bd[i * S + r] = yobs[i] / sigma + eta[i * S + r];
+    int rc = orc_cgls(P, S, sigma, prior_a, n_iter, reorth, bd, xi, samples, resid);
+    free(bd);
+    return rc;
+}
+
+/* Pointwise mean and standard deviation (1/(S-1) normalisation) of samples [N][S]. */
+void orc_stats(int N, int S, const double *samples, double *mean, double *std) {
+    for (int i = 0; i < N; ++i) {
+        double m = 0.0;
+        for (int r = 0; r < S; ++r) m += samples[(size_t)i * S + r];
+        m /= S;
+        double v = 0.0;
+        for (int r = 0; r < S; ++r) {
+            double d = samples[(size_t)i * S + r] - m;
+            v += d * d;
+        }
+        mean[i] = m;
+        std[i] = S > 1 ? sqrt(v / (S - 1)) : 0.0;
+    }
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

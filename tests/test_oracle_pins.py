@@ -1,0 +1,449 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here compares the oracle with something other than itself: closed
+forms (7-point stencil of the Kuhn split, boundary integrals of linear
+functions, d'Alembert's radial solution), exact invariants of the Stormer-Verlet
+step (discrete energy), the paper's block-matrix and factored forms of the
+propagator, dense transposes, Krylov-space minimisers and the exact posterior
+of App. A.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import _dense
+
+
+def _tiny_ball(n=4, n_steps=20, n_sens=8, absorbing=True, variable_c=True):
+    coords, tets = W.ball_mesh(n)
+    c = W.wave_speed_bumps(coords, tets, seed=2, r_taper=(0.3, 0.6), r_centres=0.3) if variable_c else None
+    h = 2.0 / n
+    P = oracle.Problem(coords, tets, c, absorbing, 0.2 * h, n_steps, sensor_pos=W.fibonacci_sphere(n_sens, 0.7))
+    return P, coords, tets, c
+
+
+@pytest.fixture(scope="module")
+def cube8():
+    w = W.make_workload("cube8_tiny")
+    return w, oracle.Problem.from_workload(w)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return _tiny_ball()
+
+
+def _faces_numpy(tets):
+    """Boundary faces (node triples) by counting sorted face keys with numpy."""
+    f = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    fs = np.sort(f, axis=1)
+    u, idx, cnt = np.unique(fs, axis=0, return_index=True, return_counts=True)
+    return f[idx[cnt == 1]]
+
+
+# ---------------------------------------------------------------------------
+# Assembly (Sec. 3, matrices under eq. (semi-discrete); lumped mass)
+# ---------------------------------------------------------------------------
+
+def test_kuhn_cube_interior_stencil(cube8):
+    """On the Kuhn-split cube with c = 1, interior rows of K are h*(6, -1 x 6) and M_L = h^3."""
+    w, P = cube8
+    n = 8
+    h = 1.0 / n
+    K = P.matrix("K").toarray()
+    m = P.lumped_mass()
+    for k in range(1, n):
+        for j in range(1, n):
+            for i in range(1, n):
+                row = i + (n + 1) * (j + (n + 1) * k)
+                expect = np.zeros(K.shape[0])
+                expect[row] = 6 * h
+                for d in (1, n + 1, (n + 1) ** 2):
+                    expect[row + d] = expect[row - d] = -h
+                np.testing.assert_allclose(K[row], expect, atol=1e-15)
+                assert abs(m[row] - h ** 3) < 1e-17
+
+
+def test_constant_speed_scales_stiffness():
+    """K scales with c^2 and B with 1/c for a constant speed c."""
+    coords, tets = W.ball_mesh(4)
+    h = 0.5
+    P1 = oracle.Problem(coords, tets, None, True, 0.1 * h, 2, sensor_nodes=[0])
+    P2 = oracle.Problem(coords, tets, np.full(tets.shape[0], 1.5), True, 0.1 * h, 2, sensor_nodes=[0])
+    np.testing.assert_allclose(P2.matrix("K").toarray(), 2.25 * P1.matrix("K").toarray(), rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(P2.matrix("B").toarray(), P1.matrix("B").toarray() / 1.5, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(P2.matrix("K1").toarray(), P1.matrix("K").toarray(), rtol=1e-14, atol=1e-16)
+
+
+@pytest.mark.parametrize("mesh", ["cube", "ball"])
+def test_stiffness_identities(mesh):
+    """K 1 = 0, K symmetric PSD, and u^T K u = |a|^2 vol for linear u = a.x (c = 1)."""
+    if mesh == "cube":
+        coords, tets = W.kuhn_cube(5, mirrored=True)
+    else:
+        coords, tets = W.ball_mesh(6)
+    P = oracle.Problem(coords, tets, None, True, 0.01, 2, sensor_nodes=[0])
+    K = P.matrix("K").toarray()
+    m = P.lumped_mass()
+    assert np.abs(K.sum(axis=1)).max() < 1e-14
+    assert np.abs(K - K.T).max() < 1e-16
+    assert np.linalg.eigvalsh(K).min() > -1e-13
+    vol = _volume_divergence(coords, tets)
+    assert abs(m.sum() - vol) < 1e-13 * vol
+    a = np.array([0.3, -1.2, 0.7])
+    u = coords @ a
+    assert abs(u @ K @ u - a @ a * vol) < 1e-12 * vol
+
+
+def _volume_divergence(coords, tets):
+    """Polyhedron volume from its boundary faces, V = (1/3) sum over faces of x . n dA."""
+    faces = _faces_numpy(tets)
+    # orient each face outward using the centroid of its own tetrahedron's opposite vertex
+    f = np.sort(faces, axis=1)
+    allf = np.concatenate([np.sort(tets[:, [1, 2, 3]], axis=1), np.sort(tets[:, [0, 2, 3]], axis=1),
+                           np.sort(tets[:, [0, 1, 3]], axis=1), np.sort(tets[:, [0, 1, 2]], axis=1)])
+    opp = np.concatenate([tets[:, 0], tets[:, 1], tets[:, 2], tets[:, 3]])
+    key = {tuple(k): o for k, o in zip(map(tuple, allf), opp)}
+    vol = 0.0
+    for tri in f:
+        x0, x1, x2 = coords[tri[0]], coords[tri[1]], coords[tri[2]]
+        nrm = np.cross(x1 - x0, x2 - x0)
+        if np.dot(nrm, x0 - coords[key[tuple(tri)]]) < 0:
+            nrm = -nrm
+        vol += np.dot(x0, nrm) / 6.0
+    return vol
+
+
+def test_boundary_mass_cube_closed_form():
+    """1^T B 1 = area(boundary) = 6 and x^T B x = int_boundary x^2 dS = 7/3 on the unit cube."""
+    coords, tets = W.kuhn_cube(4)
+    P = oracle.Problem(coords, tets, None, True, 0.01, 2, sensor_nodes=[0])
+    B = P.matrix("B").toarray()
+    one = np.ones(coords.shape[0])
+    assert abs(one @ B @ one - 6.0) < 1e-13
+    x = coords[:, 0]
+    assert abs(x @ B @ x - 7.0 / 3.0) < 1e-13
+    xy = coords[:, 0] + 2 * coords[:, 1]
+    # int over the cube surface of (x + 2y)^2: faces x=0,1: int (x+2y)^2 dy dz ; y=0,1 ; z=0,1
+    exact = (4.0 / 3.0) + (1 + 2 + 4.0 / 3.0) + (1.0 / 3.0) + (1.0 / 3.0 + 2 + 4) + 2 * (1.0 / 3.0 + 1 + 4.0 / 3.0)
+    assert abs(xy @ B @ xy - exact) < 1e-12
+    interior = np.ones(coords.shape[0], bool)
+    interior[W.cube_boundary_nodes(4)] = False
+    assert np.abs(B[interior]).max() == 0.0
+    assert np.linalg.eigvalsh(B).min() > -1e-15
+
+
+def test_boundary_mass_ball_area():
+    """1^T B 1 equals the polyhedral surface area (independent face count) and tends to 4 pi."""
+    coords, tets = W.ball_mesh(16)
+    P = oracle.Problem(coords, tets, None, True, 0.01, 2, sensor_nodes=[0])
+    faces = _faces_numpy(tets)
+    area = 0.5 * np.linalg.norm(np.cross(coords[faces[:, 1]] - coords[faces[:, 0]],
+                                         coords[faces[:, 2]] - coords[faces[:, 0]]), axis=1).sum()
+    B = P.matrix("B")
+    assert abs(B.sum() - area) < 1e-12 * area
+    assert abs(area - 4 * math.pi) < 0.005 * 4 * math.pi
+    Pr = oracle.Problem(coords, tets, None, False, 0.01, 2, sensor_nodes=[0])
+    assert Pr.matrix("B").nnz == 0
+
+
+def test_sensor_interpolation_reproduces_linear():
+    """Barycentric Pi reproduces linear functions at the sensor points; weights sum to 1."""
+    coords, tets = W.ball_mesh(8)
+    pts = W.fibonacci_sphere(50, 0.9)
+    P = oracle.Problem(coords, tets, None, True, 0.01, 2, sensor_pos=pts)
+    nodes, wts = P.sensors()
+    assert np.all(wts > -1e-12)
+    np.testing.assert_allclose(wts.sum(axis=1), 1.0, atol=1e-14)
+    recon = np.einsum("sk,skd->sd", wts, coords[nodes])
+    np.testing.assert_allclose(recon, pts, atol=1e-14)
+    with pytest.raises(ValueError):
+        oracle.Problem(coords, tets, None, True, 0.01, 2, sensor_pos=np.array([[2.0, 0.0, 0.0]]))
+
+
+# ---------------------------------------------------------------------------
+# Forward step and forward map (Sec. 3 eqs. (fully-discrete), (matrix-stromer),
+# (discrete-wave-matrix); App. B)
+# ---------------------------------------------------------------------------
+
+def test_step_matches_block_propagator(tiny):
+    P = tiny[0]
+    K, B, m = P.matrix("K").toarray(), P.matrix("B").toarray(), P.lumped_mass()
+    A = _dense.propagator_block(K, B, m, P.dt)
+    S1, S2, S3, S4 = _dense.propagator_factors(K, B, m, P.dt)
+    np.testing.assert_allclose(S4 @ S3 @ S2 @ S1, A, atol=1e-14)
+    N = P.n_nodes
+    rng = np.random.default_rng(0)
+    p, v = rng.standard_normal((3, N)), rng.standard_normal((3, N))
+    pn, vn = P.step(p, v)
+    z = A @ np.hstack([p, v]).T
+    np.testing.assert_allclose(np.hstack([pn, vn]).T, z, rtol=0, atol=1e-13 * np.abs(z).max())
+
+
+def test_transpose_step_matches_block_transpose(tiny):
+    P = tiny[0]
+    K, B, m = P.matrix("K").toarray(), P.matrix("B").toarray(), P.lumped_mass()
+    A = _dense.propagator_block(K, B, m, P.dt)
+    S1, S2, S3, S4 = _dense.propagator_factors(K, B, m, P.dt)
+    np.testing.assert_allclose(S1.T @ S2.T @ S3.T @ S4.T, A.T, atol=1e-14)
+    N = P.n_nodes
+    rng = np.random.default_rng(1)
+    ph, vh = rng.standard_normal((2, N)), rng.standard_normal((2, N))
+    a, b = P.step_transpose(ph, vh)
+    z = A.T @ np.hstack([ph, vh]).T
+    np.testing.assert_allclose(np.hstack([a, b]).T, z, rtol=0, atol=1e-13 * np.abs(z).max())
+
+
+def test_forward_map_matches_dense_powers(tiny):
+    P = tiny[0]
+    K, B, m = P.matrix("K").toarray(), P.matrix("B").toarray(), P.lumped_mass()
+    A = _dense.propagator_block(K, B, m, P.dt)
+    nodes, wts = P.sensors()
+    Pi = _dense.sensor_matrix(nodes, wts, P.n_nodes)
+    G = _dense.forward_matrix(A, Pi, P.n_steps)
+    cols = P.forward(np.eye(P.n_nodes))                     # [N][N_T][N_obs]: column i = G e_i
+    Gor = cols.reshape(P.n_nodes, -1).T
+    np.testing.assert_allclose(Gor, G, rtol=0, atol=1e-12 * np.abs(G).max())
+
+
+def test_dense_transpose(tiny):
+    """G^T assembled column by column from the backward recursion equals (G)^T."""
+    P = tiny[0]
+    N, M = P.n_nodes, P.n_steps * P.n_obs
+    G = P.forward(np.eye(N)).reshape(N, -1).T
+    GT = P.adjoint(np.eye(M).reshape(M, P.n_steps, P.n_obs))   # row j = G^T e_j
+    np.testing.assert_allclose(GT, G, rtol=0, atol=1e-13 * np.abs(G).max())
+
+
+@pytest.mark.parametrize("name", ["cube8_tiny", "ball16"])
+def test_transpose_identity(name):
+    """<G p, yhat> = <p, G^T yhat> to 1e-13 relative (Sec. 6.1)."""
+    w = W.make_workload(name)
+    P = oracle.Problem.from_workload(w)
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal((2, P.n_nodes))
+    yh = rng.standard_normal((2, P.n_steps, P.n_obs))
+    lhs = np.einsum("rts,rts->r", P.forward(p), yh)
+    rhs = np.einsum("rn,rn->r", p, P.adjoint(yh))
+    assert np.all(np.abs(lhs - rhs) <= 1e-13 * np.abs(lhs))
+
+
+def _energy(K, m, p, v, dt):
+    return 0.5 * np.sum(m * v * v) + 0.5 * p @ (K @ p) - dt ** 2 / 8 * v @ (K @ v)
+
+
+def test_energy_conserved_without_absorption(cube8):
+    """B = 0: E = v'M_L v/2 + p'Kp/2 - dt^2 v'Kv/8 is invariant under the step."""
+    w, P = cube8
+    K, m = P.matrix("K"), P.lumped_mass()
+    p, v = w.p0_true.copy(), np.zeros(P.n_nodes)
+    e0 = _energy(K, m, p, v, P.dt)
+    for _ in range(200):
+        p, v = (a[0] for a in P.step(p, v))
+        assert abs(_energy(K, m, p, v, P.dt) - e0) < 1e-13 * e0
+
+
+def test_energy_balance_with_absorption():
+    """With B: E^{n+1} - E^n = -(dt/2) v^n' B (v^n + v^{n+1}) exactly; energy decays."""
+    coords, tets = W.ball_mesh(8)
+    h = 0.25
+    P = oracle.Problem(coords, tets, None, True, 0.2 * h, 2, sensor_nodes=[0])
+    K, B, m = P.matrix("K"), P.matrix("B"), P.lumped_mass()
+    p, v = W.smooth_bump(coords, 0.6), np.zeros(P.n_nodes)
+    e = _energy(K, m, p, v, P.dt)
+    e_first = e
+    for _ in range(150):
+        pn, vn = (a[0] for a in P.step(p, v))
+        en = _energy(K, m, pn, vn, P.dt)
+        expect = -(P.dt / 2) * v @ (B @ (v + vn))
+        assert abs((en - e) - expect) < 1e-13 * e_first
+        p, v, e = pn, vn, en
+    assert e < 0.5 * e_first
+
+
+def test_radial_bump_second_order():
+    """Smooth radial p0: sensor traces converge to d'Alembert's p = [(r-t)p0(|r-t|)+(r+t)p0(r+t)]/(2r)."""
+    errs = []
+    R, r = 0.3, 0.5
+    f = lambda s: np.where(np.abs(s) < R, (1 - (s / R) ** 2) ** 3, 0.0)
+    for n in (16, 32):
+        coords, tets = W.ball_mesh(n)
+        h = 2.0 / n
+        dt = 0.2 * h
+        nt = int(round(0.85 / dt))
+        sens = np.array([[r, 0, 0], [0, -r, 0], [0, 0, r]])
+        P = oracle.Problem(coords, tets, None, True, dt, nt, sensor_pos=sens)
+        t = dt * np.arange(1, nt + 1)
+        y = P.forward(W.smooth_bump(coords, R))
+        ex = ((r - t) * f(np.abs(r - t)) + (r + t) * f(r + t)) / (2 * r)
+        errs.append(np.sqrt(np.mean((y - ex[:, None]) ** 2)) / np.sqrt(np.mean(ex ** 2)))
+    assert errs[1] < 0.4 * errs[0]          # at least ~1.3 order from h to h/2
+    assert errs[1] < 0.3
+
+
+def test_uniform_ball_n_wave():
+    """Uniform ball of initial pressure: N-wave A(r-t)/(2r) for |r-t| < R at a sensor at radius r.
+
+    The nodal indicator has effective radius R_eff = (3 sum M_L p0 / 4pi)^(1/3); the
+    time-integrated trace converges to that of the closed form under refinement."""
+    R, r = 0.3, 0.5
+    errs = []
+    for n in (16, 48):
+        coords, tets = W.ball_mesh(n)
+        h = 2.0 / n
+        dt = 0.2 * h
+        nt = int(round(0.85 / dt))
+        P = oracle.Problem(coords, tets, None, True, dt, nt, sensor_pos=np.array([[r, 0, 0], [0, 0, -r]]))
+        p0 = W.uniform_ball(coords, R)
+        Reff = (3 * np.sum(P.lumped_mass() * p0) / (4 * math.pi)) ** (1 / 3)
+        t = dt * np.arange(1, nt + 1)
+        y = P.forward(p0)
+        ex = np.where(np.abs(r - t) < Reff, (r - t) / (2 * r), 0.0)
+        cy, ce = np.cumsum(y, axis=0) * dt, np.cumsum(ex) * dt
+        errs.append(np.abs(cy - ce[:, None]).max() / np.abs(ce).max())
+        pos = (t > r - Reff) & (t < r)
+        neg = (t > r) & (t < r + Reff)
+        assert np.all(y[pos].mean(axis=0) > 0) and np.all(y[neg].mean(axis=0) < 0)
+    assert errs[1] < 0.12 and errs[1] < 0.6 * errs[0]
+
+
+# ---------------------------------------------------------------------------
+# Prior factor, CGLS and RTO (Sec. 5 eqs. (extended-matrices), (normal-equations);
+# Algorithm 1; App. A)
+# ---------------------------------------------------------------------------
+
+def _gext_dense(P, sigma, a):
+    N = P.n_nodes
+    G = P.forward(np.eye(N)).reshape(N, -1).T
+    L = P.prior_apply(np.eye(N), a).T          # column i = L e_i
+    return G, L, np.vstack([G / sigma, L])
+
+
+def test_prior_factor_properties(tiny):
+    P = tiny[0]
+    N = P.n_nodes
+    m = P.lumped_mass()
+    rng = np.random.default_rng(2)
+    x, y = rng.standard_normal(N), rng.standard_normal(N)
+    for a in (0.0, 0.05):
+        Lx = P.prior_apply(x, a)
+        assert abs(Lx @ y - x @ P.prior_apply(y, a, transpose=True)) < 1e-13 * np.abs(Lx).max() * np.abs(y).sum()
+        one = P.prior_apply(np.ones(N), a)               # K1 1 = 0  =>  L 1 = M_L^{1/2} 1
+        np.testing.assert_allclose(one, np.sqrt(m), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(P.prior_apply(x, 0.0), np.sqrt(m) * x, rtol=1e-15)
+
+
+@pytest.mark.parametrize("reorth", [True, False])
+def test_cgls_iterates_are_krylov_minimisers(tiny, reorth):
+    P = tiny[0]
+    sigma, a = 0.05, 0.02
+    G, L, A = _gext_dense(P, sigma, a)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(A.shape[0])
+    bd = b[: G.shape[0]].reshape(1, P.n_steps, P.n_obs)
+    bp = b[G.shape[0]:].reshape(1, -1)
+    Atb = A.T @ b
+    V = np.zeros((A.shape[1], 0))
+    w = Atb.copy()
+    for k in range(1, 7):
+        # orthonormal basis of K_k(A^T A, A^T b), two Gram-Schmidt passes
+        for _ in range(2):
+            w -= V @ (V.T @ w)
+        V = np.hstack([V, (w / np.linalg.norm(w))[:, None]])
+        w = A.T @ (A @ V[:, -1])
+        y, *_ = np.linalg.lstsq(A @ V, b, rcond=None)
+        xk = V @ y
+        x, res = P.cgls(bd, bp, sigma, a, k, reorth=reorth)
+        assert np.linalg.norm(x[0] - xk) < 1e-9 * np.linalg.norm(xk)
+        assert abs(res[0, -1] - np.linalg.norm(A @ x[0] - b)) < 1e-10 * np.linalg.norm(b)
+
+
+def test_cgls_converges_to_least_squares(tiny):
+    P = tiny[0]
+    sigma, a = 0.05, 0.02
+    G, L, A = _gext_dense(P, sigma, a)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal((2, A.shape[0]))
+    bd = b[:, : G.shape[0]].reshape(2, P.n_steps, P.n_obs)
+    bp = b[:, G.shape[0]:]
+    x, _ = P.cgls(bd, bp, sigma, a, 2 * P.n_nodes, reorth=True)
+    for r in range(2):
+        xs, *_ = np.linalg.lstsq(A, b[r], rcond=None)
+        assert np.linalg.norm(x[r] - xs) < 1e-8 * np.linalg.norm(xs)
+
+
+def test_rto_sample_is_closed_form(tiny):
+    """Converged RTO sample = C_post [G^T y / sigma^2 + G^T eta / sigma + L^T L p_prior] (App. A)."""
+    P = tiny[0]
+    sigma, a = 0.05, 0.02
+    G, L, _ = _gext_dense(P, sigma, a)
+    N = P.n_nodes
+    rng = np.random.default_rng(6)
+    yobs = G @ rng.standard_normal(N) + sigma * rng.standard_normal(G.shape[0])
+    S = 3
+    eta = rng.standard_normal((S, P.n_steps, P.n_obs))
+    xi = rng.standard_normal((S, N))
+    samples, _ = P.rto(yobs.reshape(P.n_steps, P.n_obs), sigma, a, 2 * N, eta, xi)
+    Cpost = np.linalg.inv(G.T @ G / sigma ** 2 + L.T @ L)
+    for s in range(S):
+        p_prior = np.linalg.solve(L, xi[s])
+        ref = Cpost @ (G.T @ yobs / sigma ** 2 + G.T @ eta[s].ravel() / sigma + L.T @ L @ p_prior)
+        assert np.linalg.norm(samples[s] - ref) < 1e-8 * np.linalg.norm(ref)
+
+
+def test_rto_distribution_matches_posterior():
+    """Converged RTO samples have mean mu_post and covariance C_post (App. A), statistically."""
+    P, *_ = _tiny_ball(n=3, n_steps=15, n_sens=6)
+    sigma, a = 0.05, 0.02
+    G, L, _ = _gext_dense(P, sigma, a)
+    N = P.n_nodes
+    rng = np.random.default_rng(7)
+    yobs = G @ rng.standard_normal(N) + sigma * rng.standard_normal(G.shape[0])
+    Cpost = np.linalg.inv(G.T @ G / sigma ** 2 + L.T @ L)
+    mu = Cpost @ G.T @ yobs / sigma ** 2
+    S = 3000
+    eta = rng.standard_normal((S, P.n_steps, P.n_obs))
+    xi = rng.standard_normal((S, N))
+    samples, _ = P.rto(yobs.reshape(P.n_steps, P.n_obs), sigma, a, 2 * N, eta, xi)
+    sd = np.sqrt(np.diag(Cpost))
+    z = (samples.mean(axis=0) - mu) / (sd / math.sqrt(S))
+    assert np.abs(z).max() < 4.5
+    var_ratio = samples.var(axis=0, ddof=1) / sd ** 2
+    assert np.abs(var_ratio - 1).max() < 5 * math.sqrt(2.0 / (S - 1))
+    C = np.cov(samples.T)
+    assert np.linalg.norm(C - Cpost) / np.linalg.norm(Cpost) < 6 / math.sqrt(S)
+
+
+def test_stats_match_numpy():
+    rng = np.random.default_rng(8)
+    s = rng.standard_normal((7, 40)) * 3 + 1
+    mean, std = oracle.stats(s)
+    np.testing.assert_allclose(mean, s.mean(axis=0), rtol=1e-14)
+    np.testing.assert_allclose(std, s.std(axis=0, ddof=1), rtol=1e-13)
+
+
+def test_noise_rule_gives_relative_level():
+    """sigma from eq. (noise-model): ||sigma eta0|| / ||Y|| = d_noise exactly."""
+    rng = np.random.default_rng(9)
+    Y, e0 = rng.standard_normal((50, 12)), rng.standard_normal((50, 12))
+    s = oracle.noise_sigma(Y, e0, 0.01, "l2")
+    assert abs(np.linalg.norm(s * e0) / np.linalg.norm(Y) - 0.01) < 1e-15
+    assert oracle.noise_sigma(Y, e0, 0.01, "max") == 0.01 * np.abs(Y).max()
+
+
+def test_batched_rhs_equal_single_rhs(tiny):
+    """Right-hand sides are independent: a batch of R gives bitwise the R single results."""
+    P = tiny[0]
+    rng = np.random.default_rng(10)
+    p = rng.standard_normal((3, P.n_nodes))
+    yh = rng.standard_normal((3, P.n_steps, P.n_obs))
+    yb, pb = P.forward(p), P.adjoint(yh)
+    xb, _ = P.cgls(yh, p, 0.1, 0.01, 7)
+    for r in range(3):
+        assert np.array_equal(yb[r], P.forward(p[r]))
+        assert np.array_equal(pb[r], P.adjoint(yh[r]))
+        x1, _ = P.cgls(yh[r:r + 1], p[r:r + 1], 0.1, 0.01, 7)
+        assert np.array_equal(xb[r], x1[0])
