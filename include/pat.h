@@ -1,0 +1,143 @@
+/*
+ * pat.h -- C ABI of libpat, the MI355X (gfx950) implementation of the
+ * matrix-free randomize-then-optimize (RTO) posterior sampler for 3D
+ * photoacoustic tomography of "3D Uncertainty Quantification for
+ * Photoacoustic Tomography" (arXiv 2607.21373).
+ *
+ * Conventions for every entry point:
+ *  - Device buffers are plain device pointers owned by the caller (for example
+ *    PyTorch allocations).  The library never frees them and never keeps them
+ *    beyond the call's stream order.  Host arrays in pat_problem_desc are copied
+ *    during pat_problem_create.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *    device work is enqueued on it asynchronously; results are ready when the
+ *    stream has reached the point of the call.
+ *  - Node-indexed vectors use the caller's node numbering (the library reorders
+ *    nodes internally and converts at the boundary).
+ *  - Errors: validation failures return a negative pat_status before any device
+ *    work is enqueued and leave outputs untouched.  pat_last_error() returns a
+ *    thread-local message for the last failing call on the calling thread.
+ *    Asynchronous device faults surface at a later call or at pat_sync().
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PAT_OK = 0,
+    PAT_ERR_INVALID_ARG = -1,   /* bad sizes, NULL pointers, ids out of range, sensor outside the mesh */
+    PAT_ERR_UNSTABLE_DT = -2,   /* dt fails the stability check at create */
+    PAT_ERR_NONFINITE = -3,     /* non-finite input or a non-finite CGLS scalar */
+    PAT_ERR_OUT_OF_MEMORY = -4, /* host or device allocation failed */
+    PAT_ERR_HIP = -5,           /* a HIP runtime call failed (including: no device) */
+    PAT_ERR_INTERNAL = -6
+} pat_status;
+
+typedef enum {
+    PAT_F64 = 0,  /* float64 state and matrices */
+    PAT_F32 = 1   /* float32 state and matrices */
+} pat_precision;
+
+typedef struct pat_problem pat_problem;
+
+/* Discrete problem of Sec. 3 (P1 tetrahedra, lumped mass, Stormer-Verlet). */
+typedef struct {
+    int32_t n_nodes;            /* N */
+    const double *coords;       /* host [N][3] node coordinates */
+    int64_t n_tets;             /* E */
+    const int32_t *tets;        /* host [E][4] node ids of each tetrahedron */
+    const double *c_tet;        /* host [E] wave speed per tetrahedron, or NULL for c = 1 */
+    int32_t absorbing;          /* 1: first-order absorbing boundary (Sec. 2 eq. (boundary)), 0: reflecting */
+    int32_t n_obs;              /* number of sensors */
+    const int32_t *sensor_nodes;/* host [n_obs] node ids (sensors at nodes, Sec. 3 eq. (lagrange)), or NULL */
+    const double *sensor_pos;   /* host [n_obs][3] sensor points (P1 interpolation in the containing tet), or NULL */
+    double dt;                  /* time step */
+    int32_t n_steps;            /* N_T: data at t_n = n dt, n = 1..N_T */
+    int32_t device;             /* HIP device ordinal, -1 = current device */
+    int32_t check_dt;           /* 1: reject dt that fails the stability check, 0: skip the check */
+} pat_problem_desc;
+
+typedef struct {
+    int32_t n_nodes, n_obs, n_steps;
+    int64_t n_tets, nnz_k, nnz_b;
+    int32_t n_boundary_nodes, max_row_nnz;
+    double dt, lambda_max;      /* lambda_max: estimate of the largest eigenvalue of M_L^{-1} K */
+    int64_t device_bytes;       /* device memory held by the handle (matrices + workspaces) */
+} pat_problem_info;
+
+/* Assemble K (c^2 stiffness), K1 (unit-coefficient stiffness), the lumped mass
+ * M_L = diag(M 1) and the consistent boundary mass B of Sec. 3 (matrices below
+ * eq. (semi-discrete)); locate the sensors; check dt; upload to the device.
+ * Exactly one of sensor_nodes / sensor_pos must be given.  On success *out owns
+ * the device copies; release with pat_problem_destroy. */
+pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out);
+pat_status pat_problem_destroy(pat_problem *p);
+pat_status pat_problem_get_info(const pat_problem *p, pat_problem_info *out);
+
+/* Forward map Y = G p0 of Sec. 3 eq. (discrete-wave-matrix): z0 = (p0, 0),
+ * z^n = A_dt^n z0, Y[n-1][s] = (Pi z^n)_s for n = 1..N_T.
+ *   p0 device [R][N], y device [R][N_T][N_obs]; both of type `prec`. */
+pat_status pat_forward(pat_problem *p, int64_t R, const void *p0, void *y, pat_precision prec, void *stream);
+
+/* Transpose map p = G^T yhat of Sec. 5.1 eqs. (transpose-definition),
+ * (backward-recursion) and (adjoint-verlet): exact transpose of pat_forward in
+ * exact arithmetic.  yhat device [R][N_T][N_obs], p device [R][N]; type `prec`. */
+pat_status pat_adjoint(pat_problem *p, int64_t R, const void *yhat, void *p_out, pat_precision prec, void *stream);
+
+/* Parameters of the RTO sampler (Sec. 5 eq. (optimization), Algorithm 1). */
+typedef struct {
+    double sigma;              /* noise standard deviation (> 0) */
+    double prior_a;            /* prior factor L = M_L^{-1/2}(M_L + a K1); a = 0 gives M_L^{1/2}, eq. (iid-prior) */
+    int32_t n_iter;            /* CGLS iterations (fixed; >= 1) */
+    int32_t reorth;            /* 1: full reorthogonalisation of the normal-equation residuals (default) */
+    pat_precision sweep_prec;  /* precision of the wave sweeps; CGLS vectors and scalars are always float64 */
+    int32_t rhs_block;         /* samples per multi-RHS block: 0 = automatic, else 1, 2, 4, ..., 64 */
+    const double *eta;         /* device [S][N_T][N_obs] standard-normal data perturbations */
+    const double *xi;          /* device [S][N] standard-normal prior perturbations */
+} pat_rto_params;
+
+/* S posterior samples by RTO.  Sample k solves
+ *   min_p || G_ext p - b_k ||_2,  G_ext = [G/sigma ; L],  b_k = [y_obs/sigma + eta_k ; xi_k]
+ * (eq. (extended-matrices) with p_prior = L^{-1} xi_k) by CGLS from p = 0.
+ *   y_obs       device [N_T][N_obs] float64
+ *   samples     device [S][N] float64 (required)
+ *   mean, std   device [N] float64 or NULL: pointwise mean and standard deviation
+ *               with 1/(S-1) normalisation (eq. (ergodic)); std needs S >= 2
+ *   resid_hist  device [S][n_iter+1] float64 or NULL: ||b_k - G_ext p_k^{(j)}||_2 per iteration
+ * Scratch memory is owned by the handle and grows to the largest block seen. */
+pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params *prm, int64_t S,
+                      double *samples, double *mean, double *std, double *resid_hist, void *stream);
+
+/* Host-only view of the setup (no device is touched): runs the validation and
+ * assembly of pat_problem_create and copies the assembled operators out in the
+ * caller's node numbering.  Call once with rowptr == NULL to get the sizes in
+ * *nnz_out (entries of the stiffness pattern); then pass
+ *   rowptr [N+1], col [nnz], kval [nnz] (K), k1val [nnz] (K1), bval [nnz] (B on
+ *   the same pattern, zero off the boundary), mass [N] (M_L), snode [n_obs][4],
+ *   sw [n_obs][4] (sensor interpolation nodes and weights), lambda_max [1].
+ * For tests and diagnostics; returns the same status pat_problem_create would
+ * return for the descriptor up to the device steps. */
+pat_status pat_host_assemble(const pat_problem_desc *desc, int64_t *nnz_out, int32_t *rowptr, int32_t *col,
+                             double *kval, double *k1val, double *bval, double *mass, int32_t *snode, double *sw,
+                             double *lambda_max);
+
+/* Wait for all work of the handle's device, report asynchronous errors. */
+pat_status pat_sync(pat_problem *p);
+
+/* Thread-local description of the last error ("" if none). */
+const char *pat_last_error(void);
+
+/* Library version string. */
+const char *pat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAT_H */

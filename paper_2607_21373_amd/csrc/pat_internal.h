@@ -1,0 +1,53 @@
+// Internal declarations shared by the host setup (pat_setup.cpp) and the
+// device code (pat_api.hip, pat_kernels.hip) of libpat.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pat.h"
+
+namespace pat {
+
+// Host-side assembled problem, all node indices in the library's internal order.
+struct HostProblem {
+    int32_t n = 0;          // nodes
+    int32_t n_obs = 0;
+    int32_t n_steps = 0;
+    int64_t n_tets = 0;
+    double dt = 0.0;
+    // stiffness pattern (CSR, columns ascending) shared by K and K1
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> kval, k1val;
+    // boundary mass: for a boundary row i, boff[i] >= 0 and B(i, col[k]) = bval[boff[i] + k - rowptr[i]]
+    // for k in [rowptr[i], rowptr[i+1]); interior rows have boff[i] = -1
+    std::vector<int32_t> boff;
+    std::vector<double> bval;
+    int64_t nnz_b = 0;
+    int32_t n_boundary = 0;
+    int32_t max_row = 0;
+    std::vector<double> mass;          // lumped mass diag(M 1)
+    // sensors: 4 (node, weight) pairs each; node-coincident sensors use one weight 1
+    std::vector<int32_t> snode;        // [n_obs][4]
+    std::vector<double> sw;            // [n_obs][4]
+    // transpose of the sensor operator as a node-major CSR: node i receives
+    // sum_e injw[e] * yhat[injs[e]] for e in [injptr[i], injptr[i+1])
+    std::vector<int32_t> injptr, injs;
+    std::vector<double> injw;
+    // internal <-> user numbering: perm[internal] = user, iperm[user] = internal
+    std::vector<int32_t> perm, iperm;
+    double lambda_max = 0.0;
+};
+
+// Assemble and validate; returns PAT_OK or an error with a message in *err.
+pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::string &err);
+
+// Largest eigenvalue of M_L^{-1} K by power iteration on M^{-1/2} K M^{-1/2}.
+double estimate_lambda_max(const HostProblem &hp, int iters);
+
+// Growth test of the explicit step (with the boundary term) in float64 on the host:
+// returns the ratio E_final / E_initial of the discrete energy after `steps` steps.
+double energy_growth(const HostProblem &hp, int steps);
+
+}  // namespace pat

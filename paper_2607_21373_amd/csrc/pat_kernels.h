@@ -1,0 +1,80 @@
+// Kernel launch interface of libpat (implemented in pat_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pat {
+
+// Device copy of the assembled operators (internal node numbering).
+struct DevOps {
+    int32_t n = 0, n_obs = 0, n_steps = 0;
+    int64_t nnz = 0;
+    const int32_t *rowptr = nullptr, *col = nullptr, *boff = nullptr;
+    const int32_t *snode = nullptr, *injptr = nullptr, *injs = nullptr, *perm = nullptr;
+    const double *kval64 = nullptr, *k1val64 = nullptr, *bval64 = nullptr, *dtm64 = nullptr;
+    const double *sqrtm = nullptr, *isqrtm = nullptr, *sw64 = nullptr, *injw64 = nullptr;
+    const float *kval32 = nullptr, *bval32 = nullptr, *dtm32 = nullptr, *sw32 = nullptr, *injw32 = nullptr;
+    double dt = 0.0;
+};
+
+enum class Prec { F64, F32 };
+
+// One forward Stormer-Verlet step on the staggered state (P = p^{n+1/2}, V = v^n),
+// optionally sampling y^{k} = Pi (P - dt/2 V) of the incoming state into
+// y_out[(t*n_obs + s)*RB + r] * yscale.  first != 0 treats V as zero.
+// rows = 0 launches only the sampling part.
+void launch_fwd_step(Prec prec, int RB, const DevOps &op, const void *P, const void *V, void *Pn, void *Vn,
+                     bool rows, bool first, bool sample, int t, void *y_out, bool y_is_f64, double yscale,
+                     hipStream_t s);
+
+// Transpose sweep: init (p = Pi^T yhat^{N_T}, q = dt/(2m) p) and one staggered
+// transpose step (p -= dt K q; unless last: q' = q - dt/m B q + dt/m (p + inj/2), p += inj,
+// inj = Pi^T yhat^{tm1}).  yhat[(t*n_obs + s)*RB + r] * yscale, f64 or the sweep type.
+void launch_adj_init(Prec prec, int RB, const DevOps &op, void *PH, void *Q, const void *yhat, bool y_is_f64,
+                     double yscale, hipStream_t s);
+void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1,
+                     const void *yhat, bool y_is_f64, double yscale, hipStream_t s);
+
+// Layout conversions.  Node vectors: user [R][N] (rows rb0..rb0+RB-1, zero-padded
+// past R) <-> internal [N][RB]; data: user [R][M] <-> internal [M][RB].
+void launch_pack(bool in_f64, bool out_f64, const void *in, int64_t R, int64_t rb0, int RB, int64_t cols,
+                 const int32_t *perm, void *out, hipStream_t s);
+void launch_unpack(bool in_f64, bool out_f64, const void *in, int64_t R, int64_t rb0, int RB, int64_t cols,
+                   const int32_t *perm, void *out, hipStream_t s);
+
+// CGLS helpers (all float64 unless noted; [rows][RB] layouts).
+void launch_fill(double *x, int64_t count, double v, hipStream_t s);
+void launch_cast_to_state(Prec prec, const double *x, void *P, int64_t count, hipStream_t s);
+void launch_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0, int RB, int64_t M, double isig,
+                      double *bd, hipStream_t s);
+void launch_prior(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s);
+void launch_gext_t_combine(Prec prec, const DevOps &op, int RB, double a, double isig, const void *PH,
+                           const double *rp, double *out, hipStream_t s);
+// partial sums: part[b][r] = sum over rows of block b of x*y (y == x gives squares)
+constexpr int kDotBlocks = 512;
+void launch_dot_partial(const double *x, const double *y, int64_t rows, int RB, double *part, hipStream_t s);
+// finalize: mode 0: out[r] = sum partA (+ sum partB if non-null)
+void launch_dot_final(const double *partA, const double *partB, int RB, double *out, hipStream_t s);
+// scalar stages of CGLS, on device arrays of length RB
+void launch_scalar_alpha(const double *gamma, const double *delta, double *alpha, int RB, hipStream_t s);
+void launch_scalar_gamma(double *gamma, const double *gnew, double *beta, double *invn, int first, int RB,
+                         hipStream_t s);
+void launch_resid(const double *a, const double *b, double *hist, int64_t ld, int64_t col, int64_t rb0, int64_t R,
+                  int RB, hipStream_t s);
+// x += alpha*d ; rp -= alpha*qp  (N rows)   and   rd -= alpha*qd (M rows)
+void launch_update_xr(double *x, const double *d, double *rp, const double *qp, const double *alpha, int64_t rows,
+                      int RB, hipStream_t s);
+void launch_axpy_neg(double *y, const double *x, const double *alpha, int64_t rows, int RB, hipStream_t s);
+// Q[k] = s * invn ; d = s + beta d
+void launch_append_dir(const double *sv, double *Qk, double *d, const double *invn, const double *beta, int first,
+                       int64_t rows, int RB, hipStream_t s);
+// reorthogonalisation: coef[j][r] = sum_i Q[j][i][r] s[i][r] (j < k); s -= sum_j coef[j] Q[j]
+void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *coef,
+                     hipStream_t s);
+void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s);
+// pointwise mean and std (1/(S-1)) of samples [S][N]
+void launch_stats(const double *samples, int64_t S, int64_t N, double *mean, double *std, hipStream_t s);
+
+}  // namespace pat

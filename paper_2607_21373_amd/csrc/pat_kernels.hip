@@ -1,0 +1,664 @@
+// HIP kernels of libpat for gfx950 (MI355X, CDNA4, wave64).
+//
+// Data layout: a block of RB right-hand sides is stored node-major with the RHS
+// fastest, x[i*RB + r], so the RB values a row gathers from one neighbour are
+// one contiguous RB*sizeof(T) segment.  For RB >= 8 one wave64 covers 64/RB
+// rows with one lane per RHS (RB = 64: one row per wave, its CSR indices and
+// values are wave-uniform scalar loads).  For RB < 8, 8/RB lanes per RHS split
+// a row's nonzeros and combine their sums with cross-lane shuffles.
+//
+// Paper: "3D Uncertainty Quantification for Photoacoustic Tomography"
+// (arXiv 2607.21373).  The time stepping is Sec. 3 eq. (fully-discrete) with
+// M replaced by M_L, written in staggered form; the transposed stepping is
+// Sec. 5.1 eq. (adjoint-verlet) with the recursion (backward-recursion).
+#include <hip/hip_runtime.h>
+
+#include "pat_kernels.h"
+
+namespace pat {
+namespace {
+
+// Workgroup b is dispatched to XCD (b % 8).  Map it to a logical tile so that
+// each XCD walks one contiguous range of rows and its L2 holds the neighbour
+// window of that range.
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
+}
+
+template <int RB>
+struct Geo {
+    static constexpr int SPLIT = RB >= 8 ? 1 : 8 / RB;  // lanes sharing one RHS of a row
+    static constexpr int LPR = RB * SPLIT;              // lanes per row
+    static constexpr int RPW = 64 / LPR;                // rows per wave
+    static constexpr int RPB = 4 * RPW;                 // rows per 256-thread workgroup
+};
+
+__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <int RB, int LPR>
+__device__ __forceinline__ float lane_sum(float v) {
+    for (int o = RB; o < LPR; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+template <int RB, int LPR>
+__device__ __forceinline__ double lane_sum(double v) {
+    for (int o = RB; o < LPR; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+struct FwdArgs {
+    const int32_t *rowptr, *col, *boff, *snode;
+    const T *kval, *bval, *dtm, *sw;
+    const T *P, *V;
+    T *Pn, *Vn;
+    void *y;
+    double yscale;
+    int n, n_obs, n_row_blocks, first, sample, t;
+    T dt, half_dt;
+};
+
+// Forward step.  State (P, V) = (p^{n+1/2}, v^n):
+//   V' = V - (dt/m) (K P + B V),  P' = P + dt V'
+// which is the three-substep Stormer-Verlet update with lumped mass.
+// Sampling workgroups (after the row workgroups) write y^n = Pi (P - dt/2 V).
+template <typename T, typename OT, int RB>
+__global__ void __launch_bounds__(256) k_fwd(const FwdArgs<T> a) {
+    using G = Geo<RB>;
+    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = lane / G::LPR, part = (lane / RB) % G::SPLIT, r = lane % RB;
+    if (b < a.n_row_blocks) {
+        int row = (b * 4 + wave) * G::RPW + slot;
+        if constexpr (RB == 64) row = __builtin_amdgcn_readfirstlane(row);
+        if (row >= a.n) return;
+        const int k0 = a.rowptr[row], k1 = a.rowptr[row + 1];
+        T acc = T(0);
+        for (int k = k0 + part; k < k1; k += G::SPLIT) acc = mad(a.kval[k], a.P[int64_t(a.col[k]) * RB + r], acc);
+        const int bo = a.boff[row];
+        if (!a.first && bo >= 0)
+            for (int k = k0 + part; k < k1; k += G::SPLIT)
+                acc = mad(a.bval[bo + (k - k0)], a.V[int64_t(a.col[k]) * RB + r], acc);
+        acc = lane_sum<RB, G::LPR>(acc);
+        if (part == 0) {
+            const int64_t id = int64_t(row) * RB + r;
+            const T v0 = a.first ? T(0) : a.V[id];
+            const T v = v0 - a.dtm[row] * acc;
+            a.Vn[id] = v;
+            a.Pn[id] = a.P[id] + a.dt * v;
+        }
+    } else if (a.sample) {
+        const int s = ((b - a.n_row_blocks) * 4 + wave) * G::RPW + slot;
+        if (s >= a.n_obs || part != 0) return;
+        T y = T(0);
+        for (int k = 0; k < 4; ++k) {
+            const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
+            const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
+            y = mad(a.sw[4 * s + k], pk, y);
+        }
+        OT *yo = static_cast<OT *>(a.y);
+        yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
+    }
+}
+
+template <typename T>
+struct AdjArgs {
+    const int32_t *rowptr, *col, *boff, *injptr, *injs;
+    const T *kval, *bval, *dtm, *injw;
+    T *PH;
+    const T *Q;
+    T *Qn;
+    const void *yh;
+    double yscale;
+    int n, n_obs, last, tm1;
+    T dt;
+};
+
+template <typename T, typename YT, int RB>
+__device__ __forceinline__ T inject(const AdjArgs<T> &a, int row, int r, int t) {
+    const YT *yh = static_cast<const YT *>(a.yh);
+    T inj = T(0);
+    for (int e = a.injptr[row]; e < a.injptr[row + 1]; ++e)
+        inj = mad(a.injw[e], static_cast<T>(static_cast<double>(yh[(int64_t(t) * a.n_obs + a.injs[e]) * RB + r]) * a.yscale),
+                  inj);
+    return inj;
+}
+
+// Transposed step on the staggered state (PH = p_hat, Q = M_L^{-1}(v_hat + dt/2 p_hat)):
+//   PH -= dt K Q ;  unless last:  Q' = Q - (dt/m) B Q + (dt/m)(PH + inj/2),  PH += inj
+// with inj = Pi^T yhat^{n-1}.  Algebraically identical to applying the five
+// transposed substeps and then adding Pi^T yhat^{n-1}.
+template <typename T, typename YT, int RB>
+__global__ void __launch_bounds__(256) k_adj(const AdjArgs<T> a) {
+    using G = Geo<RB>;
+    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = lane / G::LPR, part = (lane / RB) % G::SPLIT, r = lane % RB;
+    int row = (b * 4 + wave) * G::RPW + slot;
+    if constexpr (RB == 64) row = __builtin_amdgcn_readfirstlane(row);
+    if (row >= a.n) return;
+    const int k0 = a.rowptr[row], k1 = a.rowptr[row + 1];
+    T kq = T(0), bq = T(0);
+    for (int k = k0 + part; k < k1; k += G::SPLIT) kq = mad(a.kval[k], a.Q[int64_t(a.col[k]) * RB + r], kq);
+    const int bo = a.boff[row];
+    if (!a.last && bo >= 0)
+        for (int k = k0 + part; k < k1; k += G::SPLIT)
+            bq = mad(a.bval[bo + (k - k0)], a.Q[int64_t(a.col[k]) * RB + r], bq);
+    kq = lane_sum<RB, G::LPR>(kq);
+    bq = lane_sum<RB, G::LPR>(bq);
+    if (part != 0) return;
+    const int64_t id = int64_t(row) * RB + r;
+    T ph = a.PH[id] - a.dt * kq;
+    if (!a.last) {
+        const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
+        const T dm = a.dtm[row];
+        a.Qn[id] = a.Q[id] - dm * bq + dm * (ph + T(0.5) * inj);
+        ph += inj;
+    }
+    a.PH[id] = ph;
+}
+
+// p_hat = Pi^T yhat^{N_T}, q = (dt/2m) p_hat
+template <typename T, typename YT, int RB>
+__global__ void __launch_bounds__(256) k_adj_init(const AdjArgs<T> a) {
+    const int64_t total = int64_t(a.n) * RB;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+        const int row = int(e / RB), r = int(e % RB);
+        const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
+        a.PH[e] = inj;
+        a.Qn[e] = T(0.5) * a.dtm[row] * inj;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversions (LDS-tiled transposes)
+// ---------------------------------------------------------------------------
+
+// out[c][r] = in[rb0 + r][perm(c)] (zero for rb0 + r >= R), tile of 64 columns
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_pack(const TI *in, int64_t R, int64_t rb0, int RB, int64_t cols,
+                                              const int32_t *perm, TO *out) {
+    __shared__ double tile[64][65];
+    const int64_t c0 = int64_t(blockIdx.x) * 64;
+    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+        const int r = e / 64, c = e % 64;
+        const int64_t cc = c0 + c, rr = rb0 + r;
+        double v = 0.0;
+        if (cc < cols && rr < R) v = static_cast<double>(in[rr * cols + (perm ? perm[cc] : cc)]);
+        tile[r][c] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+        const int c = e / RB, r = e % RB;
+        const int64_t cc = c0 + c;
+        if (cc < cols) out[cc * RB + r] = static_cast<TO>(tile[r][c]);
+    }
+}
+
+// out[rb0 + r][perm(c)] = in[c][r] for rb0 + r < R
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_unpack(const TI *in, int64_t R, int64_t rb0, int RB, int64_t cols,
+                                                const int32_t *perm, TO *out) {
+    __shared__ double tile[64][65];
+    const int64_t c0 = int64_t(blockIdx.x) * 64;
+    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+        const int c = e / RB, r = e % RB;
+        const int64_t cc = c0 + c;
+        tile[r][c] = cc < cols ? static_cast<double>(in[cc * RB + r]) : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+        const int r = e / 64, c = e % 64;
+        const int64_t cc = c0 + c, rr = rb0 + r;
+        if (cc < cols && rr < R) out[rr * cols + (perm ? perm[cc] : cc)] = static_cast<TO>(tile[r][c]);
+    }
+}
+
+// bd[m][r] = yobs[m] * isig + eta[rb0 + r][m]  (zero rows past S)
+__global__ void __launch_bounds__(256) k_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0,
+                                                   int RB, int64_t M, double isig, double *bd) {
+    __shared__ double tile[64][65];
+    const int64_t c0 = int64_t(blockIdx.x) * 64;
+    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+        const int r = e / 64, c = e % 64;
+        const int64_t cc = c0 + c, rr = rb0 + r;
+        tile[r][c] = (cc < M && rr < S) ? eta[rr * M + cc] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
+        const int c = e / RB, r = e % RB;
+        const int64_t cc = c0 + c;
+        if (cc < M) bd[cc * RB + r] = (rb0 + r < S) ? yobs[cc] * isig + tile[r][c] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CGLS helpers (float64)
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(double *x, int64_t n, double v) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) x[e] = v;
+}
+
+template <typename T>
+__global__ void k_cast(const double *x, T *y, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+        y[e] = static_cast<T>(x[e]);
+}
+
+// y = L x = M_L^{1/2} x + a M_L^{-1/2} (K1 x)
+__global__ void __launch_bounds__(256) k_prior(const int32_t *rowptr, const int32_t *col, const double *k1,
+                                               const double *sqrtm, const double *isqrtm, int n, int RB, double a,
+                                               const double *x, double *y) {
+    const int64_t total = int64_t(n) * RB;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+        const int i = int(e / RB), r = int(e % RB);
+        double acc = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc = __builtin_fma(k1[k], x[int64_t(col[k]) * RB + r], acc);
+        y[e] = sqrtm[i] * x[e] + a * isqrtm[i] * acc;
+    }
+}
+
+// out = isig * PH + L^T rp,  L^T rp = M_L^{1/2} rp + a K1 (M_L^{-1/2} rp)
+template <typename T>
+__global__ void __launch_bounds__(256) k_gext_t(const int32_t *rowptr, const int32_t *col, const double *k1,
+                                                const double *sqrtm, const double *isqrtm, int n, int RB, double a,
+                                                double isig, const T *PH, const double *rp, double *out) {
+    const int64_t total = int64_t(n) * RB;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+        const int i = int(e / RB), r = int(e % RB);
+        double acc = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            acc = __builtin_fma(k1[k], isqrtm[j] * rp[int64_t(j) * RB + r], acc);
+        }
+        out[e] = isig * static_cast<double>(PH[e]) + (sqrtm[i] * rp[e] + a * acc);
+    }
+}
+
+// part[b][r] = sum over rows of block b of x[row][r] * y[row][r]
+__global__ void __launch_bounds__(256) k_dot_partial(const double *x, const double *y, int64_t rows, int RB,
+                                                     double *part) {
+    __shared__ double red[256];
+    const int G = 256 / RB;
+    const int r = threadIdx.x % RB, g = threadIdx.x / RB;
+    const int64_t chunk = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t a0 = int64_t(blockIdx.x) * chunk, a1 = a0 + chunk < rows ? a0 + chunk : rows;
+    double acc = 0.0;
+    for (int64_t row = a0 + g; row < a1; row += G) {
+        const int64_t e = row * RB + r;
+        acc = __builtin_fma(x[e], y[e], acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s >= RB; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < RB) part[int64_t(blockIdx.x) * RB + threadIdx.x] = red[threadIdx.x];
+}
+
+// out[r] = sum_b partA[b][r] (+ sum_b partB[b][r]), nb partial blocks each
+__global__ void __launch_bounds__(256) k_dot_final(const double *partA, const double *partB, int nb, int RB,
+                                                   double *out) {
+    __shared__ double red[256];
+    const int G = 256 / RB;
+    const int r = threadIdx.x % RB, g = threadIdx.x / RB;
+    double acc = 0.0;
+    for (int b = g; b < nb; b += G) acc += partA[int64_t(b) * RB + r];
+    if (partB)
+        for (int b = g; b < nb; b += G) acc += partB[int64_t(b) * RB + r];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s >= RB; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < RB) out[threadIdx.x] = red[threadIdx.x];
+}
+
+__global__ void k_alpha(const double *gamma, const double *delta, double *alpha, int RB) {
+    const int r = threadIdx.x;
+    if (r < RB) alpha[r] = delta[r] > 0.0 ? gamma[r] / delta[r] : 0.0;
+}
+
+__global__ void k_gamma(double *gamma, const double *gnew, double *beta, double *invn, int first, int RB) {
+    const int r = threadIdx.x;
+    if (r >= RB) return;
+    const double g = gnew[r];
+    beta[r] = (first || !(gamma[r] > 0.0)) ? 0.0 : g / gamma[r];
+    invn[r] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
+    gamma[r] = g;
+}
+
+__global__ void k_resid(const double *a, const double *b, double *hist, int64_t ld, int64_t col, int64_t rb0,
+                        int64_t R, int RB) {
+    const int r = threadIdx.x;
+    if (r < RB && rb0 + r < R) hist[(rb0 + r) * ld + col] = sqrt(a[r] + b[r]);
+}
+
+__global__ void k_update_xr(double *x, const double *d, double *rp, const double *qp, const double *alpha,
+                            int64_t total, int RB) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const double al = alpha[e % RB];
+        x[e] += al * d[e];
+        rp[e] -= al * qp[e];
+    }
+}
+
+__global__ void k_axpy_neg(double *y, const double *x, const double *alpha, int64_t total, int RB) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x)
+        y[e] -= alpha[e % RB] * x[e];
+}
+
+__global__ void k_append(const double *sv, double *Qk, double *d, const double *invn, const double *beta, int first,
+                         int64_t total, int RB) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int r = int(e % RB);
+        const double s = sv[e];
+        if (Qk) Qk[e] = s * invn[r];
+        d[e] = first ? s : s + beta[r] * d[e];
+    }
+}
+
+// part[b][j][r] = sum over rows of block b of Q[j][row][r] * s[row][r], j in [j0, j0+8) and < k
+__global__ void __launch_bounds__(256) k_multidot_partial(const double *Q, const double *sv, int k, int64_t rows,
+                                                          int RB, double *part) {
+    __shared__ double red[256];
+    const int G = 256 / RB;
+    const int r = threadIdx.x % RB, g = threadIdx.x / RB;
+    const int64_t chunk = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t a0 = int64_t(blockIdx.x) * chunk, a1 = a0 + chunk < rows ? a0 + chunk : rows;
+    const int64_t stride = rows * RB;
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t row = a0 + g; row < a1; row += G) {
+            const int64_t e = row * RB + r;
+            const double s = sv[e];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                if (j0 + jj < k) acc[jj] = __builtin_fma(Q[int64_t(j0 + jj) * stride + e], s, acc[jj]);
+        }
+        for (int jj = 0; jj < 8 && j0 + jj < k; ++jj) {
+            red[threadIdx.x] = acc[jj];
+            __syncthreads();
+            for (int s = 128; s >= RB; s >>= 1) {
+                if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+                __syncthreads();
+            }
+            if (threadIdx.x < RB) part[(int64_t(blockIdx.x) * k + j0 + jj) * RB + threadIdx.x] = red[threadIdx.x];
+            __syncthreads();
+        }
+    }
+}
+
+// coef[j][r] = sum_b part[b][j][r]; one workgroup per j
+__global__ void __launch_bounds__(256) k_multidot_final(const double *part, int nb, int k, int RB, double *coef) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    const int G = 256 / RB;
+    const int r = threadIdx.x % RB, g = threadIdx.x / RB;
+    double acc = 0.0;
+    for (int b = g; b < nb; b += G) acc += part[(int64_t(b) * k + j) * RB + r];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s >= RB; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < RB) coef[int64_t(j) * RB + threadIdx.x] = red[threadIdx.x];
+}
+
+// s[row][r] -= coef[j][r] * Q[j][row][r], j = 0..k-1 in order
+__global__ void k_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB) {
+    const int64_t total = rows * RB;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int r = int(e % RB);
+        double s = sv[e];
+        for (int j = 0; j < k; ++j) s -= coef[int64_t(j) * RB + r] * Q[int64_t(j) * total + e];
+        sv[e] = s;
+    }
+}
+
+__global__ void k_stats(const double *x, int64_t S, int64_t N, double *mean, double *std) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+        double m = 0.0;
+        for (int64_t s = 0; s < S; ++s) m += x[s * N + i];
+        m /= double(S);
+        double v = 0.0;
+        for (int64_t s = 0; s < S; ++s) {
+            const double d = x[s * N + i] - m;
+            v = __builtin_fma(d, d, v);
+        }
+        if (mean) mean[i] = m;
+        if (std) std[i] = S > 1 ? sqrt(v / double(S - 1)) : 0.0;
+    }
+}
+
+int grid_for(int64_t total, int per_block = 256, int cap = 65536) {
+    int64_t g = (total + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return int(g < cap ? g : cap);
+}
+
+template <typename T>
+struct OpsOf;
+template <>
+struct OpsOf<double> {
+    static const double *k(const DevOps &o) { return o.kval64; }
+    static const double *b(const DevOps &o) { return o.bval64; }
+    static const double *dtm(const DevOps &o) { return o.dtm64; }
+    static const double *sw(const DevOps &o) { return o.sw64; }
+    static const double *injw(const DevOps &o) { return o.injw64; }
+};
+template <>
+struct OpsOf<float> {
+    static const float *k(const DevOps &o) { return o.kval32; }
+    static const float *b(const DevOps &o) { return o.bval32; }
+    static const float *dtm(const DevOps &o) { return o.dtm32; }
+    static const float *sw(const DevOps &o) { return o.sw32; }
+    static const float *injw(const DevOps &o) { return o.injw32; }
+};
+
+template <typename T, typename OT, int RB>
+void fwd_impl(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
+              int t, void *y, double yscale, hipStream_t s) {
+    using G = Geo<RB>;
+    FwdArgs<T> a;
+    a.rowptr = op.rowptr; a.col = op.col; a.boff = op.boff; a.snode = op.snode;
+    a.kval = OpsOf<T>::k(op); a.bval = OpsOf<T>::b(op); a.dtm = OpsOf<T>::dtm(op); a.sw = OpsOf<T>::sw(op);
+    a.P = static_cast<const T *>(P); a.V = static_cast<const T *>(V);
+    a.Pn = static_cast<T *>(Pn); a.Vn = static_cast<T *>(Vn);
+    a.y = y; a.yscale = yscale;
+    a.n = op.n; a.n_obs = op.n_obs;
+    a.n_row_blocks = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
+    a.first = first; a.sample = sample; a.t = t;
+    a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
+    const int sblocks = sample ? (op.n_obs + G::RPB - 1) / G::RPB : 0;
+    const int grid = a.n_row_blocks + sblocks;
+    if (grid > 0) hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
+}
+
+template <typename T, typename YT, int RB>
+void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bool last, int tm1, const void *yh,
+              double yscale, hipStream_t s) {
+    using G = Geo<RB>;
+    AdjArgs<T> a;
+    a.rowptr = op.rowptr; a.col = op.col; a.boff = op.boff; a.injptr = op.injptr; a.injs = op.injs;
+    a.kval = OpsOf<T>::k(op); a.bval = OpsOf<T>::b(op); a.dtm = OpsOf<T>::dtm(op); a.injw = OpsOf<T>::injw(op);
+    a.PH = static_cast<T *>(PH); a.Q = static_cast<const T *>(Q); a.Qn = static_cast<T *>(Qn);
+    a.yh = yh; a.yscale = yscale;
+    a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
+    a.dt = T(op.dt);
+    if (init) {
+        hipLaunchKernelGGL((k_adj_init<T, YT, RB>), dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, a);
+    } else {
+        const int grid = (op.n + G::RPB - 1) / G::RPB;
+        hipLaunchKernelGGL((k_adj<T, YT, RB>), dim3(grid), dim3(256), 0, s, a);
+    }
+}
+
+#define PAT_RB_SWITCH(RBV, CALL)               \
+    switch (RBV) {                             \
+        case 1: { constexpr int RB_ = 1; CALL; break; }   \
+        case 2: { constexpr int RB_ = 2; CALL; break; }   \
+        case 4: { constexpr int RB_ = 4; CALL; break; }   \
+        case 8: { constexpr int RB_ = 8; CALL; break; }   \
+        case 16: { constexpr int RB_ = 16; CALL; break; } \
+        case 32: { constexpr int RB_ = 32; CALL; break; } \
+        default: { constexpr int RB_ = 64; CALL; break; } \
+    }
+
+}  // namespace
+
+void launch_fwd_step(Prec prec, int RB, const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows,
+                     bool first, bool sample, int t, void *y, bool y_is_f64, double yscale, hipStream_t s) {
+    if (prec == Prec::F64) {
+        PAT_RB_SWITCH(RB, (fwd_impl<double, double, RB_>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s)));
+    } else if (y_is_f64) {
+        PAT_RB_SWITCH(RB, (fwd_impl<float, double, RB_>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s)));
+    } else {
+        PAT_RB_SWITCH(RB, (fwd_impl<float, float, RB_>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s)));
+    }
+}
+
+void launch_adj_init(Prec prec, int RB, const DevOps &op, void *PH, void *Q, const void *yhat, bool y_is_f64,
+                     double yscale, hipStream_t s) {
+    const int t = op.n_steps - 1;
+    if (prec == Prec::F64) {
+        PAT_RB_SWITCH(RB, (adj_impl<double, double, RB_>(op, PH, nullptr, Q, true, false, t, yhat, yscale, s)));
+    } else if (y_is_f64) {
+        PAT_RB_SWITCH(RB, (adj_impl<float, double, RB_>(op, PH, nullptr, Q, true, false, t, yhat, yscale, s)));
+    } else {
+        PAT_RB_SWITCH(RB, (adj_impl<float, float, RB_>(op, PH, nullptr, Q, true, false, t, yhat, yscale, s)));
+    }
+}
+
+void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1,
+                     const void *yhat, bool y_is_f64, double yscale, hipStream_t s) {
+    if (prec == Prec::F64) {
+        PAT_RB_SWITCH(RB, (adj_impl<double, double, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
+    } else if (y_is_f64) {
+        PAT_RB_SWITCH(RB, (adj_impl<float, double, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
+    } else {
+        PAT_RB_SWITCH(RB, (adj_impl<float, float, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
+    }
+}
+
+void launch_pack(bool in_f64, bool out_f64, const void *in, int64_t R, int64_t rb0, int RB, int64_t cols,
+                 const int32_t *perm, void *out, hipStream_t s) {
+    const dim3 g(unsigned((cols + 63) / 64)), b(256);
+    if (in_f64 && out_f64)
+        hipLaunchKernelGGL((k_pack<double, double>), g, b, 0, s, (const double *)in, R, rb0, RB, cols, perm, (double *)out);
+    else if (in_f64)
+        hipLaunchKernelGGL((k_pack<double, float>), g, b, 0, s, (const double *)in, R, rb0, RB, cols, perm, (float *)out);
+    else if (out_f64)
+        hipLaunchKernelGGL((k_pack<float, double>), g, b, 0, s, (const float *)in, R, rb0, RB, cols, perm, (double *)out);
+    else
+        hipLaunchKernelGGL((k_pack<float, float>), g, b, 0, s, (const float *)in, R, rb0, RB, cols, perm, (float *)out);
+}
+
+void launch_unpack(bool in_f64, bool out_f64, const void *in, int64_t R, int64_t rb0, int RB, int64_t cols,
+                   const int32_t *perm, void *out, hipStream_t s) {
+    const dim3 g(unsigned((cols + 63) / 64)), b(256);
+    if (in_f64 && out_f64)
+        hipLaunchKernelGGL((k_unpack<double, double>), g, b, 0, s, (const double *)in, R, rb0, RB, cols, perm, (double *)out);
+    else if (in_f64)
+        hipLaunchKernelGGL((k_unpack<double, float>), g, b, 0, s, (const double *)in, R, rb0, RB, cols, perm, (float *)out);
+    else if (out_f64)
+        hipLaunchKernelGGL((k_unpack<float, double>), g, b, 0, s, (const float *)in, R, rb0, RB, cols, perm, (double *)out);
+    else
+        hipLaunchKernelGGL((k_unpack<float, float>), g, b, 0, s, (const float *)in, R, rb0, RB, cols, perm, (float *)out);
+}
+
+void launch_fill(double *x, int64_t count, double v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(count)), dim3(256), 0, s, x, count, v);
+}
+
+void launch_cast_to_state(Prec prec, const double *x, void *P, int64_t count, hipStream_t s) {
+    if (prec == Prec::F64)
+        hipLaunchKernelGGL((k_cast<double>), dim3(grid_for(count)), dim3(256), 0, s, x, (double *)P, count);
+    else
+        hipLaunchKernelGGL((k_cast<float>), dim3(grid_for(count)), dim3(256), 0, s, x, (float *)P, count);
+}
+
+void launch_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0, int RB, int64_t M, double isig,
+                      double *bd, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_rhs, dim3(unsigned((M + 63) / 64)), dim3(256), 0, s, yobs, eta, S, rb0, RB, M, isig, bd);
+}
+
+void launch_prior(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_prior, dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, op.rowptr, op.col, op.k1val64,
+                       op.sqrtm, op.isqrtm, op.n, RB, a, x, y);
+}
+
+void launch_gext_t_combine(Prec prec, const DevOps &op, int RB, double a, double isig, const void *PH, const double *rp,
+                           double *out, hipStream_t s) {
+    const dim3 g(grid_for(int64_t(op.n) * RB)), b(256);
+    if (prec == Prec::F64)
+        hipLaunchKernelGGL((k_gext_t<double>), g, b, 0, s, op.rowptr, op.col, op.k1val64, op.sqrtm, op.isqrtm, op.n, RB,
+                           a, isig, (const double *)PH, rp, out);
+    else
+        hipLaunchKernelGGL((k_gext_t<float>), g, b, 0, s, op.rowptr, op.col, op.k1val64, op.sqrtm, op.isqrtm, op.n, RB,
+                           a, isig, (const float *)PH, rp, out);
+}
+
+void launch_dot_partial(const double *x, const double *y, int64_t rows, int RB, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, x, y, rows, RB, part);
+}
+
+void launch_dot_final(const double *partA, const double *partB, int RB, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, partA, partB, kDotBlocks, RB, out);
+}
+
+void launch_scalar_alpha(const double *gamma, const double *delta, double *alpha, int RB, hipStream_t s) {
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, s, gamma, delta, alpha, RB);
+}
+
+void launch_scalar_gamma(double *gamma, const double *gnew, double *beta, double *invn, int first, int RB,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(64), 0, s, gamma, gnew, beta, invn, first, RB);
+}
+
+void launch_resid(const double *a, const double *b, double *hist, int64_t ld, int64_t col, int64_t rb0, int64_t R,
+                  int RB, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid, dim3(1), dim3(64), 0, s, a, b, hist, ld, col, rb0, R, RB);
+}
+
+void launch_update_xr(double *x, const double *d, double *rp, const double *qp, const double *alpha, int64_t rows,
+                      int RB, hipStream_t s) {
+    const int64_t total = rows * RB;
+    hipLaunchKernelGGL(k_update_xr, dim3(grid_for(total)), dim3(256), 0, s, x, d, rp, qp, alpha, total, RB);
+}
+
+void launch_axpy_neg(double *y, const double *x, const double *alpha, int64_t rows, int RB, hipStream_t s) {
+    const int64_t total = rows * RB;
+    hipLaunchKernelGGL(k_axpy_neg, dim3(grid_for(total)), dim3(256), 0, s, y, x, alpha, total, RB);
+}
+
+void launch_append_dir(const double *sv, double *Qk, double *d, const double *invn, const double *beta, int first,
+                       int64_t rows, int RB, hipStream_t s) {
+    const int64_t total = rows * RB;
+    hipLaunchKernelGGL(k_append, dim3(grid_for(total)), dim3(256), 0, s, sv, Qk, d, invn, beta, first, total, RB);
+}
+
+void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *coef,
+                     hipStream_t s) {
+    if (k <= 0) return;
+    hipLaunchKernelGGL(k_multidot_partial, dim3(kDotBlocks), dim3(256), 0, s, Q, sv, k, rows, RB, part);
+    hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(256), 0, s, part, kDotBlocks, k, RB, coef);
+}
+
+void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s) {
+    if (k <= 0) return;
+    hipLaunchKernelGGL(k_project, dim3(grid_for(rows * RB)), dim3(256), 0, s, Q, sv, coef, k, rows, RB);
+}
+
+void launch_stats(const double *samples, int64_t S, int64_t N, double *mean, double *std, hipStream_t s) {
+    hipLaunchKernelGGL(k_stats, dim3(grid_for(N)), dim3(256), 0, s, samples, S, N, mean, std);
+}
+
+}  // namespace pat

@@ -1,0 +1,507 @@
+// Host-side setup of libpat: P1 assembly, boundary detection, sensor location,
+// node numbering and the time-step stability check.  Runs once per problem in
+// float64; nothing here is on the timed path.
+//
+// Paper: "3D Uncertainty Quantification for Photoacoustic Tomography"
+// (arXiv 2607.21373).
+//   K, M, B     Sec. 3, matrices defined under eq. (semi-discrete)
+//   M_L         Sec. 3, lumped mass diag(M 1)
+//   Pi          Sec. 3, eq. (lagrange); sensors not at nodes use the P1
+//               interpolant of the containing tetrahedron (Sec. 5.1 remark on
+//               Pi^T for off-node sensors)
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <thread>
+
+#include "pat_internal.h"
+
+namespace pat {
+namespace {
+
+// Run f(i) for i in [0, n) on up to 16 host threads (each index exactly once).
+template <class F>
+void parallel_for(int64_t n, F &&f) {
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = std::max(1u, std::min(nt, 16u));
+    if (n < 8192) nt = 1;
+    if (nt == 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        const int64_t a = int64_t(t) * chunk, b = std::min<int64_t>(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([a, b, &f] {
+            for (int64_t i = a; i < b; ++i) f(i);
+        });
+    }
+    for (auto &x : th) x.join();
+}
+
+// Shape data of one P1 tetrahedron: volume and the gradients of its four nodal
+// basis functions, from the inverse of J = [x1-x0 | x2-x0 | x3-x0]: the
+// barycentric coordinates are lambda_{1..3} = J^{-1} (x - x0), lambda_0 = 1 - sum.
+struct Shape {
+    double vol;
+    double g[4][3];
+    double inv[3][3];
+    double x0[3];
+};
+
+bool tet_shape(const double *X, const int32_t *t, Shape &s) {
+    const double *a = X + 3 * int64_t(t[0]);
+    double J[3][3];
+    for (int k = 0; k < 3; ++k) {
+        const double *b = X + 3 * int64_t(t[k + 1]);
+        for (int d = 0; d < 3; ++d) J[d][k] = b[d] - a[d];
+    }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+    const double r = 1.0 / det;
+    s.inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * r;
+    s.inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    s.inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    s.inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * r;
+    s.inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    s.inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    s.inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * r;
+    s.inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    s.inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+    for (int d = 0; d < 3; ++d) {
+        s.g[1][d] = s.inv[0][d];
+        s.g[2][d] = s.inv[1][d];
+        s.g[3][d] = s.inv[2][d];
+        s.g[0][d] = -(s.inv[0][d] + s.inv[1][d] + s.inv[2][d]);
+        s.x0[d] = a[d];
+    }
+    s.vol = std::fabs(det) / 6.0;
+    return true;
+}
+
+// Barycentric coordinates of x in the tetrahedron; returns the smallest one.
+double barycentric(const Shape &s, const double *x, double lam[4]) {
+    const double dx[3] = {x[0] - s.x0[0], x[1] - s.x0[1], x[2] - s.x0[2]};
+    double sum = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        lam[k + 1] = s.inv[k][0] * dx[0] + s.inv[k][1] * dx[1] + s.inv[k][2] * dx[2];
+        sum += lam[k + 1];
+    }
+    lam[0] = 1.0 - sum;
+    return std::min(std::min(lam[0], lam[1]), std::min(lam[2], lam[3]));
+}
+
+int local_index(const int32_t *t, int32_t node) {
+    for (int a = 0; a < 4; ++a)
+        if (t[a] == node) return a;
+    return -1;
+}
+
+}  // namespace
+
+pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::string &err) {
+    const int32_t N = d.n_nodes;
+    const int64_t E = d.n_tets;
+    if (N < 4 || E < 1 || !d.coords || !d.tets) {
+        err = "need n_nodes >= 4, n_tets >= 1 and non-NULL coords/tets";
+        return PAT_ERR_INVALID_ARG;
+    }
+    if (!(d.dt > 0.0) || !std::isfinite(d.dt) || d.n_steps < 1) {
+        err = "dt must be positive and finite and n_steps >= 1";
+        return PAT_ERR_INVALID_ARG;
+    }
+    if (d.n_obs < 1 || (d.sensor_nodes == nullptr) == (d.sensor_pos == nullptr)) {
+        err = "need n_obs >= 1 and exactly one of sensor_nodes / sensor_pos";
+        return PAT_ERR_INVALID_ARG;
+    }
+    for (int64_t i = 0; i < 3 * int64_t(N); ++i)
+        if (!std::isfinite(d.coords[i])) {
+            err = "non-finite node coordinate";
+            return PAT_ERR_NONFINITE;
+        }
+    for (int64_t i = 0; i < 4 * E; ++i)
+        if (d.tets[i] < 0 || d.tets[i] >= N) {
+            err = "tetrahedron node id out of range";
+            return PAT_ERR_INVALID_ARG;
+        }
+    if (d.c_tet)
+        for (int64_t e = 0; e < E; ++e)
+            if (!(d.c_tet[e] > 0.0) || !std::isfinite(d.c_tet[e])) {
+                err = "wave speed must be positive and finite";
+                return PAT_ERR_INVALID_ARG;
+            }
+
+    hp.n = N;
+    hp.n_obs = d.n_obs;
+    hp.n_steps = d.n_steps;
+    hp.n_tets = E;
+    hp.dt = d.dt;
+    // Internal numbering: the caller's order (structured and sorted meshes already
+    // keep neighbours close); the permutation arrays let a reordering slot in.
+    hp.perm.resize(N);
+    hp.iperm.resize(N);
+    for (int32_t i = 0; i < N; ++i) hp.perm[i] = hp.iperm[i] = i;
+
+    // node -> incident tetrahedra (ascending tetrahedron index)
+    std::vector<int64_t> inc_ptr(size_t(N) + 1, 0);
+    for (int64_t i = 0; i < 4 * E; ++i) ++inc_ptr[size_t(d.tets[i]) + 1];
+    for (int32_t i = 0; i < N; ++i) inc_ptr[i + 1] += inc_ptr[i];
+    std::vector<int64_t> inc(static_cast<size_t>(inc_ptr[N]));
+    {
+        std::vector<int64_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (int64_t e = 0; e < E; ++e)
+            for (int a = 0; a < 4; ++a) inc[size_t(fill[d.tets[4 * e + a]]++)] = e;
+    }
+    for (int32_t i = 0; i < N; ++i)
+        if (inc_ptr[i + 1] == inc_ptr[i]) {
+            err = "node " + std::to_string(i) + " belongs to no tetrahedron";
+            return PAT_ERR_INVALID_ARG;
+        }
+
+    // geometry check (no degenerate tetrahedra)
+    {
+        int bad = 0;
+        for (int64_t e = 0; e < E && !bad; ++e) {
+            Shape s;
+            if (!tet_shape(d.coords, d.tets + 4 * e, s)) bad = 1;
+        }
+        if (bad) {
+            err = "degenerate tetrahedron (zero volume)";
+            return PAT_ERR_INVALID_ARG;
+        }
+    }
+
+    // row pattern: all nodes that share a tetrahedron with node i
+    std::vector<int32_t> rowlen(N);
+    std::vector<std::vector<int32_t>> cols(N);
+    parallel_for(N, [&](int64_t i) {
+        std::vector<int32_t> &c = cols[size_t(i)];
+        c.reserve(size_t(4 * (inc_ptr[i + 1] - inc_ptr[i])));
+        for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q)
+            for (int a = 0; a < 4; ++a) c.push_back(d.tets[4 * inc[size_t(q)] + a]);
+        std::sort(c.begin(), c.end());
+        c.erase(std::unique(c.begin(), c.end()), c.end());
+        rowlen[size_t(i)] = int32_t(c.size());
+    });
+    hp.rowptr.assign(size_t(N) + 1, 0);
+    for (int32_t i = 0; i < N; ++i) {
+        hp.rowptr[i + 1] = hp.rowptr[i] + rowlen[i];
+        hp.max_row = std::max(hp.max_row, rowlen[i]);
+    }
+    const int64_t nnz = hp.rowptr[N];
+    hp.col.resize(size_t(nnz));
+    hp.kval.assign(size_t(nnz), 0.0);
+    hp.k1val.assign(size_t(nnz), 0.0);
+    hp.mass.assign(size_t(N), 0.0);
+
+    // Stiffness rows: K_ij = sum over tetrahedra e containing i and j of
+    // c_e^2 vol_e grad(phi_i).grad(phi_j); K1 the same with c = 1; M_L = sum vol_e / 4.
+    parallel_for(N, [&](int64_t i) {
+        const int32_t r0 = hp.rowptr[i];
+        const std::vector<int32_t> &c = cols[size_t(i)];
+        std::copy(c.begin(), c.end(), hp.col.begin() + r0);
+        double m = 0.0;
+        for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
+            const int64_t e = inc[size_t(q)];
+            const int32_t *t = d.tets + 4 * e;
+            Shape s;
+            tet_shape(d.coords, t, s);
+            const int a = local_index(t, int32_t(i));
+            const double c2 = d.c_tet ? d.c_tet[e] * d.c_tet[e] : 1.0;
+            for (int b = 0; b < 4; ++b) {
+                const double gg = s.g[a][0] * s.g[b][0] + s.g[a][1] * s.g[b][1] + s.g[a][2] * s.g[b][2];
+                const int32_t j = t[b];
+                const int64_t pos = r0 + (std::lower_bound(c.begin(), c.end(), j) - c.begin());
+                hp.k1val[size_t(pos)] += s.vol * gg;
+                hp.kval[size_t(pos)] += c2 * (s.vol * gg);
+            }
+            m += 0.25 * s.vol;
+        }
+        hp.mass[size_t(i)] = m;
+    });
+    cols.clear();
+    cols.shrink_to_fit();
+
+    // Boundary faces: a face of tetrahedron e is on the boundary when no other
+    // tetrahedron holds all three of its nodes.
+    static const int kFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    std::vector<uint8_t> face_on_boundary(size_t(4 * E), 0);
+    if (d.absorbing) {
+        parallel_for(E, [&](int64_t e) {
+            const int32_t *t = d.tets + 4 * e;
+            for (int f = 0; f < 4; ++f) {
+                const int32_t a = t[kFace[f][0]], b = t[kFace[f][1]], c = t[kFace[f][2]];
+                bool shared = false;
+                for (int64_t q = inc_ptr[a]; q < inc_ptr[a + 1] && !shared; ++q) {
+                    const int64_t o = inc[size_t(q)];
+                    if (o == e) continue;
+                    const int32_t *u = d.tets + 4 * o;
+                    shared = local_index(u, b) >= 0 && local_index(u, c) >= 0;
+                }
+                face_on_boundary[size_t(4 * e + f)] = shared ? 0 : 1;
+            }
+        });
+    }
+    // B_ij = sum over boundary faces F containing i and j of (1/c_e) |F|/12 (1 + delta_ij),
+    // the consistent P1 face mass; c_e is the speed of the face's tetrahedron.
+    hp.boff.assign(size_t(N), -1);
+    hp.n_boundary = 0;
+    {
+        int64_t off = 0;
+        for (int32_t i = 0; i < N; ++i) {
+            bool onb = false;
+            for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1] && !onb; ++q) {
+                const int64_t e = inc[size_t(q)];
+                const int a = local_index(d.tets + 4 * e, i);
+                for (int f = 0; f < 4 && !onb; ++f)
+                    if (f != a && face_on_boundary[size_t(4 * e + f)]) onb = true;
+            }
+            if (onb) {
+                hp.boff[i] = int32_t(off);
+                off += hp.rowptr[i + 1] - hp.rowptr[i];
+                ++hp.n_boundary;
+            }
+        }
+        hp.bval.assign(size_t(off), 0.0);
+    }
+    parallel_for(N, [&](int64_t i) {
+        if (hp.boff[i] < 0) return;
+        const int32_t r0 = hp.rowptr[i], r1 = hp.rowptr[i + 1];
+        for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
+            const int64_t e = inc[size_t(q)];
+            const int32_t *t = d.tets + 4 * e;
+            const int a = local_index(t, int32_t(i));
+            for (int f = 0; f < 4; ++f) {
+                if (f == a || !face_on_boundary[size_t(4 * e + f)]) continue;
+                const double *x0 = d.coords + 3 * int64_t(t[kFace[f][0]]);
+                const double *x1 = d.coords + 3 * int64_t(t[kFace[f][1]]);
+                const double *x2 = d.coords + 3 * int64_t(t[kFace[f][2]]);
+                const double u[3] = {x1[0] - x0[0], x1[1] - x0[1], x1[2] - x0[2]};
+                const double v[3] = {x2[0] - x0[0], x2[1] - x0[1], x2[2] - x0[2]};
+                const double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+                const double area = 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                const double scale = (d.c_tet ? 1.0 / d.c_tet[e] : 1.0) * area / 12.0;
+                for (int k = 0; k < 3; ++k) {
+                    const int32_t j = t[kFace[f][k]];
+                    const int32_t *lo = hp.col.data() + r0, *hi = hp.col.data() + r1;
+                    const int64_t pos = std::lower_bound(lo, hi, j) - hp.col.data();
+                    hp.bval[size_t(hp.boff[i] + (pos - r0))] += (j == i ? 2.0 : 1.0) * scale;
+                }
+            }
+        }
+    });
+    hp.nnz_b = 0;
+    for (double v : hp.bval)
+        if (v != 0.0) ++hp.nnz_b;
+
+    // Sensors.
+    const int32_t S = d.n_obs;
+    hp.snode.assign(size_t(4) * S, 0);
+    hp.sw.assign(size_t(4) * S, 0.0);
+    if (d.sensor_nodes) {
+        for (int32_t s = 0; s < S; ++s) {
+            const int32_t v = d.sensor_nodes[s];
+            if (v < 0 || v >= N) {
+                err = "sensor node id out of range";
+                return PAT_ERR_INVALID_ARG;
+            }
+            for (int k = 0; k < 4; ++k) hp.snode[4 * s + k] = v;
+            hp.sw[4 * s] = 1.0;
+        }
+    } else {
+        // bucket grid over the mesh bounding box; each tetrahedron is listed in
+        // every cell its bounding box touches
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int32_t i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], d.coords[3 * i + k]);
+                hi[k] = std::max(hi[k], d.coords[3 * i + k]);
+            }
+        const int G = std::max(1, std::min(256, int(std::cbrt(double(E) / 4.0))));
+        auto cell = [&](double x, int k) {
+            const double w = (hi[k] - lo[k]) > 0 ? (hi[k] - lo[k]) : 1.0;
+            int c = int((x - lo[k]) / w * G);
+            return std::min(G - 1, std::max(0, c));
+        };
+        std::vector<int64_t> cptr(size_t(G) * G * G + 1, 0);
+        auto for_cells = [&](int64_t e, auto &&fn) {
+            const int32_t *t = d.tets + 4 * e;
+            int c0[3], c1[3];
+            for (int k = 0; k < 3; ++k) {
+                double a = 1e300, b = -1e300;
+                for (int v = 0; v < 4; ++v) {
+                    a = std::min(a, d.coords[3 * int64_t(t[v]) + k]);
+                    b = std::max(b, d.coords[3 * int64_t(t[v]) + k]);
+                }
+                c0[k] = cell(a, k);
+                c1[k] = cell(b, k);
+            }
+            for (int z = c0[2]; z <= c1[2]; ++z)
+                for (int y = c0[1]; y <= c1[1]; ++y)
+                    for (int x = c0[0]; x <= c1[0]; ++x) fn((int64_t(z) * G + y) * G + x);
+        };
+        for (int64_t e = 0; e < E; ++e) for_cells(e, [&](int64_t c) { ++cptr[size_t(c) + 1]; });
+        for (size_t c = 0; c + 1 < cptr.size(); ++c) cptr[c + 1] += cptr[c];
+        std::vector<int64_t> clist(size_t(cptr.back()));
+        {
+            std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+            for (int64_t e = 0; e < E; ++e) for_cells(e, [&](int64_t c) { clist[size_t(fill[size_t(c)]++)] = e; });
+        }
+        int bad = -1;
+        for (int32_t s = 0; s < S; ++s) {
+            const double *x = d.sensor_pos + 3 * int64_t(s);
+            if (!std::isfinite(x[0]) || !std::isfinite(x[1]) || !std::isfinite(x[2])) {
+                bad = s;
+                break;
+            }
+            const int64_t c = (int64_t(cell(x[2], 2)) * G + cell(x[1], 1)) * G + cell(x[0], 0);
+            double best = -std::numeric_limits<double>::infinity();
+            int64_t best_e = -1;
+            double best_lam[4] = {0, 0, 0, 0};
+            // candidates in ascending tetrahedron index; the tetrahedron whose
+            // smallest barycentric coordinate is largest wins (first on ties)
+            for (int64_t q = cptr[size_t(c)]; q < cptr[size_t(c) + 1]; ++q) {
+                const int64_t e = clist[size_t(q)];
+                Shape sh;
+                tet_shape(d.coords, d.tets + 4 * e, sh);
+                double lam[4];
+                const double m = barycentric(sh, x, lam);
+                if (m > best) {
+                    best = m;
+                    best_e = e;
+                    std::memcpy(best_lam, lam, sizeof(lam));
+                }
+            }
+            if (best_e < 0 || best < -1e-10) {
+                bad = s;
+                break;
+            }
+            for (int k = 0; k < 4; ++k) {
+                hp.snode[4 * s + k] = d.tets[4 * best_e + k];
+                hp.sw[4 * s + k] = best_lam[k];
+            }
+        }
+        if (bad >= 0) {
+            err = "sensor " + std::to_string(bad) + " is not inside the mesh";
+            return PAT_ERR_INVALID_ARG;
+        }
+    }
+    // map sensor nodes to the internal numbering
+    for (auto &v : hp.snode) v = hp.iperm[size_t(v)];
+
+    // Pi^T as node-major CSR (entries with a zero weight carry nothing and are dropped)
+    {
+        std::vector<std::array<int64_t, 3>> ent;  // (node, sensor, slot)
+        for (int32_t s = 0; s < S; ++s)
+            for (int k = 0; k < 4; ++k)
+                if (hp.sw[4 * s + k] != 0.0) ent.push_back({hp.snode[4 * s + k], s, k});
+        std::sort(ent.begin(), ent.end());
+        hp.injptr.assign(size_t(N) + 1, 0);
+        for (auto &t : ent) ++hp.injptr[size_t(t[0]) + 1];
+        for (int32_t i = 0; i < N; ++i) hp.injptr[i + 1] += hp.injptr[i];
+        hp.injs.resize(ent.size());
+        hp.injw.resize(ent.size());
+        for (size_t q = 0; q < ent.size(); ++q) {
+            hp.injs[q] = int32_t(ent[q][1]);
+            hp.injw[q] = hp.sw[size_t(4 * ent[q][1] + ent[q][2])];
+        }
+    }
+
+    hp.lambda_max = estimate_lambda_max(hp, 150);
+    if (d.check_dt) {
+        const double x = d.dt * d.dt * 1.02 * hp.lambda_max;
+        if (!(x < 4.0)) {
+            err = "dt violates the leapfrog CFL bound: dt^2 * lambda_max(M_L^-1 K) = " + std::to_string(x) +
+                  " >= 4 (lambda_max ~ " + std::to_string(hp.lambda_max) + ")";
+            return PAT_ERR_UNSTABLE_DT;
+        }
+        if (d.absorbing) {
+            const double g = energy_growth(hp, 300);
+            if (!(g < 2.0)) {
+                err = "explicit absorbing term makes the step unstable at this dt (energy grew by " +
+                      std::to_string(g) + " over 300 steps)";
+                return PAT_ERR_UNSTABLE_DT;
+            }
+        }
+    }
+    return PAT_OK;
+}
+
+namespace {
+void spmv_host(const HostProblem &hp, const std::vector<double> &val, const std::vector<double> &x,
+               std::vector<double> &y) {
+    parallel_for(hp.n, [&](int64_t i) {
+        double s = 0.0;
+        for (int32_t k = hp.rowptr[i]; k < hp.rowptr[i + 1]; ++k) s += val[size_t(k)] * x[size_t(hp.col[k])];
+        y[size_t(i)] = s;
+    });
+}
+}  // namespace
+
+double estimate_lambda_max(const HostProblem &hp, int iters) {
+    const int32_t N = hp.n;
+    std::vector<double> x(N), y(N), z(N);
+    for (int32_t i = 0; i < N; ++i) x[i] = ((i & 1) ? -1.0 : 1.0) + 0.25 * std::sin(0.37 * i);
+    double lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        double nx = 0.0;
+        for (double v : x) nx += v * v;
+        nx = std::sqrt(nx);
+        for (int32_t i = 0; i < N; ++i) z[i] = x[i] / nx / std::sqrt(hp.mass[i]);
+        spmv_host(hp, hp.kval, z, y);
+        double rq = 0.0;
+        for (int32_t i = 0; i < N; ++i) {
+            y[i] /= std::sqrt(hp.mass[i]);
+            rq += y[i] * x[i] / nx;
+        }
+        lam = rq;
+        x.swap(y);
+    }
+    return lam;
+}
+
+double energy_growth(const HostProblem &hp, int steps) {
+    const int32_t N = hp.n;
+    const double dt = hp.dt;
+    std::vector<double> P(N), V(N, 0.0), Vn(N), kp(N), kv(N);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    for (int32_t i = 0; i < N; ++i) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        P[i] = double(int64_t(st >> 11)) / double(1ull << 53) - 0.5;
+    }
+    // energy 1/2 v'M v + 1/2 p'K p - dt^2/8 v'K v at integer steps (p = P - dt/2 v)
+    auto energy = [&]() {
+        std::vector<double> p(N);
+        for (int32_t i = 0; i < N; ++i) p[i] = P[i] - 0.5 * dt * V[i];
+        spmv_host(hp, hp.kval, p, kp);
+        spmv_host(hp, hp.kval, V, kv);
+        double e = 0.0;
+        for (int32_t i = 0; i < N; ++i)
+            e += 0.5 * hp.mass[i] * V[i] * V[i] + 0.5 * p[i] * kp[i] - dt * dt / 8.0 * V[i] * kv[i];
+        return e;
+    };
+    // start from p(0) = random, v(0) = 0 (P = p at step 0)
+    const double e0 = energy();
+    for (int s = 0; s < steps; ++s) {
+        parallel_for(N, [&](int64_t i) {
+            double acc = 0.0;
+            for (int32_t k = hp.rowptr[i]; k < hp.rowptr[i + 1]; ++k) acc += hp.kval[size_t(k)] * P[size_t(hp.col[k])];
+            if (hp.boff[i] >= 0)
+                for (int32_t k = hp.rowptr[i]; k < hp.rowptr[i + 1]; ++k)
+                    acc += hp.bval[size_t(hp.boff[i] + k - hp.rowptr[i])] * V[size_t(hp.col[k])];
+            Vn[size_t(i)] = V[size_t(i)] - dt / hp.mass[i] * acc;
+        });
+        for (int32_t i = 0; i < N; ++i) P[i] += dt * Vn[i];
+        V.swap(Vn);
+    }
+    const double e1 = energy();
+    return std::isfinite(e1) ? e1 / e0 : std::numeric_limits<double>::infinity();
+}
+
+}  // namespace pat

@@ -1,0 +1,285 @@
+"""Thin Python binding of libpat (``include/pat.h``).
+
+Argument marshalling only: every step of the forward map, its transpose, the
+CGLS solve and the statistics runs in libpat's HIP kernels.  Tensors are
+PyTorch CUDA (HIP) tensors; work is enqueued on ``torch.cuda.current_stream()``.
+There is no CPU fallback: importing this module without a built ``libpat.so``
+raises, and every call needs a GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpat.so")
+
+PAT_F64, PAT_F32 = 0, 1
+_STATUS = {0: "PAT_OK", -1: "PAT_ERR_INVALID_ARG", -2: "PAT_ERR_UNSTABLE_DT", -3: "PAT_ERR_NONFINITE",
+           -4: "PAT_ERR_OUT_OF_MEMORY", -5: "PAT_ERR_HIP", -6: "PAT_ERR_INTERNAL"}
+
+
+class PatError(RuntimeError):
+    """A libpat call returned a non-zero pat_status."""
+
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = _STATUS.get(code, str(code))
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int32), ("coords", ctypes.POINTER(ctypes.c_double)),
+        ("n_tets", ctypes.c_int64), ("tets", ctypes.POINTER(ctypes.c_int32)),
+        ("c_tet", ctypes.POINTER(ctypes.c_double)), ("absorbing", ctypes.c_int32),
+        ("n_obs", ctypes.c_int32), ("sensor_nodes", ctypes.POINTER(ctypes.c_int32)),
+        ("sensor_pos", ctypes.POINTER(ctypes.c_double)), ("dt", ctypes.c_double),
+        ("n_steps", ctypes.c_int32), ("device", ctypes.c_int32), ("check_dt", ctypes.c_int32),
+    ]
+
+
+class ProblemInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int32), ("n_obs", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+        ("n_tets", ctypes.c_int64), ("nnz_k", ctypes.c_int64), ("nnz_b", ctypes.c_int64),
+        ("n_boundary_nodes", ctypes.c_int32), ("max_row_nnz", ctypes.c_int32),
+        ("dt", ctypes.c_double), ("lambda_max", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+    ]
+
+
+class RtoParams(ctypes.Structure):
+    _fields_ = [
+        ("sigma", ctypes.c_double), ("prior_a", ctypes.c_double), ("n_iter", ctypes.c_int32),
+        ("reorth", ctypes.c_int32), ("sweep_prec", ctypes.c_int), ("rhs_block", ctypes.c_int32),
+        ("eta", ctypes.c_void_p), ("xi", ctypes.c_void_p),
+    ]
+
+
+# names exported by libpat (the C ABI in include/pat.h)
+EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
+           "rto_sample", "pat_host_assemble", "pat_sync", "pat_last_error", "pat_version")
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libpat.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpat.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_2607_21373_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.pat_problem_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)]
+    lib.pat_problem_destroy.argtypes = [vp]
+    lib.pat_problem_get_info.argtypes = [vp, ctypes.POINTER(ProblemInfo)]
+    lib.pat_forward.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
+    lib.pat_adjoint.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
+    lib.rto_sample.argtypes = [vp, vp, ctypes.POINTER(RtoParams), ctypes.c_int64, vp, vp, vp, vp, vp]
+    lib.pat_sync.argtypes = [vp]
+    lib.pat_host_assemble.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ctypes.c_int64)] + [vp] * 9
+    lib.pat_last_error.restype = ctypes.c_char_p
+    lib.pat_version.restype = ctypes.c_char_p
+    for f in ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
+              "rto_sample", "pat_host_assemble", "pat_sync"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PatError(rc, load().pat_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(dtype):
+    import torch
+    if dtype == torch.float64:
+        return PAT_F64
+    if dtype == torch.float32:
+        return PAT_F32
+    raise TypeError("only float32 and float64 are supported")
+
+
+def pat_problem_create(coords, tets, c_tet=None, absorbing=True, dt=0.01, n_steps=100, sensor_nodes=None,
+                       sensor_pos=None, device: int = -1, check_dt: bool = True) -> "Problem":
+    return Problem(coords, tets, c_tet, absorbing, dt, n_steps, sensor_nodes, sensor_pos, device, check_dt)
+
+
+def _desc(coords, tets, c_tet, absorbing, dt, n_steps, sensor_nodes, sensor_pos, device, check_dt):
+    """Fill a pat_problem_desc; returns (desc, arrays that must stay alive)."""
+    keep = []
+
+    def arr(a, dt_):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt_)
+        keep.append(a)
+        return a
+
+    co, te = arr(coords, np.float64), arr(tets, np.int32)
+    c = arr(c_tet, np.float64)
+    sn, sp = arr(sensor_nodes, np.int32), arr(sensor_pos, np.float64)
+    d = ProblemDesc()
+    d.n_nodes = co.shape[0]
+    d.coords = co.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.n_tets = te.shape[0]
+    d.tets = te.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.c_tet = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if c is not None else None
+    d.absorbing = int(bool(absorbing))
+    d.n_obs = (sn.size if sn is not None else (sp.shape[0] if sp is not None else 0))
+    d.sensor_nodes = sn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if sn is not None else None
+    d.sensor_pos = sp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if sp is not None else None
+    d.dt = float(dt)
+    d.n_steps = int(n_steps)
+    d.device = int(device)
+    d.check_dt = int(bool(check_dt))
+    return d, keep
+
+
+def pat_host_assemble(coords, tets, c_tet=None, absorbing=True, dt=0.01, n_steps=100, sensor_nodes=None,
+                      sensor_pos=None, check_dt: bool = True) -> dict:
+    """Host-side assembly of libpat (no GPU needed): K, K1, B, M_L and sensor rows."""
+    lib = load()
+    d, keep = _desc(coords, tets, c_tet, absorbing, dt, n_steps, sensor_nodes, sensor_pos, -1, check_dt)
+    nnz = ctypes.c_int64()
+    _check(lib.pat_host_assemble(ctypes.byref(d), ctypes.byref(nnz), *([None] * 9)))
+    N, O, Z = d.n_nodes, d.n_obs, nnz.value
+    out = {"rowptr": np.empty(N + 1, np.int32), "col": np.empty(Z, np.int32), "K": np.empty(Z),
+           "K1": np.empty(Z), "B": np.empty(Z), "mass": np.empty(N), "snode": np.empty((O, 4), np.int32),
+           "sw": np.empty((O, 4)), "lambda_max": np.empty(1)}
+    ptrs = [ctypes.c_void_p(out[k].ctypes.data) for k in
+            ("rowptr", "col", "K", "K1", "B", "mass", "snode", "sw", "lambda_max")]
+    _check(lib.pat_host_assemble(ctypes.byref(d), ctypes.byref(nnz), *ptrs))
+    del keep
+    out["lambda_max"] = float(out["lambda_max"][0])
+    return out
+
+
+class Problem:
+    """Handle on a libpat problem (pat_problem_create / pat_problem_destroy)."""
+
+    def __init__(self, coords, tets, c_tet=None, absorbing=True, dt=0.01, n_steps=100, sensor_nodes=None,
+                 sensor_pos=None, device: int = -1, check_dt: bool = True):
+        lib = load()
+        d, keep = _desc(coords, tets, c_tet, absorbing, dt, n_steps, sensor_nodes, sensor_pos, device, check_dt)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(lib.pat_problem_create(ctypes.byref(d), ctypes.byref(h)))
+        del keep
+        self._h = h
+        info = self.info()
+        self.n_nodes, self.n_obs, self.n_steps = info["n_nodes"], info["n_obs"], info["n_steps"]
+        self.dt = info["dt"]
+
+    @classmethod
+    def from_workload(cls, w, n_steps: Optional[int] = None, device: int = -1, check_dt: bool = True):
+        return cls(w.coords, w.tets, w.c_tet, w.absorbing, w.dt, w.n_steps if n_steps is None else n_steps,
+                   sensor_nodes=w.sensor_nodes, sensor_pos=w.sensor_pos, device=device, check_dt=check_dt)
+
+    def info(self) -> dict:
+        out = ProblemInfo()
+        _check(load().pat_problem_get_info(self._h, ctypes.byref(out)))
+        return {name: getattr(out, name) for name, _ in ProblemInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pat_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(load().pat_sync(self._h))
+
+
+def pat_forward(problem: Problem, p0, y=None):
+    """Y = G p0 for p0 [R][N] (float32 or float64 CUDA tensor); returns y [R][N_T][N_obs]."""
+    import torch
+    R = p0.shape[0]
+    if y is None:
+        y = torch.empty((R, problem.n_steps, problem.n_obs), dtype=p0.dtype, device=p0.device)
+    pp = _dev_ptr(p0, p0.dtype, (R, problem.n_nodes), "p0")
+    yp = _dev_ptr(y, p0.dtype, (R, problem.n_steps, problem.n_obs), "y")
+    _check(load().pat_forward(problem._h, R, pp, yp, _prec(p0.dtype), _stream()))
+    return y
+
+
+def pat_adjoint(problem: Problem, yhat, p=None):
+    """p = G^T yhat for yhat [R][N_T][N_obs]; returns p [R][N]."""
+    import torch
+    R = yhat.shape[0]
+    if p is None:
+        p = torch.empty((R, problem.n_nodes), dtype=yhat.dtype, device=yhat.device)
+    yp = _dev_ptr(yhat, yhat.dtype, (R, problem.n_steps, problem.n_obs), "yhat")
+    pp = _dev_ptr(p, yhat.dtype, (R, problem.n_nodes), "p")
+    _check(load().pat_adjoint(problem._h, R, yp, pp, _prec(yhat.dtype), _stream()))
+    return p
+
+
+def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n_iter: int, reorth: bool = True,
+               sweep_prec: str = "f64", rhs_block: int = 0, stats: bool = True, resid: bool = False,
+               samples=None):
+    """RTO posterior samples (Algorithm 1) through libpat's rto_sample.
+
+    y_obs [N_T][N_obs], eta [S][N_T][N_obs], xi [S][N]: float64 CUDA tensors.
+    Returns a dict with samples [S][N] and, if requested, mean, std [N] and
+    resid [S][n_iter+1]."""
+    import torch
+    f64 = torch.float64
+    S = xi.shape[0]
+    N, T, O = problem.n_nodes, problem.n_steps, problem.n_obs
+    dev = xi.device
+    if samples is None:
+        samples = torch.empty((S, N), dtype=f64, device=dev)
+    mean = torch.empty(N, dtype=f64, device=dev) if stats else None
+    std = torch.empty(N, dtype=f64, device=dev) if stats and S >= 2 else None
+    res = torch.empty((S, n_iter + 1), dtype=f64, device=dev) if resid else None
+    prm = RtoParams()
+    prm.sigma = float(sigma)
+    prm.prior_a = float(prior_a)
+    prm.n_iter = int(n_iter)
+    prm.reorth = int(bool(reorth))
+    prm.sweep_prec = {"f64": PAT_F64, "f32": PAT_F32}[sweep_prec]
+    prm.rhs_block = int(rhs_block)
+    prm.eta = _dev_ptr(eta, f64, (S, T, O), "eta")
+    prm.xi = _dev_ptr(xi, f64, (S, N), "xi")
+    yp = _dev_ptr(y_obs, f64, (T, O), "y_obs")
+    sp = _dev_ptr(samples, f64, (S, N), "samples")
+    mp = ctypes.c_void_p(mean.data_ptr()) if mean is not None else None
+    dp = ctypes.c_void_p(std.data_ptr()) if std is not None else None
+    rp = ctypes.c_void_p(res.data_ptr()) if res is not None else None
+    _check(load().rto_sample(problem._h, yp, ctypes.byref(prm), S, sp, mp, dp, rp, _stream()))
+    return {"samples": samples, "mean": mean, "std": std, "resid": res}
+
+
+def version() -> str:
+    return load().pat_version().decode()
