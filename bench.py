@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of the batched RTO posterior sampler on one MI355X.
+
+One step = one pass of the whole hot path over one batch: 64 RTO samples of the
+195,112-node mapped-ball problem (1000 leapfrog steps, 1024 sensors), each the
+100-iteration CGLS solve of the perturbed least-squares problem, run as one
+multi-RHS block with float32 sweeps and float64 CGLS vectors, dots and scalars,
+followed by the posterior mean and standard deviation.  Inputs (mesh operators,
+data, perturbations) are resident on the GPU before the timed region.
+
+Prints one JSON line on stdout (progress goes to stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def step_bytes(info, RB, tsize, kind):
+    """Algorithmic HBM bytes of one step launch (each array element read or written once).
+
+    forward : CSR (col + value), rowptr, boundary offsets, dt/m, stored boundary values,
+              state P, V read and P', V' written, sensor rows and the float64 sample output.
+    transpose: same matrix data plus the injection CSR, state Q read, Q' written, p_hat read and written,
+              and the float64 data values injected at the sensor nodes.
+    """
+    N, nnz, nobs = info["n_nodes"], info["nnz_k"], info["n_obs"]
+    b = nnz * (4 + tsize) + (N + 1) * 4 + N * 4 + N * tsize + info["b_stored"] * tsize
+    b += 4 * N * RB * tsize
+    if kind == "fwd":
+        b += nobs * 4 * (4 + tsize) + nobs * RB * 8
+    else:
+        b += (N + 1) * 4 + 4 * nobs * (4 + tsize) + 4 * nobs * RB * 8
+    return int(b)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2607_21373_amd", "csrc", "pat_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload):
+    """HBM traffic of the step kernel from the committed rocprofv3 counter summary, if still current."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d[kernel][workload]
+        if e.get("kernels_sha") != kernel_source_sha():
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(w, eta, xi, yobs, sigma, n_iter, R, n_steps_sample=50, iters_sample=3):
+    """Oracle (plain CPU FP64) on a bounded sample of the same workload, scaled to samples/min."""
+    import oracle
+    t0 = time.time()
+    P = oracle.Problem.from_workload(w, n_steps=n_steps_sample)
+    setup = time.time() - t0
+    t0 = time.time()
+    P.rto(yobs[:n_steps_sample], sigma, w.prior_a, iters_sample, eta[:R, :n_steps_sample], xi[:R])
+    el = time.time() - t0
+    sweeps_sample = 2 * iters_sample
+    sweeps_full = 2 * n_iter
+    t_batch = el * (sweeps_full / sweeps_sample) * (w.n_steps / n_steps_sample)
+    return {
+        "value": round(R / t_batch * 60.0, 6), "unit": "samples/min", "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"oracle RTO on the same mesh with {R} RHS, {iters_sample} CGLS iterations x {n_steps_sample} steps "
+                   f"({el:.1f} s, setup {setup:.1f} s excluded), scaled by sweep-steps to {n_iter} iterations x "
+                   f"{w.n_steps} steps"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ball58_batched")
+    ap.add_argument("--iters", type=int, default=None, help="CGLS iterations (default: the workload's 100)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (samples are independent, so "
+              "N GPUs would each run their own batches)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2607_21373_amd import pat
+
+    dev = torch.device("cuda", 0)
+    w = W.make_workload(args.workload)
+    n_iter = args.iters or w.n_iter
+    R = w.n_samples
+    log(f"workload {w.name}: N={w.n_nodes} E={w.tets.shape[0]} N_T={w.n_steps} N_obs={w.n_obs} R={R} iters={n_iter}")
+    t0 = time.time()
+    G = pat.Problem.from_workload(w)
+    info = G.info()
+    log(f"libpat problem created in {time.time() - t0:.1f} s: nnz={info['nnz_k']} "
+        f"boundary nodes={info['n_boundary_nodes']} lambda_max={info['lambda_max']:.4g}")
+
+    # synthetic data from the library's own float64 forward map (same recipe as the tests)
+    p0 = torch.as_tensor(w.p0_true, dtype=torch.float64, device=dev)[None].contiguous()
+    Y = pat.pat_forward(G, p0)[0]
+    eta0 = torch.as_tensor(W.noise_draw(w.n_steps, w.n_obs, w.noise_seed), device=dev)
+    sigma = float(w.d_noise * torch.linalg.norm(Y) / torch.linalg.norm(eta0))
+    yobs = (Y + sigma * eta0).contiguous()
+    eta_h, xi_h = W.rto_draws(R, w.n_steps, w.n_obs, w.n_nodes, w.rto_seed)
+    eta = torch.as_tensor(eta_h, device=dev)
+    xi = torch.as_tensor(xi_h, device=dev)
+    torch.cuda.synchronize()
+    log(f"data ready: sigma={sigma:.4e}")
+
+    def run():
+        return pat.rto_sample(G, yobs, eta, xi, sigma, w.prior_a, n_iter, sweep_prec="f32", rhs_block=64)
+
+    for k in range(args.warmup):
+        t = time.time()
+        run()
+        log(f"warmup {k + 1}/{args.warmup}: {time.time() - t:.2f} s")
+    G.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = run()
+        log(f"step {k + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = G.profile()
+    G.profile_enable(False)
+    ms_per_step = el / args.steps * 1e3
+    value = R * args.steps / el * 60.0
+    mean_norm = float(torch.linalg.norm(out["mean"]))
+    log(f"batched f32: {ms_per_step:.1f} ms per batch of {R} -> {value:.1f} samples/min (|mean|={mean_norm:.4e})")
+
+    # roofline of the dominant kernels: each sweep = N_T step launches (+1 tiny sampling/init launch)
+    fwd_avg_s = prof["fwd_ms"] / max(prof["fwd_sweeps"], 1) / w.n_steps / 1e3
+    adj_avg_s = prof["adj_ms"] / max(prof["adj_sweeps"], 1) / w.n_steps / 1e3
+    fb = step_bytes(info, 64, 4, "fwd")
+    ab = step_bytes(info, 64, 4, "adj")
+    fwd_gbs = fb / fwd_avg_s / 1e9
+    adj_gbs = ab / adj_avg_s / 1e9
+    sweep_share = (prof["fwd_ms"] + prof["adj_ms"]) / (el * 1e3)
+    log(f"forward step: {fwd_avg_s * 1e6:.2f} us, {fb / 1e6:.1f} MB -> {fwd_gbs:.0f} GB/s; transpose step: "
+        f"{adj_avg_s * 1e6:.2f} us, {ab / 1e6:.1f} MB -> {adj_gbs:.0f} GB/s; sweeps = {100 * sweep_share:.1f}% of time")
+
+    result = {
+        "metric": "RTO samples/min at 2e5 DOF (batched FP32 sweeps, FP64 CGLS)",
+        "value": round(value, 3), "unit": "samples/min", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: {w.n_nodes}-node mapped ball (P1 tets), variable c, absorbing boundary, "
+                         f"{w.n_steps} leapfrog steps, {w.n_obs} sensors on r=0.9, {R} RTO samples x {n_iter} "
+                         f"CGLS iterations with full reorthogonalisation as one 64-RHS block; float32 sweeps, "
+                         f"float64 CGLS vectors/dots/scalars"),
+            "n_nodes": w.n_nodes, "n_steps": w.n_steps, "n_obs": w.n_obs, "samples_per_step": R,
+            "cgls_iters": n_iter, "rhs_block": 64, "cgls_dtype": "f64",
+        },
+        "roofline": {
+            "kernel": "k_fwd<float,double,64> (forward leapfrog step)", "bound": "hbm",
+            "achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic("k_fwd_f32_rb64", w.name),
+            "bytes_per_launch": fb, "avg_launch_us": round(fwd_avg_s * 1e6, 3),
+            "transpose_step": {"achieved": round(adj_gbs, 1), "bytes_per_launch": ab,
+                               "avg_launch_us": round(adj_avg_s * 1e6, 3)},
+            "sweep_time_share": round(sweep_share, 4),
+        },
+    }
+
+    if not args.no_plain:
+        # plain float64 path: one sample at a time, float64 everywhere
+        e1, x1 = eta[:1].contiguous(), xi[:1].contiguous()
+        pat.rto_sample(G, yobs, e1, x1, sigma, w.prior_a, 2, sweep_prec="f64", rhs_block=1, stats=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pat.rto_sample(G, yobs, e1, x1, sigma, w.prior_a, n_iter, sweep_prec="f64", rhs_block=1, stats=False)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        plain = 60.0 / tp
+        result["plain_fp64"] = {"value": round(plain, 3), "unit": "samples/min", "rhs_block": 1,
+                                "seconds_per_sample": round(tp, 3), "speedup_batched_f32": round(value / plain, 2)}
+        log(f"plain f64 (1 sample, R=1): {tp:.2f} s -> {plain:.2f} samples/min; speed-up {value / plain:.1f}x")
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(w, eta_h, xi_h, yobs.cpu().numpy(), sigma, n_iter, R)
+        log(f"cpu baseline: {result['cpu_baseline']['value']:.4f} samples/min on "
+            f"{result['cpu_baseline']['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -69,7 +69,16 @@ typedef struct {
     int32_t n_boundary_nodes, max_row_nnz;
     double dt, lambda_max;      /* lambda_max: estimate of the largest eigenvalue of M_L^{-1} K */
     int64_t device_bytes;       /* device memory held by the handle (matrices + workspaces) */
+    int64_t b_stored;           /* stored boundary-mass values (full stiffness rows of boundary nodes) */
 } pat_problem_info;
+
+/* Sweep timing of rto_sample, from HIP events recorded on the caller's stream
+ * around each N_T-step sweep (forward: N_T step launches + 1 sampling launch;
+ * transpose: 1 init launch + N_T step launches). */
+typedef struct {
+    double fwd_ms, adj_ms;      /* summed sweep durations */
+    int64_t fwd_sweeps, adj_sweeps;
+} pat_profile;
 
 /* Assemble K (c^2 stiffness), K1 (unit-coefficient stiffness), the lumped mass
  * M_L = diag(M 1) and the consistent boundary mass B of Sec. 3 (matrices below
@@ -126,6 +135,10 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
 pat_status pat_host_assemble(const pat_problem_desc *desc, int64_t *nnz_out, int32_t *rowptr, int32_t *col,
                              double *kval, double *k1val, double *bval, double *mass, int32_t *snode, double *sw,
                              double *lambda_max);
+
+/* Enable (1) or disable (0) sweep timing in rto_sample; enabling resets the counters. */
+pat_status pat_profile_enable(pat_problem *p, int enable);
+pat_status pat_profile_get(const pat_problem *p, pat_profile *out);
 
 /* Wait for all work of the handle's device, report asynchronous errors. */
 pat_status pat_sync(pat_problem *p);

@@ -101,6 +101,10 @@ struct pat_problem {
     std::map<int, CglsWS> cgls;
     hipStream_t cap = nullptr;
     int64_t bytes = 0;
+    // sweep timing
+    bool prof = false;
+    pat_profile prof_acc{};
+    std::vector<hipEvent_t> events;
 };
 
 namespace {
@@ -201,6 +205,24 @@ void enqueue_adjoint(pat_problem *p, SweepWS &w, const void *yhat, bool y_f64, h
         cur = 1 - cur;
     }
     pat::launch_adj_step(w.prec, w.RB, op, w.P[0], w.V[cur], nullptr, true, 0, yhat, y_f64, 1.0, s);
+}
+
+// Launch a sweep graph; with profiling on, bracket it with two events from the pool.
+pat_status launch_sweep(pat_problem *p, hipGraphExec_t g, hipStream_t s, size_t *ev_used) {
+    if (p->prof) {
+        while (p->events.size() < *ev_used + 2) {
+            hipEvent_t e;
+            PAT_HIP(hipEventCreate(&e));
+            p->events.push_back(e);
+        }
+        PAT_HIP(hipEventRecord(p->events[*ev_used], s));
+        PAT_HIP(hipGraphLaunch(g, s));
+        PAT_HIP(hipEventRecord(p->events[*ev_used + 1], s));
+        *ev_used += 2;
+        return PAT_OK;
+    }
+    PAT_HIP(hipGraphLaunch(g, s));
+    return PAT_OK;
 }
 
 pat_status check_prec(pat_precision prec, pat::Prec *out) {
@@ -336,6 +358,7 @@ pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out) {
     in.max_row_nnz = hp.max_row;
     in.dt = hp.dt;
     in.lambda_max = hp.lambda_max;
+    in.b_stored = int64_t(hp.bval.size());
     *out = p.release();
     return PAT_OK;
 }
@@ -353,6 +376,7 @@ pat_status pat_problem_destroy(pat_problem *p) {
     for (void *a : p->allocs)
         if (a) (void)hipFree(a);
     if (p->cap) (void)hipStreamDestroy(p->cap);
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     delete p;
     return PAT_OK;
 }
@@ -457,6 +481,9 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
     double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
     const int64_t ld = n_iter + 1;
     std::vector<double> gam_host(size_t(((S + RB - 1) / RB) * RB), 0.0);
+    // event pairs: even index = forward sweep, odd = transpose sweep, per kind in order
+    size_t ev_used = 0;
+    std::vector<int> ev_kind;  // 0 forward, 1 transpose, per event pair
 
     for (int64_t rb0 = 0; rb0 < S; rb0 += RB) {
         // right-hand side b = (y_obs/sigma + eta, xi); r_0 = b, x_0 = 0
@@ -471,7 +498,8 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
             pat::launch_resid(t1, t2, resid_hist, ld, 0, rb0, S, RB, s);
         }
         // s_0 = G_ext^T r_0
-        PAT_HIP(hipGraphLaunch(w->g_adj_cgls, s));
+        PAT_TRY(launch_sweep(p, w->g_adj_cgls, s, &ev_used));
+        if (p->prof) ev_kind.push_back(1);
         pat::launch_gext_t_combine(pr, op, RB, a, isig, w->P[0], c->rp, c->s, s);
         pat::launch_dot_partial(c->s, c->s, N, RB, pA, s);
         pat::launch_dot_final(pA, nullptr, RB, gnew, s);
@@ -480,7 +508,8 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
         for (int it = 1; it <= n_iter; ++it) {
             // q = G_ext d
             pat::launch_cast_to_state(pr, c->d, w->P[0], N * RB, s);
-            PAT_HIP(hipGraphLaunch(w->g_fwd_cgls, s));
+            PAT_TRY(launch_sweep(p, w->g_fwd_cgls, s, &ev_used));
+            if (p->prof) ev_kind.push_back(0);
             pat::launch_prior(op, RB, a, c->d, c->qp, s);
             pat::launch_dot_partial(c->qd, c->qd, M, RB, pA, s);
             pat::launch_dot_partial(c->qp, c->qp, N, RB, pB, s);
@@ -498,7 +527,8 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
             }
             if (it == n_iter) break;
             // s = G_ext^T r, reorthogonalised against the earlier normalised s_j
-            PAT_HIP(hipGraphLaunch(w->g_adj_cgls, s));
+            PAT_TRY(launch_sweep(p, w->g_adj_cgls, s, &ev_used));
+            if (p->prof) ev_kind.push_back(1);
             pat::launch_gext_t_combine(pr, op, RB, a, isig, w->P[0], c->rp, c->s, s);
             if (reorth) {
                 for (int pass = 0; pass < 2; ++pass) {
@@ -518,6 +548,17 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
     if (mean || std) pat::launch_stats(samples, S, N, mean, std, s);
     PAT_HIP(hipGetLastError());
     PAT_HIP(hipStreamSynchronize(s));
+    for (size_t q = 0; q < ev_kind.size(); ++q) {
+        float ms = 0.f;
+        PAT_HIP(hipEventElapsedTime(&ms, p->events[2 * q], p->events[2 * q + 1]));
+        if (ev_kind[q] == 0) {
+            p->prof_acc.fwd_ms += ms;
+            ++p->prof_acc.fwd_sweeps;
+        } else {
+            p->prof_acc.adj_ms += ms;
+            ++p->prof_acc.adj_sweeps;
+        }
+    }
     for (int64_t k = 0; k < S; ++k)
         if (!std::isfinite(gam_host[size_t(k)]))
             return fail(PAT_ERR_NONFINITE, "non-finite CGLS scalar for sample " + std::to_string(k));
@@ -561,6 +602,19 @@ pat_status pat_host_assemble(const pat_problem_desc *desc, int64_t *nnz_out, int
             if (sw) sw[4 * s + k] = hp.sw[4 * s + k];
         }
     if (lambda_max) *lambda_max = hp.lambda_max;
+    return PAT_OK;
+}
+
+pat_status pat_profile_enable(pat_problem *p, int enable) {
+    if (!p) return fail(PAT_ERR_INVALID_ARG, "NULL handle");
+    p->prof = enable != 0;
+    p->prof_acc = pat_profile{};
+    return PAT_OK;
+}
+
+pat_status pat_profile_get(const pat_problem *p, pat_profile *out) {
+    if (!p || !out) return fail(PAT_ERR_INVALID_ARG, "NULL handle or output");
+    *out = p->prof_acc;
     return PAT_OK;
 }
 

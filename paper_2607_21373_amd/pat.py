@@ -48,7 +48,13 @@ class ProblemInfo(ctypes.Structure):
         ("n_tets", ctypes.c_int64), ("nnz_k", ctypes.c_int64), ("nnz_b", ctypes.c_int64),
         ("n_boundary_nodes", ctypes.c_int32), ("max_row_nnz", ctypes.c_int32),
         ("dt", ctypes.c_double), ("lambda_max", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+        ("b_stored", ctypes.c_int64),
     ]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("fwd_ms", ctypes.c_double), ("adj_ms", ctypes.c_double), ("fwd_sweeps", ctypes.c_int64),
+                ("adj_sweeps", ctypes.c_int64)]
 
 
 class RtoParams(ctypes.Structure):
@@ -61,7 +67,8 @@ class RtoParams(ctypes.Structure):
 
 # names exported by libpat (the C ABI in include/pat.h)
 EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-           "rto_sample", "pat_host_assemble", "pat_sync", "pat_last_error", "pat_version")
+           "rto_sample", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync", "pat_last_error",
+           "pat_version")
 
 _lib = None
 
@@ -84,10 +91,12 @@ def load() -> ctypes.CDLL:
     lib.rto_sample.argtypes = [vp, vp, ctypes.POINTER(RtoParams), ctypes.c_int64, vp, vp, vp, vp, vp]
     lib.pat_sync.argtypes = [vp]
     lib.pat_host_assemble.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ctypes.c_int64)] + [vp] * 9
+    lib.pat_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.pat_profile_get.argtypes = [vp, ctypes.POINTER(Profile)]
     lib.pat_last_error.restype = ctypes.c_char_p
     lib.pat_version.restype = ctypes.c_char_p
     for f in ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-              "rto_sample", "pat_host_assemble", "pat_sync"):
+              "rto_sample", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -219,6 +228,14 @@ class Problem:
 
     def sync(self):
         _check(load().pat_sync(self._h))
+
+    def profile_enable(self, on: bool = True):
+        _check(load().pat_profile_enable(self._h, int(bool(on))))
+
+    def profile(self) -> dict:
+        out = Profile()
+        _check(load().pat_profile_get(self._h, ctypes.byref(out)))
+        return {name: getattr(out, name) for name, _ in Profile._fields_}
 
 
 def pat_forward(problem: Problem, p0, y=None):
