@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--iters", type=int, default=None, help="CGLS iterations (default: the workload's 100)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before timing, copy a float32 buffer of this many MB three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (samples are independent, so "
@@ -134,6 +136,16 @@ def main():
     xi = torch.as_tensor(xi_h, device=dev)
     torch.cuda.synchronize()
     log(f"data ready: sigma={sigma:.4e}")
+
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy probe: 3 x {args.copy_probe_mb} MiB float32 copies")
 
     def run():
         return pat.rto_sample(G, yobs, eta, xi, sigma, w.prior_a, n_iter, sweep_prec="f32", rhs_block=64)

@@ -322,24 +322,29 @@ pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out) {
     } while (0)
     UP(hp.rowptr, rowptr);
     UP(hp.col, col);
-    UP(hp.boff, boff);
     UP(hp.snode, snode);
     UP(hp.injptr, injptr);
     UP(hp.injs, injs);
     UP(hp.perm, perm);
-    UP(hp.kval, kval64);
     UP(hp.k1val, k1val64);
-    UP(hp.bval, bval64);
     UP(dtm, dtm64);
     UP(sqm, sqrtm);
     UP(isqm, isqrtm);
     UP(hp.sw, sw64);
     UP(hp.injw, injw64);
-    UP(to_f32(hp.kval), kval32);
-    UP(to_f32(hp.bval), bval32);
     UP(to_f32(dtm), dtm32);
     UP(to_f32(hp.sw), sw32);
     UP(to_f32(hp.injw), injw32);
+    UP(hp.ell_col, ell_col);
+    UP(hp.xptr, xptr);
+    UP(hp.xcol, xcol);
+    UP(hp.bsoff, bsoff);
+    UP(hp.ell_val, ell_val64);
+    UP(hp.xval, xval64);
+    UP(hp.bslot, bslot64);
+    UP(to_f32(hp.ell_val), ell_val32);
+    UP(to_f32(hp.xval), xval32);
+    UP(to_f32(hp.bslot), bslot32);
 #undef UP
     p->perm_identity = true;
     for (int32_t i = 0; i < hp.n; ++i)

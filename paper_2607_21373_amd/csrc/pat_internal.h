@@ -35,6 +35,13 @@ struct HostProblem {
     // sum_e injw[e] * yhat[injs[e]] for e in [injptr[i], injptr[i+1])
     std::vector<int32_t> injptr, injs;
     std::vector<double> injw;
+    // Padded row layout of K used by the time-step kernels: entry j < kEll of row i
+    // at i*kEll + j (padding: column i, value 0); entries beyond kEll of a long row
+    // in a small CSR (xptr, xcol, xval).  Boundary rows keep their B values per
+    // slot: B(i, slot) = bslot[bsoff[i] + slot], slot < kEll + (xptr[i+1]-xptr[i]).
+    static constexpr int kEll = 16;
+    std::vector<int32_t> ell_col, xptr, xcol, bsoff;
+    std::vector<double> ell_val, xval, bslot;
     // internal <-> user numbering: perm[internal] = user, iperm[user] = internal
     std::vector<int32_t> perm, iperm;
     double lambda_max = 0.0;
@@ -42,6 +49,9 @@ struct HostProblem {
 
 // Assemble and validate; returns PAT_OK or an error with a message in *err.
 pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::string &err);
+
+// Build the padded row layout (ell_*, x*, bs*) from the CSR arrays.
+void build_padded_rows(HostProblem &hp);
 
 // Largest eigenvalue of M_L^{-1} K by power iteration on M^{-1/2} K M^{-1/2}.
 double estimate_lambda_max(const HostProblem &hp, int iters);

@@ -11,11 +11,16 @@ namespace pat {
 struct DevOps {
     int32_t n = 0, n_obs = 0, n_steps = 0;
     int64_t nnz = 0;
-    const int32_t *rowptr = nullptr, *col = nullptr, *boff = nullptr;
+    // CSR pattern of K with the unit-coefficient stiffness K1 (prior factor)
+    const int32_t *rowptr = nullptr, *col = nullptr;
+    const double *k1val64 = nullptr;
     const int32_t *snode = nullptr, *injptr = nullptr, *injs = nullptr, *perm = nullptr;
-    const double *kval64 = nullptr, *k1val64 = nullptr, *bval64 = nullptr, *dtm64 = nullptr;
-    const double *sqrtm = nullptr, *isqrtm = nullptr, *sw64 = nullptr, *injw64 = nullptr;
-    const float *kval32 = nullptr, *bval32 = nullptr, *dtm32 = nullptr, *sw32 = nullptr, *injw32 = nullptr;
+    const double *dtm64 = nullptr, *sqrtm = nullptr, *isqrtm = nullptr, *sw64 = nullptr, *injw64 = nullptr;
+    const float *dtm32 = nullptr, *sw32 = nullptr, *injw32 = nullptr;
+    // padded row layout of K for the time-step kernels
+    const int32_t *ell_col = nullptr, *xptr = nullptr, *xcol = nullptr, *bsoff = nullptr;
+    const double *ell_val64 = nullptr, *xval64 = nullptr, *bslot64 = nullptr;
+    const float *ell_val32 = nullptr, *xval32 = nullptr, *bslot32 = nullptr;
     double dt = 0.0;
 };
 

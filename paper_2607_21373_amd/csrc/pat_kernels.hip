@@ -18,14 +18,8 @@
 namespace pat {
 namespace {
 
-// Workgroup b is dispatched to XCD (b % 8).  Map it to a logical tile so that
-// each XCD walks one contiguous range of rows and its L2 holds the neighbour
-// window of that range.
-__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
-    const int q = nb >> 3, rem = nb & 7;
-    const int x = b & 7, k = b >> 3;
-    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
-}
+__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <int RB>
 struct Geo {
@@ -33,10 +27,9 @@ struct Geo {
     static constexpr int LPR = RB * SPLIT;              // lanes per row
     static constexpr int RPW = 64 / LPR;                // rows per wave
     static constexpr int RPB = 4 * RPW;                 // rows per 256-thread workgroup
+    static constexpr int W = 16;                        // padded slots per row (HostProblem::kEll)
+    static constexpr int PER = W / SPLIT;               // padded slots per lane
 };
-
-__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <int RB, int LPR>
 __device__ __forceinline__ float lane_sum(float v) {
@@ -49,71 +42,174 @@ __device__ __forceinline__ double lane_sum(double v) {
     return v;
 }
 
+// Row operands of the padded layout (see HostProblem::kEll): slot j < 16 of row i
+// at i*16 + j, the entries beyond 16 in (xptr, xcol, xval), and for boundary rows
+// the B value of each slot at bslot[bsoff[i] + slot].
+template <typename T>
+struct RowOps {
+    const int32_t *ecol, *xptr, *xcol, *bsoff;
+    const T *eval, *xval, *bslot, *dtm;
+};
+
+// Operands of one row, loaded one row ahead of their use.
+template <typename T, int RB>
+struct RowMeta {
+    int c[Geo<RB>::PER];
+    T w[Geo<RB>::PER];
+    int bo, x0, x1;
+    T dm;
+};
+
+template <typename T, int RB>
+__device__ __forceinline__ void load_meta(const RowOps<T> &o, int row, int part, RowMeta<T, RB> &m) {
+    using G = Geo<RB>;
+    const int64_t eb = int64_t(row) * G::W;
+#pragma unroll
+    for (int j = 0; j < G::PER; ++j) {
+        m.c[j] = o.ecol[eb + part + j * G::SPLIT];
+        m.w[j] = o.eval[eb + part + j * G::SPLIT];
+    }
+    m.bo = o.bsoff[row];
+    m.x0 = o.xptr[row];
+    m.x1 = o.xptr[row + 1];
+    m.dm = o.dtm[row];
+}
+
+// sum over the row's entries of K(row, k) X[col_k][r] into acc, and of B(row, k) Y[col_k][r]
+// into bacc for a boundary row (Y == X shares the gathers).  All PER gathers of the lane
+// are issued before any is consumed; sums run in slot order, then the entries beyond 16.
+template <typename T, int RB, bool Y_IS_X>
+__device__ __forceinline__ void row_sums(const RowOps<T> &o, const RowMeta<T, RB> &m, int part, int r,
+                                         const T *__restrict__ X, const T *__restrict__ Y, bool with_b, T &acc,
+                                         T &bacc) {
+    using G = Geo<RB>;
+    T x[G::PER];
+#pragma unroll
+    for (int j = 0; j < G::PER; ++j) x[j] = X[int64_t(m.c[j]) * RB + r];
+#pragma unroll
+    for (int j = 0; j < G::PER; ++j) acc = mad(m.w[j], x[j], acc);
+    if (with_b) {
+        const T *Bv = o.bslot + m.bo;
+        T bw[G::PER];
+#pragma unroll
+        for (int j = 0; j < G::PER; ++j) bw[j] = Bv[part + j * G::SPLIT];
+        if constexpr (Y_IS_X) {
+#pragma unroll
+            for (int j = 0; j < G::PER; ++j) bacc = mad(bw[j], x[j], bacc);
+        } else {
+            T y[G::PER];
+#pragma unroll
+            for (int j = 0; j < G::PER; ++j) y[j] = Y[int64_t(m.c[j]) * RB + r];
+#pragma unroll
+            for (int j = 0; j < G::PER; ++j) bacc = mad(bw[j], y[j], bacc);
+        }
+    }
+    for (int k = m.x0 + part; k < m.x1; k += G::SPLIT) {
+        const int64_t cj = int64_t(o.xcol[k]) * RB + r;
+        const T xv = X[cj];
+        acc = mad(o.xval[k], xv, acc);
+        if (with_b) bacc = mad(o.bslot[m.bo + G::W + (k - m.x0)], Y_IS_X ? xv : Y[cj], bacc);
+    }
+}
+
+// Persistent row schedule: the grid has 8*gx workgroups; workgroup b runs on XCD
+// (b % 8) and takes tiles (RPB rows each) tx0 + (b / 8) + k*gx of that XCD's
+// contiguous tile range [tx0, tx1), so each XCD sweeps one contiguous part of
+// the rows and all its workgroups advance through it together.
+struct TileRange {
+    int first, end, stride;
+};
+__device__ __forceinline__ TileRange xcd_tiles(int ntile) {
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, gx = gridDim.x >> 3;
+    const int q = ntile >> 3, rem = ntile & 7;
+    const int tx0 = x * q + (x < rem ? x : rem);
+    const int tx1 = tx0 + q + (x < rem ? 1 : 0);
+    return TileRange{tx0 + j, tx1, gx};
+}
+
 template <typename T>
 struct FwdArgs {
-    const int32_t *rowptr, *col, *boff, *snode;
-    const T *kval, *bval, *dtm, *sw;
+    RowOps<T> o;
+    const int32_t *snode;
+    const T *sw;
     const T *P, *V;
     T *Pn, *Vn;
     void *y;
     double yscale;
-    int n, n_obs, n_row_blocks, first, sample, t;
+    int n, n_obs, n_tiles, first, sample, t;
     T dt, half_dt;
 };
 
 // Forward step.  State (P, V) = (p^{n+1/2}, v^n):
 //   V' = V - (dt/m) (K P + B V),  P' = P + dt V'
-// which is the three-substep Stormer-Verlet update with lumped mass.
-// Sampling workgroups (after the row workgroups) write y^n = Pi (P - dt/2 V).
+// which is the three-substep Stormer-Verlet update with lumped mass.  The same
+// workgroups then write the samples y^n = Pi (P - dt/2 V) of the incoming state.
 template <typename T, typename OT, int RB>
 __global__ void __launch_bounds__(256) k_fwd(const FwdArgs<T> a) {
     using G = Geo<RB>;
-    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / G::LPR, part = (lane / RB) % G::SPLIT, r = lane % RB;
-    if (b < a.n_row_blocks) {
-        int row = (b * 4 + wave) * G::RPW + slot;
+    const TileRange tr = xcd_tiles(a.n_tiles);
+    const int off = wave * G::RPW + slot;
+    int tile = tr.first;
+    if (tile < tr.end) {
+        int row = tile * G::RPB + off;
         if constexpr (RB == 64) row = __builtin_amdgcn_readfirstlane(row);
-        if (row >= a.n) return;
-        const int k0 = a.rowptr[row], k1 = a.rowptr[row + 1];
-        T acc = T(0);
-        for (int k = k0 + part; k < k1; k += G::SPLIT) acc = mad(a.kval[k], a.P[int64_t(a.col[k]) * RB + r], acc);
-        const int bo = a.boff[row];
-        if (!a.first && bo >= 0)
-            for (int k = k0 + part; k < k1; k += G::SPLIT)
-                acc = mad(a.bval[bo + (k - k0)], a.V[int64_t(a.col[k]) * RB + r], acc);
-        acc = lane_sum<RB, G::LPR>(acc);
-        if (part == 0) {
-            const int64_t id = int64_t(row) * RB + r;
-            const T v0 = a.first ? T(0) : a.V[id];
-            const T v = v0 - a.dtm[row] * acc;
-            a.Vn[id] = v;
-            a.Pn[id] = a.P[id] + a.dt * v;
+        RowMeta<T, RB> m;
+        load_meta<T, RB>(a.o, row < a.n ? row : a.n - 1, part, m);
+        for (;;) {
+            const int ntile = tile + tr.stride;
+            const bool more = ntile < tr.end;
+            int nrow = ntile * G::RPB + off;
+            if constexpr (RB == 64) nrow = __builtin_amdgcn_readfirstlane(nrow);
+            RowMeta<T, RB> mn;
+            if (more) load_meta<T, RB>(a.o, nrow < a.n ? nrow : a.n - 1, part, mn);
+            if (row < a.n) {
+                const int64_t id = int64_t(row) * RB + r;
+                const T v0 = a.first ? T(0) : a.V[id];
+                T acc = T(0), bacc = T(0);
+                row_sums<T, RB, false>(a.o, m, part, r, a.P, a.V, !a.first && m.bo >= 0, acc, bacc);
+                acc = lane_sum<RB, G::LPR>(acc + bacc);
+                if (part == 0) {
+                    const T v = v0 - m.dm * acc;
+                    a.Vn[id] = v;
+                    a.Pn[id] = a.P[id] + a.dt * v;
+                }
+            }
+            if (!more) break;
+            tile = ntile;
+            row = nrow;
+            m = mn;
         }
-    } else if (a.sample) {
-        const int s = ((b - a.n_row_blocks) * 4 + wave) * G::RPW + slot;
-        if (s >= a.n_obs || part != 0) return;
-        T y = T(0);
-        for (int k = 0; k < 4; ++k) {
-            const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
-            const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
-            y = mad(a.sw[4 * s + k], pk, y);
+    }
+    if (a.sample) {
+        // sensors spread over all workgroups: lane group g of the grid takes s = g, g + groups, ...
+        const int groups = gridDim.x * 4 * G::RPW;
+        for (int s = blockIdx.x * 4 * G::RPW + off; s < a.n_obs; s += groups) {
+            if (part != 0) continue;
+            T y = T(0);
+            for (int k = 0; k < 4; ++k) {
+                const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
+                const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
+                y = mad(a.sw[4 * s + k], pk, y);
+            }
+            OT *yo = static_cast<OT *>(a.y);
+            yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
         }
-        OT *yo = static_cast<OT *>(a.y);
-        yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
     }
 }
 
 template <typename T>
 struct AdjArgs {
-    const int32_t *rowptr, *col, *boff, *injptr, *injs;
-    const T *kval, *bval, *dtm, *injw;
+    RowOps<T> o;
+    const int32_t *injptr, *injs;
+    const T *injw;
     T *PH;
     const T *Q;
     T *Qn;
     const void *yh;
     double yscale;
-    int n, n_obs, last, tm1;
+    int n, n_obs, n_tiles, last, tm1;
     T dt;
 };
 
@@ -130,35 +226,297 @@ __device__ __forceinline__ T inject(const AdjArgs<T> &a, int row, int r, int t) 
 // Transposed step on the staggered state (PH = p_hat, Q = M_L^{-1}(v_hat + dt/2 p_hat)):
 //   PH -= dt K Q ;  unless last:  Q' = Q - (dt/m) B Q + (dt/m)(PH + inj/2),  PH += inj
 // with inj = Pi^T yhat^{n-1}.  Algebraically identical to applying the five
-// transposed substeps and then adding Pi^T yhat^{n-1}.
+// transposed substeps and then adding Pi^T yhat^{n-1}.  K Q and B Q share the
+// gathers of Q.  Same persistent schedule as the forward step.
 template <typename T, typename YT, int RB>
 __global__ void __launch_bounds__(256) k_adj(const AdjArgs<T> a) {
     using G = Geo<RB>;
-    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / G::LPR, part = (lane / RB) % G::SPLIT, r = lane % RB;
-    int row = (b * 4 + wave) * G::RPW + slot;
+    const TileRange tr = xcd_tiles(a.n_tiles);
+    const int off = wave * G::RPW + slot;
+    int tile = tr.first;
+    if (tile >= tr.end) return;
+    int row = tile * G::RPB + off;
     if constexpr (RB == 64) row = __builtin_amdgcn_readfirstlane(row);
-    if (row >= a.n) return;
-    const int k0 = a.rowptr[row], k1 = a.rowptr[row + 1];
-    T kq = T(0), bq = T(0);
-    for (int k = k0 + part; k < k1; k += G::SPLIT) kq = mad(a.kval[k], a.Q[int64_t(a.col[k]) * RB + r], kq);
-    const int bo = a.boff[row];
-    if (!a.last && bo >= 0)
-        for (int k = k0 + part; k < k1; k += G::SPLIT)
-            bq = mad(a.bval[bo + (k - k0)], a.Q[int64_t(a.col[k]) * RB + r], bq);
-    kq = lane_sum<RB, G::LPR>(kq);
-    bq = lane_sum<RB, G::LPR>(bq);
-    if (part != 0) return;
-    const int64_t id = int64_t(row) * RB + r;
-    T ph = a.PH[id] - a.dt * kq;
-    if (!a.last) {
-        const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
-        const T dm = a.dtm[row];
-        a.Qn[id] = a.Q[id] - dm * bq + dm * (ph + T(0.5) * inj);
-        ph += inj;
+    RowMeta<T, RB> m;
+    load_meta<T, RB>(a.o, row < a.n ? row : a.n - 1, part, m);
+    for (;;) {
+        const int ntile = tile + tr.stride;
+        const bool more = ntile < tr.end;
+        int nrow = ntile * G::RPB + off;
+        if constexpr (RB == 64) nrow = __builtin_amdgcn_readfirstlane(nrow);
+        RowMeta<T, RB> mn;
+        if (more) load_meta<T, RB>(a.o, nrow < a.n ? nrow : a.n - 1, part, mn);
+        if (row < a.n) {
+            const int64_t id = int64_t(row) * RB + r;
+            const T ph0 = a.PH[id];
+            T kq = T(0), bq = T(0);
+            row_sums<T, RB, true>(a.o, m, part, r, a.Q, a.Q, !a.last && m.bo >= 0, kq, bq);
+            kq = lane_sum<RB, G::LPR>(kq);
+            bq = lane_sum<RB, G::LPR>(bq);
+            if (part == 0) {
+                T ph = ph0 - a.dt * kq;
+                if (!a.last) {
+                    const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
+                    a.Qn[id] = a.Q[id] - m.dm * bq + m.dm * (ph + T(0.5) * inj);
+                    ph += inj;
+                }
+                a.PH[id] = ph;
+            }
+        }
+        if (!more) break;
+        tile = ntile;
+        row = nrow;
+        m = mn;
     }
-    a.PH[id] = ph;
+}
+
+// ---------------------------------------------------------------------------
+// Vector-lane step kernels (used when a row of the RHS block is >= 16 bytes).
+//
+// Each lane moves 16 bytes (VEC = 4 floats or 2 doubles, i.e. VEC right-hand
+// sides), a lane group of LPR = RB / VEC lanes owns one row, and one wave64
+// instruction gathers 64/LPR neighbour rows at once.  The padded row operands
+// of a tile (column, stiffness and boundary weight per slot, dt/m, overflow
+// range) are staged in LDS once per tile and read back as LDS broadcasts.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using t = float __attribute__((ext_vector_type(4)));
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    using t = double __attribute__((ext_vector_type(2)));
+    static constexpr int n = 2;
+};
+
+template <typename T, int RB>
+struct VGeo {
+    static constexpr int VEC = Vec16<T>::n;
+    static constexpr int LPR = RB / VEC;     // lanes per row
+    static constexpr int RPW = 64 / LPR;     // rows per wave
+    static constexpr int RPB = 4 * RPW;      // rows per 256-thread workgroup (one tile)
+    static constexpr int W = 16;             // padded slots per row
+};
+
+// Workgroup b is dispatched to XCD (b % 8); map it to a logical tile so that
+// each XCD walks one contiguous range of rows.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
+}
+
+// LDS image of one tile's row operands.
+template <typename T, int RB>
+struct TileOps {
+    using G = VGeo<T, RB>;
+    int col[G::RPB * G::W];
+    T kv[G::RPB * G::W];
+    T bv[G::RPB * G::W];
+    T dm[G::RPB];
+    int bo[G::RPB], x0[G::RPB], x1[G::RPB];
+};
+
+// Stage the operands of rows [row0, row0 + RPB) (rows >= n get zero weights).
+// Contains __syncthreads(); every thread of the workgroup must call it.
+template <typename T, int RB>
+__device__ __forceinline__ void stage_tile(const RowOps<T> &o, int n, int row0, bool need_b, TileOps<T, RB> &L) {
+    using G = VGeo<T, RB>;
+    for (int e = threadIdx.x; e < G::RPB * G::W; e += 256) {
+        const int rw = row0 + e / G::W;
+        const bool ok = rw < n;
+        const int64_t src = int64_t(ok ? rw : 0) * G::W + e % G::W;
+        L.col[e] = ok ? o.ecol[src] : 0;
+        L.kv[e] = ok ? o.eval[src] : T(0);
+    }
+    for (int e = threadIdx.x; e < G::RPB; e += 256) {
+        const int rw = row0 + e;
+        const bool ok = rw < n;
+        L.bo[e] = ok ? o.bsoff[rw] : -1;
+        L.x0[e] = ok ? o.xptr[rw] : 0;
+        L.x1[e] = ok ? o.xptr[rw + 1] : 0;
+        L.dm[e] = ok ? o.dtm[rw] : T(0);
+    }
+    __syncthreads();
+    if (need_b) {
+        for (int e = threadIdx.x; e < G::RPB * G::W; e += 256) {
+            const int bo = L.bo[e / G::W];
+            L.bv[e] = bo >= 0 ? o.bslot[bo + e % G::W] : T(0);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename VT, typename T>
+__device__ __forceinline__ VT vfma(T w, VT x, VT acc) {
+    VT o;
+#pragma unroll
+    for (int i = 0; i < Vec16<T>::n; ++i) o[i] = mad(w, x[i], acc[i]);
+    return o;
+}
+
+// acc += sum_slots K(row, slot) X[col][q-th vector]; with Bs, bacc += B(row, slot) Y[col]
+// (Y == X shares the gathers); then the overflow entries of long rows.
+template <typename T, int RB, bool Y_IS_X>
+__device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, RB> &L, int lr, int q,
+                                          const T *__restrict__ X, const T *__restrict__ Y, bool with_b,
+                                          typename Vec16<T>::t &acc, typename Vec16<T>::t &bacc) {
+    using G = VGeo<T, RB>;
+    using VT = typename Vec16<T>::t;
+    const int base = lr * G::W;
+    VT x[G::W];
+#pragma unroll
+    for (int j = 0; j < G::W; ++j)
+        x[j] = *reinterpret_cast<const VT *>(X + int64_t(L.col[base + j]) * RB + q * G::VEC);
+#pragma unroll
+    for (int j = 0; j < G::W; ++j) acc = vfma(L.kv[base + j], x[j], acc);
+    if (with_b) {
+        if constexpr (Y_IS_X) {
+#pragma unroll
+            for (int j = 0; j < G::W; ++j) bacc = vfma(L.bv[base + j], x[j], bacc);
+        } else {
+#pragma unroll
+            for (int j = 0; j < G::W; ++j)
+                x[j] = *reinterpret_cast<const VT *>(Y + int64_t(L.col[base + j]) * RB + q * G::VEC);
+#pragma unroll
+            for (int j = 0; j < G::W; ++j) bacc = vfma(L.bv[base + j], x[j], bacc);
+        }
+    }
+    const int x0 = L.x0[lr], x1 = L.x1[lr];
+    for (int k = x0; k < x1; ++k) {
+        const int64_t cj = int64_t(o.xcol[k]) * RB + q * G::VEC;
+        const VT xv = *reinterpret_cast<const VT *>(X + cj);
+        acc = vfma(o.xval[k], xv, acc);
+        if (with_b) {
+            const T bw = o.bslot[L.bo[lr] + G::W + (k - x0)];
+            bacc = vfma(bw, Y_IS_X ? xv : *reinterpret_cast<const VT *>(Y + cj), bacc);
+        }
+    }
+}
+
+template <typename T>
+struct VFwdArgs {
+    RowOps<T> o;
+    const int32_t *snode;
+    const T *sw;
+    const T *P, *V;
+    T *Pn, *Vn;
+    void *y;
+    double yscale;
+    int n, n_obs, n_tiles, first, sample, t;
+    T dt, half_dt;
+};
+
+// Forward step (same update as k_fwd) with vector lanes; the workgroups after
+// the row tiles write the samples y^n = Pi (P - dt/2 V) of the incoming state.
+template <typename T, typename OT, int RB>
+__global__ void __launch_bounds__(256) k_fwd_v(const VFwdArgs<T> a) {
+    using G = VGeo<T, RB>;
+    using VT = typename Vec16<T>::t;
+    __shared__ TileOps<T, RB> L;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile < a.n_tiles) {
+        const int row0 = tile * G::RPB;
+        stage_tile<T, RB>(a.o, a.n, row0, !a.first, L);
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int lr = wave * G::RPW + lane / G::LPR, q = lane % G::LPR;
+        const int row = row0 + lr;
+        if (row < a.n) {
+            const int64_t id = int64_t(row) * RB + q * G::VEC;
+            VT v0 = {};
+            if (!a.first) v0 = *reinterpret_cast<const VT *>(a.V + id);
+            const VT p0 = *reinterpret_cast<const VT *>(a.P + id);
+            VT acc = {}, bacc = {};
+            vrow_sums<T, RB, false>(a.o, L, lr, q, a.P, a.V, !a.first && L.bo[lr] >= 0, acc, bacc);
+            const T dm = L.dm[lr];
+            VT v, pn;
+#pragma unroll
+            for (int i = 0; i < G::VEC; ++i) {
+                v[i] = v0[i] - dm * (acc[i] + bacc[i]);
+                pn[i] = p0[i] + a.dt * v[i];
+            }
+            *reinterpret_cast<VT *>(a.Vn + id) = v;
+            *reinterpret_cast<VT *>(a.Pn + id) = pn;
+        }
+    } else if (a.sample) {
+        // one lane per (sensor, rhs)
+        const int64_t e = int64_t(tile - a.n_tiles) * 256 + threadIdx.x;
+        if (e >= int64_t(a.n_obs) * RB) return;
+        const int s = int(e / RB), r = int(e % RB);
+        T y = T(0);
+        for (int k = 0; k < 4; ++k) {
+            const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
+            const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
+            y = mad(a.sw[4 * s + k], pk, y);
+        }
+        OT *yo = static_cast<OT *>(a.y);
+        yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
+    }
+}
+
+template <typename T>
+struct VAdjArgs {
+    RowOps<T> o;
+    const int32_t *injptr, *injs;
+    const T *injw;
+    T *PH;
+    const T *Q;
+    T *Qn;
+    const void *yh;
+    double yscale;
+    int n, n_obs, n_tiles, last, tm1;
+    T dt;
+};
+
+// Transposed step (same update as k_adj) with vector lanes.
+template <typename T, typename YT, int RB>
+__global__ void __launch_bounds__(256) k_adj_v(const VAdjArgs<T> a) {
+    using G = VGeo<T, RB>;
+    using VT = typename Vec16<T>::t;
+    __shared__ TileOps<T, RB> L;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= a.n_tiles) return;
+    const int row0 = tile * G::RPB;
+    stage_tile<T, RB>(a.o, a.n, row0, !a.last, L);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = wave * G::RPW + lane / G::LPR, q = lane % G::LPR;
+    const int row = row0 + lr;
+    if (row >= a.n) return;
+    const int64_t id = int64_t(row) * RB + q * G::VEC;
+    const VT ph0 = *reinterpret_cast<const VT *>(a.PH + id);
+    VT q0 = {};
+    if (!a.last) q0 = *reinterpret_cast<const VT *>(a.Q + id);
+    VT kq = {}, bq = {};
+    vrow_sums<T, RB, true>(a.o, L, lr, q, a.Q, a.Q, !a.last && L.bo[lr] >= 0, kq, bq);
+    VT ph;
+#pragma unroll
+    for (int i = 0; i < G::VEC; ++i) ph[i] = ph0[i] - a.dt * kq[i];
+    if (!a.last) {
+        const T dm = L.dm[lr];
+        VT inj = {};
+        const YT *yh = static_cast<const YT *>(a.yh);
+        for (int e = a.injptr[row]; e < a.injptr[row + 1]; ++e) {
+            const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + q * G::VEC;
+            const T w = a.injw[e];
+#pragma unroll
+            for (int i = 0; i < G::VEC; ++i)
+                inj[i] = mad(w, static_cast<T>(static_cast<double>(yh[src + i]) * a.yscale), inj[i]);
+        }
+        VT qn;
+#pragma unroll
+        for (int i = 0; i < G::VEC; ++i) {
+            qn[i] = q0[i] - dm * bq[i] + dm * (ph[i] + T(0.5) * inj[i]);
+            ph[i] += inj[i];
+        }
+        *reinterpret_cast<VT *>(a.Qn + id) = qn;
+    }
+    *reinterpret_cast<VT *>(a.PH + id) = ph;
 }
 
 // p_hat = Pi^T yhat^{N_T}, q = (dt/2m) p_hat
@@ -169,7 +527,7 @@ __global__ void __launch_bounds__(256) k_adj_init(const AdjArgs<T> a) {
         const int row = int(e / RB), r = int(e % RB);
         const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
         a.PH[e] = inj;
-        a.Qn[e] = T(0.5) * a.dtm[row] * inj;
+        a.Qn[e] = T(0.5) * a.o.dtm[row] * inj;
     }
 }
 
@@ -438,6 +796,20 @@ __global__ void k_stats(const double *x, int64_t S, int64_t N, double *mean, dou
     }
 }
 
+// Workgroups of a persistent step launch: a multiple of 8 (one share per XCD),
+// PAT_WG_PER_CU resident 256-thread workgroups on each of the 256 CUs, and no
+// more than there are tiles.
+#ifndef PAT_WG_PER_CU
+#define PAT_WG_PER_CU 8
+#endif
+int persistent_grid(int ntiles) {
+    const int per_xcd = 32 * PAT_WG_PER_CU;
+    int gx = (ntiles + 7) / 8;
+    if (gx > per_xcd) gx = per_xcd;
+    if (gx < 1) gx = 1;
+    return 8 * gx;
+}
+
 int grid_for(int64_t total, int per_block = 256, int cap = 65536) {
     int64_t g = (total + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -445,41 +817,85 @@ int grid_for(int64_t total, int per_block = 256, int cap = 65536) {
 }
 
 template <typename T>
-struct OpsOf;
+RowOps<T> row_ops(const DevOps &op);
 template <>
-struct OpsOf<double> {
-    static const double *k(const DevOps &o) { return o.kval64; }
-    static const double *b(const DevOps &o) { return o.bval64; }
-    static const double *dtm(const DevOps &o) { return o.dtm64; }
-    static const double *sw(const DevOps &o) { return o.sw64; }
-    static const double *injw(const DevOps &o) { return o.injw64; }
-};
+RowOps<double> row_ops<double>(const DevOps &op) {
+    return RowOps<double>{op.ell_col, op.xptr, op.xcol, op.bsoff, op.ell_val64, op.xval64, op.bslot64, op.dtm64};
+}
 template <>
-struct OpsOf<float> {
-    static const float *k(const DevOps &o) { return o.kval32; }
-    static const float *b(const DevOps &o) { return o.bval32; }
-    static const float *dtm(const DevOps &o) { return o.dtm32; }
-    static const float *sw(const DevOps &o) { return o.sw32; }
-    static const float *injw(const DevOps &o) { return o.injw32; }
-};
+RowOps<float> row_ops<float>(const DevOps &op) {
+    return RowOps<float>{op.ell_col, op.xptr, op.xcol, op.bsoff, op.ell_val32, op.xval32, op.bslot32, op.dtm32};
+}
+template <typename T>
+const T *sw_of(const DevOps &op);
+template <>
+const double *sw_of<double>(const DevOps &op) { return op.sw64; }
+template <>
+const float *sw_of<float>(const DevOps &op) { return op.sw32; }
+template <typename T>
+const T *injw_of(const DevOps &op);
+template <>
+const double *injw_of<double>(const DevOps &op) { return op.injw64; }
+template <>
+const float *injw_of<float>(const DevOps &op) { return op.injw32; }
 
 template <typename T, typename OT, int RB>
-void fwd_impl(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
-              int t, void *y, double yscale, hipStream_t s) {
-    using G = Geo<RB>;
-    FwdArgs<T> a;
-    a.rowptr = op.rowptr; a.col = op.col; a.boff = op.boff; a.snode = op.snode;
-    a.kval = OpsOf<T>::k(op); a.bval = OpsOf<T>::b(op); a.dtm = OpsOf<T>::dtm(op); a.sw = OpsOf<T>::sw(op);
+void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
+                int t, void *y, double yscale, hipStream_t s) {
+    using G = VGeo<T, RB>;
+    VFwdArgs<T> a;
+    a.o = row_ops<T>(op);
+    a.snode = op.snode;
+    a.sw = sw_of<T>(op);
     a.P = static_cast<const T *>(P); a.V = static_cast<const T *>(V);
     a.Pn = static_cast<T *>(Pn); a.Vn = static_cast<T *>(Vn);
     a.y = y; a.yscale = yscale;
     a.n = op.n; a.n_obs = op.n_obs;
-    a.n_row_blocks = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
+    a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
     a.first = first; a.sample = sample; a.t = t;
     a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
-    const int sblocks = sample ? (op.n_obs + G::RPB - 1) / G::RPB : 0;
-    const int grid = a.n_row_blocks + sblocks;
-    if (grid > 0) hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
+    const int sblocks = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
+    const int grid = a.n_tiles + sblocks;
+    if (grid > 0) hipLaunchKernelGGL((k_fwd_v<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
+}
+
+template <typename T, typename YT, int RB>
+void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
+                double yscale, hipStream_t s) {
+    using G = VGeo<T, RB>;
+    VAdjArgs<T> a;
+    a.o = row_ops<T>(op);
+    a.injptr = op.injptr; a.injs = op.injs;
+    a.injw = injw_of<T>(op);
+    a.PH = static_cast<T *>(PH); a.Q = static_cast<const T *>(Q); a.Qn = static_cast<T *>(Qn);
+    a.yh = yh; a.yscale = yscale;
+    a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
+    a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
+    a.dt = T(op.dt);
+    hipLaunchKernelGGL((k_adj_v<T, YT, RB>), dim3(a.n_tiles), dim3(256), 0, s, a);
+}
+
+template <typename T, typename OT, int RB>
+void fwd_impl(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
+              int t, void *y, double yscale, hipStream_t s) {
+    if constexpr (RB * sizeof(T) >= 16) {
+        fwd_impl_v<T, OT, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s);
+        return;
+    }
+    using G = Geo<RB>;
+    FwdArgs<T> a;
+    a.o = row_ops<T>(op);
+    a.snode = op.snode;
+    a.sw = sw_of<T>(op);
+    a.P = static_cast<const T *>(P); a.V = static_cast<const T *>(V);
+    a.Pn = static_cast<T *>(Pn); a.Vn = static_cast<T *>(Vn);
+    a.y = y; a.yscale = yscale;
+    a.n = op.n; a.n_obs = op.n_obs;
+    a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
+    a.first = first; a.sample = sample; a.t = t;
+    a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
+    const int grid = rows ? persistent_grid(a.n_tiles) : 8 * ((op.n_obs + 8 * 4 * G::RPW - 1) / (8 * 4 * G::RPW));
+    hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
 }
 
 template <typename T, typename YT, int RB>
@@ -487,17 +903,24 @@ void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bo
               double yscale, hipStream_t s) {
     using G = Geo<RB>;
     AdjArgs<T> a;
-    a.rowptr = op.rowptr; a.col = op.col; a.boff = op.boff; a.injptr = op.injptr; a.injs = op.injs;
-    a.kval = OpsOf<T>::k(op); a.bval = OpsOf<T>::b(op); a.dtm = OpsOf<T>::dtm(op); a.injw = OpsOf<T>::injw(op);
+    a.o = row_ops<T>(op);
+    a.injptr = op.injptr; a.injs = op.injs;
+    a.injw = injw_of<T>(op);
     a.PH = static_cast<T *>(PH); a.Q = static_cast<const T *>(Q); a.Qn = static_cast<T *>(Qn);
     a.yh = yh; a.yscale = yscale;
     a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
+    a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
     a.dt = T(op.dt);
+    if constexpr (RB * sizeof(T) >= 16) {
+        if (!init) {
+            adj_impl_v<T, YT, RB>(op, PH, Q, Qn, last, tm1, yh, yscale, s);
+            return;
+        }
+    }
     if (init) {
         hipLaunchKernelGGL((k_adj_init<T, YT, RB>), dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, a);
     } else {
-        const int grid = (op.n + G::RPB - 1) / G::RPB;
-        hipLaunchKernelGGL((k_adj<T, YT, RB>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adj<T, YT, RB>), dim3(persistent_grid(a.n_tiles)), dim3(256), 0, s, a);
     }
 }
 

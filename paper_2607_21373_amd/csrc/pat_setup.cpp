@@ -97,6 +97,45 @@ double barycentric(const Shape &s, const double *x, double lam[4]) {
     return std::min(std::min(lam[0], lam[1]), std::min(lam[2], lam[3]));
 }
 
+// Locality order of the nodes for the time-step kernels: recursive coordinate
+// bisection into 8 equal parts (one per XCD of the GPU, each split at the median
+// of its longest extent), then each part sorted along its own longest extent.
+// A row's neighbours then lie within a thin slab of its part, which the part's
+// L2 holds while the part is swept.  Stable sorts keep the order deterministic.
+void locality_order(const double *X, int32_t N, std::vector<int32_t> &perm) {
+    perm.resize(size_t(N));
+    for (int32_t i = 0; i < N; ++i) perm[size_t(i)] = i;
+    auto longest_axis = [&](size_t a, size_t b) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (size_t q = a; q < b; ++q)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], X[3 * size_t(perm[q]) + k]);
+                hi[k] = std::max(hi[k], X[3 * size_t(perm[q]) + k]);
+            }
+        int ax = 0;
+        for (int k = 1; k < 3; ++k)
+            if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+        return ax;
+    };
+    auto sort_along = [&](size_t a, size_t b, int ax) {
+        std::stable_sort(perm.begin() + a, perm.begin() + b,
+                         [&](int32_t u, int32_t v) { return X[3 * size_t(u) + ax] < X[3 * size_t(v) + ax]; });
+    };
+    std::vector<std::pair<size_t, size_t>> parts = {{0, size_t(N)}};
+    for (int level = 0; level < 3; ++level) {
+        std::vector<std::pair<size_t, size_t>> next;
+        for (auto [a, b] : parts) {
+            sort_along(a, b, longest_axis(a, b));
+            const size_t m = a + (b - a) / 2;
+            next.push_back({a, m});
+            next.push_back({m, b});
+        }
+        parts.swap(next);
+    }
+    for (auto [a, b] : parts)
+        if (b > a) sort_along(a, b, longest_axis(a, b));
+}
+
 int local_index(const int32_t *t, int32_t node) {
     for (int a = 0; a < 4; ++a)
         if (t[a] == node) return a;
@@ -142,11 +181,10 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
     hp.n_steps = d.n_steps;
     hp.n_tets = E;
     hp.dt = d.dt;
-    // Internal numbering: the caller's order (structured and sorted meshes already
-    // keep neighbours close); the permutation arrays let a reordering slot in.
-    hp.perm.resize(N);
+    // Internal numbering (see locality_order): perm[internal] = user node.
+    locality_order(d.coords, N, hp.perm);
     hp.iperm.resize(N);
-    for (int32_t i = 0; i < N; ++i) hp.perm[i] = hp.iperm[i] = i;
+    for (int32_t i = 0; i < N; ++i) hp.iperm[hp.perm[i]] = i;
 
     // node -> incident tetrahedra (ascending tetrahedron index)
     std::vector<int64_t> inc_ptr(size_t(N) + 1, 0);
@@ -181,10 +219,11 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
     std::vector<int32_t> rowlen(N);
     std::vector<std::vector<int32_t>> cols(N);
     parallel_for(N, [&](int64_t i) {
+        const int32_t u = hp.perm[size_t(i)];
         std::vector<int32_t> &c = cols[size_t(i)];
-        c.reserve(size_t(4 * (inc_ptr[i + 1] - inc_ptr[i])));
-        for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q)
-            for (int a = 0; a < 4; ++a) c.push_back(d.tets[4 * inc[size_t(q)] + a]);
+        c.reserve(size_t(4 * (inc_ptr[u + 1] - inc_ptr[u])));
+        for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1]; ++q)
+            for (int a = 0; a < 4; ++a) c.push_back(hp.iperm[size_t(d.tets[4 * inc[size_t(q)] + a])]);
         std::sort(c.begin(), c.end());
         c.erase(std::unique(c.begin(), c.end()), c.end());
         rowlen[size_t(i)] = int32_t(c.size());
@@ -204,19 +243,20 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
     // c_e^2 vol_e grad(phi_i).grad(phi_j); K1 the same with c = 1; M_L = sum vol_e / 4.
     parallel_for(N, [&](int64_t i) {
         const int32_t r0 = hp.rowptr[i];
+        const int32_t u = hp.perm[size_t(i)];
         const std::vector<int32_t> &c = cols[size_t(i)];
         std::copy(c.begin(), c.end(), hp.col.begin() + r0);
         double m = 0.0;
-        for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
+        for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1]; ++q) {
             const int64_t e = inc[size_t(q)];
             const int32_t *t = d.tets + 4 * e;
             Shape s;
             tet_shape(d.coords, t, s);
-            const int a = local_index(t, int32_t(i));
+            const int a = local_index(t, u);
             const double c2 = d.c_tet ? d.c_tet[e] * d.c_tet[e] : 1.0;
             for (int b = 0; b < 4; ++b) {
                 const double gg = s.g[a][0] * s.g[b][0] + s.g[a][1] * s.g[b][1] + s.g[a][2] * s.g[b][2];
-                const int32_t j = t[b];
+                const int32_t j = hp.iperm[size_t(t[b])];
                 const int64_t pos = r0 + (std::lower_bound(c.begin(), c.end(), j) - c.begin());
                 hp.k1val[size_t(pos)] += s.vol * gg;
                 hp.kval[size_t(pos)] += c2 * (s.vol * gg);
@@ -255,10 +295,11 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
     {
         int64_t off = 0;
         for (int32_t i = 0; i < N; ++i) {
+            const int32_t u = hp.perm[size_t(i)];
             bool onb = false;
-            for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1] && !onb; ++q) {
+            for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1] && !onb; ++q) {
                 const int64_t e = inc[size_t(q)];
-                const int a = local_index(d.tets + 4 * e, i);
+                const int a = local_index(d.tets + 4 * e, u);
                 for (int f = 0; f < 4 && !onb; ++f)
                     if (f != a && face_on_boundary[size_t(4 * e + f)]) onb = true;
             }
@@ -273,10 +314,11 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
     parallel_for(N, [&](int64_t i) {
         if (hp.boff[i] < 0) return;
         const int32_t r0 = hp.rowptr[i], r1 = hp.rowptr[i + 1];
-        for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
+        const int32_t u = hp.perm[size_t(i)];
+        for (int64_t q = inc_ptr[u]; q < inc_ptr[u + 1]; ++q) {
             const int64_t e = inc[size_t(q)];
             const int32_t *t = d.tets + 4 * e;
-            const int a = local_index(t, int32_t(i));
+            const int a = local_index(t, u);
             for (int f = 0; f < 4; ++f) {
                 if (f == a || !face_on_boundary[size_t(4 * e + f)]) continue;
                 const double *x0 = d.coords + 3 * int64_t(t[kFace[f][0]]);
@@ -288,10 +330,10 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
                 const double area = 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
                 const double scale = (d.c_tet ? 1.0 / d.c_tet[e] : 1.0) * area / 12.0;
                 for (int k = 0; k < 3; ++k) {
-                    const int32_t j = t[kFace[f][k]];
+                    const int32_t j = hp.iperm[size_t(t[kFace[f][k]])];
                     const int32_t *lo = hp.col.data() + r0, *hi = hp.col.data() + r1;
                     const int64_t pos = std::lower_bound(lo, hi, j) - hp.col.data();
-                    hp.bval[size_t(hp.boff[i] + (pos - r0))] += (j == i ? 2.0 : 1.0) * scale;
+                    hp.bval[size_t(hp.boff[i] + (pos - r0))] += (j == int32_t(i) ? 2.0 : 1.0) * scale;
                 }
             }
         }
@@ -413,6 +455,7 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
         }
     }
 
+    build_padded_rows(hp);
     hp.lambda_max = estimate_lambda_max(hp, 150);
     if (d.check_dt) {
         const double x = d.dt * d.dt * 1.02 * hp.lambda_max;
@@ -431,6 +474,41 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
         }
     }
     return PAT_OK;
+}
+
+void build_padded_rows(HostProblem &hp) {
+    const int W = HostProblem::kEll;
+    const int32_t N = hp.n;
+    hp.ell_col.assign(size_t(N) * W, 0);
+    hp.ell_val.assign(size_t(N) * W, 0.0);
+    hp.xptr.assign(size_t(N) + 1, 0);
+    hp.bsoff.assign(size_t(N), -1);
+    for (int32_t i = 0; i < N; ++i) {
+        const int32_t len = hp.rowptr[i + 1] - hp.rowptr[i];
+        hp.xptr[i + 1] = hp.xptr[i] + (len > W ? len - W : 0);
+    }
+    hp.xcol.assign(size_t(hp.xptr[N]), 0);
+    hp.xval.assign(size_t(hp.xptr[N]), 0.0);
+    int64_t boff = 0;
+    for (int32_t i = 0; i < N; ++i)
+        if (hp.boff[i] >= 0) {
+            hp.bsoff[i] = int32_t(boff);
+            boff += W + (hp.xptr[i + 1] - hp.xptr[i]);
+        }
+    hp.bslot.assign(size_t(boff), 0.0);
+    for (int32_t i = 0; i < N; ++i) {
+        const int32_t k0 = hp.rowptr[i], len = hp.rowptr[i + 1] - k0;
+        for (int j = 0; j < W; ++j) {
+            hp.ell_col[size_t(i) * W + j] = j < len ? hp.col[k0 + j] : i;
+            hp.ell_val[size_t(i) * W + j] = j < len ? hp.kval[k0 + j] : 0.0;
+        }
+        for (int32_t j = W; j < len; ++j) {
+            hp.xcol[hp.xptr[i] + j - W] = hp.col[k0 + j];
+            hp.xval[hp.xptr[i] + j - W] = hp.kval[k0 + j];
+        }
+        if (hp.boff[i] >= 0)
+            for (int32_t j = 0; j < len; ++j) hp.bslot[size_t(hp.bsoff[i] + j)] = hp.bval[size_t(hp.boff[i] + j)];
+    }
 }
 
 namespace {

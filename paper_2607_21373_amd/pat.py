@@ -15,7 +15,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpat.so")
+# PAT_LIB selects an alternative build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PAT_LIB") or os.path.join(_HERE, "libpat.so")
 
 PAT_F64, PAT_F32 = 0, 1
 _STATUS = {0: "PAT_OK", -1: "PAT_ERR_INVALID_ARG", -2: "PAT_ERR_UNSTABLE_DT", -3: "PAT_ERR_NONFINITE",
