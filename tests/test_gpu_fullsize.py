@@ -1,0 +1,124 @@
+"""Full-size GPU parity on the 195,112-node mapped ball (1000 steps, 1024 sensors).
+
+* forward / transpose maps: the oracle recomputes sampled right-hand sides of the
+  same launch (64-RHS float32 block, 16-RHS float64 block) element by element;
+* the transpose identity at full size in float64 (1e-13) and float32;
+* RTO: posterior mean, standard deviation and the first sample against values
+  the CPU FP64 oracle stored under tests/golden/ (written by make_golden.py),
+  with the inputs regenerated here from the same seeds and the oracle's own
+  forward map, and checked against the stored checksums first.
+  Bars: 1e-10 relative L2 for the float64 path, 1e-4 for float32 sweeps with
+  float64 CGLS.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pat = pytest.importorskip("paper_2607_21373_amd.pat")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ball():
+    w = W.make_workload("ball58_fp64")
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    return w, O, G
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("dtype,R,picks,tol", [(torch.float64, 16, (0, 11), 1e-11),
+                                                (torch.float32, 64, (5, 63), 1e-4)])
+def test_forward_fullsize_sampled(ball, dtype, R, picks, tol):
+    w, O, G = ball
+    p0 = np.random.default_rng(21).standard_normal((R, w.n_nodes))
+    dev_in = _dev(p0, dtype)
+    y = pat.pat_forward(G, dev_in).cpu().numpy().astype(np.float64)
+    p_in = dev_in.cpu().numpy().astype(np.float64)
+    for r in picks:
+        ref = O.forward(p_in[r])
+        err = _rel_max(y[r], ref)
+        print(f"forward {dtype} R={R} rhs {r}: rel max err {err:.3e}")
+        assert err < tol
+
+
+@pytest.mark.parametrize("dtype,R,picks,tol", [(torch.float64, 16, (3,), 1e-11), (torch.float32, 64, (0, 40), 1e-4)])
+def test_adjoint_fullsize_sampled(ball, dtype, R, picks, tol):
+    w, O, G = ball
+    yh = np.random.default_rng(22).standard_normal((R, w.n_steps, w.n_obs))
+    dev_in = _dev(yh, dtype)
+    p = pat.pat_adjoint(G, dev_in).cpu().numpy().astype(np.float64)
+    y_in = dev_in.cpu().numpy().astype(np.float64)
+    for r in picks:
+        ref = O.adjoint(y_in[r])
+        err = _rel_max(p[r], ref)
+        print(f"adjoint {dtype} R={R} rhs {r}: rel max err {err:.3e}")
+        assert err < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 1e-5)])
+def test_transpose_identity_fullsize(ball, dtype, tol):
+    """<G p, yhat> = <p, G^T yhat> at full size (Sec. 6.1), both maps on the GPU."""
+    w, O, G = ball
+    rng = np.random.default_rng(4)
+    R = 2
+    p = _dev(rng.standard_normal((R, w.n_nodes)), dtype)
+    yh = _dev(rng.standard_normal((R, w.n_steps, w.n_obs)), dtype)
+    y = pat.pat_forward(G, p).double()
+    a = pat.pat_adjoint(G, yh).double()
+    lhs = (y * yh.double()).sum(dim=(1, 2)).cpu().numpy()
+    rhs = (p.double() * a).sum(dim=1).cpu().numpy()
+    rel = np.abs(lhs - rhs) / np.abs(lhs)
+    print(f"transpose identity {dtype}: {rel}")
+    assert np.all(rel < tol)
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}_rto.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated yet (python tests/golden/make_golden.py {name})")
+    return np.load(path), json.load(open(os.path.join(GOLDEN, f"{name}_rto.json")))
+
+
+def _regenerate(name, O, gold):
+    w = W.make_workload(name)
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    assert sigma == pytest.approx(float(gold["sigma"]), rel=1e-14)
+    assert np.linalg.norm(yobs) == pytest.approx(float(gold["yobs_norm"]), rel=1e-13)
+    eta, xi = W.rto_draws(w.n_samples, w.n_steps, w.n_obs, w.n_nodes, w.rto_seed)
+    return w, yobs, sigma, eta, xi
+
+
+@pytest.mark.parametrize("name,prec,tol,rb", [("ball58_fp64", "f64", 1e-10, 16), ("ball58_batched", "f32", 1e-4, 64)])
+def test_rto_fullsize_vs_stored_oracle(ball, name, prec, tol, rb):
+    _, O, G = ball
+    gold, meta = _golden(name)
+    w, yobs, sigma, eta, xi = _regenerate(name, O, gold)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, w.n_iter, sweep_prec=prec,
+                         rhs_block=rb, resid=True)
+    em = _rel_l2(out["mean"].cpu().numpy(), gold["mean"])
+    es = _rel_l2(out["std"].cpu().numpy(), gold["std"])
+    e0 = _rel_l2(out["samples"][0].cpu().numpy(), gold["sample0"])
+    er = _rel_max(out["resid"].cpu().numpy(), gold["resid"])
+    print(f"{name} ({prec}): mean {em:.3e} std {es:.3e} sample0 {e0:.3e} resid {er:.3e}")
+    assert em < tol and es < tol and e0 < max(tol, 1e-10) * 10
