@@ -194,7 +194,7 @@ def main():
             "cgls_iters": n_iter, "rhs_block": 64, "cgls_dtype": "f64",
         },
         "roofline": {
-            "kernel": "k_fwd<float,double,64> (forward leapfrog step)", "bound": "hbm",
+            "kernel": "k_fwd_v<float,double,64> (forward leapfrog step)", "bound": "hbm",
             "achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
             "traffic": stored_traffic("k_fwd_f32_rb64", w.name),

@@ -53,6 +53,7 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
 // Build the padded row layout (ell_*, x*, bs*) from the CSR arrays.
 void build_padded_rows(HostProblem &hp);
 
+
 // Largest eigenvalue of M_L^{-1} K by power iteration on M^{-1/2} K M^{-1/2}.
 double estimate_lambda_max(const HostProblem &hp, int iters);
 

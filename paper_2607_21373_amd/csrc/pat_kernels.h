@@ -26,6 +26,7 @@ struct DevOps {
 
 enum class Prec { F64, F32 };
 
+
 // One forward Stormer-Verlet step on the staggered state (P = p^{n+1/2}, V = v^n),
 // optionally sampling y^{k} = Pi (P - dt/2 V) of the incoming state into
 // y_out[(t*n_obs + s)*RB + r] * yscale.  first != 0 treats V as zero.

@@ -295,6 +295,22 @@ struct Vec16<double> {
     static constexpr int n = 2;
 };
 
+// Vector-kernel tuning (same arithmetic for every setting):
+//   PAT_VCH  gathers in flight per lane before they are consumed (16 or 8)
+//   PAT_NTS  1: non-temporal stores of the new state (written once, read next step)
+#ifndef PAT_VCH
+#define PAT_VCH 8
+#endif
+#ifndef PAT_NTS
+#define PAT_NTS 0
+#endif
+
+template <typename VT, typename T>
+__device__ __forceinline__ void vstore(T *p, VT v) {
+    if constexpr (PAT_NTS) __builtin_nontemporal_store(v, reinterpret_cast<VT *>(p));
+    else *reinterpret_cast<VT *>(p) = v;
+}
+
 template <typename T, int RB>
 struct VGeo {
     static constexpr int VEC = Vec16<T>::n;
@@ -370,22 +386,26 @@ __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, R
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
     const int base = lr * G::W;
-    VT x[G::W];
+    constexpr int CH = PAT_VCH;
 #pragma unroll
-    for (int j = 0; j < G::W; ++j)
-        x[j] = *reinterpret_cast<const VT *>(X + int64_t(L.col[base + j]) * RB + q * G::VEC);
+    for (int j0 = 0; j0 < G::W; j0 += CH) {
+        VT x[CH];
 #pragma unroll
-    for (int j = 0; j < G::W; ++j) acc = vfma(L.kv[base + j], x[j], acc);
-    if (with_b) {
-        if constexpr (Y_IS_X) {
+        for (int j = 0; j < CH; ++j)
+            x[j] = *reinterpret_cast<const VT *>(X + int64_t(L.col[base + j0 + j]) * RB + q * G::VEC);
 #pragma unroll
-            for (int j = 0; j < G::W; ++j) bacc = vfma(L.bv[base + j], x[j], bacc);
-        } else {
+        for (int j = 0; j < CH; ++j) acc = vfma(L.kv[base + j0 + j], x[j], acc);
+        if (with_b) {
+            if constexpr (Y_IS_X) {
 #pragma unroll
-            for (int j = 0; j < G::W; ++j)
-                x[j] = *reinterpret_cast<const VT *>(Y + int64_t(L.col[base + j]) * RB + q * G::VEC);
+                for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[base + j0 + j], x[j], bacc);
+            } else {
 #pragma unroll
-            for (int j = 0; j < G::W; ++j) bacc = vfma(L.bv[base + j], x[j], bacc);
+                for (int j = 0; j < CH; ++j)
+                    x[j] = *reinterpret_cast<const VT *>(Y + int64_t(L.col[base + j0 + j]) * RB + q * G::VEC);
+#pragma unroll
+                for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[base + j0 + j], x[j], bacc);
+            }
         }
     }
     const int x0 = L.x0[lr], x1 = L.x1[lr];
@@ -441,8 +461,8 @@ __global__ void __launch_bounds__(256) k_fwd_v(const VFwdArgs<T> a) {
                 v[i] = v0[i] - dm * (acc[i] + bacc[i]);
                 pn[i] = p0[i] + a.dt * v[i];
             }
-            *reinterpret_cast<VT *>(a.Vn + id) = v;
-            *reinterpret_cast<VT *>(a.Pn + id) = pn;
+            vstore<VT>(a.Vn + id, v);
+            vstore<VT>(a.Pn + id, pn);
         }
     } else if (a.sample) {
         // one lane per (sensor, rhs)
@@ -514,9 +534,9 @@ __global__ void __launch_bounds__(256) k_adj_v(const VAdjArgs<T> a) {
             qn[i] = q0[i] - dm * bq[i] + dm * (ph[i] + T(0.5) * inj[i]);
             ph[i] += inj[i];
         }
-        *reinterpret_cast<VT *>(a.Qn + id) = qn;
+        vstore<VT>(a.Qn + id, qn);
     }
-    *reinterpret_cast<VT *>(a.PH + id) = ph;
+    vstore<VT>(a.PH + id, ph);
 }
 
 // p_hat = Pi^T yhat^{N_T}, q = (dt/2m) p_hat

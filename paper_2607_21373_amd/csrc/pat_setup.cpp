@@ -98,14 +98,20 @@ double barycentric(const Shape &s, const double *x, double lam[4]) {
 }
 
 // Locality order of the nodes for the time-step kernels: recursive coordinate
-// bisection into 8 equal parts (one per XCD of the GPU, each split at the median
-// of its longest extent), then each part sorted along its own longest extent.
-// A row's neighbours then lie within a thin slab of its part, which the part's
-// L2 holds while the part is swept.  Stable sorts keep the order deterministic.
+// bisection (k-d order).  Each set is split at the median of its longest extent
+// until it holds at most 64 nodes, and the leaves are numbered depth first.  The
+// first three levels give 8 equal parts, one per XCD of the GPU; every later
+// level keeps spatially close nodes close in the numbering, so a tile of
+// consecutive rows touches few distinct neighbour rows and an XCD's L2 holds the
+// neighbourhood of the rows it is processing.  Stable sorts keep it deterministic.
 void locality_order(const double *X, int32_t N, std::vector<int32_t> &perm) {
     perm.resize(size_t(N));
     for (int32_t i = 0; i < N; ++i) perm[size_t(i)] = i;
-    auto longest_axis = [&](size_t a, size_t b) {
+    std::vector<std::pair<size_t, size_t>> stack = {{0, size_t(N)}};
+    while (!stack.empty()) {
+        const auto [a, b] = stack.back();
+        stack.pop_back();
+        if (b - a <= 64) continue;
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (size_t q = a; q < b; ++q)
             for (int k = 0; k < 3; ++k) {
@@ -115,25 +121,12 @@ void locality_order(const double *X, int32_t N, std::vector<int32_t> &perm) {
         int ax = 0;
         for (int k = 1; k < 3; ++k)
             if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
-        return ax;
-    };
-    auto sort_along = [&](size_t a, size_t b, int ax) {
         std::stable_sort(perm.begin() + a, perm.begin() + b,
                          [&](int32_t u, int32_t v) { return X[3 * size_t(u) + ax] < X[3 * size_t(v) + ax]; });
-    };
-    std::vector<std::pair<size_t, size_t>> parts = {{0, size_t(N)}};
-    for (int level = 0; level < 3; ++level) {
-        std::vector<std::pair<size_t, size_t>> next;
-        for (auto [a, b] : parts) {
-            sort_along(a, b, longest_axis(a, b));
-            const size_t m = a + (b - a) / 2;
-            next.push_back({a, m});
-            next.push_back({m, b});
-        }
-        parts.swap(next);
+        const size_t m = a + (b - a) / 2;
+        stack.push_back({m, b});
+        stack.push_back({a, m});
     }
-    for (auto [a, b] : parts)
-        if (b > a) sort_along(a, b, longest_axis(a, b));
 }
 
 int local_index(const int32_t *t, int32_t node) {
