@@ -99,6 +99,13 @@ pat_status pat_forward(pat_problem *p, int64_t R, const void *p0, void *y, pat_p
  * exact arithmetic.  yhat device [R][N_T][N_obs], p device [R][N]; type `prec`. */
 pat_status pat_adjoint(pat_problem *p, int64_t R, const void *yhat, void *p_out, pat_precision prec, void *stream);
 
+/* Prior factor L = M_L^{-1/2}(M_L + a K1) (transpose = 0) or its transpose
+ * L^T = (M_L + a K1) M_L^{-1/2} (transpose = 1), so L^T L is the prior precision;
+ * a = 0 gives M_L^{1/2}, the square root of the precision of eq. (iid-prior).
+ *   x, y device [R][N] float64 (caller numbering); y must not alias x. */
+pat_status pat_prior_apply(pat_problem *p, int64_t R, double prior_a, int transpose, const double *x, double *y,
+                           void *stream);
+
 /* Parameters of the RTO sampler (Sec. 5 eq. (optimization), Algorithm 1). */
 typedef struct {
     double sigma;              /* noise standard deviation (> 0) */

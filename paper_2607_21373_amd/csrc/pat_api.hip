@@ -570,6 +570,33 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
     return PAT_OK;
 }
 
+pat_status pat_prior_apply(pat_problem *p, int64_t R, double prior_a, int transpose, const double *x, double *y,
+                           void *stream) {
+    g_err.clear();
+    if (!p || !x || !y || R < 1) return fail(PAT_ERR_INVALID_ARG, "pat_prior_apply: NULL pointer or R < 1");
+    if (x == y) return fail(PAT_ERR_INVALID_ARG, "pat_prior_apply: y must not alias x");
+    if (!(prior_a >= 0.0) || !std::isfinite(prior_a)) return fail(PAT_ERR_INVALID_ARG, "prior_a must be >= 0");
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int RB = choose_rb(R);
+    // the f64 sweep workspace of this block width holds the packed operands
+    SweepWS *w;
+    PAT_TRY(get_sweep(p, pat::Prec::F64, RB, false, &w));
+    const int32_t *perm = p->perm_identity ? nullptr : p->ops.perm;
+    const int64_t N = p->ops.n;
+    for (int64_t rb0 = 0; rb0 < R; rb0 += RB) {
+        pat::launch_pack(true, true, x, R, rb0, RB, N, perm, w->P[0], s);
+        if (transpose)
+            pat::launch_prior_t(p->ops, RB, prior_a, static_cast<const double *>(w->P[0]), static_cast<double *>(w->P[1]), s);
+        else
+            pat::launch_prior(p->ops, RB, prior_a, static_cast<const double *>(w->P[0]), static_cast<double *>(w->P[1]), s);
+        pat::launch_unpack(true, true, w->P[1], R, rb0, RB, N, perm, y, s);
+    }
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
 pat_status pat_host_assemble(const pat_problem_desc *desc, int64_t *nnz_out, int32_t *rowptr, int32_t *col,
                              double *kval, double *k1val, double *bval, double *mass, int32_t *snode, double *sw,
                              double *lambda_max) {

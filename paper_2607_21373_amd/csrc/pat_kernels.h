@@ -56,6 +56,8 @@ void launch_cast_to_state(Prec prec, const double *x, void *P, int64_t count, hi
 void launch_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0, int RB, int64_t M, double isig,
                       double *bd, hipStream_t s);
 void launch_prior(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s);
+// y = L^T x = M_L^{1/2} x + a K1 (M_L^{-1/2} x)
+void launch_prior_t(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s);
 void launch_gext_t_combine(Prec prec, const DevOps &op, int RB, double a, double isig, const void *PH,
                            const double *rp, double *out, hipStream_t s);
 // partial sums: part[b][r] = sum over rows of block b of x*y (y == x gives squares)

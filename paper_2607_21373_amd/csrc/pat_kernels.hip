@@ -657,6 +657,22 @@ __global__ void __launch_bounds__(256) k_gext_t(const int32_t *rowptr, const int
     }
 }
 
+// y = L^T x = M_L^{1/2} x + a K1 (M_L^{-1/2} x)
+__global__ void __launch_bounds__(256) k_prior_t(const int32_t *rowptr, const int32_t *col, const double *k1,
+                                                 const double *sqrtm, const double *isqrtm, int n, int RB, double a,
+                                                 const double *x, double *y) {
+    const int64_t total = int64_t(n) * RB;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+        const int i = int(e / RB), r = int(e % RB);
+        double acc = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            acc = __builtin_fma(k1[k], isqrtm[j] * x[int64_t(j) * RB + r], acc);
+        }
+        y[e] = sqrtm[i] * x[e] + a * acc;
+    }
+}
+
 // part[b][r] = sum over rows of block b of x[row][r] * y[row][r]
 __global__ void __launch_bounds__(256) k_dot_partial(const double *x, const double *y, int64_t rows, int RB,
                                                      double *part) {
@@ -1035,6 +1051,11 @@ void launch_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t 
 
 void launch_prior(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_prior, dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, op.rowptr, op.col, op.k1val64,
+                       op.sqrtm, op.isqrtm, op.n, RB, a, x, y);
+}
+
+void launch_prior_t(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_prior_t, dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, op.rowptr, op.col, op.k1val64,
                        op.sqrtm, op.isqrtm, op.n, RB, a, x, y);
 }
 

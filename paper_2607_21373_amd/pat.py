@@ -68,8 +68,8 @@ class RtoParams(ctypes.Structure):
 
 # names exported by libpat (the C ABI in include/pat.h)
 EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-           "rto_sample", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync", "pat_last_error",
-           "pat_version")
+           "rto_sample", "pat_prior_apply", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync",
+           "pat_last_error", "pat_version")
 
 _lib = None
 
@@ -93,11 +93,13 @@ def load() -> ctypes.CDLL:
     lib.pat_sync.argtypes = [vp]
     lib.pat_host_assemble.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ctypes.c_int64)] + [vp] * 9
     lib.pat_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.pat_prior_apply.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, vp, vp, vp]
     lib.pat_profile_get.argtypes = [vp, ctypes.POINTER(Profile)]
     lib.pat_last_error.restype = ctypes.c_char_p
     lib.pat_version.restype = ctypes.c_char_p
     for f in ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-              "rto_sample", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync"):
+              "rto_sample", "pat_prior_apply", "pat_host_assemble", "pat_profile_enable", "pat_profile_get",
+              "pat_sync"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -261,6 +263,18 @@ def pat_adjoint(problem: Problem, yhat, p=None):
     pp = _dev_ptr(p, yhat.dtype, (R, problem.n_nodes), "p")
     _check(load().pat_adjoint(problem._h, R, yp, pp, _prec(yhat.dtype), _stream()))
     return p
+
+
+def pat_prior_apply(problem: Problem, x, prior_a: float, transpose: bool = False, y=None):
+    """L x (or L^T x) for L = M_L^{-1/2}(M_L + a K1); x [R][N] float64 CUDA tensor."""
+    import torch
+    R = x.shape[0]
+    if y is None:
+        y = torch.empty_like(x)
+    xp = _dev_ptr(x, torch.float64, (R, problem.n_nodes), "x")
+    yp = _dev_ptr(y, torch.float64, (R, problem.n_nodes), "y")
+    _check(load().pat_prior_apply(problem._h, R, float(prior_a), int(bool(transpose)), xp, yp, _stream()))
+    return y
 
 
 def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n_iter: int, reorth: bool = True,

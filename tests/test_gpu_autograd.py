@@ -1,0 +1,146 @@
+"""Differentiable forward operator (torch.autograd over libpat) and MAP by gradient descent.
+
+Checks:
+  * central finite differences (eps = 1e-6, float64) of the MAP objective on 20
+    seeded directions against the autograd gradient (exact transpose sweep);
+  * the transpose identity through autograd;
+  * gradient descent iterates against the same iteration written with the
+    oracle's operators (ball16, 200 iterations);
+  * on a tiny mesh, many descent steps converge to the dense MAP point, which is
+    also the converged CGLS solution with zero RTO perturbations (Sec. 5 eq. (MAP),
+    App. A with eta = xi = 0);
+  * at full size, the objective decreases monotonically, and 200 CGLS steps
+    reach a lower objective than 200 descent steps (CGLS minimises over the
+    Krylov space that contains the descent iterate).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pat = pytest.importorskip("paper_2607_21373_amd.pat")
+ag = pytest.importorskip("paper_2607_21373_amd.autograd")
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = W.make_workload("ball16")
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    return w, O, G, yobs, sigma
+
+
+@pytest.fixture(scope="module")
+def big():
+    w = W.make_workload("ball58_fp64")
+    G = pat.Problem.from_workload(w)
+    p0 = torch.as_tensor(w.p0_true, dtype=torch.float64, device="cuda")
+    Y = pat.pat_forward(G, p0[None].contiguous())[0]
+    eta0 = _dev(W.noise_draw(w.n_steps, w.n_obs, w.noise_seed))
+    sigma = float(w.d_noise * torch.linalg.norm(Y) / torch.linalg.norm(eta0))
+    return w, G, (Y + sigma * eta0).contiguous(), sigma
+
+
+@pytest.mark.parametrize("which", ["small", "big"])
+def test_finite_differences(which, request):
+    if which == "small":
+        w, O, G, yobs, sigma = request.getfixturevalue("small")
+        y = _dev(yobs)
+    else:
+        w, G, y, sigma = request.getfixturevalue("big")
+    a = w.prior_a
+    rng = np.random.default_rng(30)
+    p = _dev(rng.standard_normal(w.n_nodes) * 0.1).requires_grad_(True)
+    f = ag.map_objective(G, p, y, sigma, a)
+    (g,) = torch.autograd.grad(f, p)
+    eps = 1e-6
+    errs = []
+    with torch.no_grad():
+        for k in range(20):
+            d = _dev(np.random.default_rng(100 + k).standard_normal(w.n_nodes))
+            fp = ag.map_objective(G, p + eps * d, y, sigma, a)
+            fm = ag.map_objective(G, p - eps * d, y, sigma, a)
+            fd = float((fp - fm) / (2 * eps))
+            an = float(torch.dot(g, d))
+            errs.append(abs(fd - an) / abs(an))
+    print(f"{which}: FD rel errors max {max(errs):.2e}")
+    assert max(errs) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_transpose_through_autograd(small, dtype):
+    w, O, G, yobs, sigma = small
+    rng = np.random.default_rng(31)
+    p = _dev(rng.standard_normal((2, w.n_nodes)), dtype).requires_grad_(True)
+    yh = _dev(rng.standard_normal((2, w.n_steps, w.n_obs)), dtype)
+    y = ag.PatForward.apply(p, G)
+    assert y.dtype == dtype
+    s = torch.sum(y * yh)
+    (gp,) = torch.autograd.grad(s, p)
+    lhs = float(s)
+    rhs = float(torch.sum(p.detach().double() * gp.double()))
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+    ref = O.adjoint(yh.double().cpu().numpy())
+    assert np.abs(gp.double().cpu().numpy() - ref).max() <= (1e-11 if dtype == torch.float64 else 2e-5) * np.abs(ref).max()
+
+
+def test_map_descent_matches_oracle_iteration(small):
+    w, O, G, yobs, sigma = small
+    a = w.prior_a
+    n_iter = 200
+    p_gpu, hist, step = ag.map_gradient_descent(G, _dev(yobs), sigma, a, n_iter=n_iter, history=True)
+    # the same iteration with the oracle's operators: p <- p - step (G^T(Gp - y)/sigma^2 + L^T L p)
+    p = np.zeros(w.n_nodes)
+    for _ in range(n_iter):
+        grad = O.adjoint(O.forward(p) - yobs) / sigma ** 2 + O.prior_apply(O.prior_apply(p, a), a, transpose=True)
+        p = p - step * grad
+    err = np.linalg.norm(p_gpu.cpu().numpy() - p) / np.linalg.norm(p)
+    print(f"GD parity rel L2 {err:.3e}")
+    assert err < 1e-10
+    assert all(h1 <= h0 * (1 + 1e-12) for h0, h1 in zip(hist, hist[1:]))
+
+
+def test_map_is_converged_cgls_tiny():
+    """Tiny mesh: descent converges to the dense MAP point, which equals CGLS with eta = xi = 0."""
+    coords, tets = W.ball_mesh(3)
+    w = W.Workload(name="tiny", coords=coords, tets=tets, c_tet=None, absorbing=True, dt=0.2 * 2 / 3, n_steps=15,
+                   sensor_pos=W.fibonacci_sphere(6, 0.7), p0_true=W.smooth_bump(coords, 0.8), prior_a=0.02)
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    yobs = O.forward(w.p0_true) + 0.01 * np.random.default_rng(3).standard_normal((w.n_steps, w.n_obs))
+    sigma = 1.0            # cond(H) = 39 on this mesh: descent converges in ~600 steps
+    N = w.n_nodes
+    Gd = O.forward(np.eye(N)).reshape(N, -1).T
+    L = O.prior_apply(np.eye(N), w.prior_a).T
+    H = Gd.T @ Gd / sigma ** 2 + L.T @ L
+    p_map = np.linalg.solve(H, Gd.T @ yobs.ravel() / sigma ** 2)
+    p_gd = ag.map_gradient_descent(G, _dev(yobs), sigma, w.prior_a, n_iter=1500).cpu().numpy()
+    cg = pat.rto_sample(G, _dev(yobs), _dev(np.zeros((1, w.n_steps, w.n_obs))), _dev(np.zeros((1, N))), sigma,
+                        w.prior_a, 2 * N, stats=False)["samples"][0].cpu().numpy()
+    assert np.linalg.norm(cg - p_map) < 1e-8 * np.linalg.norm(p_map)
+    assert np.linalg.norm(p_gd - p_map) < 1e-6 * np.linalg.norm(p_map)
+
+
+def test_map_descent_fullsize(big):
+    w, G, y, sigma = big
+    a = w.prior_a
+    p_gd, hist, step = ag.map_gradient_descent(G, y, sigma, a, n_iter=200, history=True)
+    assert all(h1 <= h0 * (1 + 1e-12) for h0, h1 in zip(hist, hist[1:]))
+    with torch.no_grad():
+        f_gd = float(ag.map_objective(G, p_gd, y, sigma, a))
+        z = torch.zeros((1, w.n_steps, w.n_obs), dtype=torch.float64, device="cuda")
+        p_cg = pat.rto_sample(G, y, z, torch.zeros((1, w.n_nodes), dtype=torch.float64, device="cuda"), sigma, a, 200,
+                              stats=False)["samples"][0]
+        f_cg = float(ag.map_objective(G, p_cg, y, sigma, a))
+    print(f"MAP objective: GD(200) {f_gd:.6e}  CGLS(200) {f_cg:.6e}  start {hist[0]:.6e}")
+    assert f_cg <= f_gd * (1 + 1e-12) and f_gd < hist[0]
