@@ -62,10 +62,13 @@ def _load():
     lib.orc_prior_apply_transpose.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp]
     lib.orc_cgls.restype = ctypes.c_int
     lib.orc_cgls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                             ctypes.c_int, _dp, _dp, _dp, _dp]
+                             ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_lsqr.restype = ctypes.c_int
+    lib.orc_lsqr.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
     lib.orc_rto.restype = ctypes.c_int
     lib.orc_rto.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                            ctypes.c_int, _dp, _dp, _dp, _dp]
+                            ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
     lib.orc_stats.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -201,35 +204,44 @@ class Problem:
 
     # -- least squares and sampling ----------------------------------------
     def cgls(self, bd: np.ndarray, bp: np.ndarray, sigma: float, prior_a: float, n_iter: int,
-             reorth: bool = True):
-        """CGLS for min ||G_ext x - b||, b = (bd [R][N_T][N_obs], bp [R][N]).
+             reorth: bool = True, solver: str = "cgls", diag: bool = False):
+        """Least squares min ||G_ext x - b||, b = (bd [R][N_T][N_obs], bp [R][N]), by CGLS or LSQR.
 
-        Returns (x [R][N], resid [R][n_iter+1])."""
+        Returns (x [R][N], resid [R][n_iter+1]) and, with diag=True, also
+        [R][n_iter+1][2] = (||r_d||, ||r_p||) per iteration."""
         R = bp.shape[0]
         bdi = _f64(np.moveaxis(bd, 0, 2))
         bpi = _f64(bp.T)
         x = np.empty((self.n_nodes, R))
         res = np.empty((R, n_iter + 1))
-        rc = _load().orc_cgls(self._h, R, float(sigma), float(prior_a), int(n_iter), int(bool(reorth)),
-                              _ptr(bdi), _ptr(bpi), _ptr(x), _ptr(res))
+        dg = np.empty((R, n_iter + 1, 2))
+        f = {"cgls": _load().orc_cgls, "lsqr": _load().orc_lsqr}[solver]
+        rc = f(self._h, R, float(sigma), float(prior_a), int(n_iter), int(bool(reorth)),
+               _ptr(bdi), _ptr(bpi), _ptr(x), _ptr(res), _ptr(dg))
         if rc != 0:
-            raise MemoryError("oracle CGLS could not allocate its workspace")
-        return np.ascontiguousarray(x.T), res
+            raise MemoryError("oracle least-squares solve could not allocate its workspace")
+        out = (np.ascontiguousarray(x.T), res)
+        return out + (dg,) if diag else out
+
+    def lsqr(self, bd, bp, sigma, prior_a, n_iter, reorth=True, diag=False):
+        return self.cgls(bd, bp, sigma, prior_a, n_iter, reorth, solver="lsqr", diag=diag)
 
     def rto(self, yobs: np.ndarray, sigma: float, prior_a: float, n_iter: int, eta: np.ndarray, xi: np.ndarray,
-            reorth: bool = True):
-        """RTO samples (Algorithm 1): returns (samples [S][N], resid [S][n_iter+1])."""
+            reorth: bool = True, solver: str = "cgls", diag: bool = False):
+        """RTO samples (Algorithm 1): returns (samples [S][N], resid [S][n_iter+1]) [, diag]."""
         S = xi.shape[0]
         ya = _f64(yobs)
         ea = _f64(np.moveaxis(eta, 0, 2))
         xa = _f64(xi.T)
         out = np.empty((self.n_nodes, S))
         res = np.empty((S, n_iter + 1))
+        dg = np.empty((S, n_iter + 1, 2))
         rc = _load().orc_rto(self._h, S, _ptr(ya), float(sigma), float(prior_a), int(n_iter), int(bool(reorth)),
-                             _ptr(ea), _ptr(xa), _ptr(out), _ptr(res))
+                             _ptr(ea), _ptr(xa), _ptr(out), _ptr(res), {"cgls": 0, "lsqr": 1}[solver], _ptr(dg))
         if rc != 0:
             raise MemoryError("oracle RTO could not allocate its workspace")
-        return np.ascontiguousarray(out.T), res
+        ret = (np.ascontiguousarray(out.T), res)
+        return ret + (dg,) if diag else ret
 
 
 def stats(samples: np.ndarray):

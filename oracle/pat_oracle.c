@@ -529,7 +529,7 @@ static void dotr(size_t m, int R, const double *x, const double *y, double *out)
  * normalised ones by classical Gram-Schmidt applied twice.  Returns 0, or -1 if
  * memory could not be allocated. */
 int orc_cgls(const oproblem *P, int R, double sigma, double prior_a, int n_iter, int reorth,
-             const double *bd, const double *bp, double *x, double *resid) {
+             const double *bd, const double *bp, double *x, double *resid, double *diag) {
     const int N = P->n_nodes;
     const size_t NR = (size_t)N * R, MR = (size_t)P->n_steps * P->n_obs * R;
     const size_t M = (size_t)P->n_steps * P->n_obs;
@@ -561,9 +561,15 @@ int orc_cgls(const oproblem *P, int R, double sigma, double prior_a, int n_iter,
 
     GEXT_T(s);
     sumsq((size_t)N, R, s, gamma);
-    if (resid) {
+    if (resid || diag) {
         sumsq(M, R, rd, w1); sumsq((size_t)N, R, rp, w2);
-        for (int r = 0; r < R; ++r) resid[(size_t)r * (n_iter + 1)] = sqrt(w1[r] + w2[r]);
+        for (int r = 0; r < R; ++r) {
+            if (resid) resid[(size_t)r * (n_iter + 1)] = sqrt(w1[r] + w2[r]);
+            if (diag) {
+                diag[((size_t)r * (n_iter + 1)) * 2] = sqrt(w1[r]);
+                diag[((size_t)r * (n_iter + 1)) * 2 + 1] = sqrt(w2[r]);
+            }
+        }
     }
     if (reorth)
         for (size_t i = 0; i < N; ++i)
@@ -590,10 +596,16 @@ int orc_cgls(const oproblem *P, int R, double sigma, double prior_a, int n_iter,
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < (int64_t)M; ++i)
             for (int r = 0; r < R; ++r) rd[i * R + r] -= w1[r] * qd[i * R + r];
-        if (resid) {
+        if (resid || diag) {
             double *a1 = delta, *a2 = w2;
             sumsq(M, R, rd, a1); sumsq((size_t)N, R, rp, a2);
-            for (int r = 0; r < R; ++r) resid[(size_t)r * (n_iter + 1) + k] = sqrt(a1[r] + a2[r]);
+            for (int r = 0; r < R; ++r) {
+                if (resid) resid[(size_t)r * (n_iter + 1) + k] = sqrt(a1[r] + a2[r]);
+                if (diag) {
+                    diag[((size_t)r * (n_iter + 1) + k) * 2] = sqrt(a1[r]);
+                    diag[((size_t)r * (n_iter + 1) + k) * 2 + 1] = sqrt(a2[r]);
+                }
+            }
         }
         if (k == n_iter) break;
         /* s = G_ext^T r */
@@ -632,6 +644,154 @@ int orc_cgls(const oproblem *P, int R, double sigma, double prior_a, int n_iter,
 }
 
 /* ------------------------------------------------------------------ */
+/* LSQR (Paige and Saunders' Golub-Kahan bidiagonalisation), the paper's solver */
+/* ------------------------------------------------------------------ */
+
+/* Same problem and outputs as orc_cgls.  With reorth != 0 every new right Lanczos
+ * vector v is orthogonalised against all earlier ones (classical Gram-Schmidt
+ * applied twice) before it is normalised.  The residual r = b - G_ext x is carried
+ * alongside through z = G_ext w (diag, resid).  A new alpha or beta below 1e-15
+ * times its first value counts as the exact breakdown of the bidiagonalisation
+ * (the least-squares solution is reached); it is set to zero, which leaves x
+ * unchanged from then on. */
+int orc_lsqr(const oproblem *P, int R, double sigma, double prior_a, int n_iter, int reorth,
+             const double *bd, const double *bp, double *x, double *resid, double *diag) {
+    const int N = P->n_nodes;
+    const size_t NR = (size_t)N * R, M = (size_t)P->n_steps * P->n_obs, MR = M * R;
+    const double isig = 1.0 / sigma;
+    double *ud = malloc(sizeof(double) * MR), *up = malloc(sizeof(double) * NR);
+    double *qd = malloc(sizeof(double) * MR), *qp = malloc(sizeof(double) * NR);
+    double *zd = malloc(sizeof(double) * MR), *zp = malloc(sizeof(double) * NR);
+    double *rd = malloc(sizeof(double) * MR), *rp = malloc(sizeof(double) * NR);
+    double *v = malloc(sizeof(double) * NR), *w = malloc(sizeof(double) * NR), *sv = malloc(sizeof(double) * NR);
+    double *tmp = malloc(sizeof(double) * NR);
+    double *Q = reorth ? malloc(sizeof(double) * NR * (size_t)(n_iter + 1)) : NULL;
+    double *coef = malloc(sizeof(double) * (size_t)R * (size_t)(n_iter + 1));
+    double *alpha = malloc(sizeof(double) * R), *beta = malloc(sizeof(double) * R), *rhob = malloc(sizeof(double) * R);
+    double *phib = malloc(sizeof(double) * R), *zfac = malloc(sizeof(double) * R), *t1 = malloc(sizeof(double) * R);
+    double *a1 = malloc(sizeof(double) * R), *a2 = malloc(sizeof(double) * R);
+    double *rho = malloc(sizeof(double) * R), *cs = malloc(sizeof(double) * R), *sn = malloc(sizeof(double) * R);
+    double *alpha1 = malloc(sizeof(double) * R), *beta1 = malloc(sizeof(double) * R);
+    if (!ud || !up || !qd || !qp || !zd || !zp || !rd || !rp || !v || !w || !sv || !tmp || (reorth && !Q) || !coef ||
+        !alpha || !beta || !rhob || !phib || !zfac || !t1 || !a1 || !a2 || !rho || !cs || !sn || !alpha1 || !beta1) {
+        free(rho); free(cs); free(sn); free(alpha1); free(beta1);
+        free(ud); free(up); free(qd); free(qp); free(zd); free(zp); free(rd); free(rp); free(v); free(w); free(sv);
+        free(tmp); free(Q); free(coef); free(alpha); free(beta); free(rhob); free(phib); free(zfac); free(t1);
+        free(a1); free(a2);
+        return -1;
+    }
+#define DIAG_AT(k)                                                                          \
+    do {                                                                                    \
+        if (resid || diag) {                                                                \
+            sumsq(M, R, rd, a1); sumsq((size_t)N, R, rp, a2);                               \
+            for (int r_ = 0; r_ < R; ++r_) {                                                \
+                if (resid) resid[(size_t)r_ * (n_iter + 1) + (k)] = sqrt(a1[r_] + a2[r_]);  \
+                if (diag) {                                                                 \
+                    diag[((size_t)r_ * (n_iter + 1) + (k)) * 2] = sqrt(a1[r_]);             \
+                    diag[((size_t)r_ * (n_iter + 1) + (k)) * 2 + 1] = sqrt(a2[r_]);         \
+                }                                                                           \
+            }                                                                               \
+        }                                                                                   \
+    } while (0)
+
+    memset(x, 0, sizeof(double) * NR);
+    memcpy(rd, bd, sizeof(double) * MR);
+    memcpy(rp, bp, sizeof(double) * NR);
+    DIAG_AT(0);
+    /* beta_1 u_1 = b */
+    sumsq(M, R, bd, a1); sumsq((size_t)N, R, bp, a2);
+    for (int r = 0; r < R; ++r) {
+        beta[r] = beta1[r] = sqrt(a1[r] + a2[r]);
+        t1[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+    }
+    for (size_t i = 0; i < M; ++i) for (int r = 0; r < R; ++r) ud[i * R + r] = bd[i * R + r] * t1[r];
+    for (size_t i = 0; i < (size_t)N; ++i) for (int r = 0; r < R; ++r) up[i * R + r] = bp[i * R + r] * t1[r];
+    /* alpha_1 v_1 = G_ext^T u_1 */
+    orc_adjoint(P, R, ud, sv);
+    prior_apply_transpose(P, R, prior_a, up, qp, tmp);
+    for (size_t i = 0; i < NR; ++i) sv[i] = isig * sv[i] + qp[i];
+    sumsq((size_t)N, R, sv, a1);
+    for (int r = 0; r < R; ++r) {
+        alpha[r] = alpha1[r] = sqrt(a1[r]);
+        t1[r] = alpha[r] > 0 ? 1.0 / alpha[r] : 0.0;
+    }
+    for (size_t i = 0; i < (size_t)N; ++i)
+        for (int r = 0; r < R; ++r) { v[i * R + r] = sv[i * R + r] * t1[r]; w[i * R + r] = v[i * R + r]; }
+    if (reorth) memcpy(Q, v, sizeof(double) * NR);
+    for (int r = 0; r < R; ++r) { phib[r] = beta[r]; rhob[r] = alpha[r]; zfac[r] = 0.0; }
+
+    for (int k = 1; k <= n_iter; ++k) {
+        /* q = G_ext v_k ; z_k = q - zfac z_{k-1} (z = G_ext w) */
+        orc_forward(P, R, v, qd);
+        for (size_t i = 0; i < MR; ++i) qd[i] = isig * qd[i];
+        prior_apply(P, R, prior_a, v, qp);
+        for (size_t i = 0; i < M; ++i) for (int r = 0; r < R; ++r) zd[i * R + r] = qd[i * R + r] - zfac[r] * (k > 1 ? zd[i * R + r] : 0.0);
+        for (size_t i = 0; i < (size_t)N; ++i) for (int r = 0; r < R; ++r) zp[i * R + r] = qp[i * R + r] - zfac[r] * (k > 1 ? zp[i * R + r] : 0.0);
+        /* beta_{k+1} u_{k+1} = q - alpha_k u_k */
+        for (size_t i = 0; i < M; ++i) for (int r = 0; r < R; ++r) ud[i * R + r] = qd[i * R + r] - alpha[r] * ud[i * R + r];
+        for (size_t i = 0; i < (size_t)N; ++i) for (int r = 0; r < R; ++r) up[i * R + r] = qp[i * R + r] - alpha[r] * up[i * R + r];
+        sumsq(M, R, ud, a1); sumsq((size_t)N, R, up, a2);
+        for (int r = 0; r < R; ++r) {
+            beta[r] = sqrt(a1[r] + a2[r]);
+            if (!(beta[r] > 1e-15 * beta1[r])) beta[r] = 0.0;
+            t1[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+        }
+        for (size_t i = 0; i < M; ++i) for (int r = 0; r < R; ++r) ud[i * R + r] *= t1[r];
+        for (size_t i = 0; i < (size_t)N; ++i) for (int r = 0; r < R; ++r) up[i * R + r] *= t1[r];
+        /* plane rotation: rho_k, c_k, s_k; phi_k; x_k = x_{k-1} + (phi/rho) w_k ; r_k = r_{k-1} - (phi/rho) z_k */
+        for (int r = 0; r < R; ++r) {
+            rho[r] = sqrt(rhob[r] * rhob[r] + beta[r] * beta[r]);
+            cs[r] = rho[r] > 0 ? rhob[r] / rho[r] : 1.0;
+            sn[r] = rho[r] > 0 ? beta[r] / rho[r] : 0.0;
+            const double phi = cs[r] * phib[r];
+            phib[r] = sn[r] * phib[r];
+            t1[r] = rho[r] > 0 ? phi / rho[r] : 0.0;
+        }
+        for (size_t i = 0; i < (size_t)N; ++i)
+            for (int r = 0; r < R; ++r) { x[i * R + r] += t1[r] * w[i * R + r]; rp[i * R + r] -= t1[r] * zp[i * R + r]; }
+        for (size_t i = 0; i < M; ++i) for (int r = 0; r < R; ++r) rd[i * R + r] -= t1[r] * zd[i * R + r];
+        DIAG_AT(k);
+        if (k == n_iter) break;
+        /* alpha_{k+1} v_{k+1} = G_ext^T u_{k+1} - beta_{k+1} v_k, reorthogonalised */
+        orc_adjoint(P, R, ud, sv);
+        prior_apply_transpose(P, R, prior_a, up, qp, tmp);
+        for (size_t i = 0; i < (size_t)N; ++i)
+            for (int r = 0; r < R; ++r) sv[i * R + r] = isig * sv[i * R + r] + qp[i * R + r] - beta[r] * v[i * R + r];
+        if (reorth) {
+            for (int pass = 0; pass < 2; ++pass) {
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int j = 0; j < k; ++j) dotr((size_t)N, R, Q + (size_t)j * NR, sv, coef + (size_t)j * R);
+#pragma omp parallel for schedule(static)
+                for (int i = 0; i < N; ++i)
+                    for (int j = 0; j < k; ++j)
+                        for (int r = 0; r < R; ++r)
+                            sv[(size_t)i * R + r] -= coef[(size_t)j * R + r] * Q[(size_t)j * NR + (size_t)i * R + r];
+            }
+        }
+        sumsq((size_t)N, R, sv, a1);
+        for (int r = 0; r < R; ++r) {
+            alpha[r] = sqrt(a1[r]);
+            if (!(alpha[r] > 1e-15 * alpha1[r])) alpha[r] = 0.0;
+            const double theta = sn[r] * alpha[r];            /* theta_{k+1} = s_k alpha_{k+1} */
+            rhob[r] = -cs[r] * alpha[r];                      /* rho_bar_{k+1} = -c_k alpha_{k+1} */
+            zfac[r] = rho[r] > 0 ? theta / rho[r] : 0.0;      /* theta_{k+1} / rho_k */
+            t1[r] = alpha[r] > 0 ? 1.0 / alpha[r] : 0.0;
+        }
+        for (size_t i = 0; i < (size_t)N; ++i)
+            for (int r = 0; r < R; ++r) {
+                v[i * R + r] = sv[i * R + r] * t1[r];
+                w[i * R + r] = v[i * R + r] - zfac[r] * w[i * R + r];
+            }
+        if (reorth) memcpy(Q + (size_t)k * NR, v, sizeof(double) * NR);
+    }
+#undef DIAG_AT
+    free(ud); free(up); free(qd); free(qp); free(zd); free(zp); free(rd); free(rp); free(v); free(w); free(sv);
+    free(tmp); free(Q); free(coef); free(alpha); free(beta); free(rhob); free(phib); free(zfac); free(t1);
+    free(a1); free(a2); free(rho); free(cs); free(sn); free(alpha1); free(beta1);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* RTO samples, Algorithm 1 with the right-hand side of eq. (extended-matrices) */
 /* ------------------------------------------------------------------ */
 
@@ -640,13 +800,14 @@ int orc_cgls(const oproblem *P, int R, double sigma, double prior_a, int n_iter,
  * p_prior = L^{-1} xi, so b = ( (y + sigma eta)/sigma ; L p_prior ) = ( y/sigma + eta ; xi ).
  *   yobs [N_T][n_obs]; eta [N_T][n_obs][S]; xi [N][S]; samples [N][S]. */
 int orc_rto(const oproblem *P, int S, const double *yobs, double sigma, double prior_a, int n_iter, int reorth,
-            const double *eta, const double *xi, double *samples, double *resid) {
+            const double *eta, const double *xi, double *samples, double *resid, int solver, double *diag) {
     const size_t M = (size_t)P->n_steps * P->n_obs;
     double *bd = malloc(sizeof(double) * M * S);
     if (!bd) return -1;
     for (size_t i = 0; i < M; ++i)
         for (int r = 0; r < S; ++r) bd[i * S + r] = yobs[i] / sigma + eta[i * S + r];
-    int rc = orc_cgls(P, S, sigma, prior_a, n_iter, reorth, bd, xi, samples, resid);
+    int rc = solver == 1 ? orc_lsqr(P, S, sigma, prior_a, n_iter, reorth, bd, xi, samples, resid, diag)
+                         : orc_cgls(P, S, sigma, prior_a, n_iter, reorth, bd, xi, samples, resid, diag);
     free(bd);
     return rc;
 }

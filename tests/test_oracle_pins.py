@@ -447,3 +447,52 @@ def test_batched_rhs_equal_single_rhs(tiny):
         assert np.array_equal(pb[r], P.adjoint(yh[r]))
         x1, _ = P.cgls(yh[r:r + 1], p[r:r + 1], 0.1, 0.01, 7)
         assert np.array_equal(xb[r], x1[0])
+
+
+@pytest.mark.parametrize("reorth", [True, False])
+def test_lsqr_iterates_are_krylov_minimisers(tiny, reorth):
+    """LSQR iterate k = the same Krylov-space minimiser as CGLS (Paige-Saunders LSQR)."""
+    P = tiny[0]
+    sigma, a = 0.05, 0.02
+    G, L, A = _gext_dense(P, sigma, a)
+    rng = np.random.default_rng(13)
+    b = rng.standard_normal(A.shape[0])
+    bd = b[: G.shape[0]].reshape(1, P.n_steps, P.n_obs)
+    bp = b[G.shape[0]:].reshape(1, -1)
+    V = np.zeros((A.shape[1], 0))
+    w = A.T @ b
+    for k in range(1, 7):
+        for _ in range(2):
+            w -= V @ (V.T @ w)
+        V = np.hstack([V, (w / np.linalg.norm(w))[:, None]])
+        w = A.T @ (A @ V[:, -1])
+        y, *_ = np.linalg.lstsq(A @ V, b, rcond=None)
+        xk = V @ y
+        x, res, dg = P.lsqr(bd, bp, sigma, a, k, reorth=reorth, diag=True)
+        assert np.linalg.norm(x[0] - xk) < 1e-9 * np.linalg.norm(xk)
+        r = b - A @ x[0]
+        nd = G.shape[0]
+        assert abs(dg[0, -1, 0] - np.linalg.norm(r[:nd])) < 1e-10 * np.linalg.norm(b)
+        assert abs(dg[0, -1, 1] - np.linalg.norm(r[nd:])) < 1e-10 * np.linalg.norm(b)
+        assert abs(res[0, -1] - np.linalg.norm(r)) < 1e-10 * np.linalg.norm(b)
+
+
+def test_lsqr_equals_cgls_and_converges(tiny):
+    """With reorthogonalisation both solvers produce the same iterates; LSQR converges to lstsq."""
+    P = tiny[0]
+    sigma, a = 0.05, 0.02
+    G, L, A = _gext_dense(P, sigma, a)
+    rng = np.random.default_rng(14)
+    b = rng.standard_normal((2, A.shape[0]))
+    bd = b[:, : G.shape[0]].reshape(2, P.n_steps, P.n_obs)
+    bp = b[:, G.shape[0]:]
+    for k in (10, 60):
+        xc, rc, dc = P.cgls(bd, bp, sigma, a, k, diag=True)
+        xl, rl, dl = P.lsqr(bd, bp, sigma, a, k, diag=True)
+        assert np.linalg.norm(xl - xc) < 1e-12 * np.linalg.norm(xc)
+        np.testing.assert_allclose(dl, dc, rtol=1e-10, atol=1e-12)
+    xl, _ = P.lsqr(bd, bp, sigma, a, 2 * P.n_nodes)
+    for r in range(2):
+        xs, *_ = np.linalg.lstsq(A, b[r], rcond=None)
+        assert np.linalg.norm(xl[r] - xs) < 1e-8 * np.linalg.norm(xs)
+    assert np.all(np.isfinite(xl))
