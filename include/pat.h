@@ -106,21 +106,31 @@ pat_status pat_adjoint(pat_problem *p, int64_t R, const void *yhat, void *p_out,
 pat_status pat_prior_apply(pat_problem *p, int64_t R, double prior_a, int transpose, const double *x, double *y,
                            void *stream);
 
+/* Least-squares solver of each RTO sample (Sec. 5.2, App. A). */
+typedef enum {
+    PAT_CGLS = 0, /* CG on the normal equations; reorth acts on the normalised residuals s_j = G_ext^T r_j */
+    PAT_LSQR = 1  /* Paige-Saunders Golub-Kahan bidiagonalisation; reorth acts on the right vectors v_j */
+} pat_solver;
+
 /* Parameters of the RTO sampler (Sec. 5 eq. (optimization), Algorithm 1). */
 typedef struct {
     double sigma;              /* noise standard deviation (> 0) */
     double prior_a;            /* prior factor L = M_L^{-1/2}(M_L + a K1); a = 0 gives M_L^{1/2}, eq. (iid-prior) */
-    int32_t n_iter;            /* CGLS iterations (fixed; >= 1) */
-    int32_t reorth;            /* 1: full reorthogonalisation of the normal-equation residuals (default) */
-    pat_precision sweep_prec;  /* precision of the wave sweeps; CGLS vectors and scalars are always float64 */
+    int32_t n_iter;            /* solver iterations (fixed; >= 1) */
+    int32_t reorth;            /* 1: full reorthogonalisation (default); see pat_solver */
+    pat_precision sweep_prec;  /* precision of the wave sweeps; solver vectors and scalars are always float64 */
     int32_t rhs_block;         /* samples per multi-RHS block: 0 = automatic, else 1, 2, 4, ..., 64 */
     const double *eta;         /* device [S][N_T][N_obs] standard-normal data perturbations */
     const double *xi;          /* device [S][N] standard-normal prior perturbations */
+    int32_t solver;            /* pat_solver; 0 (CGLS) when the struct is zero-initialised */
+    double *diag_hist;         /* device [S][n_iter+1][2] float64 or NULL: per iteration the data and prior parts
+                                  (||y_obs/sigma + eta - G p/sigma||, ||xi - L p||) of the residual */
 } pat_rto_params;
 
 /* S posterior samples by RTO.  Sample k solves
  *   min_p || G_ext p - b_k ||_2,  G_ext = [G/sigma ; L],  b_k = [y_obs/sigma + eta_k ; xi_k]
- * (eq. (extended-matrices) with p_prior = L^{-1} xi_k) by CGLS from p = 0.
+ * (eq. (extended-matrices) with p_prior = L^{-1} xi_k) by CGLS or LSQR from p = 0.
+ * In exact arithmetic both solvers, with reorthogonalisation, give the same iterates.
  *   y_obs       device [N_T][N_obs] float64
  *   samples     device [S][N] float64 (required)
  *   mean, std   device [N] float64 or NULL: pointwise mean and standard deviation

@@ -89,6 +89,8 @@ struct CglsWS {
     double *x = nullptr, *d = nullptr, *s = nullptr, *rp = nullptr, *qp = nullptr;
     double *rd = nullptr, *qd = nullptr, *Q = nullptr;
     double *part = nullptr, *mpart = nullptr, *coef = nullptr, *scal = nullptr;
+    // LSQR: right vector v; z = G_ext w and the residual r = b - G_ext x, kept only for the histories
+    double *v = nullptr, *zp = nullptr, *zd = nullptr, *lrp = nullptr, *lrd = nullptr;
 };
 
 struct pat_problem {
@@ -232,7 +234,7 @@ pat_status check_prec(pat_precision prec, pat::Prec *out) {
     return PAT_OK;
 }
 
-pat_status get_cgls(pat_problem *p, int RB, int n_iter, bool reorth, CglsWS **out) {
+pat_status get_cgls(pat_problem *p, int RB, int n_iter, bool reorth, bool lsqr, bool track, CglsWS **out) {
     CglsWS &c = p->cgls[RB];
     const int64_t N = p->ops.n, M = int64_t(p->ops.n_steps) * p->ops.n_obs;
     if (c.RB == 0) {
@@ -248,6 +250,17 @@ pat_status get_cgls(pat_problem *p, int RB, int n_iter, bool reorth, CglsWS **ou
         PAT_TRY(dev_alloc(p, &v, size_t(4) * pat::kDotBlocks * RB * 8)); c.part = static_cast<double *>(v);
         PAT_TRY(dev_alloc(p, &v, size_t(16) * RB * 8)); c.scal = static_cast<double *>(v);
     }
+    if (lsqr && !c.v) {
+        void *v;
+        PAT_TRY(dev_alloc(p, &v, size_t(N) * RB * 8)); c.v = static_cast<double *>(v);
+    }
+    if (lsqr && track && !c.zd) {
+        void *v;
+        PAT_TRY(dev_alloc(p, &v, size_t(N) * RB * 8)); c.zp = static_cast<double *>(v);
+        PAT_TRY(dev_alloc(p, &v, size_t(N) * RB * 8)); c.lrp = static_cast<double *>(v);
+        PAT_TRY(dev_alloc(p, &v, size_t(M) * RB * 8)); c.zd = static_cast<double *>(v);
+        PAT_TRY(dev_alloc(p, &v, size_t(M) * RB * 8)); c.lrd = static_cast<double *>(v);
+    }
     const int need = reorth ? n_iter + 1 : 0;
     if (need > c.cap_iter) {
         dev_free(p, c.Q); dev_free(p, c.mpart); dev_free(p, c.coef);
@@ -261,6 +274,177 @@ pat_status get_cgls(pat_problem *p, int RB, int n_iter, bool reorth, CglsWS **ou
         c.cap_iter = need;
     }
     *out = &c;
+    return PAT_OK;
+}
+
+
+// State shared by the per-block solvers of rto_sample.
+struct Solve {
+    pat_problem *p;
+    SweepWS *w;
+    CglsWS *c;
+    pat::Prec pr;
+    int RB, n_iter;
+    bool reorth;
+    double isig, a;
+    int64_t N, M, ld, S;
+    double *resid_hist, *diag_hist;
+    hipStream_t s;
+    size_t *ev_used;
+    std::vector<int> *ev_kind;
+};
+
+pat_status sweep(Solve &v, bool forward) {
+    PAT_TRY(launch_sweep(v.p, forward ? v.w->g_fwd_cgls : v.w->g_adj_cgls, v.s, v.ev_used));
+    if (v.p->prof) v.ev_kind->push_back(forward ? 0 : 1);
+    return PAT_OK;
+}
+
+// Residual history column `it` from the data part rd [M][RB] and prior part rp [N][RB].
+void record(Solve &v, const double *rd, const double *rp, int it, int64_t rb0) {
+    if (!v.resid_hist && !v.diag_hist) return;
+    double *pA = v.c->part, *pB = v.c->part + pat::kDotBlocks * v.RB;
+    double *t1 = v.c->scal + 14 * v.RB, *t2 = v.c->scal + 15 * v.RB;
+    pat::launch_dot_partial(rd, rd, v.M, v.RB, pA, v.s);
+    pat::launch_dot_partial(rp, rp, v.N, v.RB, pB, v.s);
+    pat::launch_dot_final(pA, nullptr, v.RB, t1, v.s);
+    pat::launch_dot_final(pB, nullptr, v.RB, t2, v.s);
+    pat::launch_resid(t1, t2, v.resid_hist, v.diag_hist, v.ld, it, rb0, v.S, v.RB, v.s);
+}
+
+// s = G_ext^T (rd, up) = G^T rd / sigma + L^T up; the transpose graph reads rd.
+pat_status apply_gext_t(Solve &v, const double *up) {
+    PAT_TRY(sweep(v, false));
+    pat::launch_gext_t_combine(v.pr, v.p->ops, v.RB, v.a, v.isig, v.w->P[0], up, v.c->s, v.s);
+    return PAT_OK;
+}
+
+// s -= sum_j (Q_j . s) Q_j over j < k, classical Gram-Schmidt applied twice.
+void reorthogonalise(Solve &v, int k) {
+    if (!v.reorth || k <= 0) return;
+    for (int pass = 0; pass < 2; ++pass) {
+        pat::launch_multidot(v.c->Q, v.c->s, k, v.N, v.RB, v.c->mpart, v.c->coef, v.s);
+        pat::launch_project(v.c->Q, v.c->s, v.c->coef, k, v.N, v.RB, v.s);
+    }
+}
+
+// qd = G x / sigma (through the forward graph), qp = L x.
+pat_status apply_gext(Solve &v, const double *x) {
+    pat::launch_cast_to_state(v.pr, x, v.w->P[0], v.N * v.RB, v.s);
+    PAT_TRY(sweep(v, true));
+    pat::launch_prior(v.p->ops, v.RB, v.a, x, v.c->qp, v.s);
+    return PAT_OK;
+}
+
+// CGLS on one block; b in (rd, rp), x = 0 on entry.  Normal-equation residuals
+// s_j are kept orthogonal by two classical Gram-Schmidt passes (App. A).
+pat_status cgls_block(Solve &v, int64_t rb0, const double **chk) {
+    CglsWS *c = v.c;
+    const int RB = v.RB;
+    double *gamma = c->scal, *delta = c->scal + RB, *alpha = c->scal + 2 * RB, *beta = c->scal + 3 * RB;
+    double *invn = c->scal + 4 * RB, *gnew = c->scal + 5 * RB;
+    double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
+    record(v, c->rd, c->rp, 0, rb0);
+    // s_0 = G_ext^T r_0
+    PAT_TRY(apply_gext_t(v, c->rp));
+    pat::launch_dot_partial(c->s, c->s, v.N, RB, pA, v.s);
+    pat::launch_dot_final(pA, nullptr, RB, gnew, v.s);
+    pat::launch_scalar_gamma(gamma, gnew, beta, invn, 1, RB, v.s);
+    pat::launch_append_dir(c->s, v.reorth ? c->Q : nullptr, c->d, invn, beta, 1, v.N, RB, v.s);
+    for (int it = 1; it <= v.n_iter; ++it) {
+        // q = G_ext d ; alpha = gamma / ||q||^2 ; x += alpha d ; r -= alpha q
+        PAT_TRY(apply_gext(v, c->d));
+        pat::launch_dot_partial(c->qd, c->qd, v.M, RB, pA, v.s);
+        pat::launch_dot_partial(c->qp, c->qp, v.N, RB, pB, v.s);
+        pat::launch_dot_final(pA, pB, RB, delta, v.s);
+        pat::launch_scalar_alpha(gamma, delta, alpha, RB, v.s);
+        pat::launch_update_xr(c->x, c->d, c->rp, c->qp, alpha, v.N, RB, v.s);
+        pat::launch_axpy_neg(c->rd, c->qd, alpha, v.M, RB, v.s);
+        record(v, c->rd, c->rp, it, rb0);
+        if (it == v.n_iter) break;
+        // s = G_ext^T r ; beta = gamma_new / gamma ; d = s + beta d
+        PAT_TRY(apply_gext_t(v, c->rp));
+        reorthogonalise(v, it);
+        pat::launch_dot_partial(c->s, c->s, v.N, RB, pA, v.s);
+        pat::launch_dot_final(pA, nullptr, RB, gnew, v.s);
+        pat::launch_scalar_gamma(gamma, gnew, beta, invn, 0, RB, v.s);
+        pat::launch_append_dir(c->s, v.reorth ? c->Q + size_t(it) * v.N * RB : nullptr, c->d, invn, beta, 0, v.N, RB,
+                               v.s);
+    }
+    *chk = gamma;
+    return PAT_OK;
+}
+
+// LSQR on one block (Paige and Saunders' bidiagonalisation, the solver of
+// Sec. 5.2).  b in (rd, rp), x = 0 on entry.  The left vector u lives in
+// (rd, rp), so the transpose graph reads it where CGLS keeps its residual; the
+// search direction w lives in d.  The residual r = b - G_ext x is carried
+// (through z = G_ext w) only when a history is asked for.
+pat_status lsqr_block(Solve &v, int64_t rb0, const double **chk) {
+    CglsWS *c = v.c;
+    const int RB = v.RB;
+    const int64_t N = v.N, M = v.M;
+    const bool track = v.resid_hist || v.diag_hist;
+    double *sc = c->scal;
+    pat::LsqrScalars L{sc, sc + RB, sc + 2 * RB, sc + 3 * RB, sc + 4 * RB, sc + 5 * RB,
+                       sc + 6 * RB, sc + 7 * RB, sc + 8 * RB, sc + 9 * RB, sc + 10 * RB, sc + 11 * RB};
+    double *n1 = sc + 12 * RB, *n2 = sc + 13 * RB;
+    double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
+    if (track) {
+        pat::launch_lincomb(c->lrd, c->rd, nullptr, 1.0, nullptr, nullptr, 0.0, M, RB, v.s);
+        pat::launch_lincomb(c->lrp, c->rp, nullptr, 1.0, nullptr, nullptr, 0.0, N, RB, v.s);
+        record(v, c->lrd, c->lrp, 0, rb0);
+    }
+    // beta_1 u_1 = b
+    pat::launch_dot_partial(c->rd, c->rd, M, RB, pA, v.s);
+    pat::launch_dot_partial(c->rp, c->rp, N, RB, pB, v.s);
+    pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
+    pat::launch_dot_final(pB, nullptr, RB, n2, v.s);
+    pat::launch_lsqr_scalar(pat::LsqrStage::InitBeta, L, n1, n2, RB, v.s);
+    pat::launch_lincomb(c->rd, c->rd, L.inv, 1.0, nullptr, nullptr, 0.0, M, RB, v.s);
+    pat::launch_lincomb(c->rp, c->rp, L.inv, 1.0, nullptr, nullptr, 0.0, N, RB, v.s);
+    // alpha_1 v_1 = G_ext^T u_1 ; w_1 = v_1
+    PAT_TRY(apply_gext_t(v, c->rp));
+    pat::launch_dot_partial(c->s, c->s, N, RB, pA, v.s);
+    pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
+    pat::launch_lsqr_scalar(pat::LsqrStage::InitAlpha, L, n1, nullptr, RB, v.s);
+    pat::launch_lsqr_vw(c->s, L.inv, L.zfac, c->v, c->d, v.reorth ? c->Q : nullptr, 1, N, RB, v.s);
+    for (int k = 1; k <= v.n_iter; ++k) {
+        // q = G_ext v_k ; z_k = q - zfac z_{k-1}
+        PAT_TRY(apply_gext(v, c->v));
+        if (track) {
+            pat::launch_lincomb(c->zd, c->qd, nullptr, 1.0, k > 1 ? c->zd : nullptr, L.zfac, -1.0, M, RB, v.s);
+            pat::launch_lincomb(c->zp, c->qp, nullptr, 1.0, k > 1 ? c->zp : nullptr, L.zfac, -1.0, N, RB, v.s);
+        }
+        // beta_{k+1} u_{k+1} = q - alpha_k u_k ; rotation
+        pat::launch_lincomb(c->rd, c->qd, nullptr, 1.0, c->rd, L.alpha, -1.0, M, RB, v.s);
+        pat::launch_lincomb(c->rp, c->qp, nullptr, 1.0, c->rp, L.alpha, -1.0, N, RB, v.s);
+        pat::launch_dot_partial(c->rd, c->rd, M, RB, pA, v.s);
+        pat::launch_dot_partial(c->rp, c->rp, N, RB, pB, v.s);
+        pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
+        pat::launch_dot_final(pB, nullptr, RB, n2, v.s);
+        pat::launch_lsqr_scalar(pat::LsqrStage::Beta, L, n1, n2, RB, v.s);
+        pat::launch_lincomb(c->rd, c->rd, L.inv, 1.0, nullptr, nullptr, 0.0, M, RB, v.s);
+        pat::launch_lincomb(c->rp, c->rp, L.inv, 1.0, nullptr, nullptr, 0.0, N, RB, v.s);
+        // x += (phi/rho) w ; r -= (phi/rho) z
+        pat::launch_lincomb(c->x, c->x, nullptr, 1.0, c->d, L.step, 1.0, N, RB, v.s);
+        if (track) {
+            pat::launch_lincomb(c->lrd, c->lrd, nullptr, 1.0, c->zd, L.step, -1.0, M, RB, v.s);
+            pat::launch_lincomb(c->lrp, c->lrp, nullptr, 1.0, c->zp, L.step, -1.0, N, RB, v.s);
+            record(v, c->lrd, c->lrp, k, rb0);
+        }
+        if (k == v.n_iter) break;
+        // alpha_{k+1} v_{k+1} = G_ext^T u_{k+1} - beta_{k+1} v_k, reorthogonalised
+        PAT_TRY(apply_gext_t(v, c->rp));
+        pat::launch_lincomb(c->s, c->s, nullptr, 1.0, c->v, L.beta, -1.0, N, RB, v.s);
+        reorthogonalise(v, k);
+        pat::launch_dot_partial(c->s, c->s, N, RB, pA, v.s);
+        pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
+        pat::launch_lsqr_scalar(pat::LsqrStage::Alpha, L, n1, nullptr, RB, v.s);
+        pat::launch_lsqr_vw(c->s, L.inv, L.zfac, c->v, c->d, v.reorth ? c->Q + size_t(k) * N * RB : nullptr, 0, N, RB,
+                            v.s);
+    }
+    *chk = L.phib;
     return PAT_OK;
 }
 
@@ -454,6 +638,8 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
     if (std && S < 2) return fail(PAT_ERR_INVALID_ARG, "std needs S >= 2");
     if (prm->rhs_block != 0 && !valid_rb(prm->rhs_block))
         return fail(PAT_ERR_INVALID_ARG, "rhs_block must be 0 or a power of two <= 64");
+    if (prm->solver != PAT_CGLS && prm->solver != PAT_LSQR)
+        return fail(PAT_ERR_INVALID_ARG, "solver must be PAT_CGLS or PAT_LSQR");
     pat::Prec pr;
     PAT_TRY(check_prec(prm->sweep_prec, &pr));
     DeviceGuard guard(p->device);
@@ -470,8 +656,9 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
 
     SweepWS *w;
     PAT_TRY(get_sweep(p, pr, RB, false, &w));
+    const bool lsqr = prm->solver == PAT_LSQR;
     CglsWS *c;
-    PAT_TRY(get_cgls(p, RB, n_iter, reorth, &c));
+    PAT_TRY(get_cgls(p, RB, n_iter, reorth, lsqr, resid_hist || prm->diag_hist, &c));
     if (!w->g_fwd_cgls || w->g_fwd_cgls_scale != isig || w->g_fwd_cgls_out != c->qd) {
         PAT_TRY(capture(p, &w->g_fwd_cgls, [&](hipStream_t cs) { enqueue_forward(p, *w, c->qd, true, isig, cs); }));
         w->g_fwd_cgls_scale = isig;
@@ -481,74 +668,26 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
         PAT_TRY(capture(p, &w->g_adj_cgls, [&](hipStream_t cs) { enqueue_adjoint(p, *w, c->rd, true, cs); }));
         w->g_adj_cgls_in = c->rd;
     }
-    double *gamma = c->scal, *delta = c->scal + RB, *alpha = c->scal + 2 * RB, *beta = c->scal + 3 * RB;
-    double *invn = c->scal + 4 * RB, *gnew = c->scal + 5 * RB, *t1 = c->scal + 6 * RB, *t2 = c->scal + 7 * RB;
-    double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
     const int64_t ld = n_iter + 1;
-    std::vector<double> gam_host(size_t(((S + RB - 1) / RB) * RB), 0.0);
+    std::vector<double> chk_host(size_t(((S + RB - 1) / RB) * RB), 0.0);
     // event pairs: even index = forward sweep, odd = transpose sweep, per kind in order
     size_t ev_used = 0;
     std::vector<int> ev_kind;  // 0 forward, 1 transpose, per event pair
+    Solve sv{p, w, c, pr, RB, n_iter, reorth, isig, a, N, M, ld, S, resid_hist, prm->diag_hist, s, &ev_used, &ev_kind};
 
     for (int64_t rb0 = 0; rb0 < S; rb0 += RB) {
-        // right-hand side b = (y_obs/sigma + eta, xi); r_0 = b, x_0 = 0
+        // right-hand side b = (y_obs/sigma + eta, xi) in (rd, rp)
         pat::launch_build_rhs(y_obs, prm->eta, S, rb0, RB, M, isig, c->rd, s);
         pat::launch_pack(true, true, prm->xi, S, rb0, RB, N, perm, c->rp, s);
         pat::launch_fill(c->x, N * RB, 0.0, s);
-        if (resid_hist) {
-            pat::launch_dot_partial(c->rd, c->rd, M, RB, pA, s);
-            pat::launch_dot_partial(c->rp, c->rp, N, RB, pB, s);
-            pat::launch_dot_final(pA, nullptr, RB, t1, s);
-            pat::launch_dot_final(pB, nullptr, RB, t2, s);
-            pat::launch_resid(t1, t2, resid_hist, ld, 0, rb0, S, RB, s);
-        }
-        // s_0 = G_ext^T r_0
-        PAT_TRY(launch_sweep(p, w->g_adj_cgls, s, &ev_used));
-        if (p->prof) ev_kind.push_back(1);
-        pat::launch_gext_t_combine(pr, op, RB, a, isig, w->P[0], c->rp, c->s, s);
-        pat::launch_dot_partial(c->s, c->s, N, RB, pA, s);
-        pat::launch_dot_final(pA, nullptr, RB, gnew, s);
-        pat::launch_scalar_gamma(gamma, gnew, beta, invn, 1, RB, s);
-        pat::launch_append_dir(c->s, reorth ? c->Q : nullptr, c->d, invn, beta, 1, N, RB, s);
-        for (int it = 1; it <= n_iter; ++it) {
-            // q = G_ext d
-            pat::launch_cast_to_state(pr, c->d, w->P[0], N * RB, s);
-            PAT_TRY(launch_sweep(p, w->g_fwd_cgls, s, &ev_used));
-            if (p->prof) ev_kind.push_back(0);
-            pat::launch_prior(op, RB, a, c->d, c->qp, s);
-            pat::launch_dot_partial(c->qd, c->qd, M, RB, pA, s);
-            pat::launch_dot_partial(c->qp, c->qp, N, RB, pB, s);
-            pat::launch_dot_final(pA, pB, RB, delta, s);
-            // alpha = gamma / ||q||^2 ; x += alpha d ; r -= alpha q
-            pat::launch_scalar_alpha(gamma, delta, alpha, RB, s);
-            pat::launch_update_xr(c->x, c->d, c->rp, c->qp, alpha, N, RB, s);
-            pat::launch_axpy_neg(c->rd, c->qd, alpha, M, RB, s);
-            if (resid_hist) {
-                pat::launch_dot_partial(c->rd, c->rd, M, RB, pA, s);
-                pat::launch_dot_partial(c->rp, c->rp, N, RB, pB, s);
-                pat::launch_dot_final(pA, nullptr, RB, t1, s);
-                pat::launch_dot_final(pB, nullptr, RB, t2, s);
-                pat::launch_resid(t1, t2, resid_hist, ld, it, rb0, S, RB, s);
-            }
-            if (it == n_iter) break;
-            // s = G_ext^T r, reorthogonalised against the earlier normalised s_j
-            PAT_TRY(launch_sweep(p, w->g_adj_cgls, s, &ev_used));
-            if (p->prof) ev_kind.push_back(1);
-            pat::launch_gext_t_combine(pr, op, RB, a, isig, w->P[0], c->rp, c->s, s);
-            if (reorth) {
-                for (int pass = 0; pass < 2; ++pass) {
-                    pat::launch_multidot(c->Q, c->s, it, N, RB, c->mpart, c->coef, s);
-                    pat::launch_project(c->Q, c->s, c->coef, it, N, RB, s);
-                }
-            }
-            pat::launch_dot_partial(c->s, c->s, N, RB, pA, s);
-            pat::launch_dot_final(pA, nullptr, RB, gnew, s);
-            // beta = gamma_new / gamma ; d = s + beta d
-            pat::launch_scalar_gamma(gamma, gnew, beta, invn, 0, RB, s);
-            pat::launch_append_dir(c->s, reorth ? c->Q + size_t(it) * N * RB : nullptr, c->d, invn, beta, 0, N, RB, s);
+        const double *chk = nullptr;
+        if (lsqr) {
+            PAT_TRY(lsqr_block(sv, rb0, &chk));
+        } else {
+            PAT_TRY(cgls_block(sv, rb0, &chk));
         }
         pat::launch_unpack(true, true, c->x, S, rb0, RB, N, perm, samples, s);
-        PAT_HIP(hipMemcpyAsync(gam_host.data() + rb0, gamma, RB * sizeof(double), hipMemcpyDeviceToHost, s));
+        PAT_HIP(hipMemcpyAsync(chk_host.data() + rb0, chk, RB * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     if (mean || std) pat::launch_stats(samples, S, N, mean, std, s);
     PAT_HIP(hipGetLastError());
@@ -565,8 +704,9 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
         }
     }
     for (int64_t k = 0; k < S; ++k)
-        if (!std::isfinite(gam_host[size_t(k)]))
-            return fail(PAT_ERR_NONFINITE, "non-finite CGLS scalar for sample " + std::to_string(k));
+        if (!std::isfinite(chk_host[size_t(k)]))
+            return fail(PAT_ERR_NONFINITE, std::string("non-finite ") + (lsqr ? "LSQR" : "CGLS") +
+                                               " scalar for sample " + std::to_string(k));
     return PAT_OK;
 }
 

@@ -69,8 +69,9 @@ void launch_dot_final(const double *partA, const double *partB, int RB, double *
 void launch_scalar_alpha(const double *gamma, const double *delta, double *alpha, int RB, hipStream_t s);
 void launch_scalar_gamma(double *gamma, const double *gnew, double *beta, double *invn, int first, int RB,
                          hipStream_t s);
-void launch_resid(const double *a, const double *b, double *hist, int64_t ld, int64_t col, int64_t rb0, int64_t R,
-                  int RB, hipStream_t s);
+// hist[(rb0+r)*ld + col] = sqrt(a + b) and diag[2*(that)] = (sqrt(a), sqrt(b)); either may be null
+void launch_resid(const double *a, const double *b, double *hist, double *diag, int64_t ld, int64_t col, int64_t rb0,
+                  int64_t R, int RB, hipStream_t s);
 // x += alpha*d ; rp -= alpha*qp  (N rows)   and   rd -= alpha*qd (M rows)
 void launch_update_xr(double *x, const double *d, double *rp, const double *qp, const double *alpha, int64_t rows,
                       int RB, hipStream_t s);
@@ -82,6 +83,23 @@ void launch_append_dir(const double *sv, double *Qk, double *d, const double *in
 void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *coef,
                      hipStream_t s);
 void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s);
+// LSQR scalar recurrences (device arrays of length RB each).
+struct LsqrScalars {
+    double *alpha, *beta, *alpha1, *beta1, *rhob, *phib, *cs, *sn, *rho, *zfac, *step, *inv;
+};
+// InitBeta:  beta_1 = sqrt(n1 + n2), inv = 1/beta_1
+// InitAlpha: alpha_1 = sqrt(n1), inv = 1/alpha_1, phi_bar = beta_1, rho_bar = alpha_1
+// Beta:      beta_{k+1} = sqrt(n1 + n2), inv = 1/beta, rotation (rho, c, s), phi_bar, step = phi/rho
+// Alpha:     alpha_{k+1} = sqrt(n1), inv = 1/alpha, rho_bar = -c alpha, zfac = s alpha / rho
+enum class LsqrStage : int { InitBeta, InitAlpha, Beta, Alpha };
+void launch_lsqr_scalar(LsqrStage st, const LsqrScalars &c, const double *n1, const double *n2, int RB,
+                        hipStream_t s);
+// out = sa*ca[r]*a + sb*cb[r]*b (null ca/cb: 1; null b: no second term); out may alias a or b
+void launch_lincomb(double *out, const double *a, const double *ca, double sa, const double *b, const double *cb,
+                    double sb, int64_t rows, int RB, hipStream_t s);
+// v = inv*sv ; w = v - zfac*w (first: w = v) ; Qk = v if non-null
+void launch_lsqr_vw(const double *sv, const double *inv, const double *zfac, double *v, double *w, double *Qk,
+                    int first, int64_t rows, int RB, hipStream_t s);
 // pointwise mean and std (1/(S-1)) of samples [S][N]
 void launch_stats(const double *samples, int64_t S, int64_t N, double *mean, double *std, hipStream_t s);
 

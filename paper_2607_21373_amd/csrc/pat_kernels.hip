@@ -728,10 +728,16 @@ __global__ void k_gamma(double *gamma, const double *gnew, double *beta, double 
     gamma[r] = g;
 }
 
-__global__ void k_resid(const double *a, const double *b, double *hist, int64_t ld, int64_t col, int64_t rb0,
-                        int64_t R, int RB) {
+__global__ void k_resid(const double *a, const double *b, double *hist, double *diag, int64_t ld, int64_t col,
+                        int64_t rb0, int64_t R, int RB) {
     const int r = threadIdx.x;
-    if (r < RB && rb0 + r < R) hist[(rb0 + r) * ld + col] = sqrt(a[r] + b[r]);
+    if (r >= RB || rb0 + r >= R) return;
+    const int64_t at = (rb0 + r) * ld + col;
+    if (hist) hist[at] = sqrt(a[r] + b[r]);
+    if (diag) {
+        diag[2 * at] = sqrt(a[r]);
+        diag[2 * at + 1] = sqrt(b[r]);
+    }
 }
 
 __global__ void k_update_xr(double *x, const double *d, double *rp, const double *qp, const double *alpha,
@@ -759,6 +765,75 @@ __global__ void k_append(const double *sv, double *Qk, double *d, const double *
 }
 
 // part[b][j][r] = sum over rows of block b of Q[j][row][r] * s[row][r], j in [j0, j0+8) and < k
+// ---- LSQR (Golub-Kahan bidiagonalisation) ---------------------------------
+// Per-RHS scalar stages; one thread per right-hand side.  A new alpha or beta
+// below 1e-15 of its first value is exact breakdown and is set to zero.
+__global__ void k_lsqr_scalar(LsqrStage st, LsqrScalars c, const double *n1, const double *n2, int RB) {
+    const int r = threadIdx.x;
+    if (r >= RB) return;
+    const double nrm = sqrt(n1[r] + (n2 ? n2[r] : 0.0));
+    switch (st) {
+    case LsqrStage::InitBeta:
+        c.beta[r] = c.beta1[r] = nrm;
+        c.inv[r] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        break;
+    case LsqrStage::InitAlpha:
+        c.alpha[r] = c.alpha1[r] = nrm;
+        c.inv[r] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        c.phib[r] = c.beta[r];
+        c.rhob[r] = nrm;
+        c.zfac[r] = 0.0;
+        break;
+    case LsqrStage::Beta: {
+        const double be = nrm > 1e-15 * c.beta1[r] ? nrm : 0.0;
+        c.beta[r] = be;
+        c.inv[r] = be > 0.0 ? 1.0 / be : 0.0;
+        // plane rotation eliminating beta_{k+1} below rho_bar_k
+        const double rb = c.rhob[r];
+        const double rho = sqrt(rb * rb + be * be);
+        const double cs = rho > 0.0 ? rb / rho : 1.0, sn = rho > 0.0 ? be / rho : 0.0;
+        const double phi = cs * c.phib[r];
+        c.rho[r] = rho;
+        c.cs[r] = cs;
+        c.sn[r] = sn;
+        c.phib[r] = sn * c.phib[r];
+        c.step[r] = rho > 0.0 ? phi / rho : 0.0;
+        break;
+    }
+    case LsqrStage::Alpha: {
+        const double al = nrm > 1e-15 * c.alpha1[r] ? nrm : 0.0;
+        c.alpha[r] = al;
+        c.inv[r] = al > 0.0 ? 1.0 / al : 0.0;
+        c.rhob[r] = -c.cs[r] * al;
+        c.zfac[r] = c.rho[r] > 0.0 ? c.sn[r] * al / c.rho[r] : 0.0;
+        break;
+    }
+    }
+}
+
+// out = (sa * ca[r]) a + (sb * cb[r]) b; a null coefficient pointer means 1, b may be null.
+__global__ void k_lincomb(double *out, const double *a, const double *ca, double sa, const double *b, const double *cb,
+                          double sb, int64_t total, int RB) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int r = int(e % RB);
+        double v = sa * (ca ? ca[r] : 1.0) * a[e];
+        if (b) v += sb * (cb ? cb[r] : 1.0) * b[e];
+        out[e] = v;
+    }
+}
+
+// v = inv * sv ; w = v - zfac * w (w = v on the first call) ; Qk = v
+__global__ void k_lsqr_vw(const double *sv, const double *inv, const double *zfac, double *v, double *w, double *Qk,
+                          int first, int64_t total, int RB) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int r = int(e % RB);
+        const double vv = inv[r] * sv[e];
+        v[e] = vv;
+        w[e] = first ? vv : vv - zfac[r] * w[e];
+        if (Qk) Qk[e] = vv;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_multidot_partial(const double *Q, const double *sv, int k, int64_t rows,
                                                           int RB, double *part) {
     __shared__ double red[256];
@@ -1087,9 +1162,26 @@ void launch_scalar_gamma(double *gamma, const double *gnew, double *beta, double
     hipLaunchKernelGGL(k_gamma, dim3(1), dim3(64), 0, s, gamma, gnew, beta, invn, first, RB);
 }
 
-void launch_resid(const double *a, const double *b, double *hist, int64_t ld, int64_t col, int64_t rb0, int64_t R,
-                  int RB, hipStream_t s) {
-    hipLaunchKernelGGL(k_resid, dim3(1), dim3(64), 0, s, a, b, hist, ld, col, rb0, R, RB);
+void launch_resid(const double *a, const double *b, double *hist, double *diag, int64_t ld, int64_t col, int64_t rb0,
+                  int64_t R, int RB, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid, dim3(1), dim3(64), 0, s, a, b, hist, diag, ld, col, rb0, R, RB);
+}
+
+void launch_lsqr_scalar(LsqrStage st, const LsqrScalars &c, const double *n1, const double *n2, int RB,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_lsqr_scalar, dim3(1), dim3(64), 0, s, st, c, n1, n2, RB);
+}
+
+void launch_lincomb(double *out, const double *a, const double *ca, double sa, const double *b, const double *cb,
+                    double sb, int64_t rows, int RB, hipStream_t s) {
+    const int64_t total = rows * RB;
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(total)), dim3(256), 0, s, out, a, ca, sa, b, cb, sb, total, RB);
+}
+
+void launch_lsqr_vw(const double *sv, const double *inv, const double *zfac, double *v, double *w, double *Qk,
+                    int first, int64_t rows, int RB, hipStream_t s) {
+    const int64_t total = rows * RB;
+    hipLaunchKernelGGL(k_lsqr_vw, dim3(grid_for(total)), dim3(256), 0, s, sv, inv, zfac, v, w, Qk, first, total, RB);
 }
 
 void launch_update_xr(double *x, const double *d, double *rp, const double *qp, const double *alpha, int64_t rows,

@@ -62,8 +62,11 @@ class RtoParams(ctypes.Structure):
     _fields_ = [
         ("sigma", ctypes.c_double), ("prior_a", ctypes.c_double), ("n_iter", ctypes.c_int32),
         ("reorth", ctypes.c_int32), ("sweep_prec", ctypes.c_int), ("rhs_block", ctypes.c_int32),
-        ("eta", ctypes.c_void_p), ("xi", ctypes.c_void_p),
+        ("eta", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("solver", ctypes.c_int32), ("diag_hist", ctypes.c_void_p),
     ]
+
+
+PAT_CGLS, PAT_LSQR = 0, 1
 
 
 # names exported by libpat (the C ABI in include/pat.h)
@@ -279,12 +282,13 @@ def pat_prior_apply(problem: Problem, x, prior_a: float, transpose: bool = False
 
 def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n_iter: int, reorth: bool = True,
                sweep_prec: str = "f64", rhs_block: int = 0, stats: bool = True, resid: bool = False,
-               samples=None):
+               samples=None, solver: str = "cgls", diag: bool = False):
     """RTO posterior samples (Algorithm 1) through libpat's rto_sample.
 
     y_obs [N_T][N_obs], eta [S][N_T][N_obs], xi [S][N]: float64 CUDA tensors.
-    Returns a dict with samples [S][N] and, if requested, mean, std [N] and
-    resid [S][n_iter+1]."""
+    solver: "cgls" or "lsqr" (Sec. 5.2, App. A).
+    Returns a dict with samples [S][N] and, if requested, mean, std [N],
+    resid [S][n_iter+1] and diag [S][n_iter+1][2] (data and prior residual norms)."""
     import torch
     f64 = torch.float64
     S = xi.shape[0]
@@ -295,7 +299,10 @@ def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n
     mean = torch.empty(N, dtype=f64, device=dev) if stats else None
     std = torch.empty(N, dtype=f64, device=dev) if stats and S >= 2 else None
     res = torch.empty((S, n_iter + 1), dtype=f64, device=dev) if resid else None
+    dg = torch.empty((S, n_iter + 1, 2), dtype=f64, device=dev) if diag else None
     prm = RtoParams()
+    prm.solver = {"cgls": PAT_CGLS, "lsqr": PAT_LSQR}[solver]
+    prm.diag_hist = dg.data_ptr() if dg is not None else None
     prm.sigma = float(sigma)
     prm.prior_a = float(prior_a)
     prm.n_iter = int(n_iter)
@@ -310,7 +317,7 @@ def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n
     dp = ctypes.c_void_p(std.data_ptr()) if std is not None else None
     rp = ctypes.c_void_p(res.data_ptr()) if res is not None else None
     _check(load().rto_sample(problem._h, yp, ctypes.byref(prm), S, sp, mp, dp, rp, _stream()))
-    return {"samples": samples, "mean": mean, "std": std, "resid": res}
+    return {"samples": samples, "mean": mean, "std": std, "resid": res, "diag": dg}
 
 
 def version() -> str:

@@ -1,0 +1,159 @@
+"""GPU LSQR and residual diagnostics against the CPU FP64 oracle.
+
+LSQR (Paige-Saunders bidiagonalisation, the least-squares solver of Sec. 5.2)
+runs on the same sweeps and reductions as CGLS.  Checks:
+  * float64 sweeps: samples, mean, std, the residual history and the split
+    (data, prior) residual norms against the oracle's LSQR, 1e-10;
+  * the split norms of the GPU CGLS against the oracle's CGLS, 1e-10;
+  * LSQR against CGLS on the GPU: equal iterates in exact arithmetic with
+    reorthogonalisation, so rounding-level agreement (1e-9);
+  * float32 sweeps with float64 LSQR: mean and std within 1e-4 relative L2;
+  * one iteration, no reorthogonalisation, a single sample, a ragged block;
+  * running past the Krylov dimension on a tiny mesh: the breakdown rule keeps
+    the iterate finite and at the least-squares solution;
+  * an unknown solver id is rejected.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pat = pytest.importorskip("paper_2607_21373_amd.pat")
+
+CASES = {}
+
+
+def _case(name):
+    if name not in CASES:
+        w = W.make_workload(name)
+        CASES[name] = (w, oracle.Problem.from_workload(w), pat.Problem.from_workload(w))
+    return CASES[name]
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _inputs(w, O, S):
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    eta, xi = W.rto_draws(S, w.n_steps, w.n_obs, w.n_nodes, w.rto_seed)
+    return yobs, sigma, eta, xi
+
+
+@pytest.mark.parametrize("name,S,rb", [("cube8_tiny", 10, 0), ("ball16", 16, 4), ("ball16", 5, 1), ("ball16", 3, 0)])
+def test_lsqr_f64_matches_oracle(name, S, rb):
+    w, O, G = _case(name)
+    yobs, sigma, eta, xi = _inputs(w, O, S)
+    ref, rres, rdg = O.rto(yobs, sigma, w.prior_a, w.n_iter, eta, xi, solver="lsqr", diag=True)
+    rmean, rstd = oracle.stats(ref)
+    print(f"case {name} S={S} rb={rb}", flush=True)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, w.n_iter, sweep_prec="f64",
+                         rhs_block=rb, resid=True, solver="lsqr", diag=True)
+    errs = (_rel_l2(out["samples"].cpu().numpy(), ref), _rel_l2(out["mean"].cpu().numpy(), rmean),
+            _rel_l2(out["std"].cpu().numpy(), rstd), _rel_max(out["resid"].cpu().numpy(), rres),
+            _rel_max(out["diag"].cpu().numpy(), rdg))
+    print(f"{name} LSQR f64: samples {errs[0]:.2e} mean {errs[1]:.2e} std {errs[2]:.2e} "
+          f"resid {errs[3]:.2e} diag {errs[4]:.2e}")
+    assert max(errs) < 1e-10
+
+
+def test_cgls_diag_matches_oracle():
+    w, O, G = _case("ball16")
+    yobs, sigma, eta, xi = _inputs(w, O, 6)
+    ref, rres, rdg = O.rto(yobs, sigma, w.prior_a, w.n_iter, eta, xi, diag=True)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, w.n_iter, resid=True, diag=True)
+    dg = out["diag"].cpu().numpy()
+    assert _rel_max(dg, rdg) < 1e-10
+    # the split norms recombine to the total residual
+    np.testing.assert_allclose(np.hypot(dg[..., 0], dg[..., 1]), out["resid"].cpu().numpy(), rtol=1e-13)
+
+
+def test_lsqr_equals_cgls_on_gpu():
+    w, O, G = _case("ball16")
+    yobs, sigma, eta, xi = _inputs(w, O, 8)
+    args = (G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, w.n_iter)
+    a = pat.rto_sample(*args, solver="cgls", diag=True)
+    b = pat.rto_sample(*args, solver="lsqr", diag=True)
+    e = _rel_l2(b["samples"].cpu().numpy(), a["samples"].cpu().numpy())
+    ed = _rel_max(b["diag"].cpu().numpy(), a["diag"].cpu().numpy())
+    print(f"LSQR vs CGLS on the GPU: samples {e:.2e} diag {ed:.2e}")
+    assert e < 1e-9 and ed < 1e-9
+
+
+def test_lsqr_f32_sweeps():
+    w, O, G = _case("ball16")
+    S = 64
+    yobs, sigma, eta, xi = _inputs(w, O, S)
+    ref, _ = O.rto(yobs, sigma, w.prior_a, w.n_iter, eta, xi, solver="lsqr")
+    rmean, rstd = oracle.stats(ref)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, w.n_iter, sweep_prec="f32",
+                         solver="lsqr")
+    em = _rel_l2(out["mean"].cpu().numpy(), rmean)
+    es = _rel_l2(out["std"].cpu().numpy(), rstd)
+    print(f"LSQR f32 sweeps: mean {em:.2e} std {es:.2e}")
+    assert em < 1e-4 and es < 1e-4
+
+
+def test_lsqr_edge_cases():
+    w, O, G = _case("ball16")
+    yobs, sigma, eta, xi = _inputs(w, O, 3)
+    for n_iter, reorth, S in ((1, True, 1), (3, False, 3), (2, True, 3)):
+        ref, _ = O.rto(yobs, sigma, w.prior_a, n_iter, eta[:S], xi[:S], reorth=reorth, solver="lsqr")
+        out = pat.rto_sample(G, _dev(yobs), _dev(eta[:S]), _dev(xi[:S]), sigma, w.prior_a, n_iter,
+                             reorth=reorth, stats=S > 1, solver="lsqr")
+        assert _rel_l2(out["samples"].cpu().numpy(), ref) < 1e-11
+
+
+def test_lsqr_past_krylov_dimension():
+    """2N iterations on a mesh of N nodes: exact breakdown is reached and handled."""
+    coords, tets = W.ball_mesh(3)
+    w = W.Workload(name="tiny", coords=coords, tets=tets, c_tet=None, absorbing=True, dt=0.2 * 2 / 3, n_steps=15,
+                   sensor_pos=W.fibonacci_sphere(6, 0.7), p0_true=W.smooth_bump(coords, 0.8), prior_a=0.02)
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    N = w.n_nodes
+    rng = np.random.default_rng(40)
+    yobs = rng.standard_normal((w.n_steps, w.n_obs))
+    eta = rng.standard_normal((2, w.n_steps, w.n_obs))
+    xi = rng.standard_normal((2, N))
+    sigma = 0.3
+    Gd = O.forward(np.eye(N)).reshape(N, -1).T
+    L = O.prior_apply(np.eye(N), w.prior_a).T
+    A = np.vstack([Gd / sigma, L])
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, 2 * N, solver="lsqr", stats=False)
+    got = out["samples"].cpu().numpy()
+    assert np.all(np.isfinite(got))
+    for r in range(2):
+        b = np.concatenate([(yobs / sigma + eta[r]).ravel(), xi[r]])
+        xs, *_ = np.linalg.lstsq(A, b, rcond=None)
+        assert np.linalg.norm(got[r] - xs) < 1e-8 * np.linalg.norm(xs)
+
+
+def test_unknown_solver_rejected():
+    w, O, G = _case("cube8_tiny")
+    yobs = _dev(np.zeros((w.n_steps, w.n_obs)))
+    eta = _dev(np.zeros((2, w.n_steps, w.n_obs)))
+    xi = _dev(np.zeros((2, w.n_nodes)))
+    smp = _dev(np.zeros((2, w.n_nodes)))
+    prm = pat.RtoParams()
+    prm.sigma, prm.prior_a, prm.n_iter, prm.reorth = 1.0, 0.01, 2, 1
+    prm.sweep_prec, prm.rhs_block = pat.PAT_F64, 0
+    prm.eta, prm.xi, prm.solver = eta.data_ptr(), xi.data_ptr(), 7
+    rc = pat.load().rto_sample(G._h, ctypes.c_void_p(yobs.data_ptr()), ctypes.byref(prm), 2,
+                               ctypes.c_void_p(smp.data_ptr()), None, None, None, None)
+    assert rc == -1
+    assert "solver" in pat.load().pat_last_error().decode()

@@ -143,3 +143,27 @@ def test_create_without_device_reports_hip_error():
     with pytest.raises(PatError) as ei:
         pat.Problem(**_tiny())
     assert ei.value.name == "PAT_ERR_HIP"
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Field offsets and sizes of the ctypes structs equal those gcc computes from include/pat.h."""
+    import subprocess
+    structs = {"pat_problem_desc": pat.ProblemDesc, "pat_problem_info": pat.ProblemInfo,
+               "pat_rto_params": pat.RtoParams, "pat_profile": pat.Profile}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pat.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        py = structs[cname]
+        got = ctypes.sizeof(py) if field == "sizeof" else getattr(py, field).offset
+        assert got == int(val), (cname, field, got, val)
