@@ -70,6 +70,9 @@ def _load():
     lib.orc_rto.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                             ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
     lib.orc_stats.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+    _u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.orc_philox4x64.argtypes = [_u64p, _u64p, _u64p]
+    lib.orc_normals.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _dp]
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -251,6 +254,28 @@ def stats(samples: np.ndarray):
     mean = np.empty(N); std = np.empty(N)
     _load().orc_stats(N, S, _ptr(a), _ptr(mean), _ptr(std))
     return mean, std
+
+
+def philox4x64(ctr, key) -> np.ndarray:
+    """Philox4x64-10 block (Salmon et al., SC'11) of counter ctr[4] under key[2]."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.empty(4, dtype=np.uint64)
+    u = ctypes.POINTER(ctypes.c_uint64)
+    _load().orc_philox4x64(c.ctypes.data_as(u), k.ctypes.data_as(u), out.ctypes.data_as(u))
+    return out
+
+
+def normals(seed: int, kind: int, k0: int, S: int, length: int) -> np.ndarray:
+    """[S][length] standard normals of streams (seed, kind, k0..k0+S-1): Philox4x64-10 + Box-Muller."""
+    out = np.empty((S, length))
+    _load().orc_normals(int(seed), int(kind), int(k0), int(S), int(length), _ptr(out))
+    return out
+
+
+def rto_normals(seed: int, S: int, n_steps: int, n_obs: int, n_nodes: int):
+    """eta [S][N_T][N_obs] (kind 0) and xi [S][N] (kind 1) as the sampler draws them itself."""
+    return (normals(seed, 0, 0, S, n_steps * n_obs).reshape(S, n_steps, n_obs), normals(seed, 1, 0, S, n_nodes))
 
 
 def noise_sigma(Y: np.ndarray, eta0: np.ndarray, d_noise: float, rule: str) -> float:

@@ -25,8 +25,13 @@
  *                       action eqs. (lsqr-residual), (lsqr-transpose-action)
  *   CGLS                least-squares solve of eq. (normal-equations), with full
  *                       reorthogonalisation of the normal-equation residuals
+ *   LSQR                the same least squares by Paige and Saunders' Golub-Kahan
+ *                       bidiagonalisation, the solver named in Sec. 5.2
  *   RTO sample          Sec. 5, eq. (optimization); Algorithm 1
  *   mean / std          Sec. 6.2, eq. (ergodic)
+ *   perturbations       the standard-normal draws eta, xi of Algorithm 1 when the
+ *                       sampler makes its own: Philox4x64-10 (Salmon, Moraes, Dror
+ *                       and Shaw, SC'11) followed by the Box-Muller transform
  */
 #include <math.h>
 #include <stdint.h>
@@ -826,6 +831,61 @@ void orc_stats(int N, int S, const double *samples, double *mean, double *std) {
         mean[i] = m;
         std[i] = S > 1 ? sqrt(v / (S - 1)) : 0.0;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Counter-based standard normals                                        */
+/* ------------------------------------------------------------------ */
+
+/* Philox4x64-10 block cipher of Salmon et al. (SC'11): ten rounds of two
+ * 64x64 -> 128-bit products (multipliers 0xD2E7470EE14C6C93 on word 0 and
+ * 0xCA5A826395121157 on word 2), the high halves xored with the other two words
+ * and the round key, the key advanced by the Weyl increments 0x9E3779B97F4A7C15
+ * and 0xBB67AE8584CAA73B between rounds. */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B97F4A7C15ULL;
+            k1 += 0xBB67AE8584CAA73BULL;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ULL * c0;
+        const unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ULL * c2;
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Standard normal number j of stream (seed, kind, k): kind 0 = data
+ * perturbation eta_k (j = t*N_obs + s), kind 1 = prior perturbation xi_k (j = node).
+ * Block j/4 of the cipher with counter (j/4, k, kind, 0) and key (seed, 0) gives
+ * four 64-bit words; words (0, 1) and (2, 3) are two Box-Muller pairs: with
+ * U(x) = (x >> 11) 2^-53 in [0, 1), u1 = 1 - U(first) in (0, 1], u2 = U(second),
+ * the pair is sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2). */
+static double normal_at(uint64_t seed, int kind, int64_t k, int64_t j) {
+    const uint64_t ctr[4] = {(uint64_t)j / 4, (uint64_t)k, (uint64_t)kind, 0};
+    const uint64_t key[2] = {seed, 0};
+    uint64_t w[4];
+    orc_philox4x64(ctr, key, w);
+    const int lane = (int)(j % 4), pair = lane / 2;
+    const double u1 = 1.0 - (double)(w[2 * pair] >> 11) * 0x1p-53;
+    const double u2 = (double)(w[2 * pair + 1] >> 11) * 0x1p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 6.283185307179586476925286766559 * u2; /* 2 pi */
+    return (lane % 2 == 0) ? rad * cos(ang) : rad * sin(ang);
+}
+
+/* out[s*len + j] = normal j of stream (seed, kind, k0 + s), s < S, j < len. */
+void orc_normals(uint64_t seed, int kind, int64_t k0, int64_t S, int64_t len, double *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < S; ++s)
+        for (int64_t j = 0; j < len; ++j) out[s * len + j] = normal_at(seed, kind, k0 + s, j);
 }
 
 int orc_num_threads(void) {

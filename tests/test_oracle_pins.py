@@ -496,3 +496,58 @@ def test_lsqr_equals_cgls_and_converges(tiny):
         xs, *_ = np.linalg.lstsq(A, b[r], rcond=None)
         assert np.linalg.norm(xl[r] - xs) < 1e-8 * np.linalg.norm(xs)
     assert np.all(np.isfinite(xl))
+
+
+# ---- counter-based perturbations (the sampler's own eta, xi) --------------------------------
+
+def _numpy_philox_block(ctr, key):
+    """numpy's Philox (4x64-10) advances its 256-bit counter before each block: start it at ctr - 1."""
+    c = [int(x) for x in ctr]
+    for i in range(4):                      # 256-bit decrement with borrow
+        if c[i] > 0:
+            c[i] -= 1
+            break
+        c[i] = (1 << 64) - 1
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    return bg.random_raw(4)
+
+
+def test_philox_matches_numpy():
+    rng = np.random.default_rng(50)
+    cases = [([1, 0, 0, 0], [0, 0]), ([0, 1, 0, 0], [0, 0]), ([0, 0, 0, 0], [1, 2]),
+             ([2**64 - 1] * 4, [2**64 - 1] * 2)]
+    cases += [(rng.integers(0, 2**64, 4, dtype=np.uint64, endpoint=False), rng.integers(0, 2**64, 2, dtype=np.uint64))
+              for _ in range(200)]
+    for ctr, key in cases:
+        if all(int(x) == 0 for x in ctr):
+            continue
+        np.testing.assert_array_equal(oracle.philox4x64(ctr, key), _numpy_philox_block(ctr, key))
+
+
+def test_normals_distribution():
+    """Box-Muller on Philox words: every lane of the block is N(0, 1), pairs are independent."""
+    from scipy import stats as st
+    z = oracle.normals(123, 0, 0, 4, 2**20)
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1) < 5 * np.sqrt(2 / z.size)
+    assert abs(st.skew(z.ravel())) < 5 * np.sqrt(6 / z.size)
+    assert abs(st.kurtosis(z.ravel())) < 5 * np.sqrt(24 / z.size)
+    for lane in range(4):                    # cos and sin branches of both pairs
+        assert st.kstest(z[:, lane::4].ravel(), "norm").pvalue > 1e-4
+    r2 = z[:, 0::2] ** 2 + z[:, 1::2] ** 2   # chi^2 with 2 degrees of freedom
+    assert st.kstest(r2.ravel(), "expon", args=(0, 2)).pvalue > 1e-4
+    # neighbouring lanes, streams, kinds and seeds are uncorrelated
+    lim = 5 / np.sqrt(z.shape[1])
+    for a, b in ((z[0, 0::4], z[0, 1::4]), (z[0, 0::4], z[0, 2::4]), (z[0], z[1])):
+        assert abs(np.corrcoef(a, b)[0, 1]) < 5 / np.sqrt(a.size)
+    assert abs(np.corrcoef(z[0], oracle.normals(123, 1, 0, 1, 2**20)[0])[0, 1]) < lim
+    assert abs(np.corrcoef(z[0], oracle.normals(124, 0, 0, 1, 2**20)[0])[0, 1]) < lim
+
+
+def test_normals_stream_addressing():
+    a = oracle.normals(7, 1, 0, 6, 37)
+    np.testing.assert_array_equal(oracle.normals(7, 1, 3, 2, 37), a[3:5])
+    np.testing.assert_array_equal(oracle.normals(7, 1, 0, 6, 10), a[:, :10])
+    eta, xi = oracle.rto_normals(7, 6, 4, 9, 37)
+    np.testing.assert_array_equal(xi, a)
+    np.testing.assert_array_equal(eta.reshape(6, -1), oracle.normals(7, 0, 0, 6, 36))
