@@ -120,11 +120,13 @@ typedef struct {
     int32_t reorth;            /* 1: full reorthogonalisation (default); see pat_solver */
     pat_precision sweep_prec;  /* precision of the wave sweeps; solver vectors and scalars are always float64 */
     int32_t rhs_block;         /* samples per multi-RHS block: 0 = automatic, else 1, 2, 4, ..., 64 */
-    const double *eta;         /* device [S][N_T][N_obs] standard-normal data perturbations */
-    const double *xi;          /* device [S][N] standard-normal prior perturbations */
+    const double *eta;         /* device [S][N_T][N_obs] standard-normal data perturbations, or NULL */
+    const double *xi;          /* device [S][N] standard-normal prior perturbations, or NULL (both or neither) */
     int32_t solver;            /* pat_solver; 0 (CGLS) when the struct is zero-initialised */
     double *diag_hist;         /* device [S][n_iter+1][2] float64 or NULL: per iteration the data and prior parts
                                   (||y_obs/sigma + eta - G p/sigma||, ||xi - L p||) of the residual */
+    uint64_t seed;             /* eta == xi == NULL: the sampler draws them itself, see pat_draw_normals */
+    int64_t sample0;           /* stream index of the first sample (disjoint ranges give independent samples) */
 } pat_rto_params;
 
 /* S posterior samples by RTO.  Sample k solves
@@ -139,6 +141,18 @@ typedef struct {
  * Scratch memory is owned by the handle and grows to the largest block seen. */
 pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params *prm, int64_t S,
                       double *samples, double *mean, double *std, double *resid_hist, void *stream);
+
+/* Standard normals of the sampler's own perturbations (Algorithm 1 draws eta_k and
+ * xi_k): out[s][j] = normal j of stream (seed, kind, k0 + s), s < S, j < len,
+ * device float64 [S][len].  kind 0 is eta (j = t*N_obs + sensor), kind 1 is xi
+ * (j = node id in the caller's numbering); rto_sample with eta == xi == NULL uses
+ * streams (seed, kind, sample0 + k) for its sample k.  Normal j is lane j%4 of
+ * the Philox4x64-10 block (Salmon, Moraes, Dror and Shaw, SC'11) with counter
+ * (j/4, k, kind, 0) and key (seed, 0); lanes (0,1) and (2,3) are Box-Muller pairs
+ * with u1 = 1 - U(first word), u2 = U(second word), U(w) = (w >> 11) 2^-53.
+ * Runs on the current device; kind must be 0 or 1. */
+pat_status pat_draw_normals(uint64_t seed, int32_t kind, int64_t k0, int64_t S, int64_t len, double *out,
+                            void *stream);
 
 /* Host-only view of the setup (no device is touched): runs the validation and
  * assembly of pat_problem_create and copies the assembled operators out in the

@@ -631,7 +631,9 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
                       double *mean, double *std, double *resid_hist, void *stream) {
     g_err.clear();
     if (!p || !y_obs || !prm || !samples || S < 1) return fail(PAT_ERR_INVALID_ARG, "rto_sample: NULL pointer or S < 1");
-    if (!prm->eta || !prm->xi) return fail(PAT_ERR_INVALID_ARG, "rto_sample: eta and xi are required");
+    if ((prm->eta == nullptr) != (prm->xi == nullptr))
+        return fail(PAT_ERR_INVALID_ARG, "rto_sample: pass both eta and xi, or neither (device draws)");
+    if (prm->sample0 < 0) return fail(PAT_ERR_INVALID_ARG, "rto_sample: sample0 must be >= 0");
     if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return fail(PAT_ERR_INVALID_ARG, "sigma must be > 0");
     if (!(prm->prior_a >= 0.0) || !std::isfinite(prm->prior_a)) return fail(PAT_ERR_INVALID_ARG, "prior_a must be >= 0");
     if (prm->n_iter < 1) return fail(PAT_ERR_INVALID_ARG, "n_iter must be >= 1");
@@ -677,8 +679,13 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
 
     for (int64_t rb0 = 0; rb0 < S; rb0 += RB) {
         // right-hand side b = (y_obs/sigma + eta, xi) in (rd, rp)
-        pat::launch_build_rhs(y_obs, prm->eta, S, rb0, RB, M, isig, c->rd, s);
-        pat::launch_pack(true, true, prm->xi, S, rb0, RB, N, perm, c->rp, s);
+        if (prm->eta) {
+            pat::launch_build_rhs(y_obs, prm->eta, S, rb0, RB, M, isig, c->rd, s);
+            pat::launch_pack(true, true, prm->xi, S, rb0, RB, N, perm, c->rp, s);
+        } else {
+            pat::launch_build_rhs_rng(y_obs, prm->seed, prm->sample0, S, rb0, RB, M, isig, c->rd, s);
+            pat::launch_xi_rng(prm->seed, prm->sample0, S, rb0, RB, N, perm, c->rp, s);
+        }
         pat::launch_fill(c->x, N * RB, 0.0, s);
         const double *chk = nullptr;
         if (lsqr) {
@@ -707,6 +714,18 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
         if (!std::isfinite(chk_host[size_t(k)]))
             return fail(PAT_ERR_NONFINITE, std::string("non-finite ") + (lsqr ? "LSQR" : "CGLS") +
                                                " scalar for sample " + std::to_string(k));
+    return PAT_OK;
+}
+
+pat_status pat_draw_normals(uint64_t seed, int32_t kind, int64_t k0, int64_t S, int64_t len, double *out,
+                            void *stream) {
+    g_err.clear();
+    if (kind != 0 && kind != 1) return fail(PAT_ERR_INVALID_ARG, "pat_draw_normals: kind must be 0 or 1");
+    if (S < 0 || len < 0 || k0 < 0) return fail(PAT_ERR_INVALID_ARG, "pat_draw_normals: negative size or offset");
+    if (S == 0 || len == 0) return PAT_OK;
+    if (!out) return fail(PAT_ERR_INVALID_ARG, "pat_draw_normals: NULL output");
+    pat::launch_normals(seed, kind, k0, S, len, out, static_cast<hipStream_t>(stream));
+    PAT_HIP(hipGetLastError());
     return PAT_OK;
 }
 

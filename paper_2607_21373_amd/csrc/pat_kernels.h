@@ -55,6 +55,15 @@ void launch_fill(double *x, int64_t count, double v, hipStream_t s);
 void launch_cast_to_state(Prec prec, const double *x, void *P, int64_t count, hipStream_t s);
 void launch_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0, int RB, int64_t M, double isig,
                       double *bd, hipStream_t s);
+// Counter-based standard normals (Philox4x64-10 + Box-Muller): normal j of stream
+// (seed, kind, k); kind 0 = eta (j = t*N_obs + s), kind 1 = xi (j = caller node id).
+void launch_normals(uint64_t seed, int kind, int64_t k0, int64_t S, int64_t len, double *out, hipStream_t s);
+// as launch_build_rhs with eta_{k0+rb0+r} drawn on the fly
+void launch_build_rhs_rng(const double *yobs, uint64_t seed, int64_t k0, int64_t S, int64_t rb0, int RB, int64_t M,
+                          double isig, double *bd, hipStream_t s);
+// xi [N][RB] (internal order) drawn for samples k0+rb0+r, zero past S
+void launch_xi_rng(uint64_t seed, int64_t k0, int64_t S, int64_t rb0, int RB, int64_t N, const int32_t *perm,
+                   double *xi, hipStream_t s);
 void launch_prior(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s);
 // y = L^T x = M_L^{1/2} x + a K1 (M_L^{-1/2} x)
 void launch_prior_t(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s);

@@ -595,6 +595,91 @@ __global__ void __launch_bounds__(256) k_unpack(const TI *in, int64_t R, int64_t
     }
 }
 
+// ---- counter-based standard normals -------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11) and the Box-Muller transform.  Normal j
+// of stream (seed, kind, k) is lane j%4 of the cipher block with counter
+// (j/4, k, kind, 0) and key (seed, 0); lanes (0,1) and (2,3) are Box-Muller
+// pairs with u1 = 1 - U(w_even) in (0, 1], u2 = U(w_odd), U(w) = (w >> 11) 2^-53.
+struct Normals4 {
+    double z[4];
+};
+
+__device__ inline Normals4 philox_normals(uint64_t seed, uint64_t kind, uint64_t k, uint64_t blk) {
+    uint64_t c0 = blk, c1 = k, c2 = kind, c3 = 0, k0 = seed, k1 = 0;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B97F4A7C15ULL;
+            k1 += 0xBB67AE8584CAA73BULL;
+        }
+        const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ULL, c0), lo0 = 0xD2E7470EE14C6C93ULL * c0;
+        const uint64_t hi1 = __umul64hi(0xCA5A826395121157ULL, c2), lo1 = 0xCA5A826395121157ULL * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    Normals4 o;
+    const uint64_t w[4] = {c0, c1, c2, c3};
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+        const double u1 = 1.0 - double(w[2 * pr] >> 11) * 0x1p-53;
+        const double u2 = double(w[2 * pr + 1] >> 11) * 0x1p-53;
+        const double rad = sqrt(-2.0 * log(u1));
+        const double ang = 6.283185307179586476925286766559 * u2;
+        o.z[2 * pr] = rad * cos(ang);
+        o.z[2 * pr + 1] = rad * sin(ang);
+    }
+    return o;
+}
+
+// out[s*len + j] = normal j of stream (seed, kind, k0 + s)
+__global__ void __launch_bounds__(256) k_normals(uint64_t seed, int kind, int64_t k0, int64_t S, int64_t len,
+                                                 double *out) {
+    const int64_t nblk = (len + 3) / 4, total = S * nblk;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t sm = e / nblk, b = e % nblk;
+        const Normals4 z = philox_normals(seed, uint64_t(kind), uint64_t(k0 + sm), uint64_t(b));
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+            if (4 * b + l < len) out[sm * len + 4 * b + l] = z.z[l];
+    }
+}
+
+// bd[m][r] = yobs[m] * isig + eta_{k0+rb0+r}[m] drawn on the fly (zero rows past S)
+__global__ void __launch_bounds__(256) k_build_rhs_rng(const double *yobs, uint64_t seed, int64_t k0, int64_t S,
+                                                       int64_t rb0, int RB, int64_t M, double isig, double *bd) {
+    const int64_t nblk = (M + 3) / 4, total = nblk * RB;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t b = e / RB;
+        const int r = int(e % RB);
+        const bool live = rb0 + r < S;
+        Normals4 z{};
+        if (live) z = philox_normals(seed, 0, uint64_t(k0 + rb0 + r), uint64_t(b));
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int64_t m = 4 * b + l;
+            if (m < M) bd[m * RB + r] = live ? yobs[m] * isig + z.z[l] : 0.0;
+        }
+    }
+}
+
+// xi[q][r] = normal perm(q) of stream (seed, 1, k0+rb0+r), internal node order (zero rows past S)
+__global__ void __launch_bounds__(256) k_xi_rng(uint64_t seed, int64_t k0, int64_t S, int64_t rb0, int RB, int64_t N,
+                                                const int32_t *perm, double *xi) {
+    const int64_t total = N * RB;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t q = e / RB;
+        const int r = int(e % RB);
+        double v = 0.0;
+        if (rb0 + r < S) {
+            const int64_t j = perm ? perm[q] : q;
+            v = philox_normals(seed, 1, uint64_t(k0 + rb0 + r), uint64_t(j / 4)).z[j % 4];
+        }
+        xi[e] = v;
+    }
+}
+
 // bd[m][r] = yobs[m] * isig + eta[rb0 + r][m]  (zero rows past S)
 __global__ void __launch_bounds__(256) k_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0,
                                                    int RB, int64_t M, double isig, double *bd) {
@@ -1119,6 +1204,18 @@ void launch_cast_to_state(Prec prec, const double *x, void *P, int64_t count, hi
         hipLaunchKernelGGL((k_cast<float>), dim3(grid_for(count)), dim3(256), 0, s, x, (float *)P, count);
 }
 
+void launch_normals(uint64_t seed, int kind, int64_t k0, int64_t S, int64_t len, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_normals, dim3(grid_for(S * ((len + 3) / 4))), dim3(256), 0, s, seed, kind, k0, S, len, out);
+}
+void launch_build_rhs_rng(const double *yobs, uint64_t seed, int64_t k0, int64_t S, int64_t rb0, int RB, int64_t M,
+                          double isig, double *bd, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_rhs_rng, dim3(grid_for(((M + 3) / 4) * RB)), dim3(256), 0, s, yobs, seed, k0, S, rb0, RB,
+                       M, isig, bd);
+}
+void launch_xi_rng(uint64_t seed, int64_t k0, int64_t S, int64_t rb0, int RB, int64_t N, const int32_t *perm,
+                   double *xi, hipStream_t s) {
+    hipLaunchKernelGGL(k_xi_rng, dim3(grid_for(N * RB)), dim3(256), 0, s, seed, k0, S, rb0, RB, N, perm, xi);
+}
 void launch_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0, int RB, int64_t M, double isig,
                       double *bd, hipStream_t s) {
     hipLaunchKernelGGL(k_build_rhs, dim3(unsigned((M + 63) / 64)), dim3(256), 0, s, yobs, eta, S, rb0, RB, M, isig, bd);

@@ -63,6 +63,7 @@ class RtoParams(ctypes.Structure):
         ("sigma", ctypes.c_double), ("prior_a", ctypes.c_double), ("n_iter", ctypes.c_int32),
         ("reorth", ctypes.c_int32), ("sweep_prec", ctypes.c_int), ("rhs_block", ctypes.c_int32),
         ("eta", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("solver", ctypes.c_int32), ("diag_hist", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64), ("sample0", ctypes.c_int64),
     ]
 
 
@@ -71,8 +72,8 @@ PAT_CGLS, PAT_LSQR = 0, 1
 
 # names exported by libpat (the C ABI in include/pat.h)
 EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-           "rto_sample", "pat_prior_apply", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync",
-           "pat_last_error", "pat_version")
+           "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_host_assemble", "pat_profile_enable",
+           "pat_profile_get", "pat_sync", "pat_last_error", "pat_version")
 
 _lib = None
 
@@ -97,11 +98,13 @@ def load() -> ctypes.CDLL:
     lib.pat_host_assemble.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ctypes.c_int64)] + [vp] * 9
     lib.pat_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.pat_prior_apply.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, vp, vp, vp]
+    lib.pat_draw_normals.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                     vp, vp]
     lib.pat_profile_get.argtypes = [vp, ctypes.POINTER(Profile)]
     lib.pat_last_error.restype = ctypes.c_char_p
     lib.pat_version.restype = ctypes.c_char_p
     for f in ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-              "rto_sample", "pat_prior_apply", "pat_host_assemble", "pat_profile_enable", "pat_profile_get",
+              "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_host_assemble", "pat_profile_enable", "pat_profile_get",
               "pat_sync"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -282,18 +285,29 @@ def pat_prior_apply(problem: Problem, x, prior_a: float, transpose: bool = False
 
 def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n_iter: int, reorth: bool = True,
                sweep_prec: str = "f64", rhs_block: int = 0, stats: bool = True, resid: bool = False,
-               samples=None, solver: str = "cgls", diag: bool = False):
+               samples=None, solver: str = "cgls", diag: bool = False, n_samples: int = None, seed: int = 0,
+               sample0: int = 0):
     """RTO posterior samples (Algorithm 1) through libpat's rto_sample.
 
     y_obs [N_T][N_obs], eta [S][N_T][N_obs], xi [S][N]: float64 CUDA tensors.
+    With eta = xi = None the library draws them itself (streams seed,
+    sample0 + k; see draw_normals) and n_samples gives S.
     solver: "cgls" or "lsqr" (Sec. 5.2, App. A).
     Returns a dict with samples [S][N] and, if requested, mean, std [N],
     resid [S][n_iter+1] and diag [S][n_iter+1][2] (data and prior residual norms)."""
     import torch
     f64 = torch.float64
-    S = xi.shape[0]
+    if (eta is None) != (xi is None):
+        raise ValueError("pass both eta and xi, or neither")
+    if xi is not None:
+        S = xi.shape[0]
+        dev = xi.device
+    else:
+        if n_samples is None:
+            raise ValueError("n_samples is required when the library draws eta and xi")
+        S = int(n_samples)
+        dev = y_obs.device
     N, T, O = problem.n_nodes, problem.n_steps, problem.n_obs
-    dev = xi.device
     if samples is None:
         samples = torch.empty((S, N), dtype=f64, device=dev)
     mean = torch.empty(N, dtype=f64, device=dev) if stats else None
@@ -309,8 +323,11 @@ def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n
     prm.reorth = int(bool(reorth))
     prm.sweep_prec = {"f64": PAT_F64, "f32": PAT_F32}[sweep_prec]
     prm.rhs_block = int(rhs_block)
-    prm.eta = _dev_ptr(eta, f64, (S, T, O), "eta")
-    prm.xi = _dev_ptr(xi, f64, (S, N), "xi")
+    prm.seed = int(seed)
+    prm.sample0 = int(sample0)
+    if eta is not None:
+        prm.eta = _dev_ptr(eta, f64, (S, T, O), "eta")
+        prm.xi = _dev_ptr(xi, f64, (S, N), "xi")
     yp = _dev_ptr(y_obs, f64, (T, O), "y_obs")
     sp = _dev_ptr(samples, f64, (S, N), "samples")
     mp = ctypes.c_void_p(mean.data_ptr()) if mean is not None else None
@@ -318,6 +335,39 @@ def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n
     rp = ctypes.c_void_p(res.data_ptr()) if res is not None else None
     _check(load().rto_sample(problem._h, yp, ctypes.byref(prm), S, sp, mp, dp, rp, _stream()))
     return {"samples": samples, "mean": mean, "std": std, "resid": res, "diag": dg}
+
+
+def solver_diagnostics(diag, n_data: int, tau: float = 1.0):
+    """Per-iteration convergence diagnostics of Sec. 6.1 from a diag history.
+
+    diag [S][n_iter+1][2] holds (||r_d||, ||r_p||) with r_d = b_d - G p / sigma (whitened
+    data residual) and r_p = b_p - L p.  Returns a dict of [S][n_iter+1] arrays:
+      data      ||r_d|| / sqrt(n_data)   (1 at the discrepancy level sigma sqrt(N_T N_obs))
+      prior     ||r_p|| / ||b||
+      extended  ||r|| / ||b||            (residual of the extended system)
+    and "discrepancy" [S]: the first iteration with ||r_d|| <= tau sqrt(n_data), or -1
+    (the discrepancy principle, Sec. 6.1).  Accepts a torch tensor or a numpy array."""
+    import numpy as np
+    d = diag.detach().cpu().numpy() if hasattr(diag, "detach") else np.asarray(diag, dtype=np.float64)
+    if d.ndim != 3 or d.shape[2] != 2:
+        raise ValueError("diag must have shape [S][n_iter+1][2]")
+    nd, npr = d[..., 0], d[..., 1]
+    ext = np.hypot(nd, npr)
+    b = ext[:, :1]
+    b = np.where(b > 0, b, 1.0)
+    hit = nd <= tau * np.sqrt(n_data)
+    first = np.where(hit.any(axis=1), hit.argmax(axis=1), -1)
+    return {"data": nd / np.sqrt(n_data), "prior": npr / b, "extended": ext / b, "discrepancy": first}
+
+
+def draw_normals(seed: int, kind: int, k0: int, S: int, length: int, device="cuda"):
+    """[S][length] float64 standard normals of streams (seed, kind, k0 + s), drawn on the GPU
+    (Philox4x64-10 + Box-Muller); kind 0 = eta (j = t*N_obs + sensor), kind 1 = xi (j = node)."""
+    import torch
+    out = torch.empty((S, length), dtype=torch.float64, device=device)
+    _check(load().pat_draw_normals(int(seed), int(kind), int(k0), int(S), int(length),
+                                   ctypes.c_void_p(out.data_ptr()) if out.numel() else None, _stream()))
+    return out
 
 
 def version() -> str:

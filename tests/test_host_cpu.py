@@ -167,3 +167,25 @@ def test_binding_structs_match_header(tmp_path):
         py = structs[cname]
         got = ctypes.sizeof(py) if field == "sizeof" else getattr(py, field).offset
         assert got == int(val), (cname, field, got, val)
+
+
+def test_solver_diagnostics_on_oracle_histories():
+    """Discrepancy principle on the whitened data residual of the MAP solve (eta = xi = 0)."""
+    w = W.make_workload("cube8_tiny")
+    O = oracle.Problem.from_workload(w)
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    M = w.n_steps * w.n_obs
+    zeros_d = np.zeros((1, w.n_steps, w.n_obs))
+    x, res, dg = O.lsqr(yobs[None] / sigma + zeros_d, np.zeros((1, w.n_nodes)), sigma, w.prior_a, 30, diag=True)
+    out = pat.solver_diagnostics(dg, M)
+    np.testing.assert_allclose(out["extended"][0], res[0] / res[0, 0], rtol=1e-14)
+    assert out["extended"][0, 0] == 1.0 and out["prior"][0, 0] == 0.0
+    # the LSQR residual of the extended system is non-increasing
+    assert np.all(np.diff(res[0]) <= 1e-12 * res[0, 0])
+    k = int(out["discrepancy"][0])
+    assert k >= 1 and out["data"][0, k] <= 1.0 and np.all(out["data"][0, :k] > 1.0)
+    # tau large enough: satisfied at iteration 0; tau tiny: never
+    assert pat.solver_diagnostics(dg, M, tau=1e9)["discrepancy"][0] == 0
+    assert pat.solver_diagnostics(dg, M, tau=1e-9)["discrepancy"][0] == -1
+    with pytest.raises(ValueError):
+        pat.solver_diagnostics(dg[..., 0], M)
