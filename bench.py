@@ -93,6 +93,90 @@ def cpu_baseline(w, eta, xi, yobs, sigma, n_iter, R, n_steps_sample=50, iters_sa
     }
 
 
+def _synth(pat, W, w, G, dev):
+    """Noisy data from the library's float64 forward map (the paper's relative-L2 noise rule)."""
+    import torch
+    p0 = torch.as_tensor(w.p0_true, dtype=torch.float64, device=dev)[None].contiguous()
+    Y = pat.pat_forward(G, p0)[0]
+    eta0 = torch.as_tensor(W.noise_draw(w.n_steps, w.n_obs, w.noise_seed), device=dev)
+    sigma = float(w.d_noise * torch.linalg.norm(Y) / torch.linalg.norm(eta0))
+    return (Y + sigma * eta0).contiguous(), sigma
+
+
+def uneven_leg(pat, W, dev, n_iter):
+    """Three meshes of different sizes sampled together (one merged launch per time step),
+    16 samples each with device-drawn perturbations, against the same three solves run
+    one after another with the same RHS block."""
+    import torch
+    names = ("cube40", "ball60", "slab120")
+    ws = [W.make_workload(n) for n in names]
+    t0 = time.time()
+    probs = [pat.Problem.from_workload(w) for w in ws]
+    log(f"uneven batch: {', '.join(f'{w.name} N={w.n_nodes}' for w in ws)} set up in {time.time() - t0:.1f} s")
+    data = [_synth(pat, W, w, G, dev) for w, G in zip(ws, probs)]
+    B = pat.Batch(probs)
+    S = 16
+    rb, us = B.autotune(S, "f32")
+    log(f"uneven batch: autotuned RHS block {rb} (priced {us:.1f} us per merged forward+transpose step)")
+
+    def batched():
+        return pat.rto_sample_batch(B, [d[0] for d in data], None, None, [d[1] for d in data],
+                                    [w.prior_a for w in ws], n_iter, sweep_prec="f32", n_samples=S, seed=17)
+
+    def serial():
+        return [pat.rto_sample(G, d[0], None, None, d[1], w.prior_a, n_iter, sweep_prec="f32", rhs_block=rb,
+                               n_samples=S, seed=17) for w, G, d in zip(ws, probs, data)]
+
+    batched()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    outs = batched()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    serial()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ref = serial()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    same = all(torch.equal(a["samples"], b["samples"]) for a, b in zip(outs, ref))
+    res = {"meshes": {w.name: w.n_nodes for w in ws}, "samples": S * len(ws), "iters": n_iter, "rhs_block": rb,
+           "seconds": round(tb, 3), "value": round(S * len(ws) / tb * 60.0, 3), "unit": "samples/min",
+           "serial_seconds": round(ts, 3), "speedup_vs_serial": round(ts / tb, 3), "equal_to_serial": same}
+    log(f"uneven batch: {tb:.2f} s for {S * len(ws)} samples ({res['value']:.1f} samples/min); one mesh after "
+        f"another {ts:.2f} s; results identical: {same}")
+    return res
+
+
+def big_leg(pat, W, dev, n_iter):
+    """One sample on the 10^6-node ball: float32 sweeps and the plain float64 path."""
+    import torch
+    w = W.make_workload("ball100")
+    t0 = time.time()
+    G = pat.Problem.from_workload(w)
+    info = G.info()
+    log(f"ball100: N={w.n_nodes} nnz={info['nnz_k']} set up in {time.time() - t0:.1f} s")
+    yobs, sigma = _synth(pat, W, w, G, dev)
+    res = {"n_nodes": w.n_nodes, "n_steps": w.n_steps, "iters": n_iter}
+    for prec in ("f32", "f64"):
+        G.profile_enable(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pat.rto_sample(G, yobs, None, None, sigma, w.prior_a, n_iter, sweep_prec=prec, rhs_block=1, n_samples=1,
+                       seed=1, stats=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        prof = G.profile()
+        G.profile_enable(False)
+        tsz = 4 if prec == "f32" else 8
+        fwd_s = prof["fwd_ms"] / max(prof["fwd_sweeps"], 1) / w.n_steps / 1e3
+        gbs = step_bytes(info, 1, tsz, "fwd") / fwd_s / 1e9
+        res[prec] = {"seconds_per_sample": round(el, 3), "samples_per_min": round(60.0 / el, 3),
+                     "fwd_step_us": round(fwd_s * 1e6, 3), "fwd_step_GBs": round(gbs, 1)}
+        log(f"ball100 {prec}: {el:.2f} s per sample; forward step {fwd_s * 1e6:.1f} us ({gbs:.0f} GB/s)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +188,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy a float32 buffer of this many MB three times (counter calibration)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
+    ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (samples are independent, so "
@@ -218,6 +304,11 @@ def main():
         result["plain_fp64"] = {"value": round(plain, 3), "unit": "samples/min", "rhs_block": 1,
                                 "seconds_per_sample": round(tp, 3), "speedup_batched_f32": round(value / plain, 2)}
         log(f"plain f64 (1 sample, R=1): {tp:.2f} s -> {plain:.2f} samples/min; speed-up {value / plain:.1f}x")
+
+    if not args.no_uneven:
+        result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter)
+    if args.big:
+        result["ball100_single_sample"] = big_leg(pat, W, dev, n_iter)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -112,6 +112,13 @@ typedef enum {
     PAT_LSQR = 1  /* Paige-Saunders Golub-Kahan bidiagonalisation; reorth acts on the right vectors v_j */
 } pat_solver;
 
+/* Prior of the RTO sampler. */
+typedef enum {
+    PAT_PRIOR_FE = 0,       /* the FE prior factor L = M_L^{-1/2}(M_L + a K1) (prior_a) on the nodal values */
+    PAT_PRIOR_SPECTRAL = 1  /* the Whittle-Matern spectral prior set with pat_spectral_prior_set; the solve runs
+                               in its latent space (Sec. 6.4) */
+} pat_prior_kind;
+
 /* Parameters of the RTO sampler (Sec. 5 eq. (optimization), Algorithm 1). */
 typedef struct {
     double sigma;              /* noise standard deviation (> 0) */
@@ -119,7 +126,9 @@ typedef struct {
     int32_t n_iter;            /* solver iterations (fixed; >= 1) */
     int32_t reorth;            /* 1: full reorthogonalisation (default); see pat_solver */
     pat_precision sweep_prec;  /* precision of the wave sweeps; solver vectors and scalars are always float64 */
-    int32_t rhs_block;         /* samples per multi-RHS block: 0 = automatic, else 1, 2, 4, ..., 64 */
+    int32_t rhs_block;         /* samples per multi-RHS block: 1, 2, 4, ..., 64, or 0 = the autotuned block for
+                                  (S, sweep_prec) if pat_autotune / pat_batch_autotune ran, else the
+                                  smallest power of two >= S (at most 64) */
     const double *eta;         /* device [S][N_T][N_obs] standard-normal data perturbations, or NULL */
     const double *xi;          /* device [S][N] standard-normal prior perturbations, or NULL (both or neither) */
     int32_t solver;            /* pat_solver; 0 (CGLS) when the struct is zero-initialised */
@@ -127,6 +136,11 @@ typedef struct {
                                   (||y_obs/sigma + eta - G p/sigma||, ||xi - L p||) of the residual */
     uint64_t seed;             /* eta == xi == NULL: the sampler draws them itself, see pat_draw_normals */
     int64_t sample0;           /* stream index of the first sample (disjoint ranges give independent samples) */
+    int32_t prior;             /* pat_prior_kind; 0 (FE) when the struct is zero-initialised.  With
+                                  PAT_PRIOR_SPECTRAL, xi is device [S][n^3] (latent white noise, grid order),
+                                  prior_a is ignored, the unknown of each solve is the latent vector w and the
+                                  samples are p0 = P w */
+    double *latent;            /* PAT_PRIOR_SPECTRAL: device [S][n^3] latent samples w, or NULL */
 } pat_rto_params;
 
 /* S posterior samples by RTO.  Sample k solves
@@ -141,6 +155,68 @@ typedef struct {
  * Scratch memory is owned by the handle and grows to the largest block seen. */
 pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params *prm, int64_t S,
                       double *samples, double *mean, double *std, double *resid_hist, void *stream);
+
+/* Whittle-Matern prior of Sec. 4.1 eq. (matern-cov-op), built as in Sec. 6.4: a
+ * latent white-noise vector w on a periodic grid of n^3 points over the cube
+ * [lo, lo + side)^3 (index (k*n + j)*n + i for the point lo + h (i, j, k), h = side/n)
+ * gives the field u = F^* diag(a) F w, F the unitary 3D DFT and
+ * a(k) = c (ell^-2 + |k|^2)^(-expo/2), expo = nu + d/2 (3 for the paper's s = 1.5),
+ * c chosen so that the pointwise variance of u is sigma^2.  Trilinear
+ * interpolation I_h to the mesh nodes gives p0 = P w, P = I_h F^* diag(a) F. */
+typedef struct {
+    int32_t n;       /* grid points per axis: a power of two in [8, 128] */
+    double lo[3];    /* box corner */
+    double side;     /* box side; every mesh node must satisfy lo <= x < lo + side */
+    double ell;      /* correlation length */
+    double sigma;    /* marginal standard deviation */
+    double expo;     /* covariance exponent nu + d/2 */
+} pat_spectral_desc;
+
+/* Set (or, with d == NULL, clear) the handle's spectral prior; replaces any earlier one
+ * and frees the latent-space workspaces.  Synchronises the device. */
+pat_status pat_spectral_prior_set(pat_problem *p, const pat_spectral_desc *d);
+
+/* transpose = 0: y = P x, x device [R][n^3] -> y device [R][N];
+ * transpose = 1: y = P^T x, x device [R][N] -> y device [R][n^3].  float64. */
+pat_status pat_spectral_apply(pat_problem *p, int64_t R, int transpose, const double *x, double *y, void *stream);
+
+/* Autotuner of the RHS block.  For each candidate block RB (powers of two from
+ * 1/16 of the smallest block holding S up to it) it times 8 forward and 8
+ * transpose steps with HIP events after a warm-up, prices S samples as
+ * ceil(S/RB) * (forward + transpose step) and records the cheapest RB for
+ * (S, prec) in the handle, where rto_sample's rhs_block = 0 finds it.
+ *   rhs_block  host int32 or NULL: the chosen block
+ *   step_us    host double or NULL: its priced cost of one forward plus one
+ *              transpose step for all S samples, in microseconds
+ * Synchronises `stream`; overwrites the handle's sweep workspaces. */
+pat_status pat_autotune(pat_problem *p, int64_t S, pat_precision prec, int32_t *rhs_block, double *step_us,
+                        void *stream);
+
+/* Several problems sampled together ("uneven batch"): their forward and transpose
+ * sweeps run as one launch per time step over the row tiles of all meshes (a
+ * workgroup finds its mesh from the running tile counts), while each keeps its own
+ * solver state.  Needs the same device and the same number of time steps; at
+ * most 4 problems, each at most once.  The problems must outlive the batch.  One
+ * launch per step covers all meshes when RB * sizeof(sweep type) >= 16 bytes;
+ * smaller blocks launch per mesh within the same step. */
+typedef struct pat_batch pat_batch;
+pat_status pat_batch_create(pat_problem *const *problems, int32_t n, pat_batch **out);
+pat_status pat_batch_destroy(pat_batch *b);
+
+/* pat_autotune for the batch's merged steps (S = the largest per-problem sample count). */
+pat_status pat_batch_autotune(pat_batch *b, int64_t S, pat_precision prec, int32_t *rhs_block, double *step_us,
+                              void *stream);
+
+/* rto_sample for every problem m of the batch at once: arrays of n entries
+ * (n = problems in the batch).  prm[m] gives problem m's sigma, prior_a,
+ * perturbations (eta, xi or seed, sample0) and diag_hist; n_iter, reorth,
+ * sweep_prec, rhs_block and solver must agree across m.  All problems use one RHS
+ * block; with unequal S the smaller ones run zero right-hand sides in the later
+ * blocks.  mean, std, resid_hist: arrays or NULL, entries may be NULL.  Results
+ * equal rto_sample on each problem alone. */
+pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_rto_params *prm, const int64_t *S,
+                            double *const *samples, double *const *mean, double *const *std,
+                            double *const *resid_hist, void *stream);
 
 /* Standard normals of the sampler's own perturbations (Algorithm 1 draws eta_k and
  * xi_k): out[s][j] = normal j of stream (seed, kind, k0 + s), s < S, j < len,

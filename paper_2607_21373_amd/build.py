@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpat.so")
-SOURCES = ["pat_setup.cpp", "pat_kernels.hip", "pat_api.hip"]
+SOURCES = ["pat_setup.cpp", "pat_kernels.hip", "pat_spectral.hip", "pat_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")

@@ -83,6 +83,12 @@ struct SweepWS {
     const void *g_fwd_cgls_out = nullptr, *g_adj_cgls_in = nullptr;
 };
 
+// Work buffers of the spectral prior for one RHS block.
+struct SpecWS {
+    double *gr = nullptr, *gc = nullptr;  // real and complex grid vectors [G][RB]
+    double *ym = nullptr, *lx = nullptr;  // mesh [N][RB] and latent [G][RB] staging (float64)
+};
+
 struct CglsWS {
     int RB = 0;
     int cap_iter = -1;
@@ -100,13 +106,34 @@ struct pat_problem {
     bool perm_identity = true;
     std::vector<void *> allocs;
     std::map<std::pair<int, int>, SweepWS> sweeps;
-    std::map<int, CglsWS> cgls;
+    std::map<std::pair<int, int64_t>, CglsWS> cgls;  // by (RB, unknowns per RHS)
     hipStream_t cap = nullptr;
     int64_t bytes = 0;
     // sweep timing
     bool prof = false;
     pat_profile prof_acc{};
     std::vector<hipEvent_t> events;
+    // autotuned RHS block per (sample count, sweep precision)
+    std::map<std::pair<int64_t, int>, int> tuned;
+    // node coordinates in internal order [N][3] (for the spectral prior's interpolation)
+    std::vector<double> xyz;
+    // Whittle-Matern spectral prior (pat_spectral_prior_set)
+    bool spec = false;
+    pat_spectral_desc spec_desc{};
+    pat::SpecOps sops;
+    std::vector<void *> spec_allocs;
+    std::map<int, SpecWS> specws;
+};
+
+// Several problems whose sweeps share launches (rto_sample_batch).
+struct pat_batch {
+    int device = 0;
+    std::vector<pat_problem *> probs;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t g_fwd = nullptr, g_adj = nullptr;
+    std::vector<const void *> key_fwd, key_adj;
+    std::vector<double> key_scale;
+    std::map<std::pair<int64_t, int>, int> tuned;
 };
 
 namespace {
@@ -165,21 +192,26 @@ pat_status get_sweep(pat_problem *p, pat::Prec prec, int RB, bool need_y, SweepW
     return PAT_OK;
 }
 
-// Capture the N_T launches of one sweep on the handle's capture stream.
+// Capture the launches of one sweep on a capture stream.
 template <class F>
-pat_status capture(pat_problem *p, hipGraphExec_t *exec, F &&body) {
+pat_status capture_on(hipStream_t cap, hipGraphExec_t *exec, F &&body) {
     if (*exec) {
         (void)hipGraphExecDestroy(*exec);
         *exec = nullptr;
     }
-    PAT_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-    body(p->cap);
+    PAT_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    body(cap);
     hipGraph_t g = nullptr;
-    PAT_HIP(hipStreamEndCapture(p->cap, &g));
+    PAT_HIP(hipStreamEndCapture(cap, &g));
     hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(PAT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     return PAT_OK;
+}
+
+template <class F>
+pat_status capture(pat_problem *p, hipGraphExec_t *exec, F &&body) {
+    return capture_on(p->cap, exec, std::forward<F>(body));
 }
 
 // Forward sweep: input state in w.P[0]; y^n (n = 1..N_T) written to y_out [N_T][N_obs][RB].
@@ -234,9 +266,12 @@ pat_status check_prec(pat_precision prec, pat::Prec *out) {
     return PAT_OK;
 }
 
-pat_status get_cgls(pat_problem *p, int RB, int n_iter, bool reorth, bool lsqr, bool track, CglsWS **out) {
-    CglsWS &c = p->cgls[RB];
-    const int64_t N = p->ops.n, M = int64_t(p->ops.n_steps) * p->ops.n_obs;
+// Solver workspace for RB right-hand sides with NX unknowns each (N, or n^3 in the
+// latent space of the spectral prior).
+pat_status get_cgls(pat_problem *p, int RB, int64_t NX, int n_iter, bool reorth, bool lsqr, bool track,
+                    CglsWS **out) {
+    CglsWS &c = p->cgls[{RB, NX}];
+    const int64_t N = NX, M = int64_t(p->ops.n_steps) * p->ops.n_obs;
     if (c.RB == 0) {
         c.RB = RB;
         void *v;
@@ -278,173 +313,475 @@ pat_status get_cgls(pat_problem *p, int RB, int n_iter, bool reorth, bool lsqr, 
 }
 
 
-// State shared by the per-block solvers of rto_sample.
+pat_status get_spec(pat_problem *p, int RB, SpecWS **out) {
+    SpecWS &w = p->specws[RB];
+    if (!w.gr) {
+        const size_t G = size_t(p->sops.G), N = size_t(p->ops.n);
+        void *v;
+        PAT_TRY(dev_alloc(p, &v, G * RB * 8)); w.gr = static_cast<double *>(v);
+        PAT_TRY(dev_alloc(p, &v, G * RB * 16)); w.gc = static_cast<double *>(v);
+        PAT_TRY(dev_alloc(p, &v, N * RB * 8)); w.ym = static_cast<double *>(v);
+        PAT_TRY(dev_alloc(p, &v, G * RB * 8)); w.lx = static_cast<double *>(v);
+    }
+    *out = &w;
+    return PAT_OK;
+}
+
+int auto_rb(const std::map<std::pair<int64_t, int>, int> &tuned, int64_t S, pat::Prec pr) {
+    auto it = tuned.find({S, int(pr)});
+    return it != tuned.end() ? it->second : choose_rb(S);
+}
+
+// ---- several meshes per sweep launch ------------------------------------
+
+// One launch per time step for all meshes (vector-lane RHS blocks), else one per mesh.
+void fwd_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::FwdStep> &st, hipStream_t s) {
+    if (pat::multi_step_supported(prec, RB)) {
+        pat::launch_fwd_multi(prec, RB, y_f64, st.data(), int(st.size()), s);
+        return;
+    }
+    for (const pat::FwdStep &f : st)
+        pat::launch_fwd_step(prec, RB, *f.op, f.P, f.V, f.Pn, f.Vn, f.rows, f.first, f.sample, f.t, f.y, y_f64,
+                             f.yscale, s);
+}
+
+void adj_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::AdjStep> &st, hipStream_t s) {
+    if (pat::multi_step_supported(prec, RB)) {
+        pat::launch_adj_multi(prec, RB, y_f64, st.data(), int(st.size()), s);
+        return;
+    }
+    for (const pat::AdjStep &a : st)
+        pat::launch_adj_step(prec, RB, *a.op, a.PH, a.Q, a.Qn, a.last, a.tm1, a.yh, y_f64, a.yscale, s);
+}
+
+// enqueue_forward for several meshes with equal N_T: the same launches, merged per step.
+void enqueue_forward_multi(const std::vector<pat_problem *> &P, const std::vector<SweepWS *> &W,
+                           const std::vector<void *> &yout, bool y_f64, const std::vector<double> &scale,
+                           hipStream_t s) {
+    const size_t n = P.size();
+    const int NT = P[0]->ops.n_steps;
+    const pat::Prec prec = W[0]->prec;
+    const int RB = W[0]->RB;
+    std::vector<pat::FwdStep> st(n);
+    for (size_t m = 0; m < n; ++m)
+        st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->P[1], W[m]->V[1], true, true, false, 0,
+                             yout[m], scale[m]};
+    fwd_steps(prec, RB, y_f64, st, s);
+    int cur = 1;
+    for (int t = 2; t <= NT; ++t) {
+        for (size_t m = 0; m < n; ++m)
+            st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[cur], W[m]->V[cur], W[m]->P[1 - cur], W[m]->V[1 - cur], true,
+                                 false, true, t - 2, yout[m], scale[m]};
+        fwd_steps(prec, RB, y_f64, st, s);
+        cur = 1 - cur;
+    }
+    for (size_t m = 0; m < n; ++m)
+        st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[cur], W[m]->V[cur], nullptr, nullptr, false, false, true, NT - 1,
+                             yout[m], scale[m]};
+    fwd_steps(prec, RB, y_f64, st, s);
+}
+
+// enqueue_adjoint for several meshes with equal N_T.
+void enqueue_adjoint_multi(const std::vector<pat_problem *> &P, const std::vector<SweepWS *> &W,
+                           const std::vector<const void *> &yin, bool y_f64, hipStream_t s) {
+    const size_t n = P.size();
+    const int NT = P[0]->ops.n_steps;
+    const pat::Prec prec = W[0]->prec;
+    const int RB = W[0]->RB;
+    for (size_t m = 0; m < n; ++m) pat::launch_adj_init(prec, RB, P[m]->ops, W[m]->P[0], W[m]->V[0], yin[m], y_f64, 1.0, s);
+    std::vector<pat::AdjStep> st(n);
+    int cur = 0;
+    for (int t = NT; t >= 2; --t) {
+        for (size_t m = 0; m < n; ++m)
+            st[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[cur], W[m]->V[1 - cur], false, t - 2, yin[m], 1.0};
+        adj_steps(prec, RB, y_f64, st, s);
+        cur = 1 - cur;
+    }
+    for (size_t m = 0; m < n; ++m)
+        st[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[cur], nullptr, true, 0, yin[m], 1.0};
+    adj_steps(prec, RB, y_f64, st, s);
+}
+
+// Autotuner: for each candidate RHS block, time `reps` merged forward and
+// transpose steps of all meshes (after a warm-up) with HIP events and price a
+// run of S samples as ceil(S/RB) * (forward + transpose step); return the cheapest.
+pat_status tune_rb(const std::vector<pat_problem *> &P, int64_t S, pat::Prec pr, hipStream_t s, int *best,
+                   double *best_us) {
+    const int top = choose_rb(S);
+    const int lo = std::max(1, top / 16);
+    const int reps = 8;
+    hipEvent_t ev[3];
+    for (auto &e : ev) PAT_HIP(hipEventCreate(&e));
+    *best = top;
+    *best_us = 1e300;
+    pat_status st = PAT_OK;
+    for (int RB = lo; RB <= top && st == PAT_OK; RB <<= 1) {
+        std::vector<SweepWS *> W(P.size());
+        std::vector<void *> Y(P.size());
+        std::vector<double> one(P.size(), 1.0);
+        for (size_t m = 0; m < P.size() && st == PAT_OK; ++m) {
+            st = get_sweep(P[m], pr, RB, true, &W[m]);
+            if (st != PAT_OK) break;
+            const size_t nb = size_t(P[m]->ops.n) * RB * tsize(pr);
+            const size_t yb = size_t(P[m]->ops.n_steps) * P[m]->ops.n_obs * RB * tsize(pr);
+            for (int k = 0; k < 2; ++k) {
+                if (hipMemsetAsync(W[m]->P[k], 0, nb, s) != hipSuccess || hipMemsetAsync(W[m]->V[k], 0, nb, s) != hipSuccess)
+                    st = fail(PAT_ERR_HIP, "autotune: hipMemsetAsync failed");
+            }
+            if (hipMemsetAsync(W[m]->Y, 0, yb, s) != hipSuccess) st = fail(PAT_ERR_HIP, "autotune: hipMemsetAsync failed");
+            Y[m] = W[m]->Y;
+        }
+        if (st != PAT_OK) break;
+        const bool yf = pr == pat::Prec::F64;
+        std::vector<pat::FwdStep> fs(P.size());
+        std::vector<pat::AdjStep> as(P.size());
+        for (size_t m = 0; m < P.size(); ++m) {
+            fs[m] = pat::FwdStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->P[1], W[m]->V[1], true, false, true, 0,
+                                 Y[m], 1.0};
+            as[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->V[1], false, 0, Y[m], 1.0};
+        }
+        for (int k = 0; k < 2; ++k) {
+            fwd_steps(pr, RB, yf, fs, s);
+            adj_steps(pr, RB, yf, as, s);
+        }
+        (void)hipEventRecord(ev[0], s);
+        for (int k = 0; k < reps; ++k) fwd_steps(pr, RB, yf, fs, s);
+        (void)hipEventRecord(ev[1], s);
+        for (int k = 0; k < reps; ++k) adj_steps(pr, RB, yf, as, s);
+        (void)hipEventRecord(ev[2], s);
+        if (hipEventSynchronize(ev[2]) != hipSuccess) {
+            st = fail(PAT_ERR_HIP, "autotune: a timed step failed");
+            break;
+        }
+        float f_ms = 0.f, a_ms = 0.f;
+        (void)hipEventElapsedTime(&f_ms, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&a_ms, ev[1], ev[2]);
+        const double us = double((S + RB - 1) / RB) * 1e3 * double(f_ms + a_ms) / reps;
+        if (us < *best_us) {
+            *best_us = us;
+            *best = RB;
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (st == PAT_OK && hipGetLastError() != hipSuccess) st = fail(PAT_ERR_HIP, "autotune: launch failed");
+    return st;
+}
+
+// One RHS block's least-squares solve, split into the phases between sweeps so
+// that several blocks (of several meshes) can share each sweep launch:
+//   init, [transpose sweep], post_adj(0),
+//   then for k = 1..n_iter: pre_fwd(k), [forward sweep], post_fwd(k),
+//   and unless k = n_iter: [transpose sweep], post_adj(k).
+// The forward graph reads w->P[0] and writes qd = G x / sigma; the transpose
+// graph reads rd and leaves G^T rd in w->P[0].
+// With the spectral prior the unknowns are the latent grid vector (NX = n^3):
+// G_ext = [G P / sigma ; I], the forward input is P x and the transpose output
+// P^T (G^T r_d) / sigma + r_p.
 struct Solve {
     pat_problem *p;
     SweepWS *w;
     CglsWS *c;
     pat::Prec pr;
     int RB, n_iter;
-    bool reorth;
+    bool reorth, lsqr;
     double isig, a;
-    int64_t N, M, ld, S;
+    int64_t N, M, ld, S, rb0;
     double *resid_hist, *diag_hist;
     hipStream_t s;
-    size_t *ev_used;
-    std::vector<int> *ev_kind;
+    int64_t NX;       // unknowns per RHS
+    SpecWS *sw;       // spectral prior work buffers, or null for the FE prior factor
 };
 
-pat_status sweep(Solve &v, bool forward) {
-    PAT_TRY(launch_sweep(v.p, forward ? v.w->g_fwd_cgls : v.w->g_adj_cgls, v.s, v.ev_used));
-    if (v.p->prof) v.ev_kind->push_back(forward ? 0 : 1);
-    return PAT_OK;
-}
-
 // Residual history column `it` from the data part rd [M][RB] and prior part rp [N][RB].
-void record(Solve &v, const double *rd, const double *rp, int it, int64_t rb0) {
+void record(Solve &v, const double *rd, const double *rp, int it) {
     if (!v.resid_hist && !v.diag_hist) return;
     double *pA = v.c->part, *pB = v.c->part + pat::kDotBlocks * v.RB;
     double *t1 = v.c->scal + 14 * v.RB, *t2 = v.c->scal + 15 * v.RB;
     pat::launch_dot_partial(rd, rd, v.M, v.RB, pA, v.s);
-    pat::launch_dot_partial(rp, rp, v.N, v.RB, pB, v.s);
+    pat::launch_dot_partial(rp, rp, v.NX, v.RB, pB, v.s);
     pat::launch_dot_final(pA, nullptr, v.RB, t1, v.s);
     pat::launch_dot_final(pB, nullptr, v.RB, t2, v.s);
-    pat::launch_resid(t1, t2, v.resid_hist, v.diag_hist, v.ld, it, rb0, v.S, v.RB, v.s);
-}
-
-// s = G_ext^T (rd, up) = G^T rd / sigma + L^T up; the transpose graph reads rd.
-pat_status apply_gext_t(Solve &v, const double *up) {
-    PAT_TRY(sweep(v, false));
-    pat::launch_gext_t_combine(v.pr, v.p->ops, v.RB, v.a, v.isig, v.w->P[0], up, v.c->s, v.s);
-    return PAT_OK;
+    pat::launch_resid(t1, t2, v.resid_hist, v.diag_hist, v.ld, it, v.rb0, v.S, v.RB, v.s);
 }
 
 // s -= sum_j (Q_j . s) Q_j over j < k, classical Gram-Schmidt applied twice.
 void reorthogonalise(Solve &v, int k) {
     if (!v.reorth || k <= 0) return;
     for (int pass = 0; pass < 2; ++pass) {
-        pat::launch_multidot(v.c->Q, v.c->s, k, v.N, v.RB, v.c->mpart, v.c->coef, v.s);
-        pat::launch_project(v.c->Q, v.c->s, v.c->coef, k, v.N, v.RB, v.s);
+        pat::launch_multidot(v.c->Q, v.c->s, k, v.NX, v.RB, v.c->mpart, v.c->coef, v.s);
+        pat::launch_project(v.c->Q, v.c->s, v.c->coef, k, v.NX, v.RB, v.s);
     }
 }
 
-// qd = G x / sigma (through the forward graph), qp = L x.
-pat_status apply_gext(Solve &v, const double *x) {
-    pat::launch_cast_to_state(v.pr, x, v.w->P[0], v.N * v.RB, v.s);
-    PAT_TRY(sweep(v, true));
-    pat::launch_prior(v.p->ops, v.RB, v.a, x, v.c->qp, v.s);
-    return PAT_OK;
+// s = G^T rd / sigma + L^T up (spectral prior: P^T G^T rd / sigma + up), from the transpose sweep's result.
+void combine_t(Solve &v, const double *up) {
+    if (v.sw)
+        pat::launch_spectral_t(v.p->sops, v.RB, v.w->P[0], v.pr, v.isig, up, v.sw->gr, v.sw->gc, v.c->s, v.s);
+    else
+        pat::launch_gext_t_combine(v.pr, v.p->ops, v.RB, v.a, v.isig, v.w->P[0], up, v.c->s, v.s);
 }
 
-// CGLS on one block; b in (rd, rp), x = 0 on entry.  Normal-equation residuals
+// qp = L x (spectral prior: the identity on the latent vector).
+void prior_part(Solve &v, const double *x) {
+    if (v.sw) pat::launch_lincomb(v.c->qp, x, nullptr, 1.0, nullptr, nullptr, 0.0, v.NX, v.RB, v.s);
+    else pat::launch_prior(v.p->ops, v.RB, v.a, x, v.c->qp, v.s);
+}
+
+// ---- CGLS: b in (rd, rp) and x = 0 on entry.  The normal-equation residuals
 // s_j are kept orthogonal by two classical Gram-Schmidt passes (App. A).
-pat_status cgls_block(Solve &v, int64_t rb0, const double **chk) {
+struct CglsScal {
+    double *gamma, *delta, *alpha, *beta, *invn, *gnew;
+    explicit CglsScal(const Solve &v)
+        : gamma(v.c->scal), delta(v.c->scal + v.RB), alpha(v.c->scal + 2 * v.RB), beta(v.c->scal + 3 * v.RB),
+          invn(v.c->scal + 4 * v.RB), gnew(v.c->scal + 5 * v.RB) {}
+};
+
+void cgls_post_adj(Solve &v, int k) {
     CglsWS *c = v.c;
-    const int RB = v.RB;
-    double *gamma = c->scal, *delta = c->scal + RB, *alpha = c->scal + 2 * RB, *beta = c->scal + 3 * RB;
-    double *invn = c->scal + 4 * RB, *gnew = c->scal + 5 * RB;
-    double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
-    record(v, c->rd, c->rp, 0, rb0);
-    // s_0 = G_ext^T r_0
-    PAT_TRY(apply_gext_t(v, c->rp));
-    pat::launch_dot_partial(c->s, c->s, v.N, RB, pA, v.s);
-    pat::launch_dot_final(pA, nullptr, RB, gnew, v.s);
-    pat::launch_scalar_gamma(gamma, gnew, beta, invn, 1, RB, v.s);
-    pat::launch_append_dir(c->s, v.reorth ? c->Q : nullptr, c->d, invn, beta, 1, v.N, RB, v.s);
-    for (int it = 1; it <= v.n_iter; ++it) {
-        // q = G_ext d ; alpha = gamma / ||q||^2 ; x += alpha d ; r -= alpha q
-        PAT_TRY(apply_gext(v, c->d));
-        pat::launch_dot_partial(c->qd, c->qd, v.M, RB, pA, v.s);
-        pat::launch_dot_partial(c->qp, c->qp, v.N, RB, pB, v.s);
-        pat::launch_dot_final(pA, pB, RB, delta, v.s);
-        pat::launch_scalar_alpha(gamma, delta, alpha, RB, v.s);
-        pat::launch_update_xr(c->x, c->d, c->rp, c->qp, alpha, v.N, RB, v.s);
-        pat::launch_axpy_neg(c->rd, c->qd, alpha, v.M, RB, v.s);
-        record(v, c->rd, c->rp, it, rb0);
-        if (it == v.n_iter) break;
-        // s = G_ext^T r ; beta = gamma_new / gamma ; d = s + beta d
-        PAT_TRY(apply_gext_t(v, c->rp));
-        reorthogonalise(v, it);
-        pat::launch_dot_partial(c->s, c->s, v.N, RB, pA, v.s);
-        pat::launch_dot_final(pA, nullptr, RB, gnew, v.s);
-        pat::launch_scalar_gamma(gamma, gnew, beta, invn, 0, RB, v.s);
-        pat::launch_append_dir(c->s, v.reorth ? c->Q + size_t(it) * v.N * RB : nullptr, c->d, invn, beta, 0, v.N, RB,
-                               v.s);
-    }
-    *chk = gamma;
-    return PAT_OK;
+    const CglsScal z(v);
+    double *pA = c->part;
+    combine_t(v, c->rp);
+    reorthogonalise(v, k);
+    pat::launch_dot_partial(c->s, c->s, v.NX, v.RB, pA, v.s);
+    pat::launch_dot_final(pA, nullptr, v.RB, z.gnew, v.s);
+    // beta = gamma_new / gamma ; d = s + beta d ; Q[k] = s / ||s||
+    pat::launch_scalar_gamma(z.gamma, z.gnew, z.beta, z.invn, k == 0, v.RB, v.s);
+    pat::launch_append_dir(c->s, v.reorth ? c->Q + size_t(k) * v.NX * v.RB : nullptr, c->d, z.invn, z.beta, k == 0,
+                           v.NX, v.RB, v.s);
 }
 
-// LSQR on one block (Paige and Saunders' bidiagonalisation, the solver of
-// Sec. 5.2).  b in (rd, rp), x = 0 on entry.  The left vector u lives in
-// (rd, rp), so the transpose graph reads it where CGLS keeps its residual; the
-// search direction w lives in d.  The residual r = b - G_ext x is carried
-// (through z = G_ext w) only when a history is asked for.
-pat_status lsqr_block(Solve &v, int64_t rb0, const double **chk) {
+void cgls_post_fwd(Solve &v, int k) {
     CglsWS *c = v.c;
+    const CglsScal z(v);
+    double *pA = c->part, *pB = c->part + pat::kDotBlocks * v.RB;
+    // q = (G d / sigma, L d) ; alpha = gamma / ||q||^2 ; x += alpha d ; r -= alpha q
+    prior_part(v, c->d);
+    pat::launch_dot_partial(c->qd, c->qd, v.M, v.RB, pA, v.s);
+    pat::launch_dot_partial(c->qp, c->qp, v.NX, v.RB, pB, v.s);
+    pat::launch_dot_final(pA, pB, v.RB, z.delta, v.s);
+    pat::launch_scalar_alpha(z.gamma, z.delta, z.alpha, v.RB, v.s);
+    pat::launch_update_xr(c->x, c->d, c->rp, c->qp, z.alpha, v.NX, v.RB, v.s);
+    pat::launch_axpy_neg(c->rd, c->qd, z.alpha, v.M, v.RB, v.s);
+    record(v, c->rd, c->rp, k);
+}
+
+// ---- LSQR (Paige and Saunders' bidiagonalisation, the solver of Sec. 5.2):
+// b in (rd, rp) and x = 0 on entry.  The left vector u lives in (rd, rp), so
+// the transpose graph reads it where CGLS keeps its residual; the search
+// direction w lives in d.  The residual b - G_ext x is carried (through
+// z = G_ext w) only when a history is asked for.
+struct LsqrState {
+    pat::LsqrScalars L;
+    double *n1, *n2;
+    bool track;
+    explicit LsqrState(const Solve &v) {
+        double *sc = v.c->scal;
+        const int RB = v.RB;
+        L = pat::LsqrScalars{sc, sc + RB, sc + 2 * RB, sc + 3 * RB, sc + 4 * RB, sc + 5 * RB,
+                             sc + 6 * RB, sc + 7 * RB, sc + 8 * RB, sc + 9 * RB, sc + 10 * RB, sc + 11 * RB};
+        n1 = sc + 12 * RB;
+        n2 = sc + 13 * RB;
+        track = v.resid_hist || v.diag_hist;
+    }
+};
+
+void lsqr_init(Solve &v) {
+    CglsWS *c = v.c;
+    const LsqrState z(v);
     const int RB = v.RB;
-    const int64_t N = v.N, M = v.M;
-    const bool track = v.resid_hist || v.diag_hist;
-    double *sc = c->scal;
-    pat::LsqrScalars L{sc, sc + RB, sc + 2 * RB, sc + 3 * RB, sc + 4 * RB, sc + 5 * RB,
-                       sc + 6 * RB, sc + 7 * RB, sc + 8 * RB, sc + 9 * RB, sc + 10 * RB, sc + 11 * RB};
-    double *n1 = sc + 12 * RB, *n2 = sc + 13 * RB;
     double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
-    if (track) {
-        pat::launch_lincomb(c->lrd, c->rd, nullptr, 1.0, nullptr, nullptr, 0.0, M, RB, v.s);
-        pat::launch_lincomb(c->lrp, c->rp, nullptr, 1.0, nullptr, nullptr, 0.0, N, RB, v.s);
-        record(v, c->lrd, c->lrp, 0, rb0);
+    if (z.track) {
+        pat::launch_lincomb(c->lrd, c->rd, nullptr, 1.0, nullptr, nullptr, 0.0, v.M, RB, v.s);
+        pat::launch_lincomb(c->lrp, c->rp, nullptr, 1.0, nullptr, nullptr, 0.0, v.NX, RB, v.s);
+        record(v, c->lrd, c->lrp, 0);
     }
     // beta_1 u_1 = b
+    pat::launch_dot_partial(c->rd, c->rd, v.M, RB, pA, v.s);
+    pat::launch_dot_partial(c->rp, c->rp, v.NX, RB, pB, v.s);
+    pat::launch_dot_final(pA, nullptr, RB, z.n1, v.s);
+    pat::launch_dot_final(pB, nullptr, RB, z.n2, v.s);
+    pat::launch_lsqr_scalar(pat::LsqrStage::InitBeta, z.L, z.n1, z.n2, RB, v.s);
+    pat::launch_lincomb(c->rd, c->rd, z.L.inv, 1.0, nullptr, nullptr, 0.0, v.M, RB, v.s);
+    pat::launch_lincomb(c->rp, c->rp, z.L.inv, 1.0, nullptr, nullptr, 0.0, v.NX, RB, v.s);
+}
+
+void lsqr_post_adj(Solve &v, int k) {
+    CglsWS *c = v.c;
+    const LsqrState z(v);
+    double *pA = c->part;
+    // alpha_{k+1} v_{k+1} = G_ext^T u_{k+1} - beta_{k+1} v_k, reorthogonalised ; w = v - zfac w
+    combine_t(v, c->rp);
+    if (k > 0) pat::launch_lincomb(c->s, c->s, nullptr, 1.0, c->v, z.L.beta, -1.0, v.NX, v.RB, v.s);
+    reorthogonalise(v, k);
+    pat::launch_dot_partial(c->s, c->s, v.NX, v.RB, pA, v.s);
+    pat::launch_dot_final(pA, nullptr, v.RB, z.n1, v.s);
+    pat::launch_lsqr_scalar(k == 0 ? pat::LsqrStage::InitAlpha : pat::LsqrStage::Alpha, z.L, z.n1, nullptr, v.RB, v.s);
+    pat::launch_lsqr_vw(c->s, z.L.inv, z.L.zfac, c->v, c->d, v.reorth ? c->Q + size_t(k) * v.NX * v.RB : nullptr,
+                        k == 0, v.NX, v.RB, v.s);
+}
+
+void lsqr_post_fwd(Solve &v, int k) {
+    CglsWS *c = v.c;
+    const LsqrState z(v);
+    const int RB = v.RB;
+    const int64_t N = v.NX, M = v.M;
+    double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
+    // q = G_ext v_k ; z_k = q - zfac z_{k-1}
+    prior_part(v, c->v);
+    if (z.track) {
+        pat::launch_lincomb(c->zd, c->qd, nullptr, 1.0, k > 1 ? c->zd : nullptr, z.L.zfac, -1.0, M, RB, v.s);
+        pat::launch_lincomb(c->zp, c->qp, nullptr, 1.0, k > 1 ? c->zp : nullptr, z.L.zfac, -1.0, N, RB, v.s);
+    }
+    // beta_{k+1} u_{k+1} = q - alpha_k u_k ; plane rotation
+    pat::launch_lincomb(c->rd, c->qd, nullptr, 1.0, c->rd, z.L.alpha, -1.0, M, RB, v.s);
+    pat::launch_lincomb(c->rp, c->qp, nullptr, 1.0, c->rp, z.L.alpha, -1.0, N, RB, v.s);
     pat::launch_dot_partial(c->rd, c->rd, M, RB, pA, v.s);
     pat::launch_dot_partial(c->rp, c->rp, N, RB, pB, v.s);
-    pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
-    pat::launch_dot_final(pB, nullptr, RB, n2, v.s);
-    pat::launch_lsqr_scalar(pat::LsqrStage::InitBeta, L, n1, n2, RB, v.s);
-    pat::launch_lincomb(c->rd, c->rd, L.inv, 1.0, nullptr, nullptr, 0.0, M, RB, v.s);
-    pat::launch_lincomb(c->rp, c->rp, L.inv, 1.0, nullptr, nullptr, 0.0, N, RB, v.s);
-    // alpha_1 v_1 = G_ext^T u_1 ; w_1 = v_1
-    PAT_TRY(apply_gext_t(v, c->rp));
-    pat::launch_dot_partial(c->s, c->s, N, RB, pA, v.s);
-    pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
-    pat::launch_lsqr_scalar(pat::LsqrStage::InitAlpha, L, n1, nullptr, RB, v.s);
-    pat::launch_lsqr_vw(c->s, L.inv, L.zfac, c->v, c->d, v.reorth ? c->Q : nullptr, 1, N, RB, v.s);
-    for (int k = 1; k <= v.n_iter; ++k) {
-        // q = G_ext v_k ; z_k = q - zfac z_{k-1}
-        PAT_TRY(apply_gext(v, c->v));
-        if (track) {
-            pat::launch_lincomb(c->zd, c->qd, nullptr, 1.0, k > 1 ? c->zd : nullptr, L.zfac, -1.0, M, RB, v.s);
-            pat::launch_lincomb(c->zp, c->qp, nullptr, 1.0, k > 1 ? c->zp : nullptr, L.zfac, -1.0, N, RB, v.s);
-        }
-        // beta_{k+1} u_{k+1} = q - alpha_k u_k ; rotation
-        pat::launch_lincomb(c->rd, c->qd, nullptr, 1.0, c->rd, L.alpha, -1.0, M, RB, v.s);
-        pat::launch_lincomb(c->rp, c->qp, nullptr, 1.0, c->rp, L.alpha, -1.0, N, RB, v.s);
-        pat::launch_dot_partial(c->rd, c->rd, M, RB, pA, v.s);
-        pat::launch_dot_partial(c->rp, c->rp, N, RB, pB, v.s);
-        pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
-        pat::launch_dot_final(pB, nullptr, RB, n2, v.s);
-        pat::launch_lsqr_scalar(pat::LsqrStage::Beta, L, n1, n2, RB, v.s);
-        pat::launch_lincomb(c->rd, c->rd, L.inv, 1.0, nullptr, nullptr, 0.0, M, RB, v.s);
-        pat::launch_lincomb(c->rp, c->rp, L.inv, 1.0, nullptr, nullptr, 0.0, N, RB, v.s);
-        // x += (phi/rho) w ; r -= (phi/rho) z
-        pat::launch_lincomb(c->x, c->x, nullptr, 1.0, c->d, L.step, 1.0, N, RB, v.s);
-        if (track) {
-            pat::launch_lincomb(c->lrd, c->lrd, nullptr, 1.0, c->zd, L.step, -1.0, M, RB, v.s);
-            pat::launch_lincomb(c->lrp, c->lrp, nullptr, 1.0, c->zp, L.step, -1.0, N, RB, v.s);
-            record(v, c->lrd, c->lrp, k, rb0);
-        }
-        if (k == v.n_iter) break;
-        // alpha_{k+1} v_{k+1} = G_ext^T u_{k+1} - beta_{k+1} v_k, reorthogonalised
-        PAT_TRY(apply_gext_t(v, c->rp));
-        pat::launch_lincomb(c->s, c->s, nullptr, 1.0, c->v, L.beta, -1.0, N, RB, v.s);
-        reorthogonalise(v, k);
-        pat::launch_dot_partial(c->s, c->s, N, RB, pA, v.s);
-        pat::launch_dot_final(pA, nullptr, RB, n1, v.s);
-        pat::launch_lsqr_scalar(pat::LsqrStage::Alpha, L, n1, nullptr, RB, v.s);
-        pat::launch_lsqr_vw(c->s, L.inv, L.zfac, c->v, c->d, v.reorth ? c->Q + size_t(k) * N * RB : nullptr, 0, N, RB,
-                            v.s);
+    pat::launch_dot_final(pA, nullptr, RB, z.n1, v.s);
+    pat::launch_dot_final(pB, nullptr, RB, z.n2, v.s);
+    pat::launch_lsqr_scalar(pat::LsqrStage::Beta, z.L, z.n1, z.n2, RB, v.s);
+    pat::launch_lincomb(c->rd, c->rd, z.L.inv, 1.0, nullptr, nullptr, 0.0, M, RB, v.s);
+    pat::launch_lincomb(c->rp, c->rp, z.L.inv, 1.0, nullptr, nullptr, 0.0, N, RB, v.s);
+    // x += (phi/rho) w ; r -= (phi/rho) z
+    pat::launch_lincomb(c->x, c->x, nullptr, 1.0, c->d, z.L.step, 1.0, N, RB, v.s);
+    if (z.track) {
+        pat::launch_lincomb(c->lrd, c->lrd, nullptr, 1.0, c->zd, z.L.step, -1.0, M, RB, v.s);
+        pat::launch_lincomb(c->lrp, c->lrp, nullptr, 1.0, c->zp, z.L.step, -1.0, N, RB, v.s);
+        record(v, c->lrd, c->lrp, k);
     }
-    *chk = L.phib;
+}
+
+// ---- phase dispatch
+void ph_init(Solve &v) {
+    if (v.lsqr) lsqr_init(v);
+    else record(v, v.c->rd, v.c->rp, 0);
+}
+void ph_post_adj(Solve &v, int k) { v.lsqr ? lsqr_post_adj(v, k) : cgls_post_adj(v, k); }
+void ph_pre_fwd(Solve &v, int) {
+    // the forward graph reads its input from P[0] in the sweep precision
+    const double *x = v.lsqr ? v.c->v : v.c->d;
+    if (v.sw) pat::launch_spectral(v.p->sops, v.RB, x, v.sw->gr, v.sw->gc, v.pr, v.w->P[0], v.N, v.s);
+    else pat::launch_cast_to_state(v.pr, x, v.w->P[0], v.N * v.RB, v.s);
+}
+void ph_post_fwd(Solve &v, int k) { v.lsqr ? lsqr_post_fwd(v, k) : cgls_post_fwd(v, k); }
+// per-RHS scalar that turns non-finite when the solve breaks down (CGLS gamma, LSQR phi_bar)
+const double *ph_check(const Solve &v) { return v.lsqr ? v.c->scal + 5 * v.RB : v.c->scal; }
+
+// Run the blocks in lockstep; fwd() and adj() launch one shared sweep each.
+template <class Fwd, class Adj>
+pat_status drive(std::vector<Solve> &blocks, int n_iter, Fwd &&fwd, Adj &&adj) {
+    for (Solve &v : blocks) ph_init(v);
+    PAT_TRY(adj());
+    for (Solve &v : blocks) ph_post_adj(v, 0);
+    for (int k = 1; k <= n_iter; ++k) {
+        for (Solve &v : blocks) ph_pre_fwd(v, k);
+        PAT_TRY(fwd());
+        for (Solve &v : blocks) ph_post_fwd(v, k);
+        if (k == n_iter) break;
+        PAT_TRY(adj());
+        for (Solve &v : blocks) ph_post_adj(v, k);
+    }
+    return PAT_OK;
+}
+
+// b = (y_obs/sigma + eta, xi) of block rb0 in (rd, rp), from the caller's draws or the device streams.
+void build_rhs(Solve &v, const double *y_obs, const pat_rto_params *prm) {
+    const pat::DevOps &op = v.p->ops;
+    // latent grid vectors keep the caller's (grid) order
+    const int32_t *perm = (v.sw || v.p->perm_identity) ? nullptr : op.perm;
+    if (prm->eta) {
+        pat::launch_build_rhs(y_obs, prm->eta, v.S, v.rb0, v.RB, v.M, v.isig, v.c->rd, v.s);
+        pat::launch_pack(true, true, prm->xi, v.S, v.rb0, v.RB, v.NX, perm, v.c->rp, v.s);
+    } else {
+        pat::launch_build_rhs_rng(y_obs, prm->seed, prm->sample0, v.S, v.rb0, v.RB, v.M, v.isig, v.c->rd, v.s);
+        pat::launch_xi_rng(prm->seed, prm->sample0, v.S, v.rb0, v.RB, v.NX, perm, v.c->rp, v.s);
+    }
+    pat::launch_fill(v.c->x, v.NX * v.RB, 0.0, v.s);
+}
+
+// Samples of the finished block in the caller's layout: p0 = x (FE prior) or p0 = P x
+// (spectral prior, whose latent x also goes to prm->latent when given).
+void finish_block(Solve &v, const pat_rto_params *prm, double *samples) {
+    const pat::DevOps &op = v.p->ops;
+    const int32_t *perm = v.p->perm_identity ? nullptr : op.perm;
+    if (v.sw) {
+        pat::launch_spectral(v.p->sops, v.RB, v.c->x, v.sw->gr, v.sw->gc, pat::Prec::F64, v.sw->ym, v.N, v.s);
+        pat::launch_unpack(true, true, v.sw->ym, v.S, v.rb0, v.RB, v.N, perm, samples, v.s);
+        if (prm->latent) pat::launch_unpack(true, true, v.c->x, v.S, v.rb0, v.RB, v.NX, nullptr, prm->latent, v.s);
+    } else {
+        pat::launch_unpack(true, true, v.c->x, v.S, v.rb0, v.RB, v.N, perm, samples, v.s);
+    }
+}
+
+// The solver state of block rb0 of problem p.
+pat_status make_solve(pat_problem *p, const pat_rto_params *prm, pat::Prec pr, int RB, int64_t S, int64_t rb0,
+                      double *resid_hist, hipStream_t s, Solve *out) {
+    const bool spec = prm->prior == PAT_PRIOR_SPECTRAL;
+    const bool reorth = prm->reorth != 0, lsqr = prm->solver == PAT_LSQR;
+    const int64_t N = p->ops.n, M = int64_t(p->ops.n_steps) * p->ops.n_obs;
+    const int64_t NX = spec ? p->sops.G : N;
+    SweepWS *w;
+    PAT_TRY(get_sweep(p, pr, RB, false, &w));
+    CglsWS *c;
+    PAT_TRY(get_cgls(p, RB, NX, prm->n_iter, reorth, lsqr, resid_hist || prm->diag_hist, &c));
+    SpecWS *sw = nullptr;
+    if (spec) PAT_TRY(get_spec(p, RB, &sw));
+    *out = Solve{p, w, c, pr, RB, prm->n_iter, reorth, lsqr, 1.0 / prm->sigma, prm->prior_a, N, M,
+                 int64_t(prm->n_iter) + 1, S, rb0, resid_hist, prm->diag_hist, s, NX, sw};
+    return PAT_OK;
+}
+
+pat_status check_rto_params(const pat_rto_params *prm, int64_t S, bool want_std) {
+    if ((prm->eta == nullptr) != (prm->xi == nullptr))
+        return fail(PAT_ERR_INVALID_ARG, "rto_sample: pass both eta and xi, or neither (device draws)");
+    if (prm->sample0 < 0) return fail(PAT_ERR_INVALID_ARG, "rto_sample: sample0 must be >= 0");
+    if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return fail(PAT_ERR_INVALID_ARG, "sigma must be > 0");
+    if (!(prm->prior_a >= 0.0) || !std::isfinite(prm->prior_a)) return fail(PAT_ERR_INVALID_ARG, "prior_a must be >= 0");
+    if (prm->n_iter < 1) return fail(PAT_ERR_INVALID_ARG, "n_iter must be >= 1");
+    if (want_std && S < 2) return fail(PAT_ERR_INVALID_ARG, "std needs S >= 2");
+    if (prm->rhs_block != 0 && !valid_rb(prm->rhs_block))
+        return fail(PAT_ERR_INVALID_ARG, "rhs_block must be 0 or a power of two <= 64");
+    if (prm->solver != PAT_CGLS && prm->solver != PAT_LSQR)
+        return fail(PAT_ERR_INVALID_ARG, "solver must be PAT_CGLS or PAT_LSQR");
+    if (prm->prior != PAT_PRIOR_FE && prm->prior != PAT_PRIOR_SPECTRAL)
+        return fail(PAT_ERR_INVALID_ARG, "prior must be PAT_PRIOR_FE or PAT_PRIOR_SPECTRAL");
+    return PAT_OK;
+}
+
+pat_status check_spectral(const pat_problem *p, const pat_rto_params *prm, int RB) {
+    if (prm->prior != PAT_PRIOR_SPECTRAL) return PAT_OK;
+    if (!p->spec) return fail(PAT_ERR_INVALID_ARG, "spectral prior requested but none set (pat_spectral_prior_set)");
+    if (!pat::spectral_rb_ok(RB)) return fail(PAT_ERR_INVALID_ARG, "rhs_block not supported by the spectral prior");
+    return PAT_OK;
+}
+
+// Per-sweep event timings of the last call, folded into the handle's profile.
+pat_status fold_profile(pat_problem *p, const std::vector<int> &ev_kind) {
+    for (size_t q = 0; q < ev_kind.size(); ++q) {
+        float ms = 0.f;
+        PAT_HIP(hipEventElapsedTime(&ms, p->events[2 * q], p->events[2 * q + 1]));
+        if (ev_kind[q] == 0) {
+            p->prof_acc.fwd_ms += ms;
+            ++p->prof_acc.fwd_sweeps;
+        } else {
+            p->prof_acc.adj_ms += ms;
+            ++p->prof_acc.adj_sweeps;
+        }
+    }
+    return PAT_OK;
+}
+
+// Capture (or reuse) a problem's solver sweep graphs for output scale isig.
+pat_status solver_graphs(pat_problem *p, SweepWS *w, CglsWS *c, double isig) {
+    if (!w->g_fwd_cgls || w->g_fwd_cgls_scale != isig || w->g_fwd_cgls_out != c->qd) {
+        PAT_TRY(capture(p, &w->g_fwd_cgls, [&](hipStream_t cs) { enqueue_forward(p, *w, c->qd, true, isig, cs); }));
+        w->g_fwd_cgls_scale = isig;
+        w->g_fwd_cgls_out = c->qd;
+    }
+    if (!w->g_adj_cgls || w->g_adj_cgls_in != c->rd) {
+        PAT_TRY(capture(p, &w->g_adj_cgls, [&](hipStream_t cs) { enqueue_adjoint(p, *w, c->rd, true, cs); }));
+        w->g_adj_cgls_in = c->rd;
+    }
     return PAT_OK;
 }
 
@@ -533,6 +870,9 @@ pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out) {
     p->perm_identity = true;
     for (int32_t i = 0; i < hp.n; ++i)
         if (hp.perm[i] != i) p->perm_identity = false;
+    p->xyz.resize(size_t(hp.n) * 3);
+    for (int32_t i = 0; i < hp.n; ++i)
+        for (int d = 0; d < 3; ++d) p->xyz[size_t(i) * 3 + d] = desc->coords[size_t(hp.perm[i]) * 3 + d];
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return cleanup(fail(PAT_ERR_HIP, "hipStreamCreateWithFlags failed"));
 
@@ -631,89 +971,365 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
                       double *mean, double *std, double *resid_hist, void *stream) {
     g_err.clear();
     if (!p || !y_obs || !prm || !samples || S < 1) return fail(PAT_ERR_INVALID_ARG, "rto_sample: NULL pointer or S < 1");
-    if ((prm->eta == nullptr) != (prm->xi == nullptr))
-        return fail(PAT_ERR_INVALID_ARG, "rto_sample: pass both eta and xi, or neither (device draws)");
-    if (prm->sample0 < 0) return fail(PAT_ERR_INVALID_ARG, "rto_sample: sample0 must be >= 0");
-    if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return fail(PAT_ERR_INVALID_ARG, "sigma must be > 0");
-    if (!(prm->prior_a >= 0.0) || !std::isfinite(prm->prior_a)) return fail(PAT_ERR_INVALID_ARG, "prior_a must be >= 0");
-    if (prm->n_iter < 1) return fail(PAT_ERR_INVALID_ARG, "n_iter must be >= 1");
-    if (std && S < 2) return fail(PAT_ERR_INVALID_ARG, "std needs S >= 2");
-    if (prm->rhs_block != 0 && !valid_rb(prm->rhs_block))
-        return fail(PAT_ERR_INVALID_ARG, "rhs_block must be 0 or a power of two <= 64");
-    if (prm->solver != PAT_CGLS && prm->solver != PAT_LSQR)
-        return fail(PAT_ERR_INVALID_ARG, "solver must be PAT_CGLS or PAT_LSQR");
+    PAT_TRY(check_rto_params(prm, S, std != nullptr));
     pat::Prec pr;
     PAT_TRY(check_prec(prm->sweep_prec, &pr));
     DeviceGuard guard(p->device);
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    const int RB = prm->rhs_block ? prm->rhs_block : choose_rb(S);
+    const int RB = prm->rhs_block ? prm->rhs_block : auto_rb(p->tuned, S, pr);
+    PAT_TRY(check_spectral(p, prm, RB));
     const int n_iter = prm->n_iter;
-    const bool reorth = prm->reorth != 0;
-    const pat::DevOps &op = p->ops;
-    const int64_t N = op.n, M = int64_t(op.n_steps) * op.n_obs;
-    const double isig = 1.0 / prm->sigma, a = prm->prior_a;
-    const int32_t *perm = p->perm_identity ? nullptr : op.perm;
-
-    SweepWS *w;
-    PAT_TRY(get_sweep(p, pr, RB, false, &w));
     const bool lsqr = prm->solver == PAT_LSQR;
-    CglsWS *c;
-    PAT_TRY(get_cgls(p, RB, n_iter, reorth, lsqr, resid_hist || prm->diag_hist, &c));
-    if (!w->g_fwd_cgls || w->g_fwd_cgls_scale != isig || w->g_fwd_cgls_out != c->qd) {
-        PAT_TRY(capture(p, &w->g_fwd_cgls, [&](hipStream_t cs) { enqueue_forward(p, *w, c->qd, true, isig, cs); }));
-        w->g_fwd_cgls_scale = isig;
-        w->g_fwd_cgls_out = c->qd;
-    }
-    if (!w->g_adj_cgls || w->g_adj_cgls_in != c->rd) {
-        PAT_TRY(capture(p, &w->g_adj_cgls, [&](hipStream_t cs) { enqueue_adjoint(p, *w, c->rd, true, cs); }));
-        w->g_adj_cgls_in = c->rd;
-    }
-    const int64_t ld = n_iter + 1;
-    std::vector<double> chk_host(size_t(((S + RB - 1) / RB) * RB), 0.0);
-    // event pairs: even index = forward sweep, odd = transpose sweep, per kind in order
-    size_t ev_used = 0;
-    std::vector<int> ev_kind;  // 0 forward, 1 transpose, per event pair
-    Solve sv{p, w, c, pr, RB, n_iter, reorth, isig, a, N, M, ld, S, resid_hist, prm->diag_hist, s, &ev_used, &ev_kind};
+    const int64_t N = p->ops.n;
 
+    Solve proto;
+    PAT_TRY(make_solve(p, prm, pr, RB, S, 0, resid_hist, s, &proto));
+    SweepWS *w = proto.w;
+    PAT_TRY(solver_graphs(p, w, proto.c, proto.isig));
+    std::vector<double> chk_host(size_t(((S + RB - 1) / RB) * RB), 0.0);
+    size_t ev_used = 0;
+    std::vector<int> ev_kind;  // per event pair: 0 forward, 1 transpose
+    auto fwd = [&]() -> pat_status {
+        PAT_TRY(launch_sweep(p, w->g_fwd_cgls, s, &ev_used));
+        if (p->prof) ev_kind.push_back(0);
+        return PAT_OK;
+    };
+    auto adj = [&]() -> pat_status {
+        PAT_TRY(launch_sweep(p, w->g_adj_cgls, s, &ev_used));
+        if (p->prof) ev_kind.push_back(1);
+        return PAT_OK;
+    };
     for (int64_t rb0 = 0; rb0 < S; rb0 += RB) {
-        // right-hand side b = (y_obs/sigma + eta, xi) in (rd, rp)
-        if (prm->eta) {
-            pat::launch_build_rhs(y_obs, prm->eta, S, rb0, RB, M, isig, c->rd, s);
-            pat::launch_pack(true, true, prm->xi, S, rb0, RB, N, perm, c->rp, s);
-        } else {
-            pat::launch_build_rhs_rng(y_obs, prm->seed, prm->sample0, S, rb0, RB, M, isig, c->rd, s);
-            pat::launch_xi_rng(prm->seed, prm->sample0, S, rb0, RB, N, perm, c->rp, s);
-        }
-        pat::launch_fill(c->x, N * RB, 0.0, s);
-        const double *chk = nullptr;
-        if (lsqr) {
-            PAT_TRY(lsqr_block(sv, rb0, &chk));
-        } else {
-            PAT_TRY(cgls_block(sv, rb0, &chk));
-        }
-        pat::launch_unpack(true, true, c->x, S, rb0, RB, N, perm, samples, s);
-        PAT_HIP(hipMemcpyAsync(chk_host.data() + rb0, chk, RB * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<Solve> blk{proto};
+        blk[0].rb0 = rb0;
+        build_rhs(blk[0], y_obs, prm);
+        PAT_TRY(drive(blk, n_iter, fwd, adj));
+        finish_block(blk[0], prm, samples);
+        PAT_HIP(hipMemcpyAsync(chk_host.data() + rb0, ph_check(blk[0]), RB * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     if (mean || std) pat::launch_stats(samples, S, N, mean, std, s);
     PAT_HIP(hipGetLastError());
     PAT_HIP(hipStreamSynchronize(s));
-    for (size_t q = 0; q < ev_kind.size(); ++q) {
-        float ms = 0.f;
-        PAT_HIP(hipEventElapsedTime(&ms, p->events[2 * q], p->events[2 * q + 1]));
-        if (ev_kind[q] == 0) {
-            p->prof_acc.fwd_ms += ms;
-            ++p->prof_acc.fwd_sweeps;
-        } else {
-            p->prof_acc.adj_ms += ms;
-            ++p->prof_acc.adj_sweeps;
-        }
-    }
+    PAT_TRY(fold_profile(p, ev_kind));
     for (int64_t k = 0; k < S; ++k)
         if (!std::isfinite(chk_host[size_t(k)]))
             return fail(PAT_ERR_NONFINITE, std::string("non-finite ") + (lsqr ? "LSQR" : "CGLS") +
                                                " scalar for sample " + std::to_string(k));
+    return PAT_OK;
+}
+
+pat_status pat_autotune(pat_problem *p, int64_t S, pat_precision prec, int32_t *rhs_block, double *step_us,
+                        void *stream) {
+    g_err.clear();
+    if (!p || S < 1) return fail(PAT_ERR_INVALID_ARG, "pat_autotune: NULL handle or S < 1");
+    pat::Prec pr;
+    PAT_TRY(check_prec(prec, &pr));
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    int rb = 0;
+    double us = 0.0;
+    PAT_TRY(tune_rb({p}, S, pr, static_cast<hipStream_t>(stream), &rb, &us));
+    p->tuned[{S, int(pr)}] = rb;
+    if (rhs_block) *rhs_block = rb;
+    if (step_us) *step_us = us;
+    return PAT_OK;
+}
+
+pat_status pat_batch_create(pat_problem *const *problems, int32_t n, pat_batch **out) {
+    g_err.clear();
+    if (!problems || !out || n < 1) return fail(PAT_ERR_INVALID_ARG, "pat_batch_create: NULL pointer or n < 1");
+    if (n > pat::kMaxMeshes)
+        return fail(PAT_ERR_INVALID_ARG, "pat_batch_create: at most " + std::to_string(pat::kMaxMeshes) + " problems");
+    *out = nullptr;
+    for (int32_t m = 0; m < n; ++m) {
+        if (!problems[m]) return fail(PAT_ERR_INVALID_ARG, "pat_batch_create: NULL problem");
+        if (problems[m]->device != problems[0]->device)
+            return fail(PAT_ERR_INVALID_ARG, "pat_batch_create: problems on different devices");
+        if (problems[m]->ops.n_steps != problems[0]->ops.n_steps)
+            return fail(PAT_ERR_INVALID_ARG, "pat_batch_create: problems need the same number of time steps");
+        for (int32_t q = 0; q < m; ++q)
+            if (problems[q] == problems[m]) return fail(PAT_ERR_INVALID_ARG, "pat_batch_create: repeated problem");
+    }
+    DeviceGuard guard(problems[0]->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    std::unique_ptr<pat_batch> b(new pat_batch());
+    b->device = problems[0]->device;
+    b->probs.assign(problems, problems + n);
+    PAT_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    *out = b.release();
+    return PAT_OK;
+}
+
+pat_status pat_batch_destroy(pat_batch *b) {
+    if (!b) return PAT_OK;
+    DeviceGuard guard(b->device);
+    if (b->g_fwd) (void)hipGraphExecDestroy(b->g_fwd);
+    if (b->g_adj) (void)hipGraphExecDestroy(b->g_adj);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return PAT_OK;
+}
+
+pat_status pat_batch_autotune(pat_batch *b, int64_t S, pat_precision prec, int32_t *rhs_block, double *step_us,
+                              void *stream) {
+    g_err.clear();
+    if (!b || S < 1) return fail(PAT_ERR_INVALID_ARG, "pat_batch_autotune: NULL handle or S < 1");
+    pat::Prec pr;
+    PAT_TRY(check_prec(prec, &pr));
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    int rb = 0;
+    double us = 0.0;
+    PAT_TRY(tune_rb(b->probs, S, pr, static_cast<hipStream_t>(stream), &rb, &us));
+    b->tuned[{S, int(pr)}] = rb;
+    if (rhs_block) *rhs_block = rb;
+    if (step_us) *step_us = us;
+    return PAT_OK;
+}
+
+pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_rto_params *prm, const int64_t *S,
+                            double *const *samples, double *const *mean, double *const *std,
+                            double *const *resid_hist, void *stream) {
+    g_err.clear();
+    if (!b || !y_obs || !prm || !S || !samples) return fail(PAT_ERR_INVALID_ARG, "rto_sample_batch: NULL pointer");
+    const size_t n = b->probs.size();
+    int64_t smax = 0;
+    for (size_t m = 0; m < n; ++m) {
+        if (!y_obs[m] || !samples[m] || S[m] < 1)
+            return fail(PAT_ERR_INVALID_ARG, "rto_sample_batch: NULL y_obs or samples, or S < 1, for problem " +
+                                                 std::to_string(m));
+        PAT_TRY(check_rto_params(&prm[m], S[m], std && std[m]));
+        if (prm[m].n_iter != prm[0].n_iter || prm[m].reorth != prm[0].reorth ||
+            prm[m].sweep_prec != prm[0].sweep_prec || prm[m].rhs_block != prm[0].rhs_block ||
+            prm[m].solver != prm[0].solver)
+            return fail(PAT_ERR_INVALID_ARG,
+                        "rto_sample_batch: n_iter, reorth, sweep_prec, rhs_block and solver must agree");
+        smax = std::max(smax, S[m]);
+    }
+    pat::Prec pr;
+    PAT_TRY(check_prec(prm[0].sweep_prec, &pr));
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int RB = prm[0].rhs_block ? prm[0].rhs_block : auto_rb(b->tuned, smax, pr);
+    const int n_iter = prm[0].n_iter;
+    const bool lsqr = prm[0].solver == PAT_LSQR;
+
+    std::vector<Solve> proto(n);
+    std::vector<SweepWS *> W(n);
+    std::vector<CglsWS *> C(n);
+    std::vector<double> scale(n);
+    std::vector<void *> yout(n);
+    std::vector<const void *> yin(n), kf, ka;
+    for (size_t m = 0; m < n; ++m) {
+        pat_problem *p = b->probs[m];
+        PAT_TRY(check_spectral(p, &prm[m], RB));
+        PAT_TRY(make_solve(p, &prm[m], pr, RB, S[m], 0, resid_hist ? resid_hist[m] : nullptr, s, &proto[m]));
+        W[m] = proto[m].w;
+        C[m] = proto[m].c;
+        scale[m] = 1.0 / prm[m].sigma;
+        yout[m] = C[m]->qd;
+        yin[m] = C[m]->rd;
+        kf.push_back(W[m]);
+        kf.push_back(C[m]->qd);
+        ka.push_back(W[m]);
+        ka.push_back(C[m]->rd);
+    }
+    if (!b->g_fwd || kf != b->key_fwd || scale != b->key_scale) {
+        PAT_TRY(capture_on(b->cap, &b->g_fwd,
+                           [&](hipStream_t cs) { enqueue_forward_multi(b->probs, W, yout, true, scale, cs); }));
+        b->key_fwd = kf;
+        b->key_scale = scale;
+    }
+    if (!b->g_adj || ka != b->key_adj) {
+        PAT_TRY(capture_on(b->cap, &b->g_adj, [&](hipStream_t cs) { enqueue_adjoint_multi(b->probs, W, yin, true, cs); }));
+        b->key_adj = ka;
+    }
+    auto fwd = [&]() -> pat_status {
+        PAT_HIP(hipGraphLaunch(b->g_fwd, s));
+        return PAT_OK;
+    };
+    auto adj = [&]() -> pat_status {
+        PAT_HIP(hipGraphLaunch(b->g_adj, s));
+        return PAT_OK;
+    };
+    std::vector<std::vector<double>> chk(n, std::vector<double>(size_t(((smax + RB - 1) / RB) * RB), 0.0));
+    for (int64_t rb0 = 0; rb0 < smax; rb0 += RB) {
+        std::vector<Solve> blk = proto;
+        for (size_t m = 0; m < n; ++m) {
+            blk[m].rb0 = rb0;
+            build_rhs(blk[m], y_obs[m], &prm[m]);
+        }
+        PAT_TRY(drive(blk, n_iter, fwd, adj));
+        for (size_t m = 0; m < n; ++m) {
+            if (rb0 < S[m]) finish_block(blk[m], &prm[m], samples[m]);
+            PAT_HIP(hipMemcpyAsync(chk[m].data() + rb0, ph_check(blk[m]), RB * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+    }
+    for (size_t m = 0; m < n; ++m) {
+        double *mm = mean ? mean[m] : nullptr, *sd = std ? std[m] : nullptr;
+        if (mm || sd) pat::launch_stats(samples[m], S[m], b->probs[m]->ops.n, mm, sd, s);
+    }
+    PAT_HIP(hipGetLastError());
+    PAT_HIP(hipStreamSynchronize(s));
+    for (size_t m = 0; m < n; ++m)
+        for (int64_t k = 0; k < S[m]; ++k)
+            if (!std::isfinite(chk[m][size_t(k)]))
+                return fail(PAT_ERR_NONFINITE, std::string("non-finite ") + (lsqr ? "LSQR" : "CGLS") +
+                                                   " scalar for problem " + std::to_string(m) + " sample " +
+                                                   std::to_string(k));
+    return PAT_OK;
+}
+
+pat_status pat_spectral_prior_set(pat_problem *p, const pat_spectral_desc *d) {
+    g_err.clear();
+    if (!p) return fail(PAT_ERR_INVALID_ARG, "pat_spectral_prior_set: NULL handle");
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    PAT_HIP(hipDeviceSynchronize());
+    // drop the previous prior and its work buffers
+    for (void *a : p->spec_allocs) dev_free(p, a);
+    p->spec_allocs.clear();
+    for (auto &kv : p->specws) {
+        dev_free(p, kv.second.gr);
+        dev_free(p, kv.second.gc);
+        dev_free(p, kv.second.ym);
+        dev_free(p, kv.second.lx);
+    }
+    p->specws.clear();
+    for (auto it = p->cgls.begin(); it != p->cgls.end();) {  // latent-space solver workspaces
+        if (it->first.second != p->ops.n) {
+            CglsWS &c = it->second;
+            double *bufs[] = {c.x, c.d, c.s, c.rp, c.qp, c.rd, c.qd, c.Q, c.part, c.mpart, c.coef, c.scal,
+                              c.v, c.zp, c.zd, c.lrp, c.lrd};
+            for (double *q : bufs) dev_free(p, q);
+            it = p->cgls.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    p->spec = false;
+    p->sops = pat::SpecOps{};
+    if (!d) return PAT_OK;
+    const int n = d->n;
+    if (n < 8 || n > 128 || (n & (n - 1)))
+        return fail(PAT_ERR_INVALID_ARG, "spectral prior: n must be a power of two in [8, 128]");
+    if (!(d->side > 0.0) || !(d->ell > 0.0) || !(d->sigma > 0.0) || !(d->expo > 0.0) || !std::isfinite(d->side) ||
+        !std::isfinite(d->ell) || !std::isfinite(d->sigma) || !std::isfinite(d->expo) || !std::isfinite(d->lo[0]) ||
+        !std::isfinite(d->lo[1]) || !std::isfinite(d->lo[2]))
+        return fail(PAT_ERR_INVALID_ARG, "spectral prior: side, ell, sigma and expo must be positive and finite");
+    const int64_t G = int64_t(n) * n * n, N = p->ops.n;
+    const double h = d->side / n;
+    // square-root spectrum a(k) = c (ell^-2 + |k|^2)^(-expo/2), c giving pointwise variance sigma^2
+    std::vector<double> amp(static_cast<size_t>(G));
+    double sum = 0.0;
+    for (int64_t g = 0; g < G; ++g) {
+        const int64_t f[3] = {g % n, (g / n) % n, g / (int64_t(n) * n)};
+        double k2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double fa = double(f[a] < n / 2 ? f[a] : f[a] - n);
+            const double ka = 2.0 * M_PI * fa / d->side;
+            k2 += ka * ka;
+        }
+        amp[size_t(g)] = std::pow(1.0 / (d->ell * d->ell) + k2, -0.5 * d->expo);
+        sum += amp[size_t(g)] * amp[size_t(g)];
+    }
+    const double c = d->sigma * std::sqrt(double(G) / sum);
+    for (double &v : amp) v *= c;
+    std::vector<double> tw(static_cast<size_t>(n));  // (re, im) pairs of exp(-2 pi i j / n), j < n/2
+    for (int j = 0; j < n / 2; ++j) {
+        tw[size_t(2 * j)] = std::cos(2.0 * M_PI * j / n);
+        tw[size_t(2 * j + 1)] = -std::sin(2.0 * M_PI * j / n);
+    }
+    // trilinear interpolation rows (internal node order) and their transpose by grid point
+    std::vector<int32_t> ig(static_cast<size_t>(N) * 8);
+    std::vector<double> iw(static_cast<size_t>(N) * 8);
+    for (int64_t q = 0; q < N; ++q) {
+        int64_t i0[3];
+        double fr[3];
+        for (int a = 0; a < 3; ++a) {
+            const double t = (p->xyz[size_t(q) * 3 + a] - d->lo[a]) / h;
+            if (!(t >= 0.0) || !(t < double(n)))
+                return fail(PAT_ERR_INVALID_ARG, "spectral prior: a mesh node lies outside the grid box");
+            i0[a] = int64_t(std::floor(t));
+            fr[a] = t - double(i0[a]);
+        }
+        int c8 = 0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx, ++c8) {
+                    const double wgt = (dx ? fr[0] : 1.0 - fr[0]) * (dy ? fr[1] : 1.0 - fr[1]) * (dz ? fr[2] : 1.0 - fr[2]);
+                    const int64_t ix = (i0[0] + dx) % n, iy = (i0[1] + dy) % n, iz = (i0[2] + dz) % n;
+                    ig[size_t(q * 8 + c8)] = int32_t((iz * n + iy) * n + ix);
+                    iw[size_t(q * 8 + c8)] = wgt;
+                }
+    }
+    std::vector<int32_t> tptr(static_cast<size_t>(G) + 1, 0), tq(static_cast<size_t>(N) * 8);
+    std::vector<double> tw8(static_cast<size_t>(N) * 8);
+    for (int64_t e = 0; e < N * 8; ++e) ++tptr[size_t(ig[size_t(e)]) + 1];
+    for (int64_t g = 0; g < G; ++g) tptr[size_t(g) + 1] += tptr[size_t(g)];
+    std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t e = 0; e < N * 8; ++e) {
+        const int32_t g = ig[size_t(e)];
+        tq[size_t(fill[size_t(g)])] = int32_t(e / 8);
+        tw8[size_t(fill[size_t(g)]++)] = iw[size_t(e)];
+    }
+    pat::SpecOps so;
+    so.n = n;
+    so.logn = 0;
+    while ((1 << so.logn) < n) ++so.logn;
+    so.G = G;
+    const size_t before = p->allocs.size();
+    auto up = [&](const auto &vec, const auto **field) -> pat_status {
+        pat_status st = upload(p, vec, field);
+        return st;
+    };
+    pat_status st = PAT_OK;
+    if (st == PAT_OK) st = up(amp, &so.amp);
+    if (st == PAT_OK) st = up(tw, &so.tw);
+    if (st == PAT_OK) st = up(ig, &so.ig);
+    if (st == PAT_OK) st = up(iw, &so.iw);
+    if (st == PAT_OK) st = up(tptr, &so.tptr);
+    if (st == PAT_OK) st = up(tq, &so.tq);
+    if (st == PAT_OK) st = up(tw8, &so.tw8);
+    for (size_t k = before; k < p->allocs.size(); ++k) p->spec_allocs.push_back(p->allocs[k]);
+    if (st != PAT_OK) {
+        for (void *a : p->spec_allocs) dev_free(p, a);
+        p->spec_allocs.clear();
+        return st;
+    }
+    p->sops = so;
+    p->spec_desc = *d;
+    p->spec = true;
+    return PAT_OK;
+}
+
+pat_status pat_spectral_apply(pat_problem *p, int64_t R, int transpose, const double *x, double *y, void *stream) {
+    g_err.clear();
+    if (!p || !x || !y || R < 1) return fail(PAT_ERR_INVALID_ARG, "pat_spectral_apply: NULL pointer or R < 1");
+    if (!p->spec) return fail(PAT_ERR_INVALID_ARG, "pat_spectral_apply: no spectral prior set");
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int RB = choose_rb(R);
+    SpecWS *sw;
+    PAT_TRY(get_spec(p, RB, &sw));
+    const int64_t N = p->ops.n, G = p->sops.G;
+    const int32_t *perm = p->perm_identity ? nullptr : p->ops.perm;
+    for (int64_t rb0 = 0; rb0 < R; rb0 += RB) {
+        if (!transpose) {
+            pat::launch_pack(true, true, x, R, rb0, RB, G, nullptr, sw->lx, s);
+            pat::launch_spectral(p->sops, RB, sw->lx, sw->gr, sw->gc, pat::Prec::F64, sw->ym, N, s);
+            pat::launch_unpack(true, true, sw->ym, R, rb0, RB, N, perm, y, s);
+        } else {
+            pat::launch_pack(true, true, x, R, rb0, RB, N, perm, sw->ym, s);
+            pat::launch_spectral_t(p->sops, RB, sw->ym, pat::Prec::F64, 1.0, nullptr, sw->gr, sw->gc, sw->lx, s);
+            pat::launch_unpack(true, true, sw->lx, R, rb0, RB, G, nullptr, y, s);
+        }
+    }
+    PAT_HIP(hipGetLastError());
     return PAT_OK;
 }
 

@@ -43,6 +43,54 @@ void launch_adj_init(Prec prec, int RB, const DevOps &op, void *PH, void *Q, con
 void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1,
                      const void *yhat, bool y_is_f64, double yscale, hipStream_t s);
 
+// Several meshes' steps in one launch (vector-lane kernels only: RB * sizeof(T) >= 16,
+// see multi_step_supported; at most kMaxMeshes meshes).  Each entry is one mesh's
+// arguments of launch_fwd_step / launch_adj_step; all share prec, RB and y type.
+constexpr int kMaxMeshes = 4;
+struct FwdStep {
+    const DevOps *op;
+    const void *P, *V;
+    void *Pn, *Vn;
+    bool rows, first, sample;
+    int t;
+    void *y;
+    double yscale;
+};
+struct AdjStep {
+    const DevOps *op;
+    void *PH;
+    const void *Q;
+    void *Qn;
+    bool last;
+    int tm1;
+    const void *yh;
+    double yscale;
+};
+bool multi_step_supported(Prec prec, int RB);
+void launch_fwd_multi(Prec prec, int RB, bool y_is_f64, const FwdStep *st, int n, hipStream_t s);
+void launch_adj_multi(Prec prec, int RB, bool y_is_f64, const AdjStep *st, int n, hipStream_t s);
+
+// Whittle-Matern spectral prior (pat_spectral.hip): p0 = P w, P = I_h F^* diag(a) F on a
+// periodic n^3 grid (G = n^3 points, index (k*n + j)*n + i), I_h trilinear to the nodes.
+struct SpecOps {
+    int n = 0, logn = 0;
+    int64_t G = 0;
+    const double *amp = nullptr;                   // a(k) [G]
+    const double *tw = nullptr;                    // exp(-2 pi i j / n), j < n/2, as (re, im) pairs
+    const int32_t *ig = nullptr;                   // [N][8] grid corners of each (internal) node
+    const double *iw = nullptr;                    // [N][8] trilinear weights
+    const int32_t *tptr = nullptr, *tq = nullptr;  // transpose of I_h by grid point (CSR: nodes)
+    const double *tw8 = nullptr;                   // its weights
+};
+bool spectral_rb_ok(int RB);
+// y (mesh [N][RB], float64 or the sweep type) = P x, x latent [G][RB] float64;
+// gr [G][RB] and gc [G][RB] complex are work buffers
+void launch_spectral(const SpecOps &sp, int RB, const double *x, double *gr, double *gc, Prec out_prec, void *y,
+                     int64_t N, hipStream_t s);
+// y (latent [G][RB]) = scale * P^T v + add (add may be null); v mesh [N][RB] in in_prec
+void launch_spectral_t(const SpecOps &sp, int RB, const void *v, Prec in_prec, double scale, const double *add,
+                       double *gr, double *gc, double *y, hipStream_t s);
+
 // Layout conversions.  Node vectors: user [R][N] (rows rb0..rb0+RB-1, zero-padded
 // past R) <-> internal [N][RB]; data: user [R][M] <-> internal [M][RB].
 void launch_pack(bool in_f64, bool out_f64, const void *in, int64_t R, int64_t rb0, int RB, int64_t cols,

@@ -304,6 +304,20 @@ struct Vec16<double> {
 #ifndef PAT_NTS
 #define PAT_NTS 0
 #endif
+//   PAT_VWPE waves per SIMD the register allocation of the float32 step kernels must
+//            allow (float64 ones: at most 5); 0 leaves it to the compiler
+#ifndef PAT_VWPE
+#define PAT_VWPE 8
+#endif
+// waves per SIMD to ask for: the setting above, capped by what the tile's LDS image
+// allows (160 KiB per CU; one 4-wave workgroup per tile, one wave per SIMD)
+template <typename T, int RB, typename Ops>
+constexpr int vwaves() {
+    const int want = PAT_VWPE == 0 ? 1 : sizeof(T) == 4 ? PAT_VWPE : (PAT_VWPE < 5 ? PAT_VWPE : 5);
+    const int lds = int(163840 / sizeof(Ops));
+    return want < lds ? want : (lds > 0 ? lds : 1);
+}
+#define PAT_VOCC(T, RB) __attribute__((amdgpu_waves_per_eu(vwaves<T, RB, TileOps<T, RB>>())))
 
 template <typename VT, typename T>
 __device__ __forceinline__ void vstore(T *p, VT v) {
@@ -377,9 +391,11 @@ __device__ __forceinline__ VT vfma(T w, VT x, VT acc) {
     return o;
 }
 
-// acc += sum_slots K(row, slot) X[col][q-th vector]; with Bs, bacc += B(row, slot) Y[col]
-// (Y == X shares the gathers); then the overflow entries of long rows.
-template <typename T, int RB, bool Y_IS_X>
+// acc += sum_slots K(row, slot) X[col][q-th vector]; with_b: bacc += B(row, slot) Y[col].
+// The B sums (boundary rows only) run after the K sums have been consumed, with
+// their own gathers, so the two sets of gathers are never live together and the
+// kernel keeps the register budget (and occupancy) of the interior rows.
+template <typename T, int RB>
 __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, RB> &L, int lr, int q,
                                           const T *__restrict__ X, const T *__restrict__ Y, bool with_b,
                                           typename Vec16<T>::t &acc, typename Vec16<T>::t &bacc) {
@@ -387,35 +403,43 @@ __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, R
     using VT = typename Vec16<T>::t;
     const int base = lr * G::W;
     constexpr int CH = PAT_VCH;
+    // 32-bit byte offsets from the uniform bases (state arrays are < 4 GiB)
+    const char *Xc = reinterpret_cast<const char *>(X);
+    const char *Yc = reinterpret_cast<const char *>(Y);
+    const uint32_t qoff = uint32_t(q) * 16u;
+    constexpr uint32_t ROWB = uint32_t(RB * sizeof(T));
 #pragma unroll
     for (int j0 = 0; j0 < G::W; j0 += CH) {
         VT x[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j)
-            x[j] = *reinterpret_cast<const VT *>(X + int64_t(L.col[base + j0 + j]) * RB + q * G::VEC);
+            x[j] = *reinterpret_cast<const VT *>(Xc + (uint32_t(L.col[base + j0 + j]) * ROWB + qoff));
 #pragma unroll
         for (int j = 0; j < CH; ++j) acc = vfma(L.kv[base + j0 + j], x[j], acc);
-        if (with_b) {
-            if constexpr (Y_IS_X) {
-#pragma unroll
-                for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[base + j0 + j], x[j], bacc);
-            } else {
-#pragma unroll
-                for (int j = 0; j < CH; ++j)
-                    x[j] = *reinterpret_cast<const VT *>(Y + int64_t(L.col[base + j0 + j]) * RB + q * G::VEC);
-#pragma unroll
-                for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[base + j0 + j], x[j], bacc);
-            }
-        }
     }
     const int x0 = L.x0[lr], x1 = L.x1[lr];
     for (int k = x0; k < x1; ++k) {
-        const int64_t cj = int64_t(o.xcol[k]) * RB + q * G::VEC;
-        const VT xv = *reinterpret_cast<const VT *>(X + cj);
+        const VT xv = *reinterpret_cast<const VT *>(Xc + (uint32_t(o.xcol[k]) * ROWB + qoff));
         acc = vfma(o.xval[k], xv, acc);
+    }
+    {
         if (with_b) {
-            const T bw = o.bslot[L.bo[lr] + G::W + (k - x0)];
-            bacc = vfma(bw, Y_IS_X ? xv : *reinterpret_cast<const VT *>(Y + cj), bacc);
+            // re-read the slot operands from LDS instead of keeping them live across the K sums
+            int bbase = base;
+            asm volatile("" : "+v"(bbase));
+#pragma unroll
+            for (int j0 = 0; j0 < G::W; j0 += CH) {
+                VT y[CH];
+#pragma unroll
+                for (int j = 0; j < CH; ++j)
+                    y[j] = *reinterpret_cast<const VT *>(Yc + (uint32_t(L.col[bbase + j0 + j]) * ROWB + qoff));
+#pragma unroll
+                for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[bbase + j0 + j], y[j], bacc);
+            }
+            for (int k = x0; k < x1; ++k) {
+                const VT yv = *reinterpret_cast<const VT *>(Yc + (uint32_t(o.xcol[k]) * ROWB + qoff));
+                bacc = vfma(o.bslot[L.bo[lr] + G::W + (k - x0)], yv, bacc);
+            }
         }
     }
 }
@@ -433,14 +457,13 @@ struct VFwdArgs {
     T dt, half_dt;
 };
 
-// Forward step (same update as k_fwd) with vector lanes; the workgroups after
-// the row tiles write the samples y^n = Pi (P - dt/2 V) of the incoming state.
+// Forward step (same update as k_fwd) with vector lanes on logical tile `tile`;
+// the tiles after the row tiles write the samples y^n = Pi (P - dt/2 V) of the
+// incoming state.
 template <typename T, typename OT, int RB>
-__global__ void __launch_bounds__(256) k_fwd_v(const VFwdArgs<T> a) {
+__device__ __forceinline__ void fwd_tile(const VFwdArgs<T> &a, int tile, TileOps<T, RB> &L) {
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
-    __shared__ TileOps<T, RB> L;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile < a.n_tiles) {
         const int row0 = tile * G::RPB;
         stage_tile<T, RB>(a.o, a.n, row0, !a.first, L);
@@ -453,7 +476,7 @@ __global__ void __launch_bounds__(256) k_fwd_v(const VFwdArgs<T> a) {
             if (!a.first) v0 = *reinterpret_cast<const VT *>(a.V + id);
             const VT p0 = *reinterpret_cast<const VT *>(a.P + id);
             VT acc = {}, bacc = {};
-            vrow_sums<T, RB, false>(a.o, L, lr, q, a.P, a.V, !a.first && L.bo[lr] >= 0, acc, bacc);
+            vrow_sums<T, RB>(a.o, L, lr, q, a.P, a.V, !a.first && L.bo[lr] >= 0, acc, bacc);
             const T dm = L.dm[lr];
             VT v, pn;
 #pragma unroll
@@ -480,6 +503,38 @@ __global__ void __launch_bounds__(256) k_fwd_v(const VFwdArgs<T> a) {
     }
 }
 
+template <typename T, typename OT, int RB>
+__global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_v(const VFwdArgs<T> a) {
+    __shared__ TileOps<T, RB> L;
+    fwd_tile<T, OT, RB>(a, xcd_tile(blockIdx.x, gridDim.x), L);
+}
+
+// Several meshes in one launch: mesh m owns logical tiles [end[m-1], end[m]).
+template <typename A>
+struct Multi {
+    A a[kMaxMeshes];
+    int end[kMaxMeshes];
+    int n;
+};
+
+__device__ __forceinline__ int mesh_of(const int *end, int n, int tile, int *local) {
+    int m = 0, begin = 0;
+    while (m + 1 < n && tile >= end[m]) {
+        begin = end[m];
+        ++m;
+    }
+    *local = tile - begin;
+    return m;
+}
+
+template <typename T, typename OT, int RB>
+__global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_vm(const Multi<VFwdArgs<T>> mm) {
+    __shared__ TileOps<T, RB> L;
+    int local;
+    const int m = mesh_of(mm.end, mm.n, xcd_tile(blockIdx.x, gridDim.x), &local);
+    fwd_tile<T, OT, RB>(mm.a[m], local, L);
+}
+
 template <typename T>
 struct VAdjArgs {
     RowOps<T> o;
@@ -494,13 +549,11 @@ struct VAdjArgs {
     T dt;
 };
 
-// Transposed step (same update as k_adj) with vector lanes.
+// Transposed step (same update as k_adj) with vector lanes on logical tile `tile`.
 template <typename T, typename YT, int RB>
-__global__ void __launch_bounds__(256) k_adj_v(const VAdjArgs<T> a) {
+__device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps<T, RB> &L) {
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
-    __shared__ TileOps<T, RB> L;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= a.n_tiles) return;
     const int row0 = tile * G::RPB;
     stage_tile<T, RB>(a.o, a.n, row0, !a.last, L);
@@ -513,7 +566,7 @@ __global__ void __launch_bounds__(256) k_adj_v(const VAdjArgs<T> a) {
     VT q0 = {};
     if (!a.last) q0 = *reinterpret_cast<const VT *>(a.Q + id);
     VT kq = {}, bq = {};
-    vrow_sums<T, RB, true>(a.o, L, lr, q, a.Q, a.Q, !a.last && L.bo[lr] >= 0, kq, bq);
+    vrow_sums<T, RB>(a.o, L, lr, q, a.Q, a.Q, !a.last && L.bo[lr] >= 0, kq, bq);
     VT ph;
 #pragma unroll
     for (int i = 0; i < G::VEC; ++i) ph[i] = ph0[i] - a.dt * kq[i];
@@ -537,6 +590,20 @@ __global__ void __launch_bounds__(256) k_adj_v(const VAdjArgs<T> a) {
         vstore<VT>(a.Qn + id, qn);
     }
     vstore<VT>(a.PH + id, ph);
+}
+
+template <typename T, typename YT, int RB>
+__global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_v(const VAdjArgs<T> a) {
+    __shared__ TileOps<T, RB> L;
+    adj_tile<T, YT, RB>(a, xcd_tile(blockIdx.x, gridDim.x), L);
+}
+
+template <typename T, typename YT, int RB>
+__global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdjArgs<T>> mm) {
+    __shared__ TileOps<T, RB> L;
+    int local;
+    const int m = mesh_of(mm.end, mm.n, xcd_tile(blockIdx.x, gridDim.x), &local);
+    adj_tile<T, YT, RB>(mm.a[m], local, L);
 }
 
 // p_hat = Pi^T yhat^{N_T}, q = (dt/2m) p_hat
@@ -1035,9 +1102,9 @@ const double *injw_of<double>(const DevOps &op) { return op.injw64; }
 template <>
 const float *injw_of<float>(const DevOps &op) { return op.injw32; }
 
-template <typename T, typename OT, int RB>
-void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
-                int t, void *y, double yscale, hipStream_t s) {
+template <typename T, int RB>
+VFwdArgs<T> fwd_args_v(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first,
+                       bool sample, int t, void *y, double yscale, int *blocks) {
     using G = VGeo<T, RB>;
     VFwdArgs<T> a;
     a.o = row_ops<T>(op);
@@ -1051,13 +1118,36 @@ void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *
     a.first = first; a.sample = sample; a.t = t;
     a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
     const int sblocks = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
-    const int grid = a.n_tiles + sblocks;
+    *blocks = a.n_tiles + sblocks;
+    return a;
+}
+
+template <typename T, typename OT, int RB>
+void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
+                int t, void *y, double yscale, hipStream_t s) {
+    int grid = 0;
+    const VFwdArgs<T> a = fwd_args_v<T, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, &grid);
     if (grid > 0) hipLaunchKernelGGL((k_fwd_v<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
 }
 
-template <typename T, typename YT, int RB>
-void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
-                double yscale, hipStream_t s) {
+template <typename T, typename OT, int RB>
+void fwd_impl_vm(const FwdStep *st, int n, hipStream_t s) {
+    Multi<VFwdArgs<T>> mm{};
+    int total = 0;
+    for (int m = 0; m < n; ++m) {
+        int b = 0;
+        mm.a[m] = fwd_args_v<T, RB>(*st[m].op, st[m].P, st[m].V, st[m].Pn, st[m].Vn, st[m].rows, st[m].first,
+                                    st[m].sample, st[m].t, st[m].y, st[m].yscale, &b);
+        total += b;
+        mm.end[m] = total;
+    }
+    mm.n = n;
+    if (total > 0) hipLaunchKernelGGL((k_fwd_vm<T, OT, RB>), dim3(total), dim3(256), 0, s, mm);
+}
+
+template <typename T, int RB>
+VAdjArgs<T> adj_args_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
+                       double yscale) {
     using G = VGeo<T, RB>;
     VAdjArgs<T> a;
     a.o = row_ops<T>(op);
@@ -1068,7 +1158,28 @@ void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, 
     a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
     a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
     a.dt = T(op.dt);
+    return a;
+}
+
+template <typename T, typename YT, int RB>
+void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
+                double yscale, hipStream_t s) {
+    const VAdjArgs<T> a = adj_args_v<T, RB>(op, PH, Q, Qn, last, tm1, yh, yscale);
     hipLaunchKernelGGL((k_adj_v<T, YT, RB>), dim3(a.n_tiles), dim3(256), 0, s, a);
+}
+
+template <typename T, typename YT, int RB>
+void adj_impl_vm(const AdjStep *st, int n, hipStream_t s) {
+    Multi<VAdjArgs<T>> mm{};
+    int total = 0;
+    for (int m = 0; m < n; ++m) {
+        mm.a[m] = adj_args_v<T, RB>(*st[m].op, st[m].PH, st[m].Q, st[m].Qn, st[m].last, st[m].tm1, st[m].yh,
+                                    st[m].yscale);
+        total += mm.a[m].n_tiles;
+        mm.end[m] = total;
+    }
+    mm.n = n;
+    hipLaunchKernelGGL((k_adj_vm<T, YT, RB>), dim3(total), dim3(256), 0, s, mm);
 }
 
 template <typename T, typename OT, int RB>
@@ -1120,6 +1231,15 @@ void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bo
     }
 }
 
+template <typename T, typename OT, int RB>
+void fwd_multi(const FwdStep *st, int n, hipStream_t s) {
+    if constexpr (RB * sizeof(T) >= 16) fwd_impl_vm<T, OT, RB>(st, n, s);
+}
+template <typename T, typename YT, int RB>
+void adj_multi(const AdjStep *st, int n, hipStream_t s) {
+    if constexpr (RB * sizeof(T) >= 16) adj_impl_vm<T, YT, RB>(st, n, s);
+}
+
 #define PAT_RB_SWITCH(RBV, CALL)               \
     switch (RBV) {                             \
         case 1: { constexpr int RB_ = 1; CALL; break; }   \
@@ -1164,6 +1284,28 @@ void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *
         PAT_RB_SWITCH(RB, (adj_impl<float, double, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
     } else {
         PAT_RB_SWITCH(RB, (adj_impl<float, float, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
+    }
+}
+
+bool multi_step_supported(Prec prec, int RB) { return RB * (prec == Prec::F64 ? 8 : 4) >= 16; }
+
+void launch_fwd_multi(Prec prec, int RB, bool y_is_f64, const FwdStep *st, int n, hipStream_t s) {
+    if (prec == Prec::F64) {
+        PAT_RB_SWITCH(RB, (fwd_multi<double, double, RB_>(st, n, s)));
+    } else if (y_is_f64) {
+        PAT_RB_SWITCH(RB, (fwd_multi<float, double, RB_>(st, n, s)));
+    } else {
+        PAT_RB_SWITCH(RB, (fwd_multi<float, float, RB_>(st, n, s)));
+    }
+}
+
+void launch_adj_multi(Prec prec, int RB, bool y_is_f64, const AdjStep *st, int n, hipStream_t s) {
+    if (prec == Prec::F64) {
+        PAT_RB_SWITCH(RB, (adj_multi<double, double, RB_>(st, n, s)));
+    } else if (y_is_f64) {
+        PAT_RB_SWITCH(RB, (adj_multi<float, double, RB_>(st, n, s)));
+    } else {
+        PAT_RB_SWITCH(RB, (adj_multi<float, float, RB_>(st, n, s)));
     }
 }
 

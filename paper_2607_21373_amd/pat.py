@@ -63,16 +63,25 @@ class RtoParams(ctypes.Structure):
         ("sigma", ctypes.c_double), ("prior_a", ctypes.c_double), ("n_iter", ctypes.c_int32),
         ("reorth", ctypes.c_int32), ("sweep_prec", ctypes.c_int), ("rhs_block", ctypes.c_int32),
         ("eta", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("solver", ctypes.c_int32), ("diag_hist", ctypes.c_void_p),
-        ("seed", ctypes.c_uint64), ("sample0", ctypes.c_int64),
+        ("seed", ctypes.c_uint64), ("sample0", ctypes.c_int64), ("prior", ctypes.c_int32),
+        ("latent", ctypes.c_void_p),
     ]
 
 
 PAT_CGLS, PAT_LSQR = 0, 1
+PAT_PRIOR_FE, PAT_PRIOR_SPECTRAL = 0, 1
+
+
+class SpectralDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("lo", ctypes.c_double * 3), ("side", ctypes.c_double),
+                ("ell", ctypes.c_double), ("sigma", ctypes.c_double), ("expo", ctypes.c_double)]
 
 
 # names exported by libpat (the C ABI in include/pat.h)
 EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-           "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_host_assemble", "pat_profile_enable",
+           "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_spectral_prior_set", "pat_spectral_apply",
+           "pat_autotune", "pat_batch_create",
+           "pat_batch_destroy", "pat_batch_autotune", "rto_sample_batch", "pat_host_assemble", "pat_profile_enable",
            "pat_profile_get", "pat_sync", "pat_last_error", "pat_version")
 
 _lib = None
@@ -101,12 +110,20 @@ def load() -> ctypes.CDLL:
     lib.pat_draw_normals.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                      vp, vp]
     lib.pat_profile_get.argtypes = [vp, ctypes.POINTER(Profile)]
+    i32p, f64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    lib.pat_autotune.argtypes = [vp, ctypes.c_int64, ctypes.c_int, i32p, f64p, vp]
+    lib.pat_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.pat_batch_destroy.argtypes = [vp]
+    lib.pat_spectral_prior_set.argtypes = [vp, ctypes.POINTER(SpectralDesc)]
+    lib.pat_spectral_apply.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp, vp, vp]
+    lib.pat_batch_autotune.argtypes = [vp, ctypes.c_int64, ctypes.c_int, i32p, f64p, vp]
+    lib.rto_sample_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(RtoParams), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.pat_last_error.restype = ctypes.c_char_p
     lib.pat_version.restype = ctypes.c_char_p
-    for f in ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
-              "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_host_assemble", "pat_profile_enable", "pat_profile_get",
-              "pat_sync"):
-        getattr(lib, f).restype = ctypes.c_int
+    for f in EXPORTS:
+        if f not in ("pat_last_error", "pat_version"):
+            getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -283,18 +300,38 @@ def pat_prior_apply(problem: Problem, x, prior_a: float, transpose: bool = False
     return y
 
 
-def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n_iter: int, reorth: bool = True,
-               sweep_prec: str = "f64", rhs_block: int = 0, stats: bool = True, resid: bool = False,
-               samples=None, solver: str = "cgls", diag: bool = False, n_samples: int = None, seed: int = 0,
-               sample0: int = 0):
-    """RTO posterior samples (Algorithm 1) through libpat's rto_sample.
+def spectral_prior_set(problem: Problem, n: int, lo, side: float, ell: float, sigma: float, expo: float = 3.0):
+    """pat_spectral_prior_set: Whittle-Matern prior on an n^3 grid over [lo, lo + side)^3 (None clears)."""
+    if n is None:
+        _check(load().pat_spectral_prior_set(problem._h, None))
+        problem.spectral_size = None
+        return
+    d = SpectralDesc()
+    d.n = int(n)
+    d.lo[0], d.lo[1], d.lo[2] = (float(v) for v in (lo if hasattr(lo, "__len__") else (lo, lo, lo)))
+    d.side, d.ell, d.sigma, d.expo = float(side), float(ell), float(sigma), float(expo)
+    _check(load().pat_spectral_prior_set(problem._h, ctypes.byref(d)))
+    problem.spectral_size = int(n) ** 3
 
-    y_obs [N_T][N_obs], eta [S][N_T][N_obs], xi [S][N]: float64 CUDA tensors.
-    With eta = xi = None the library draws them itself (streams seed,
-    sample0 + k; see draw_normals) and n_samples gives S.
-    solver: "cgls" or "lsqr" (Sec. 5.2, App. A).
-    Returns a dict with samples [S][N] and, if requested, mean, std [N],
-    resid [S][n_iter+1] and diag [S][n_iter+1][2] (data and prior residual norms)."""
+
+def spectral_apply(problem: Problem, x, transpose: bool = False):
+    """y = P x (x [R][n^3] -> [R][N]) or P^T x (x [R][N] -> [R][n^3]), float64 CUDA tensors."""
+    import torch
+    G = getattr(problem, "spectral_size", None)
+    if G is None:
+        raise ValueError("no spectral prior set on this problem")
+    R = x.shape[0]
+    rows_in, rows_out = (problem.n_nodes, G) if transpose else (G, problem.n_nodes)
+    xp = _dev_ptr(x, torch.float64, (R, rows_in), "x")
+    y = torch.empty((R, rows_out), dtype=torch.float64, device=x.device)
+    _check(load().pat_spectral_apply(problem._h, R, int(bool(transpose)), xp, ctypes.c_void_p(y.data_ptr()),
+                                     _stream()))
+    return y
+
+
+def _rto_call(problem, y_obs, eta, xi, sigma, prior_a, n_iter, reorth, sweep_prec, rhs_block, stats, resid, samples,
+              solver, diag, n_samples, seed, sample0, prior="fe", latent=False):
+    """Allocate outputs and fill RtoParams for one problem; returns (prm, S, outputs, pointers)."""
     import torch
     f64 = torch.float64
     if (eta is None) != (xi is None):
@@ -308,15 +345,22 @@ def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n
         S = int(n_samples)
         dev = y_obs.device
     N, T, O = problem.n_nodes, problem.n_steps, problem.n_obs
+    NX = N
+    if prior == "spectral":
+        NX = getattr(problem, "spectral_size", None)
+        if NX is None:
+            raise ValueError("no spectral prior set on this problem")
     if samples is None:
         samples = torch.empty((S, N), dtype=f64, device=dev)
-    mean = torch.empty(N, dtype=f64, device=dev) if stats else None
-    std = torch.empty(N, dtype=f64, device=dev) if stats and S >= 2 else None
-    res = torch.empty((S, n_iter + 1), dtype=f64, device=dev) if resid else None
-    dg = torch.empty((S, n_iter + 1, 2), dtype=f64, device=dev) if diag else None
+    out = {"latent": torch.empty((S, NX), dtype=f64, device=dev) if latent and prior == "spectral" else None,
+           "samples": samples,
+           "mean": torch.empty(N, dtype=f64, device=dev) if stats else None,
+           "std": torch.empty(N, dtype=f64, device=dev) if stats and S >= 2 else None,
+           "resid": torch.empty((S, n_iter + 1), dtype=f64, device=dev) if resid else None,
+           "diag": torch.empty((S, n_iter + 1, 2), dtype=f64, device=dev) if diag else None}
     prm = RtoParams()
     prm.solver = {"cgls": PAT_CGLS, "lsqr": PAT_LSQR}[solver]
-    prm.diag_hist = dg.data_ptr() if dg is not None else None
+    prm.diag_hist = out["diag"].data_ptr() if diag else None
     prm.sigma = float(sigma)
     prm.prior_a = float(prior_a)
     prm.n_iter = int(n_iter)
@@ -325,16 +369,106 @@ def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n
     prm.rhs_block = int(rhs_block)
     prm.seed = int(seed)
     prm.sample0 = int(sample0)
+    prm.prior = {"fe": PAT_PRIOR_FE, "spectral": PAT_PRIOR_SPECTRAL}[prior]
+    prm.latent = out["latent"].data_ptr() if out["latent"] is not None else None
     if eta is not None:
         prm.eta = _dev_ptr(eta, f64, (S, T, O), "eta")
-        prm.xi = _dev_ptr(xi, f64, (S, N), "xi")
-    yp = _dev_ptr(y_obs, f64, (T, O), "y_obs")
-    sp = _dev_ptr(samples, f64, (S, N), "samples")
-    mp = ctypes.c_void_p(mean.data_ptr()) if mean is not None else None
-    dp = ctypes.c_void_p(std.data_ptr()) if std is not None else None
-    rp = ctypes.c_void_p(res.data_ptr()) if res is not None else None
-    _check(load().rto_sample(problem._h, yp, ctypes.byref(prm), S, sp, mp, dp, rp, _stream()))
-    return {"samples": samples, "mean": mean, "std": std, "resid": res, "diag": dg}
+        prm.xi = _dev_ptr(xi, f64, (S, NX), "xi")
+    ptr = {"y": _dev_ptr(y_obs, f64, (T, O), "y_obs"), "samples": _dev_ptr(samples, f64, (S, N), "samples")}
+    for k in ("mean", "std", "resid"):
+        ptr[k] = ctypes.c_void_p(out[k].data_ptr()) if out[k] is not None else None
+    return prm, S, out, ptr
+
+
+def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n_iter: int, reorth: bool = True,
+               sweep_prec: str = "f64", rhs_block: int = 0, stats: bool = True, resid: bool = False,
+               samples=None, solver: str = "cgls", diag: bool = False, n_samples: int = None, seed: int = 0,
+               sample0: int = 0, prior: str = "fe", latent: bool = False):
+    """RTO posterior samples (Algorithm 1) through libpat's rto_sample.
+
+    y_obs [N_T][N_obs], eta [S][N_T][N_obs], xi [S][N]: float64 CUDA tensors.
+    With eta = xi = None the library draws them itself (streams seed,
+    sample0 + k; see draw_normals) and n_samples gives S.
+    solver: "cgls" or "lsqr" (Sec. 5.2, App. A).
+    prior: "fe" (the factor L with prior_a) or "spectral" (the Whittle-Matern prior set
+    with spectral_prior_set; xi is then [S][n^3] and latent=True also returns the
+    latent samples).
+    Returns a dict with samples [S][N] and, if requested, mean, std [N],
+    resid [S][n_iter+1] and diag [S][n_iter+1][2] (data and prior residual norms)."""
+    prm, S, out, ptr = _rto_call(problem, y_obs, eta, xi, sigma, prior_a, n_iter, reorth, sweep_prec, rhs_block, stats,
+                                 resid, samples, solver, diag, n_samples, seed, sample0, prior, latent)
+    _check(load().rto_sample(problem._h, ptr["y"], ctypes.byref(prm), S, ptr["samples"], ptr["mean"], ptr["std"],
+                             ptr["resid"], _stream()))
+    return out
+
+
+def autotune(problem: Problem, n_samples: int, sweep_prec: str = "f32"):
+    """pat_autotune: the RHS block rto_sample(rhs_block=0) will use for n_samples; returns (block, priced us/step)."""
+    rb, us = ctypes.c_int32(), ctypes.c_double()
+    _check(load().pat_autotune(problem._h, int(n_samples), {"f64": PAT_F64, "f32": PAT_F32}[sweep_prec],
+                               ctypes.byref(rb), ctypes.byref(us), _stream()))
+    return rb.value, us.value
+
+
+class Batch:
+    """Handle on several problems sampled together (pat_batch_create / rto_sample_batch)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (ctypes.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(load().pat_batch_create(arr, len(self.problems), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pat_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def autotune(self, n_samples: int, sweep_prec: str = "f32"):
+        rb, us = ctypes.c_int32(), ctypes.c_double()
+        _check(load().pat_batch_autotune(self._h, int(n_samples), {"f64": PAT_F64, "f32": PAT_F32}[sweep_prec],
+                                         ctypes.byref(rb), ctypes.byref(us), _stream()))
+        return rb.value, us.value
+
+
+def rto_sample_batch(batch: Batch, y_obs, eta, xi, sigma, prior_a, n_iter: int, reorth: bool = True,
+                     sweep_prec: str = "f32", rhs_block: int = 0, stats: bool = True, resid: bool = False,
+                     solver: str = "cgls", diag: bool = False, n_samples=None, seed=0, sample0=0):
+    """rto_sample for every problem of the batch in one call (sweeps merged per time step).
+
+    Per-problem lists: y_obs, eta, xi (entries None for device draws), sigma,
+    prior_a, n_samples, seed, sample0 (scalars are broadcast).  Returns one
+    result dict per problem."""
+    n = len(batch.problems)
+
+    def per(v):
+        return list(v) if isinstance(v, (list, tuple)) else [v] * n
+
+    eta, xi, sigma, prior_a = per(eta), per(xi), per(sigma), per(prior_a)
+    n_samples, seed, sample0 = per(n_samples), per(seed), per(sample0)
+    prms = (RtoParams * n)()
+    S = (ctypes.c_int64 * n)()
+    ys, smp, mn, sd, rs = [(ctypes.c_void_p * n)() for _ in range(5)]
+    outs = []
+    for m, p in enumerate(batch.problems):
+        prm, S[m], out, ptr = _rto_call(p, y_obs[m], eta[m], xi[m], sigma[m], prior_a[m], n_iter, reorth, sweep_prec,
+                                        rhs_block, stats, resid, None, solver, diag, n_samples[m], seed[m], sample0[m])
+        prms[m] = prm
+        ys[m], smp[m] = ptr["y"].value, ptr["samples"].value
+        mn[m] = ptr["mean"].value if ptr["mean"] is not None else None
+        sd[m] = ptr["std"].value if ptr["std"] is not None else None
+        rs[m] = ptr["resid"].value if ptr["resid"] is not None else None
+        outs.append(out)
+    _check(load().rto_sample_batch(batch._h, ys, prms, S, smp, mn, sd, rs, _stream()))
+    return outs
 
 
 def solver_diagnostics(diag, n_data: int, tau: float = 1.0):

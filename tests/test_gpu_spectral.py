@@ -1,0 +1,146 @@
+"""GPU Whittle-Matern spectral prior (hand-written FFT, interpolation) and latent RTO vs the oracle.
+
+* P and P^T (pat_spectral_apply) against oracle/spectral.py (numpy FFT), several
+  grid sizes and ragged RHS counts: 1e-12 of the largest output;
+* the transpose identity on the GPU;
+* latent-space RTO (float64 sweeps) against the oracle's latent CGLS: 1e-10;
+  LSQR against it (equal iterates in exact arithmetic): 1e-9; float32 sweeps:
+  mean and std within 1e-4; device-drawn latent perturbations;
+* argument errors;
+* the 195k-node ball with the 128^3 grid: sampled P / P^T against the oracle and
+  a short latent solve whose samples are P of its latent samples.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.spectral import SpectralPrior, latent_rto
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pat = pytest.importorskip("paper_2607_21373_amd.pat")
+
+BOX = dict(lo=-1.25, side=2.5)
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def ball16():
+    w = W.make_workload("ball16")
+    return w, oracle.Problem.from_workload(w), pat.Problem.from_workload(w)
+
+
+@pytest.mark.parametrize("n,R,ell", [(8, 1, 0.4), (16, 5, 0.2), (32, 20, 0.15), (32, 64, 0.075)])
+def test_spectral_apply_matches_oracle(ball16, n, R, ell):
+    w, O, G = ball16
+    pr = SpectralPrior(n, BOX["lo"], BOX["side"], ell, 3.0)
+    I = pr.interp_matrix(w.coords)
+    pat.spectral_prior_set(G, n, BOX["lo"], BOX["side"], ell, 3.0)
+    rng = np.random.default_rng(40 + n)
+    x = rng.standard_normal((R, pr.size))
+    v = rng.standard_normal((R, w.n_nodes))
+    print(f"spectral n={n} R={R}", flush=True)
+    y = pat.spectral_apply(G, _dev(x)).cpu().numpy()
+    ref = pr.apply(x, I)
+    assert np.abs(y - ref).max() < 1e-12 * np.abs(ref).max()
+    yt = pat.spectral_apply(G, _dev(v), transpose=True).cpu().numpy()
+    reft = pr.apply_t(v, I)
+    assert np.abs(yt - reft).max() < 1e-12 * np.abs(reft).max()
+    # <P x, v> = <x, P^T v>, to rounding relative to the sizes of the factors
+    lhs, rhs = np.sum(y * v, axis=1), np.sum(x * yt, axis=1)
+    scale = np.linalg.norm(y, axis=1) * np.linalg.norm(v, axis=1)
+    assert np.all(np.abs(lhs - rhs) < 1e-13 * scale)
+
+
+@pytest.mark.parametrize("solver,prec,tol", [("cgls", "f64", 1e-10), ("lsqr", "f64", 1e-9), ("cgls", "f32", 1e-4)])
+def test_latent_rto_matches_oracle(ball16, solver, prec, tol):
+    w, O, G = ball16
+    n, ell = 16, 0.2
+    pr = SpectralPrior(n, BOX["lo"], BOX["side"], ell, 3.0)
+    I = pr.interp_matrix(w.coords)
+    pat.spectral_prior_set(G, n, BOX["lo"], BOX["side"], ell, 3.0)
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    S, n_iter = 6, 20
+    rng = np.random.default_rng(41)
+    eta = rng.standard_normal((S, w.n_steps, w.n_obs))
+    xi = rng.standard_normal((S, pr.size))
+    ref, lat, res = latent_rto(O, pr, I, yobs, sigma, n_iter, eta, xi)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, 0.0, n_iter, sweep_prec=prec, solver=solver,
+                         prior="spectral", latent=True, resid=True)
+    got, glat = out["samples"].cpu().numpy(), out["latent"].cpu().numpy()
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    el = float(np.linalg.norm(glat - lat) / np.linalg.norm(lat))
+    rmean, rstd = oracle.stats(ref)
+    em = float(np.linalg.norm(out["mean"].cpu().numpy() - rmean) / np.linalg.norm(rmean))
+    es = float(np.linalg.norm(out["std"].cpu().numpy() - rstd) / np.linalg.norm(rstd))
+    print(f"latent RTO {solver} {prec}: samples {e:.2e} latent {el:.2e} mean {em:.2e} std {es:.2e}")
+    assert em < tol and es < tol
+    if prec == "f64":
+        assert e < tol and el < tol
+        assert np.abs(out["resid"].cpu().numpy() - res).max() < tol * res.max()
+
+
+def test_latent_rto_device_draws(ball16):
+    w, O, G = ball16
+    n = 8
+    pat.spectral_prior_set(G, n, BOX["lo"], BOX["side"], 0.3, 3.0)
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    a = pat.rto_sample(G, _dev(yobs), None, None, sigma, 0.0, 8, prior="spectral", n_samples=4, seed=5, sample0=2)
+    eta = pat.draw_normals(5, 0, 2, 4, w.n_steps * w.n_obs).reshape(4, w.n_steps, w.n_obs)
+    xi = pat.draw_normals(5, 1, 2, 4, n ** 3)
+    b = pat.rto_sample(G, _dev(yobs), eta, xi, sigma, 0.0, 8, prior="spectral")
+    assert torch.equal(a["samples"], b["samples"])
+
+
+def test_spectral_errors(ball16):
+    w, O, G = ball16
+    pat.spectral_prior_set(G, None, 0, 0, 0, 0)
+    y = _dev(np.zeros((w.n_steps, w.n_obs)))
+    G.spectral_size = 512                       # bypass the binding's own check
+    with pytest.raises(pat.PatError) as ei:
+        pat.rto_sample(G, y, _dev(np.zeros((2, w.n_steps, w.n_obs))), _dev(np.zeros((2, 512))), 1.0, 0.0, 2,
+                       prior="spectral")
+    assert ei.value.name == "PAT_ERR_INVALID_ARG"
+    for bad in (dict(n=12, lo=-1.25, side=2.5), dict(n=16, lo=-0.5, side=1.0), dict(n=256, lo=-1.25, side=2.5)):
+        with pytest.raises(pat.PatError) as ei:
+            pat.spectral_prior_set(G, bad["n"], bad["lo"], bad["side"], 0.2, 3.0)
+        assert ei.value.name == "PAT_ERR_INVALID_ARG"
+
+
+def test_spectral_fullsize():
+    """ball58 (195,112 nodes), 128^3 grid on [-1.25, 1.25)^3, ell = 0.075 (the paper's ell = 0.15 at half
+    the paper's domain size), sigma = 3, expo = 3."""
+    w = W.make_workload("ball58_fp64")
+    G = pat.Problem.from_workload(w)
+    n, ell = 128, 0.075
+    pat.spectral_prior_set(G, n, BOX["lo"], BOX["side"], ell, 3.0)
+    pr = SpectralPrior(n, BOX["lo"], BOX["side"], ell, 3.0)
+    I = pr.interp_matrix(w.coords)
+    rng = np.random.default_rng(42)
+    x = rng.standard_normal((2, pr.size))
+    y = pat.spectral_apply(G, _dev(x)).cpu().numpy()
+    ref = pr.apply(x, I)
+    assert np.abs(y - ref).max() < 1e-12 * np.abs(ref).max()
+    v = rng.standard_normal((2, w.n_nodes))
+    yt = pat.spectral_apply(G, _dev(v), transpose=True).cpu().numpy()
+    reft = pr.apply_t(v, I)
+    assert np.abs(yt - reft).max() < 1e-12 * np.abs(reft).max()
+    # pointwise prior std of the mapped field: close to sigma (interpolation lowers it a little)
+    z = pat.draw_normals(1, 1, 0, 64, pr.size)
+    f = pat.spectral_apply(G, z)
+    sd = float(f.std(dim=0).mean())
+    print(f"fullsize P: prior std at nodes {sd:.3f} (sigma 3)", flush=True)
+    assert 2.0 < sd < 3.3
+    p0 = _dev(w.p0_true[None])
+    Y = pat.pat_forward(G, p0)[0]
+    sigma = float(0.01 * torch.linalg.norm(Y) / np.sqrt(Y.numel()))
+    out = pat.rto_sample(G, (Y + 0.0).contiguous(), None, None, sigma, 0.0, 3, sweep_prec="f32", prior="spectral",
+                         n_samples=16, seed=3, latent=True)
+    assert torch.isfinite(out["samples"]).all()
+    again = pat.spectral_apply(G, out["latent"])
+    assert torch.allclose(again, out["samples"], rtol=0, atol=1e-12 * float(again.abs().max()))

@@ -149,7 +149,7 @@ def test_binding_structs_match_header(tmp_path):
     """Field offsets and sizes of the ctypes structs equal those gcc computes from include/pat.h."""
     import subprocess
     structs = {"pat_problem_desc": pat.ProblemDesc, "pat_problem_info": pat.ProblemInfo,
-               "pat_rto_params": pat.RtoParams, "pat_profile": pat.Profile}
+               "pat_rto_params": pat.RtoParams, "pat_profile": pat.Profile, "pat_spectral_desc": pat.SpectralDesc}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pat.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')

@@ -272,6 +272,32 @@ def _ball(n_cells: int, n_sensors: int, n_steps: int, name: str, n_samples: int,
         rto_seed=rto_seed, h=h)
 
 
+def _top_face_grid(nx: int, ny: int, nz: int, gx: int = 32, gy: int = 16) -> np.ndarray:
+    """gx x gy node sensors (at most the face) centred on the top face z = max of an (nx+1)(ny+1)(nz+1) grid."""
+    gx, gy = min(gx, nx + 1), min(gy, ny + 1)
+    i0, j0 = (nx + 1 - gx) // 2, (ny + 1 - gy) // 2
+    i, j = np.meshgrid(np.arange(i0, i0 + gx), np.arange(j0, j0 + gy), indexing="ij")
+    k = nz
+    return (i.ravel() + (nx + 1) * (j.ravel() + (ny + 1) * k)).astype(np.int32)
+
+
+def _box(name: str, nx: int, ny: int, nz: int, n_samples: int = 16, rto_seed: int = 11) -> Workload:
+    """Absorbing box [0,1] x [0,1] x [0, nz/nx] with cubic cells of side h = 1/nx."""
+    h = 1.0 / nx
+    coords, tets = box_mesh(nx, ny, nz, hi=(1.0, ny * h, nz * h), mirrored=True)
+    depth = nz * h
+    centre = np.array([0.5, 0.5 * ny * h, 0.5 * depth])
+    rng = np.random.default_rng(13)
+    p0 = np.zeros(coords.shape[0])
+    for _ in range(3):                       # three smooth bumps inside the box
+        R = 0.4 * min(depth, 0.5) * rng.uniform(0.6, 1.0)
+        c = centre + rng.uniform(-0.25, 0.25, size=3) * np.array([1.0, 1.0, depth - 2 * R])
+        p0 += rng.uniform(0.5, 1.0) * smooth_bump(coords - c, R)
+    return Workload(name=name, coords=coords, tets=tets, c_tet=None, absorbing=True, dt=0.2 * h, n_steps=1000,
+                    sensor_nodes=_top_face_grid(nx, ny, nz), p0_true=p0, noise_rule="l2", noise_seed=3,
+                    prior_a=0.01, n_samples=n_samples, n_iter=100, rto_seed=rto_seed, h=h)
+
+
 def make_workload(name: str) -> Workload:
     """Build a named workload.
 
@@ -283,6 +309,11 @@ def make_workload(name: str) -> Workload:
     * ``ball58_batched``: same problem, 64 samples (one multi-RHS batch).
     * ``ball16``: 17^3-node ball with the same recipe (for fast parity tests),
       200 steps, 64 sensors.
+    * ``cube40``, ``ball60``, ``slab120``: the uneven three-mesh batch: 40^3-node
+      cube, 60^3-node ball, 120 x 120 x 30-node slab; absorbing, dt = 0.2h,
+      1000 steps, 512 sensors (a 32 x 16 node grid on the top face of the cube
+      and the slab, a Fibonacci lattice on r = 0.9 for the ball), 16 samples each.
+    * ``ball100``: 100^3-node ball (10^6 nodes) with the ball58 recipe, one sample.
     """
     if name == "cube8_tiny":
         return _cube_tiny()
@@ -294,10 +325,18 @@ def make_workload(name: str) -> Workload:
         w = _ball(16, 64, 200, name, n_samples=16, rto_seed=7)
         w.n_iter = 50
         return w
+    if name == "cube40":
+        return _box(name, 39, 39, 39, rto_seed=11)
+    if name == "slab120":
+        return _box(name, 119, 119, 29, rto_seed=12)
+    if name == "ball60":
+        return _ball(59, 512, 1000, name, n_samples=16, rto_seed=13)
+    if name == "ball100":
+        return _ball(99, 1024, 1000, name, n_samples=1, rto_seed=14)
     raise KeyError(name)
 
 
-WORKLOADS = ("cube8_tiny", "ball58_fp64", "ball58_batched", "ball16")
+WORKLOADS = ("cube8_tiny", "ball58_fp64", "ball58_batched", "ball16", "cube40", "ball60", "slab120", "ball100")
 
 
 def rto_draws(n_samples: int, n_steps: int, n_obs: int, n_nodes: int, seed: int):
