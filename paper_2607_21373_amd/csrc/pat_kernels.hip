@@ -509,29 +509,47 @@ __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_v(const VFwdArgs<T>
     fwd_tile<T, OT, RB>(a, xcd_tile(blockIdx.x, gridDim.x), L);
 }
 
-// Several meshes in one launch: mesh m owns logical tiles [end[m-1], end[m]).
+// Several meshes in one launch; mesh m has tiles[m] logical tiles.  Every XCD
+// takes one eighth of each mesh (a contiguous range of its k-d order), as a
+// launch of that mesh alone would, so each mesh's state stays spread over all
+// eight L2 caches: XCD x walks, mesh after mesh, tiles
+// [x q_m + min(x, r_m), +q_m + (x < r_m)) with q_m = tiles[m] / 8, r_m = tiles[m] % 8.
+// The grid is 8 x the largest per-XCD count; blocks past their XCD's count idle.
 template <typename A>
 struct Multi {
     A a[kMaxMeshes];
-    int end[kMaxMeshes];
+    int tiles[kMaxMeshes];
     int n;
 };
 
-__device__ __forceinline__ int mesh_of(const int *end, int n, int tile, int *local) {
-    int m = 0, begin = 0;
-    while (m + 1 < n && tile >= end[m]) {
-        begin = end[m];
-        ++m;
+__device__ __forceinline__ bool mesh_tile(const int *tiles, int n, int b, int *mesh, int *local) {
+    const int x = b & 7;
+    int k = b >> 3;
+    for (int m = 0; m < n; ++m) {
+        const int q = tiles[m] >> 3, r = tiles[m] & 7;
+        const int cnt = q + (x < r ? 1 : 0);
+        if (k < cnt) {
+            *mesh = m;
+            *local = x * q + (x < r ? x : r) + k;
+            return true;
+        }
+        k -= cnt;
     }
-    *local = tile - begin;
-    return m;
+    return false;
+}
+
+// grid size of a merged launch (see Multi)
+inline int multi_grid(const int *tiles, int n) {
+    int c = 0;
+    for (int m = 0; m < n; ++m) c += (tiles[m] >> 3) + ((tiles[m] & 7) ? 1 : 0);
+    return 8 * c;
 }
 
 template <typename T, typename OT, int RB>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_vm(const Multi<VFwdArgs<T>> mm) {
     __shared__ TileOps<T, RB> L;
-    int local;
-    const int m = mesh_of(mm.end, mm.n, xcd_tile(blockIdx.x, gridDim.x), &local);
+    int m, local;
+    if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
     fwd_tile<T, OT, RB>(mm.a[m], local, L);
 }
 
@@ -601,8 +619,8 @@ __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_v(const VAdjArgs<T>
 template <typename T, typename YT, int RB>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdjArgs<T>> mm) {
     __shared__ TileOps<T, RB> L;
-    int local;
-    const int m = mesh_of(mm.end, mm.n, xcd_tile(blockIdx.x, gridDim.x), &local);
+    int m, local;
+    if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
     adj_tile<T, YT, RB>(mm.a[m], local, L);
 }
 
@@ -1133,16 +1151,12 @@ void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *
 template <typename T, typename OT, int RB>
 void fwd_impl_vm(const FwdStep *st, int n, hipStream_t s) {
     Multi<VFwdArgs<T>> mm{};
-    int total = 0;
-    for (int m = 0; m < n; ++m) {
-        int b = 0;
+    for (int m = 0; m < n; ++m)
         mm.a[m] = fwd_args_v<T, RB>(*st[m].op, st[m].P, st[m].V, st[m].Pn, st[m].Vn, st[m].rows, st[m].first,
-                                    st[m].sample, st[m].t, st[m].y, st[m].yscale, &b);
-        total += b;
-        mm.end[m] = total;
-    }
+                                    st[m].sample, st[m].t, st[m].y, st[m].yscale, &mm.tiles[m]);
     mm.n = n;
-    if (total > 0) hipLaunchKernelGGL((k_fwd_vm<T, OT, RB>), dim3(total), dim3(256), 0, s, mm);
+    const int grid = multi_grid(mm.tiles, n);
+    if (grid > 0) hipLaunchKernelGGL((k_fwd_vm<T, OT, RB>), dim3(grid), dim3(256), 0, s, mm);
 }
 
 template <typename T, int RB>
@@ -1171,15 +1185,14 @@ void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, 
 template <typename T, typename YT, int RB>
 void adj_impl_vm(const AdjStep *st, int n, hipStream_t s) {
     Multi<VAdjArgs<T>> mm{};
-    int total = 0;
     for (int m = 0; m < n; ++m) {
         mm.a[m] = adj_args_v<T, RB>(*st[m].op, st[m].PH, st[m].Q, st[m].Qn, st[m].last, st[m].tm1, st[m].yh,
                                     st[m].yscale);
-        total += mm.a[m].n_tiles;
-        mm.end[m] = total;
+        mm.tiles[m] = mm.a[m].n_tiles;
     }
     mm.n = n;
-    hipLaunchKernelGGL((k_adj_vm<T, YT, RB>), dim3(total), dim3(256), 0, s, mm);
+    const int grid = multi_grid(mm.tiles, n);
+    if (grid > 0) hipLaunchKernelGGL((k_adj_vm<T, YT, RB>), dim3(grid), dim3(256), 0, s, mm);
 }
 
 template <typename T, typename OT, int RB>
