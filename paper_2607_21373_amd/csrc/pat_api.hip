@@ -860,6 +860,7 @@ pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out) {
     UP(hp.xptr, xptr);
     UP(hp.xcol, xcol);
     UP(hp.bsoff, bsoff);
+    UP(hp.bnum, bnum);
     UP(hp.ell_val, ell_val64);
     UP(hp.xval, xval64);
     UP(hp.bslot, bslot64);

@@ -42,6 +42,9 @@ struct HostProblem {
     static constexpr int kEll = 16;
     std::vector<int32_t> ell_col, xptr, xcol, bsoff;
     std::vector<double> ell_val, xval, bslot;
+    // Boundary rows list their slots with a nonzero B first: B(i, slot) = 0 for
+    // slot >= bnum[i] (bnum = 0 for interior rows).
+    std::vector<int32_t> bnum;
     // internal <-> user numbering: perm[internal] = user, iperm[user] = internal
     std::vector<int32_t> perm, iperm;
     double lambda_max = 0.0;

@@ -18,7 +18,7 @@ struct DevOps {
     const double *dtm64 = nullptr, *sqrtm = nullptr, *isqrtm = nullptr, *sw64 = nullptr, *injw64 = nullptr;
     const float *dtm32 = nullptr, *sw32 = nullptr, *injw32 = nullptr;
     // padded row layout of K for the time-step kernels
-    const int32_t *ell_col = nullptr, *xptr = nullptr, *xcol = nullptr, *bsoff = nullptr;
+    const int32_t *ell_col = nullptr, *xptr = nullptr, *xcol = nullptr, *bsoff = nullptr, *bnum = nullptr;
     const double *ell_val64 = nullptr, *xval64 = nullptr, *bslot64 = nullptr;
     const float *ell_val32 = nullptr, *xval32 = nullptr, *bslot32 = nullptr;
     double dt = 0.0;

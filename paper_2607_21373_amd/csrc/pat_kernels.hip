@@ -49,6 +49,7 @@ template <typename T>
 struct RowOps {
     const int32_t *ecol, *xptr, *xcol, *bsoff;
     const T *eval, *xval, *bslot, *dtm;
+    const int32_t *bnum;  // boundary rows: slots with a nonzero B come first, bnum of them
 };
 
 // Operands of one row, loaded one row ahead of their use.
@@ -350,7 +351,7 @@ struct TileOps {
     T kv[G::RPB * G::W];
     T bv[G::RPB * G::W];
     T dm[G::RPB];
-    int bo[G::RPB], x0[G::RPB], x1[G::RPB];
+    int bo[G::RPB], bn[G::RPB], x0[G::RPB], x1[G::RPB];
 };
 
 // Stage the operands of rows [row0, row0 + RPB) (rows >= n get zero weights).
@@ -369,6 +370,7 @@ __device__ __forceinline__ void stage_tile(const RowOps<T> &o, int n, int row0, 
         const int rw = row0 + e;
         const bool ok = rw < n;
         L.bo[e] = ok ? o.bsoff[rw] : -1;
+        L.bn[e] = ok ? o.bnum[rw] : 0;
         L.x0[e] = ok ? o.xptr[rw] : 0;
         L.x1[e] = ok ? o.xptr[rw + 1] : 0;
         L.dm[e] = ok ? o.dtm[rw] : T(0);
@@ -424,19 +426,26 @@ __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, R
     }
     {
         if (with_b) {
-            // re-read the slot operands from LDS instead of keeping them live across the K sums
+            // only the row's first bnum slots carry B; re-read the slot operands from LDS
+            // instead of keeping them live across the K sums
             int bbase = base;
             asm volatile("" : "+v"(bbase));
+            const int nb = L.bn[lr];
 #pragma unroll
             for (int j0 = 0; j0 < G::W; j0 += CH) {
-                VT y[CH];
+                if (j0 < nb) {
+                    VT y[CH];
 #pragma unroll
-                for (int j = 0; j < CH; ++j)
-                    y[j] = *reinterpret_cast<const VT *>(Yc + (uint32_t(L.col[bbase + j0 + j]) * ROWB + qoff));
+                    for (int j = 0; j < CH; ++j) {
+                        y[j] = VT{};
+                        if (j0 + j < nb)
+                            y[j] = *reinterpret_cast<const VT *>(Yc + (uint32_t(L.col[bbase + j0 + j]) * ROWB + qoff));
+                    }
 #pragma unroll
-                for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[bbase + j0 + j], y[j], bacc);
+                    for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[bbase + j0 + j], y[j], bacc);
+                }
             }
-            for (int k = x0; k < x1; ++k) {
+            for (int k = x0; k < x0 + nb - G::W; ++k) {
                 const VT yv = *reinterpret_cast<const VT *>(Yc + (uint32_t(o.xcol[k]) * ROWB + qoff));
                 bacc = vfma(o.bslot[L.bo[lr] + G::W + (k - x0)], yv, bacc);
             }
@@ -1101,11 +1110,13 @@ template <typename T>
 RowOps<T> row_ops(const DevOps &op);
 template <>
 RowOps<double> row_ops<double>(const DevOps &op) {
-    return RowOps<double>{op.ell_col, op.xptr, op.xcol, op.bsoff, op.ell_val64, op.xval64, op.bslot64, op.dtm64};
+    return RowOps<double>{op.ell_col, op.xptr, op.xcol, op.bsoff, op.ell_val64, op.xval64, op.bslot64, op.dtm64,
+                          op.bnum};
 }
 template <>
 RowOps<float> row_ops<float>(const DevOps &op) {
-    return RowOps<float>{op.ell_col, op.xptr, op.xcol, op.bsoff, op.ell_val32, op.xval32, op.bslot32, op.dtm32};
+    return RowOps<float>{op.ell_col, op.xptr, op.xcol, op.bsoff, op.ell_val32, op.xval32, op.bslot32, op.dtm32,
+                         op.bnum};
 }
 template <typename T>
 const T *sw_of(const DevOps &op);

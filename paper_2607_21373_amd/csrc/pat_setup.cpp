@@ -489,18 +489,35 @@ void build_padded_rows(HostProblem &hp) {
             boff += W + (hp.xptr[i + 1] - hp.xptr[i]);
         }
     hp.bslot.assign(size_t(boff), 0.0);
+    hp.bnum.assign(size_t(N), 0);
+    std::vector<int32_t> order;
     for (int32_t i = 0; i < N; ++i) {
         const int32_t k0 = hp.rowptr[i], len = hp.rowptr[i + 1] - k0;
+        // slot order: for boundary rows the entries with a nonzero B first (so the
+        // boundary sums touch only bnum[i] slots), then the rest, each in column order
+        order.resize(size_t(len));
+        int32_t nb = 0;
+        if (hp.boff[i] >= 0) {
+            for (int32_t j = 0; j < len; ++j)
+                if (hp.bval[size_t(hp.boff[i] + j)] != 0.0) order[size_t(nb++)] = j;
+            int32_t o = nb;
+            for (int32_t j = 0; j < len; ++j)
+                if (hp.bval[size_t(hp.boff[i] + j)] == 0.0) order[size_t(o++)] = j;
+        } else {
+            for (int32_t j = 0; j < len; ++j) order[size_t(j)] = j;
+        }
+        hp.bnum[size_t(i)] = nb;
         for (int j = 0; j < W; ++j) {
-            hp.ell_col[size_t(i) * W + j] = j < len ? hp.col[k0 + j] : i;
-            hp.ell_val[size_t(i) * W + j] = j < len ? hp.kval[k0 + j] : 0.0;
+            hp.ell_col[size_t(i) * W + j] = j < len ? hp.col[k0 + order[size_t(j)]] : i;
+            hp.ell_val[size_t(i) * W + j] = j < len ? hp.kval[k0 + order[size_t(j)]] : 0.0;
         }
         for (int32_t j = W; j < len; ++j) {
-            hp.xcol[hp.xptr[i] + j - W] = hp.col[k0 + j];
-            hp.xval[hp.xptr[i] + j - W] = hp.kval[k0 + j];
+            hp.xcol[hp.xptr[i] + j - W] = hp.col[k0 + order[size_t(j)]];
+            hp.xval[hp.xptr[i] + j - W] = hp.kval[k0 + order[size_t(j)]];
         }
         if (hp.boff[i] >= 0)
-            for (int32_t j = 0; j < len; ++j) hp.bslot[size_t(hp.bsoff[i] + j)] = hp.bval[size_t(hp.boff[i] + j)];
+            for (int32_t j = 0; j < len; ++j)
+                hp.bslot[size_t(hp.bsoff[i] + j)] = hp.bval[size_t(hp.boff[i] + order[size_t(j)])];
     }
 }
 
