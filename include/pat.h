@@ -182,7 +182,8 @@ pat_status pat_spectral_apply(pat_problem *p, int64_t R, int transpose, const do
 
 /* Autotuner of the RHS block.  For each candidate block RB (powers of two from
  * 1/16 of the smallest block holding S up to it) it times 8 forward and 8
- * transpose steps with HIP events after a warm-up, prices S samples as
+ * transpose steps, captured in graphs as the sweeps are, with HIP events after a
+ * warm-up, prices S samples as
  * ceil(S/RB) * (forward + transpose step) and records the cheapest RB for
  * (S, prec) in the handle, where rto_sample's rhs_block = 0 finds it.
  *   rhs_block  host int32 or NULL: the chosen block
@@ -203,9 +204,19 @@ typedef struct pat_batch pat_batch;
 pat_status pat_batch_create(pat_problem *const *problems, int32_t n, pat_batch **out);
 pat_status pat_batch_destroy(pat_batch *b);
 
-/* pat_autotune for the batch's merged steps (S = the largest per-problem sample count). */
+/* pat_autotune for the batch (S = the largest per-problem sample count).  For each
+ * candidate block it also times, per direction (forward, transpose), the three
+ * launch modes of pat_batch_merge and keeps the fastest; rto_sample_batch uses
+ * these choices when rhs_block is 0 or equals the tuned block (otherwise it merges). */
 pat_status pat_batch_autotune(pat_batch *b, int64_t S, pat_precision prec, int32_t *rhs_block, double *step_us,
                               void *stream);
+
+/* Launch mode of rto_sample_batch per sweep direction: 1 = one merged launch per
+ * time step for all problems; 0 = one launch per problem within each time step;
+ * 2 = each problem's whole sweep in turn (keeps a small mesh's working set in
+ * cache across its steps); -1 = the autotuned choice (merged when not tuned).
+ * Results do not depend on it. */
+pat_status pat_batch_merge(pat_batch *b, int32_t forward, int32_t transpose);
 
 /* rto_sample for every problem m of the batch at once: arrays of n entries
  * (n = problems in the batch).  prm[m] gives problem m's sigma, prior_a,

@@ -133,7 +133,16 @@ struct pat_batch {
     hipGraphExec_t g_fwd = nullptr, g_adj = nullptr;
     std::vector<const void *> key_fwd, key_adj;
     std::vector<double> key_scale;
-    std::map<std::pair<int64_t, int>, int> tuned;
+    bool key_mf = true, key_ma = true;
+    // launch mode per direction (pat_batch_merge): 0 one launch per problem within each step,
+    // 1 one merged launch per step, 2 each problem's whole sweep in turn; -1 tuned
+    int force_mf = -1, force_ma = -1;
+    // autotuned (RHS block, forward mode, transpose mode) per (S, precision)
+    struct Tune {
+        int rb;
+        int mf, ma;
+    };
+    std::map<std::pair<int64_t, int>, Tune> tune;
 };
 
 namespace {
@@ -334,9 +343,10 @@ int auto_rb(const std::map<std::pair<int64_t, int>, int> &tuned, int64_t S, pat:
 
 // ---- several meshes per sweep launch ------------------------------------
 
-// One launch per time step for all meshes (vector-lane RHS blocks), else one per mesh.
-void fwd_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::FwdStep> &st, hipStream_t s) {
-    if (pat::multi_step_supported(prec, RB)) {
+// One launch per time step for all meshes (merge, vector-lane RHS blocks), else one per mesh.
+void fwd_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::FwdStep> &st, hipStream_t s,
+               bool merge = true) {
+    if (merge && pat::multi_step_supported(prec, RB)) {
         pat::launch_fwd_multi(prec, RB, y_f64, st.data(), int(st.size()), s);
         return;
     }
@@ -345,8 +355,9 @@ void fwd_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::FwdSte
                              f.yscale, s);
 }
 
-void adj_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::AdjStep> &st, hipStream_t s) {
-    if (pat::multi_step_supported(prec, RB)) {
+void adj_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::AdjStep> &st, hipStream_t s,
+               bool merge = true) {
+    if (merge && pat::multi_step_supported(prec, RB)) {
         pat::launch_adj_multi(prec, RB, y_f64, st.data(), int(st.size()), s);
         return;
     }
@@ -357,7 +368,7 @@ void adj_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::AdjSte
 // enqueue_forward for several meshes with equal N_T: the same launches, merged per step.
 void enqueue_forward_multi(const std::vector<pat_problem *> &P, const std::vector<SweepWS *> &W,
                            const std::vector<void *> &yout, bool y_f64, const std::vector<double> &scale,
-                           hipStream_t s) {
+                           hipStream_t s, bool merge) {
     const size_t n = P.size();
     const int NT = P[0]->ops.n_steps;
     const pat::Prec prec = W[0]->prec;
@@ -366,24 +377,24 @@ void enqueue_forward_multi(const std::vector<pat_problem *> &P, const std::vecto
     for (size_t m = 0; m < n; ++m)
         st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->P[1], W[m]->V[1], true, true, false, 0,
                              yout[m], scale[m]};
-    fwd_steps(prec, RB, y_f64, st, s);
+    fwd_steps(prec, RB, y_f64, st, s, merge);
     int cur = 1;
     for (int t = 2; t <= NT; ++t) {
         for (size_t m = 0; m < n; ++m)
             st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[cur], W[m]->V[cur], W[m]->P[1 - cur], W[m]->V[1 - cur], true,
                                  false, true, t - 2, yout[m], scale[m]};
-        fwd_steps(prec, RB, y_f64, st, s);
+        fwd_steps(prec, RB, y_f64, st, s, merge);
         cur = 1 - cur;
     }
     for (size_t m = 0; m < n; ++m)
         st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[cur], W[m]->V[cur], nullptr, nullptr, false, false, true, NT - 1,
                              yout[m], scale[m]};
-    fwd_steps(prec, RB, y_f64, st, s);
+    fwd_steps(prec, RB, y_f64, st, s, merge);
 }
 
 // enqueue_adjoint for several meshes with equal N_T.
 void enqueue_adjoint_multi(const std::vector<pat_problem *> &P, const std::vector<SweepWS *> &W,
-                           const std::vector<const void *> &yin, bool y_f64, hipStream_t s) {
+                           const std::vector<const void *> &yin, bool y_f64, hipStream_t s, bool merge) {
     const size_t n = P.size();
     const int NT = P[0]->ops.n_steps;
     const pat::Prec prec = W[0]->prec;
@@ -394,26 +405,30 @@ void enqueue_adjoint_multi(const std::vector<pat_problem *> &P, const std::vecto
     for (int t = NT; t >= 2; --t) {
         for (size_t m = 0; m < n; ++m)
             st[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[cur], W[m]->V[1 - cur], false, t - 2, yin[m], 1.0};
-        adj_steps(prec, RB, y_f64, st, s);
+        adj_steps(prec, RB, y_f64, st, s, merge);
         cur = 1 - cur;
     }
     for (size_t m = 0; m < n; ++m)
         st[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[cur], nullptr, true, 0, yin[m], 1.0};
-    adj_steps(prec, RB, y_f64, st, s);
+    adj_steps(prec, RB, y_f64, st, s, merge);
 }
 
-// Autotuner: for each candidate RHS block, time `reps` merged forward and
-// transpose steps of all meshes (after a warm-up) with HIP events and price a
-// run of S samples as ceil(S/RB) * (forward + transpose step); return the cheapest.
-pat_status tune_rb(const std::vector<pat_problem *> &P, int64_t S, pat::Prec pr, hipStream_t s, int *best,
-                   double *best_us) {
+// Autotuner: for each candidate RHS block, time `reps` forward and transpose
+// steps of all meshes (after a warm-up) with HIP events and price a run of S
+// samples as ceil(S/RB) * (forward + transpose step); return the cheapest.  With
+// several meshes each direction is timed merged (one launch per step) and one
+// launch per mesh, and the faster is kept (*mf, *ma).
+pat_status tune_rb(const std::vector<pat_problem *> &P, hipStream_t cap, int64_t S, pat::Prec pr, hipStream_t s,
+                   int *best, double *best_us, int *mf = nullptr, int *ma = nullptr) {
     const int top = choose_rb(S);
     const int lo = std::max(1, top / 16);
     const int reps = 8;
-    hipEvent_t ev[3];
+    hipEvent_t ev[5];
     for (auto &e : ev) PAT_HIP(hipEventCreate(&e));
     *best = top;
     *best_us = 1e300;
+    if (mf) *mf = 1;
+    if (ma) *ma = 1;
     pat_status st = PAT_OK;
     for (int RB = lo; RB <= top && st == PAT_OK; RB <<= 1) {
         std::vector<SweepWS *> W(P.size());
@@ -440,26 +455,61 @@ pat_status tune_rb(const std::vector<pat_problem *> &P, int64_t S, pat::Prec pr,
                                  Y[m], 1.0};
             as[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->V[1], false, 0, Y[m], 1.0};
         }
-        for (int k = 0; k < 2; ++k) {
-            fwd_steps(pr, RB, yf, fs, s);
-            adj_steps(pr, RB, yf, as, s);
+        // The sweeps replay captured graphs, so time captured sequences of `reps` steps
+        // (sequence q: direction q % 2).  Several meshes: q = 0, 1 merged launches per
+        // step; q = 2, 3 one launch per mesh within each step; then one graph per mesh
+        // and direction (that mesh alone, as a whole sweep per mesh runs it).
+        const size_t nm = P.size();
+        const bool multi = nm > 1;
+        const int nq = multi ? 4 + 2 * int(nm) : 2;
+        std::vector<hipGraphExec_t> g(size_t(nq), nullptr);
+        for (int q = 0; q < nq && st == PAT_OK; ++q)
+            st = capture_on(cap, &g[size_t(q)], [&](hipStream_t cs) {
+                for (int k = 0; k < reps; ++k) {
+                    if (q < 4) {
+                        if (q % 2 == 0) fwd_steps(pr, RB, yf, fs, cs, q < 2);
+                        else adj_steps(pr, RB, yf, as, cs, q < 2);
+                    } else {
+                        const size_t m = size_t(q - 4) / 2;
+                        if (q % 2 == 0) fwd_steps(pr, RB, yf, {fs[m]}, cs, false);
+                        else adj_steps(pr, RB, yf, {as[m]}, cs, false);
+                    }
+                }
+            });
+        std::vector<float> ms(size_t(nq), 0.f);
+        if (st == PAT_OK) {
+            for (int q = 0; q < nq && st == PAT_OK; ++q) {
+                (void)hipGraphLaunch(g[size_t(q)], s);  // warm-up
+                (void)hipEventRecord(ev[0], s);
+                (void)hipGraphLaunch(g[size_t(q)], s);
+                (void)hipEventRecord(ev[1], s);
+                if (hipEventSynchronize(ev[1]) != hipSuccess) st = fail(PAT_ERR_HIP, "autotune: a timed step failed");
+                else (void)hipEventElapsedTime(&ms[size_t(q)], ev[0], ev[1]);
+            }
         }
-        (void)hipEventRecord(ev[0], s);
-        for (int k = 0; k < reps; ++k) fwd_steps(pr, RB, yf, fs, s);
-        (void)hipEventRecord(ev[1], s);
-        for (int k = 0; k < reps; ++k) adj_steps(pr, RB, yf, as, s);
-        (void)hipEventRecord(ev[2], s);
-        if (hipEventSynchronize(ev[2]) != hipSuccess) {
-            st = fail(PAT_ERR_HIP, "autotune: a timed step failed");
-            break;
+        for (auto &x : g)
+            if (x) (void)hipGraphExecDestroy(x);
+        if (st != PAT_OK) break;
+        float f_ms = ms[0], a_ms = ms[1];
+        int m_f = 1, m_a = 1;
+        if (multi) {
+            const bool merged_ok = pat::multi_step_supported(pr, RB);
+            if (!merged_ok || ms[2] < f_ms) { f_ms = ms[2]; m_f = 0; }
+            if (!merged_ok || ms[3] < a_ms) { a_ms = ms[3]; m_a = 0; }
+            float sf = 0.f, sa = 0.f;
+            for (size_t m = 0; m < nm; ++m) {
+                sf += ms[4 + 2 * m];
+                sa += ms[5 + 2 * m];
+            }
+            if (sf < f_ms) { f_ms = sf; m_f = 2; }
+            if (sa < a_ms) { a_ms = sa; m_a = 2; }
         }
-        float f_ms = 0.f, a_ms = 0.f;
-        (void)hipEventElapsedTime(&f_ms, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&a_ms, ev[1], ev[2]);
         const double us = double((S + RB - 1) / RB) * 1e3 * double(f_ms + a_ms) / reps;
         if (us < *best_us) {
             *best_us = us;
             *best = RB;
+            if (mf) *mf = m_f;
+            if (ma) *ma = m_a;
         }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
@@ -1031,7 +1081,7 @@ pat_status pat_autotune(pat_problem *p, int64_t S, pat_precision prec, int32_t *
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     int rb = 0;
     double us = 0.0;
-    PAT_TRY(tune_rb({p}, S, pr, static_cast<hipStream_t>(stream), &rb, &us));
+    PAT_TRY(tune_rb({p}, p->cap, S, pr, static_cast<hipStream_t>(stream), &rb, &us));
     p->tuned[{S, int(pr)}] = rb;
     if (rhs_block) *rhs_block = rb;
     if (step_us) *step_us = us;
@@ -1073,6 +1123,16 @@ pat_status pat_batch_destroy(pat_batch *b) {
     return PAT_OK;
 }
 
+pat_status pat_batch_merge(pat_batch *b, int32_t forward, int32_t transpose) {
+    g_err.clear();
+    if (!b) return fail(PAT_ERR_INVALID_ARG, "pat_batch_merge: NULL handle");
+    if (forward < -1 || forward > 2 || transpose < -1 || transpose > 2)
+        return fail(PAT_ERR_INVALID_ARG, "pat_batch_merge: values must be -1, 0, 1 or 2");
+    b->force_mf = forward;
+    b->force_ma = transpose;
+    return PAT_OK;
+}
+
 pat_status pat_batch_autotune(pat_batch *b, int64_t S, pat_precision prec, int32_t *rhs_block, double *step_us,
                               void *stream) {
     g_err.clear();
@@ -1083,8 +1143,9 @@ pat_status pat_batch_autotune(pat_batch *b, int64_t S, pat_precision prec, int32
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     int rb = 0;
     double us = 0.0;
-    PAT_TRY(tune_rb(b->probs, S, pr, static_cast<hipStream_t>(stream), &rb, &us));
-    b->tuned[{S, int(pr)}] = rb;
+    int mf = 1, ma = 1;
+    PAT_TRY(tune_rb(b->probs, b->cap, S, pr, static_cast<hipStream_t>(stream), &rb, &us, &mf, &ma));
+    b->tune[{S, int(pr)}] = pat_batch::Tune{rb, mf, ma};
     if (rhs_block) *rhs_block = rb;
     if (step_us) *step_us = us;
     return PAT_OK;
@@ -1114,7 +1175,18 @@ pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_
     DeviceGuard guard(b->device);
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int RB = prm[0].rhs_block ? prm[0].rhs_block : auto_rb(b->tuned, smax, pr);
+    int RB = prm[0].rhs_block ? prm[0].rhs_block : choose_rb(smax);
+    int mf = 1, ma = 1;
+    {
+        auto it = b->tune.find({smax, int(pr)});
+        if (it != b->tune.end() && (prm[0].rhs_block == 0 || prm[0].rhs_block == it->second.rb)) {
+            RB = it->second.rb;
+            mf = it->second.mf;
+            ma = it->second.ma;
+        }
+        if (b->force_mf >= 0) mf = b->force_mf;
+        if (b->force_ma >= 0) ma = b->force_ma;
+    }
     const int n_iter = prm[0].n_iter;
     const bool lsqr = prm[0].solver == PAT_LSQR;
 
@@ -1138,22 +1210,35 @@ pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_
         ka.push_back(W[m]);
         ka.push_back(C[m]->rd);
     }
-    if (!b->g_fwd || kf != b->key_fwd || scale != b->key_scale) {
+    if (mf == 2 || ma == 2)  // whole sweeps per problem use each problem's own solver graphs
+        for (size_t m = 0; m < n; ++m) PAT_TRY(solver_graphs(b->probs[m], W[m], C[m], scale[m]));
+    if (mf != 2 && (!b->g_fwd || kf != b->key_fwd || scale != b->key_scale || (mf == 1) != b->key_mf)) {
         PAT_TRY(capture_on(b->cap, &b->g_fwd,
-                           [&](hipStream_t cs) { enqueue_forward_multi(b->probs, W, yout, true, scale, cs); }));
+                           [&](hipStream_t cs) { enqueue_forward_multi(b->probs, W, yout, true, scale, cs, mf == 1); }));
         b->key_fwd = kf;
         b->key_scale = scale;
+        b->key_mf = mf == 1;
     }
-    if (!b->g_adj || ka != b->key_adj) {
-        PAT_TRY(capture_on(b->cap, &b->g_adj, [&](hipStream_t cs) { enqueue_adjoint_multi(b->probs, W, yin, true, cs); }));
+    if (ma != 2 && (!b->g_adj || ka != b->key_adj || (ma == 1) != b->key_ma)) {
+        PAT_TRY(capture_on(b->cap, &b->g_adj,
+                           [&](hipStream_t cs) { enqueue_adjoint_multi(b->probs, W, yin, true, cs, ma == 1); }));
         b->key_adj = ka;
+        b->key_ma = ma == 1;
     }
     auto fwd = [&]() -> pat_status {
-        PAT_HIP(hipGraphLaunch(b->g_fwd, s));
+        if (mf == 2) {
+            for (size_t m = 0; m < n; ++m) PAT_HIP(hipGraphLaunch(W[m]->g_fwd_cgls, s));
+        } else {
+            PAT_HIP(hipGraphLaunch(b->g_fwd, s));
+        }
         return PAT_OK;
     };
     auto adj = [&]() -> pat_status {
-        PAT_HIP(hipGraphLaunch(b->g_adj, s));
+        if (ma == 2) {
+            for (size_t m = 0; m < n; ++m) PAT_HIP(hipGraphLaunch(W[m]->g_adj_cgls, s));
+        } else {
+            PAT_HIP(hipGraphLaunch(b->g_adj, s));
+        }
         return PAT_OK;
     };
     std::vector<std::vector<double>> chk(n, std::vector<double>(size_t(((smax + RB - 1) / RB) * RB), 0.0));

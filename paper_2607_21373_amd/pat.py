@@ -80,9 +80,9 @@ class SpectralDesc(ctypes.Structure):
 # names exported by libpat (the C ABI in include/pat.h)
 EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
            "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_spectral_prior_set", "pat_spectral_apply",
-           "pat_autotune", "pat_batch_create",
-           "pat_batch_destroy", "pat_batch_autotune", "rto_sample_batch", "pat_host_assemble", "pat_profile_enable",
-           "pat_profile_get", "pat_sync", "pat_last_error", "pat_version")
+           "pat_autotune", "pat_batch_create", "pat_batch_destroy", "pat_batch_autotune", "pat_batch_merge",
+           "rto_sample_batch", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync",
+           "pat_last_error", "pat_version")
 
 _lib = None
 
@@ -114,6 +114,7 @@ def load() -> ctypes.CDLL:
     lib.pat_autotune.argtypes = [vp, ctypes.c_int64, ctypes.c_int, i32p, f64p, vp]
     lib.pat_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]
     lib.pat_batch_destroy.argtypes = [vp]
+    lib.pat_batch_merge.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.pat_spectral_prior_set.argtypes = [vp, ctypes.POINTER(SpectralDesc)]
     lib.pat_spectral_apply.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp, vp, vp]
     lib.pat_batch_autotune.argtypes = [vp, ctypes.c_int64, ctypes.c_int, i32p, f64p, vp]
@@ -431,6 +432,11 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def merge(self, forward: int = -1, transpose: int = -1):
+        """pat_batch_merge: 1 merged launch per step, 0 one launch per problem per step,
+        2 each problem's whole sweep in turn, -1 tuned."""
+        _check(load().pat_batch_merge(self._h, int(forward), int(transpose)))
 
     def autotune(self, n_samples: int, sweep_prec: str = "f32"):
         rb, us = ctypes.c_int32(), ctypes.c_double()

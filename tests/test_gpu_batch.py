@@ -6,6 +6,7 @@
   block that launches them one after another within each step);
 * against the oracle on small meshes (float64: 1e-10);
 * unequal sample counts spanning several RHS blocks;
+* the three launch modes of the batch give identical results;
 * the autotuner returns a valid block and rto_sample(rhs_block=0) then uses it;
 * argument errors;
 * the three full-size meshes (40^3 cube, 60^3 ball, 120x120x30 slab, 512
@@ -71,6 +72,24 @@ def test_batch_equals_single(small, prec, rb, solver):
                              resid=True, diag=True)
         for k in ("samples", "mean", "std", "resid", "diag"):
             assert torch.equal(o[k], ref[k]), (w.name, k)
+
+
+@pytest.mark.parametrize("mf,ma", [(0, 0), (1, 1), (2, 2), (2, 1), (0, 2)])
+def test_batch_launch_modes_agree(small, mf, ma):
+    """Merged per step, one launch per problem per step, whole sweeps per problem: identical results."""
+    S = (6, 9, 4)
+    inp = _inputs(small, S)
+    B = pat.Batch([c[2] for c in small])
+    args = ([i[0] for i in inp], [i[1] for i in inp], [i[2] for i in inp], [i[3] for i in inp],
+            [c[0].prior_a for c in small], 12)
+    B.merge(1, 1)
+    ref = pat.rto_sample_batch(B, *args, sweep_prec="f32", rhs_block=16)
+    B.merge(mf, ma)
+    out = pat.rto_sample_batch(B, *args, sweep_prec="f32", rhs_block=16)
+    for a, b in zip(out, ref):
+        assert torch.equal(a["samples"], b["samples"])
+    with pytest.raises(pat.PatError):
+        B.merge(3, 0)
 
 
 def test_batch_matches_oracle(small):
