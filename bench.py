@@ -103,7 +103,7 @@ def _synth(pat, W, w, G, dev):
     return (Y + sigma * eta0).contiguous(), sigma
 
 
-def uneven_leg(pat, W, dev, n_iter):
+def uneven_leg(pat, W, dev, n_iter, modes=False):
     """Three meshes of different sizes sampled together (one merged launch per time step),
     16 samples each with device-drawn perturbations, against the same three solves run
     one after another with the same RHS block."""
@@ -140,9 +140,26 @@ def uneven_leg(pat, W, dev, n_iter):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t
     same = all(torch.equal(a["samples"], b["samples"]) for a, b in zip(outs, ref))
+    mode_times = {}
+    if modes:
+        # each launch mode of pat_batch_merge forced for both directions (1 merged per step,
+        # 0 one launch per mesh per step, 2 whole sweep per mesh), then back to the tuned choice
+        for m in (1, 0, 2):
+            B.merge(m, m)
+            batched()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            batched()
+            torch.cuda.synchronize()
+            mode_times[{1: "merged_per_step", 0: "per_mesh_per_step", 2: "whole_sweep_per_mesh"}[m]] = \
+                round(time.perf_counter() - t, 3)
+        B.merge(-1, -1)
+        log(f"uneven batch launch modes: {mode_times}")
     res = {"meshes": {w.name: w.n_nodes for w in ws}, "samples": S * len(ws), "iters": n_iter, "rhs_block": rb,
            "seconds": round(tb, 3), "value": round(S * len(ws) / tb * 60.0, 3), "unit": "samples/min",
            "serial_seconds": round(ts, 3), "speedup_vs_serial": round(ts / tb, 3), "equal_to_serial": same}
+    if mode_times:
+        res["mode_seconds"] = mode_times
     log(f"uneven batch: {tb:.2f} s for {S * len(ws)} samples ({res['value']:.1f} samples/min); one mesh after "
         f"another {ts:.2f} s; results identical: {same}")
     return res
@@ -190,6 +207,7 @@ def main():
                     help="before timing, copy a float32 buffer of this many MB three times (counter calibration)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
     ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
+    ap.add_argument("--uneven-modes", action="store_true", help="also time each launch mode of the uneven batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (samples are independent, so "
@@ -306,7 +324,7 @@ def main():
         log(f"plain f64 (1 sample, R=1): {tp:.2f} s -> {plain:.2f} samples/min; speed-up {value / plain:.1f}x")
 
     if not args.no_uneven:
-        result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter)
+        result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter, modes=args.uneven_modes)
     if args.big:
         result["ball100_single_sample"] = big_leg(pat, W, dev, n_iter)
 

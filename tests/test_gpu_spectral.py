@@ -5,7 +5,8 @@
 * the transpose identity on the GPU;
 * latent-space RTO (float64 sweeps) against the oracle's latent CGLS: 1e-10;
   LSQR against it (equal iterates in exact arithmetic): 1e-9; float32 sweeps:
-  mean and std within 1e-4; device-drawn latent perturbations;
+  samples and mean within 1e-4, std within the Lipschitz bound of the sample
+  differences; device-drawn latent perturbations;
 * argument errors;
 * the 195k-node ball with the 128^3 grid: sampled P / P^T against the oracle and
   a short latent solve whose samples are P of its latent samples.
@@ -79,9 +80,15 @@ def test_latent_rto_matches_oracle(ball16, solver, prec, tol):
     em = float(np.linalg.norm(out["mean"].cpu().numpy() - rmean) / np.linalg.norm(rmean))
     es = float(np.linalg.norm(out["std"].cpu().numpy() - rstd) / np.linalg.norm(rstd))
     print(f"latent RTO {solver} {prec}: samples {e:.2e} latent {el:.2e} mean {em:.2e} std {es:.2e}")
-    assert em < tol and es < tol
+    assert e < tol and el < tol and em < tol
+    # The pointwise std is 1-Lipschitz in the centred samples: per node
+    # |std(a) - std(b)| <= ||a - b|| / sqrt(S - 1).  With few samples whose spread is
+    # small against their size this amplifies the sample error, so bound it by that.
+    dstd = np.abs(out["std"].cpu().numpy() - rstd)
+    bound = np.linalg.norm(got - ref, axis=0) / np.sqrt(S - 1)
+    assert np.all(dstd <= bound * (1 + 1e-6) + 1e-12 * rstd.max())
     if prec == "f64":
-        assert e < tol and el < tol
+        assert es < tol
         assert np.abs(out["resid"].cpu().numpy() - res).max() < tol * res.max()
 
 
