@@ -397,10 +397,13 @@ __device__ __forceinline__ VT vfma(T w, VT x, VT acc) {
 // The B sums (boundary rows only) run after the K sums have been consumed, with
 // their own gathers, so the two sets of gathers are never live together and the
 // kernel keeps the register budget (and occupancy) of the interior rows.
+// Slot 0 of every row is its diagonal, so the first gather is the row's own X
+// value; it is returned in `own`.
 template <typename T, int RB>
 __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, RB> &L, int lr, int q,
                                           const T *__restrict__ X, const T *__restrict__ Y, bool with_b,
-                                          typename Vec16<T>::t &acc, typename Vec16<T>::t &bacc) {
+                                          typename Vec16<T>::t &acc, typename Vec16<T>::t &bacc,
+                                          typename Vec16<T>::t &own) {
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
     const int base = lr * G::W;
@@ -416,6 +419,7 @@ __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, R
 #pragma unroll
         for (int j = 0; j < CH; ++j)
             x[j] = *reinterpret_cast<const VT *>(Xc + (uint32_t(L.col[base + j0 + j]) * ROWB + qoff));
+        if (j0 == 0) own = x[0];
 #pragma unroll
         for (int j = 0; j < CH; ++j) acc = vfma(L.kv[base + j0 + j], x[j], acc);
     }
@@ -483,9 +487,8 @@ __device__ __forceinline__ void fwd_tile(const VFwdArgs<T> &a, int tile, TileOps
             const int64_t id = int64_t(row) * RB + q * G::VEC;
             VT v0 = {};
             if (!a.first) v0 = *reinterpret_cast<const VT *>(a.V + id);
-            const VT p0 = *reinterpret_cast<const VT *>(a.P + id);
-            VT acc = {}, bacc = {};
-            vrow_sums<T, RB>(a.o, L, lr, q, a.P, a.V, !a.first && L.bo[lr] >= 0, acc, bacc);
+            VT acc = {}, bacc = {}, p0;
+            vrow_sums<T, RB>(a.o, L, lr, q, a.P, a.V, !a.first && L.bo[lr] >= 0, acc, bacc, p0);
             const T dm = L.dm[lr];
             VT v, pn;
 #pragma unroll
@@ -590,10 +593,8 @@ __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps
     if (row >= a.n) return;
     const int64_t id = int64_t(row) * RB + q * G::VEC;
     const VT ph0 = *reinterpret_cast<const VT *>(a.PH + id);
-    VT q0 = {};
-    if (!a.last) q0 = *reinterpret_cast<const VT *>(a.Q + id);
-    VT kq = {}, bq = {};
-    vrow_sums<T, RB>(a.o, L, lr, q, a.Q, a.Q, !a.last && L.bo[lr] >= 0, kq, bq);
+    VT kq = {}, bq = {}, q0;
+    vrow_sums<T, RB>(a.o, L, lr, q, a.Q, a.Q, !a.last && L.bo[lr] >= 0, kq, bq, q0);
     VT ph;
 #pragma unroll
     for (int i = 0; i < G::VEC; ++i) ph[i] = ph0[i] - a.dt * kq[i];

@@ -493,19 +493,23 @@ void build_padded_rows(HostProblem &hp) {
     std::vector<int32_t> order;
     for (int32_t i = 0; i < N; ++i) {
         const int32_t k0 = hp.rowptr[i], len = hp.rowptr[i + 1] - k0;
-        // slot order: for boundary rows the entries with a nonzero B first (so the
-        // boundary sums touch only bnum[i] slots), then the rest, each in column order
+        // slot order: the diagonal first (the step kernels read the row's own state
+        // from that gather), then for boundary rows the other entries with a nonzero B
+        // (so the boundary sums touch only bnum[i] slots), then the rest, each group in
+        // column order
         order.resize(size_t(len));
-        int32_t nb = 0;
-        if (hp.boff[i] >= 0) {
-            for (int32_t j = 0; j < len; ++j)
-                if (hp.bval[size_t(hp.boff[i] + j)] != 0.0) order[size_t(nb++)] = j;
-            int32_t o = nb;
-            for (int32_t j = 0; j < len; ++j)
-                if (hp.bval[size_t(hp.boff[i] + j)] == 0.0) order[size_t(o++)] = j;
-        } else {
-            for (int32_t j = 0; j < len; ++j) order[size_t(j)] = j;
-        }
+        int32_t diag = -1;
+        for (int32_t j = 0; j < len; ++j)
+            if (hp.col[k0 + j] == i) diag = j;
+        const bool bnd = hp.boff[i] >= 0;
+        auto has_b = [&](int32_t j) { return bnd && hp.bval[size_t(hp.boff[i] + j)] != 0.0; };
+        int32_t o = 0;
+        if (diag >= 0) order[size_t(o++)] = diag;
+        for (int32_t j = 0; j < len; ++j)
+            if (j != diag && has_b(j)) order[size_t(o++)] = j;
+        const int32_t nb = bnd ? o : 0;
+        for (int32_t j = 0; j < len; ++j)
+            if (j != diag && !has_b(j)) order[size_t(o++)] = j;
         hp.bnum[size_t(i)] = nb;
         for (int j = 0; j < W; ++j) {
             hp.ell_col[size_t(i) * W + j] = j < len ? hp.col[k0 + order[size_t(j)]] : i;
