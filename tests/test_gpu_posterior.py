@@ -1,0 +1,55 @@
+"""The GPU sampler draws from the exact Gaussian posterior (App. A; the small-problem
+validation of Sec. 6.2).
+
+On a 64-node ball the posterior is available in closed form,
+    C_post = (G^T G / sigma^2 + L^T L)^-1,  mu_post = C_post G^T y / sigma^2,
+with G and L assembled densely by the oracle.  RTO samples solved to convergence
+(n_iter = N, float64 sweeps, device-drawn perturbations) must reproduce mu_post and
+diag(C_post) within their sampling error: |mean - mu| < 5 sqrt(C_ii / S) per node and
+|var / C_ii - 1| < 5 sqrt(2 / (S - 1)).  Both solvers and both priors-as-factors
+(a = 0.01 and a = 0, the paper's i.i.d. prior of eq. (iid-prior)) are covered.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pat = pytest.importorskip("paper_2607_21373_amd.pat")
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    coords, tets = W.ball_mesh(3)
+    w = W.Workload(name="tiny", coords=coords, tets=tets, c_tet=None, absorbing=True, dt=0.2 * 2 / 3, n_steps=30,
+                   sensor_pos=W.fibonacci_sphere(12, 0.7), p0_true=W.smooth_bump(coords, 0.8))
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    N = w.n_nodes
+    Gd = O.forward(np.eye(N)).reshape(N, -1).T
+    return w, O, G, Gd
+
+
+@pytest.mark.parametrize("solver,a", [("cgls", 0.01), ("lsqr", 0.01), ("cgls", 0.0)])
+def test_samples_follow_exact_posterior(tiny, solver, a):
+    w, O, G, Gd = tiny
+    N = w.n_nodes
+    L = O.prior_apply(np.eye(N), a).T
+    y = O.forward(w.p0_true) + 0.02 * np.random.default_rng(8).standard_normal((w.n_steps, w.n_obs))
+    sigma = 0.02
+    H = Gd.T @ Gd / sigma ** 2 + L.T @ L
+    C = np.linalg.inv(H)
+    mu = C @ (Gd.T @ y.ravel()) / sigma ** 2
+    S = 4096
+    out = pat.rto_sample(G, torch.as_tensor(y, device="cuda"), None, None, sigma, a, N, sweep_prec="f64",
+                         rhs_block=64, n_samples=S, seed=11, solver=solver)
+    mean = out["mean"].cpu().numpy()
+    var = out["std"].cpu().numpy() ** 2
+    d = np.diag(C)
+    zm = np.abs(mean - mu) / np.sqrt(d / S)
+    zv = np.abs(var / d - 1) / np.sqrt(2.0 / (S - 1))
+    print(f"{solver} a={a}: max |mean - mu| / se = {zm.max():.2f}, max |var/C_ii - 1| / se = {zv.max():.2f}")
+    assert zm.max() < 5 and zv.max() < 5
