@@ -103,12 +103,11 @@ def _synth(pat, W, w, G, dev):
     return (Y + sigma * eta0).contiguous(), sigma
 
 
-def uneven_leg(pat, W, dev, n_iter, modes=False):
-    """Three meshes of different sizes sampled together (one merged launch per time step),
-    16 samples each with device-drawn perturbations, against the same three solves run
-    one after another with the same RHS block."""
+def uneven_leg(pat, W, dev, n_iter, modes=False, names=("cube40", "ball60", "slab120")):
+    """Meshes of different sizes sampled together (rto_sample_batch, autotuned launch mode),
+    16 samples each with device-drawn perturbations, against the same solves run one
+    after another with the same RHS block."""
     import torch
-    names = ("cube40", "ball60", "slab120")
     ws = [W.make_workload(n) for n in names]
     t0 = time.time()
     probs = [pat.Problem.from_workload(w) for w in ws]
@@ -208,6 +207,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
     ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
     ap.add_argument("--uneven-modes", action="store_true", help="also time each launch mode of the uneven batch")
+    ap.add_argument("--uneven-set", default="cube40,ball60,slab120",
+                    help="workloads of the uneven batch (equal step counts), comma-separated")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (samples are independent, so "
@@ -241,15 +242,25 @@ def main():
     torch.cuda.synchronize()
     log(f"data ready: sigma={sigma:.4e}")
 
+    copy_probe = None
     if args.copy_probe_mb:
+        # device-to-device copies of a known size: counter calibration and the practical
+        # read+write bandwidth of the memory system
         n = args.copy_probe_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        dst.copy_(src)
+        e0.record()
         for _ in range(3):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 3 / 1e3
+        copy_probe = {"mib": args.copy_probe_mb, "GBs_read_plus_write": round(2 * n * 4 / sec / 1e9, 1)}
         del src, dst
-        log(f"copy probe: 3 x {args.copy_probe_mb} MiB float32 copies")
+        log(f"copy probe: {args.copy_probe_mb} MiB float32 copies at {copy_probe['GBs_read_plus_write']} GB/s "
+            f"(read + write)")
 
     def run():
         return pat.rto_sample(G, yobs, eta, xi, sigma, w.prior_a, n_iter, sweep_prec="f32", rhs_block=64)
@@ -323,8 +334,11 @@ def main():
                                 "seconds_per_sample": round(tp, 3), "speedup_batched_f32": round(value / plain, 2)}
         log(f"plain f64 (1 sample, R=1): {tp:.2f} s -> {plain:.2f} samples/min; speed-up {value / plain:.1f}x")
 
+    if copy_probe:
+        result["copy_probe"] = copy_probe
     if not args.no_uneven:
-        result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter, modes=args.uneven_modes)
+        names = tuple(args.uneven_set.split(","))
+        result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter, modes=args.uneven_modes, names=names)
     if args.big:
         result["ball100_single_sample"] = big_leg(pat, W, dev, n_iter)
 

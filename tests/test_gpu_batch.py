@@ -29,16 +29,9 @@ def _dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-def _small_box():
-    w = W._box("box12", 11, 11, 5, rto_seed=21)
-    w.n_steps = 200
-    w.n_iter = 30
-    return w
-
-
 @pytest.fixture(scope="module")
 def small():
-    ws = [W.make_workload("cube8_tiny"), W.make_workload("ball16"), _small_box()]
+    ws = [W.make_workload("cube8_tiny"), W.make_workload("ball16"), W.make_workload("box12")]
     cases = []
     for w in ws:
         O = oracle.Problem.from_workload(w)

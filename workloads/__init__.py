@@ -314,6 +314,7 @@ def make_workload(name: str) -> Workload:
       1000 steps, 512 sensors (a 32 x 16 node grid on the top face of the cube
       and the slab, a Fibonacci lattice on r = 0.9 for the ball), 16 samples each.
     * ``ball100``: 100^3-node ball (10^6 nodes) with the ball58 recipe, one sample.
+    * ``box12``: 12 x 12 x 6-node absorbing box, 200 steps (a small uneven-batch member).
     """
     if name == "cube8_tiny":
         return _cube_tiny()
@@ -324,6 +325,11 @@ def make_workload(name: str) -> Workload:
     if name == "ball16":
         w = _ball(16, 64, 200, name, n_samples=16, rto_seed=7)
         w.n_iter = 50
+        return w
+    if name == "box12":
+        w = _box(name, 11, 11, 5, rto_seed=21)
+        w.n_steps = 200
+        w.n_iter = 30
         return w
     if name == "cube40":
         return _box(name, 39, 39, 39, rto_seed=11)
@@ -336,7 +342,8 @@ def make_workload(name: str) -> Workload:
     raise KeyError(name)
 
 
-WORKLOADS = ("cube8_tiny", "ball58_fp64", "ball58_batched", "ball16", "cube40", "ball60", "slab120", "ball100")
+WORKLOADS = ("cube8_tiny", "ball58_fp64", "ball58_batched", "ball16", "box12", "cube40", "ball60", "slab120",
+             "ball100")
 
 
 def rto_draws(n_samples: int, n_steps: int, n_obs: int, n_nodes: int, seed: int):
