@@ -3,8 +3,9 @@
 ``PatForward`` applies Y = G p0 (Sec. 3 eq. (discrete-wave-matrix)); its backward
 is the hand-written transpose sweep G^T (Sec. 5.1, eqs. (backward-recursion) and
 (adjoint-verlet)), which is the exact algebraic transpose, so gradients of any
-loss of Y are exact.  ``PatPrior`` applies the prior factor L with backward L^T.
-Both run entirely in libpat's kernels.
+loss of Y are exact.  ``PatPrior`` applies the prior factor L with backward L^T,
+and ``PatSpectral`` the spectral-prior map P (latent grid -> nodes) with backward
+P^T.  All run entirely in libpat's kernels.
 
 ``map_gradient_descent`` minimises the MAP objective of Sec. 5 eq. (MAP),
     f(p) = 1/(2 sigma^2) ||G p - y||^2 + 1/2 ||L p||^2,
@@ -43,6 +44,27 @@ class PatPrior(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gy):
         return _pat.pat_prior_apply(ctx.problem, gy.contiguous(), ctx.prior_a, transpose=True), None, None
+
+
+class PatSpectral(torch.autograd.Function):
+    """p0 = P w for latent w [R][n^3] (float64) with the handle's spectral prior
+    (Sec. 4.1 eq. (matern-cov-op), Sec. 6.4); backward: P^T."""
+
+    @staticmethod
+    def forward(ctx, w, problem):
+        ctx.problem = problem
+        return _pat.spectral_apply(problem, w.contiguous())
+
+    @staticmethod
+    def backward(ctx, gy):
+        return _pat.spectral_apply(ctx.problem, gy.contiguous(), transpose=True), None
+
+
+def spectral_op(problem, w):
+    """Differentiable P w; w may be [n^3] or [R][n^3] (float64)."""
+    if w.dim() == 1:
+        return PatSpectral.apply(w[None], problem)[0]
+    return PatSpectral.apply(w, problem)
 
 
 def forward_op(problem, p0):

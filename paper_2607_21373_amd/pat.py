@@ -447,11 +447,11 @@ class Batch:
 
 def rto_sample_batch(batch: Batch, y_obs, eta, xi, sigma, prior_a, n_iter: int, reorth: bool = True,
                      sweep_prec: str = "f32", rhs_block: int = 0, stats: bool = True, resid: bool = False,
-                     solver: str = "cgls", diag: bool = False, n_samples=None, seed=0, sample0=0):
-    """rto_sample for every problem of the batch in one call (sweeps merged per time step).
+                     solver: str = "cgls", diag: bool = False, n_samples=None, seed=0, sample0=0, prior="fe"):
+    """rto_sample for every problem of the batch in one call (shared sweep launches).
 
     Per-problem lists: y_obs, eta, xi (entries None for device draws), sigma,
-    prior_a, n_samples, seed, sample0 (scalars are broadcast).  Returns one
+    prior_a, n_samples, seed, sample0, prior (scalars are broadcast).  Returns one
     result dict per problem."""
     n = len(batch.problems)
 
@@ -460,13 +460,15 @@ def rto_sample_batch(batch: Batch, y_obs, eta, xi, sigma, prior_a, n_iter: int, 
 
     eta, xi, sigma, prior_a = per(eta), per(xi), per(sigma), per(prior_a)
     n_samples, seed, sample0 = per(n_samples), per(seed), per(sample0)
+    prior = [prior] * n if isinstance(prior, str) else list(prior)
     prms = (RtoParams * n)()
     S = (ctypes.c_int64 * n)()
     ys, smp, mn, sd, rs = [(ctypes.c_void_p * n)() for _ in range(5)]
     outs = []
     for m, p in enumerate(batch.problems):
         prm, S[m], out, ptr = _rto_call(p, y_obs[m], eta[m], xi[m], sigma[m], prior_a[m], n_iter, reorth, sweep_prec,
-                                        rhs_block, stats, resid, None, solver, diag, n_samples[m], seed[m], sample0[m])
+                                        rhs_block, stats, resid, None, solver, diag, n_samples[m], seed[m], sample0[m],
+                                        prior[m])
         prms[m] = prm
         ys[m], smp[m] = ptr["y"].value, ptr["samples"].value
         mn[m] = ptr["mean"].value if ptr["mean"] is not None else None

@@ -144,3 +144,27 @@ def test_map_descent_fullsize(big):
         f_cg = float(ag.map_objective(G, p_cg, y, sigma, a))
     print(f"MAP objective: GD(200) {f_gd:.6e}  CGLS(200) {f_cg:.6e}  start {hist[0]:.6e}")
     assert f_cg <= f_gd * (1 + 1e-12) and f_gd < hist[0]
+
+
+def test_spectral_op_gradient(small):
+    """d/dw of 0.5 ||G P w - y||^2: autograd through PatSpectral and PatForward against central differences."""
+    w, O, G, yobs, sigma = small
+    n = 8
+    pat.spectral_prior_set(G, n, -1.25, 2.5, 0.3, 3.0)
+    rng = np.random.default_rng(33)
+    lat = _dev(rng.standard_normal(n ** 3)).requires_grad_(True)
+    y = _dev(yobs)
+
+    def f(v):
+        r = ag.forward_op(G, ag.spectral_op(G, v)) - y
+        return 0.5 * torch.sum(r * r)
+
+    (g,) = torch.autograd.grad(f(lat), lat)
+    eps = 1e-6
+    with torch.no_grad():
+        for k in range(5):
+            d = _dev(np.random.default_rng(200 + k).standard_normal(n ** 3))
+            fd = float((f(lat + eps * d) - f(lat - eps * d)) / (2 * eps))
+            an = float(torch.dot(g, d))
+            assert abs(fd - an) <= 1e-6 * abs(an)
+    pat.spectral_prior_set(G, None, 0, 0, 0, 0)

@@ -85,6 +85,24 @@ def test_batch_launch_modes_agree(small, mf, ma):
         B.merge(3, 0)
 
 
+def test_batch_mixed_priors(small):
+    """One problem with the spectral prior (latent-space solve), the others with the FE factor."""
+    G1 = small[1][2]
+    pat.spectral_prior_set(G1, 8, -1.25, 2.5, 0.3, 3.0)
+    try:
+        B = pat.Batch([c[2] for c in small])
+        ys = [_dev(c[3]) for c in small]
+        prior, S = ["fe", "spectral", "fe"], [4, 6, 5]
+        outs = pat.rto_sample_batch(B, ys, None, None, [c[4] for c in small], 0.01, 10, sweep_prec="f32",
+                                    rhs_block=8, n_samples=S, seed=[1, 2, 3], prior=prior)
+        for m, c in enumerate(small):
+            ref = pat.rto_sample(c[2], ys[m], None, None, c[4], 0.01, 10, sweep_prec="f32", rhs_block=8,
+                                 n_samples=S[m], seed=m + 1, prior=prior[m])
+            assert torch.equal(outs[m]["samples"], ref["samples"]), m
+    finally:
+        pat.spectral_prior_set(G1, None, 0, 0, 0, 0)
+
+
 def test_batch_matches_oracle(small):
     S = (10, 16, 6)
     inp = _inputs(small, S)
