@@ -11,6 +11,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <string>
@@ -186,13 +187,22 @@ std::vector<float> to_f32(const std::vector<double> &v) {
 pat_status get_sweep(pat_problem *p, pat::Prec prec, int RB, bool need_y, SweepWS **out) {
     SweepWS &w = p->sweeps[{int(prec), RB}];
     if (w.RB == 0) {
+        // all four state buffers or none (a failed allocation leaves the workspace empty)
+        const size_t bytes = size_t(p->ops.n) * RB * tsize(prec);
+        void *v[4] = {nullptr, nullptr, nullptr, nullptr};
+        for (int k = 0; k < 4; ++k) {
+            pat_status st = dev_alloc(p, &v[k], bytes);
+            if (st != PAT_OK) {
+                for (int q = 0; q < k; ++q) dev_free(p, v[q]);
+                return st;
+            }
+        }
+        w.P[0] = v[0];
+        w.P[1] = v[1];
+        w.V[0] = v[2];
+        w.V[1] = v[3];
         w.prec = prec;
         w.RB = RB;
-        const size_t bytes = size_t(p->ops.n) * RB * tsize(prec);
-        for (int k = 0; k < 2; ++k) {
-            PAT_TRY(dev_alloc(p, &w.P[k], bytes));
-            PAT_TRY(dev_alloc(p, &w.V[k], bytes));
-        }
     }
     if (need_y && !w.Y) {
         PAT_TRY(dev_alloc(p, &w.Y, size_t(p->ops.n_steps) * p->ops.n_obs * RB * tsize(prec)));
@@ -281,40 +291,39 @@ pat_status get_cgls(pat_problem *p, int RB, int64_t NX, int n_iter, bool reorth,
                     CglsWS **out) {
     CglsWS &c = p->cgls[{RB, NX}];
     const int64_t N = NX, M = int64_t(p->ops.n_steps) * p->ops.n_obs;
-    if (c.RB == 0) {
-        c.RB = RB;
-        void *v;
-        double **vec[] = {&c.x, &c.d, &c.s, &c.rp, &c.qp};
-        for (double **q : vec) {
-            PAT_TRY(dev_alloc(p, &v, size_t(N) * RB * 8));
-            *q = static_cast<double *>(v);
+    // each group of buffers is committed to the workspace only once all of it is allocated,
+    // so a failed allocation never leaves a half-filled workspace behind
+    auto alloc_group = [&](std::initializer_list<std::pair<double **, size_t>> group) -> pat_status {
+        std::vector<void *> got;
+        for (const auto &g : group) {
+            void *v = nullptr;
+            pat_status st = dev_alloc(p, &v, g.second);
+            if (st != PAT_OK) {
+                for (void *q : got) dev_free(p, q);
+                return st;
+            }
+            got.push_back(v);
         }
-        PAT_TRY(dev_alloc(p, &v, size_t(M) * RB * 8)); c.rd = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, size_t(M) * RB * 8)); c.qd = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, size_t(4) * pat::kDotBlocks * RB * 8)); c.part = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, size_t(16) * RB * 8)); c.scal = static_cast<double *>(v);
+        size_t k = 0;
+        for (const auto &g : group) *g.first = static_cast<double *>(got[k++]);
+        return PAT_OK;
+    };
+    const size_t nb = size_t(N) * RB * 8, mb = size_t(M) * RB * 8;
+    if (c.RB == 0) {
+        PAT_TRY(alloc_group({{&c.x, nb}, {&c.d, nb}, {&c.s, nb}, {&c.rp, nb}, {&c.qp, nb}, {&c.rd, mb},
+                             {&c.qd, mb}, {&c.part, size_t(4) * pat::kDotBlocks * RB * 8},
+                             {&c.scal, size_t(16) * RB * 8}}));
+        c.RB = RB;
     }
-    if (lsqr && !c.v) {
-        void *v;
-        PAT_TRY(dev_alloc(p, &v, size_t(N) * RB * 8)); c.v = static_cast<double *>(v);
-    }
-    if (lsqr && track && !c.zd) {
-        void *v;
-        PAT_TRY(dev_alloc(p, &v, size_t(N) * RB * 8)); c.zp = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, size_t(N) * RB * 8)); c.lrp = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, size_t(M) * RB * 8)); c.zd = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, size_t(M) * RB * 8)); c.lrd = static_cast<double *>(v);
-    }
+    if (lsqr && !c.v) PAT_TRY(alloc_group({{&c.v, nb}}));
+    if (lsqr && track && !c.zd) PAT_TRY(alloc_group({{&c.zp, nb}, {&c.lrp, nb}, {&c.lrd, mb}, {&c.zd, mb}}));
     const int need = reorth ? n_iter + 1 : 0;
     if (need > c.cap_iter) {
         dev_free(p, c.Q); dev_free(p, c.mpart); dev_free(p, c.coef);
         c.Q = c.mpart = c.coef = nullptr;
-        void *v;
-        if (need > 0) {
-            PAT_TRY(dev_alloc(p, &v, size_t(need) * N * RB * 8)); c.Q = static_cast<double *>(v);
-            PAT_TRY(dev_alloc(p, &v, size_t(need) * pat::kDotBlocks * RB * 8)); c.mpart = static_cast<double *>(v);
-            PAT_TRY(dev_alloc(p, &v, size_t(need) * RB * 8)); c.coef = static_cast<double *>(v);
-        }
+        c.cap_iter = 0;
+        PAT_TRY(alloc_group({{&c.Q, size_t(need) * nb}, {&c.mpart, size_t(need) * pat::kDotBlocks * RB * 8},
+                             {&c.coef, size_t(need) * RB * 8}}));
         c.cap_iter = need;
     }
     *out = &c;
@@ -326,11 +335,19 @@ pat_status get_spec(pat_problem *p, int RB, SpecWS **out) {
     SpecWS &w = p->specws[RB];
     if (!w.gr) {
         const size_t G = size_t(p->sops.G), N = size_t(p->ops.n);
-        void *v;
-        PAT_TRY(dev_alloc(p, &v, G * RB * 8)); w.gr = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, G * RB * 16)); w.gc = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, N * RB * 8)); w.ym = static_cast<double *>(v);
-        PAT_TRY(dev_alloc(p, &v, G * RB * 8)); w.lx = static_cast<double *>(v);
+        const size_t sizes[4] = {G * RB * 8, G * RB * 16, N * RB * 8, G * RB * 8};
+        void *v[4] = {nullptr, nullptr, nullptr, nullptr};
+        for (int k = 0; k < 4; ++k) {
+            pat_status st = dev_alloc(p, &v[k], sizes[k]);
+            if (st != PAT_OK) {
+                for (int q = 0; q < k; ++q) dev_free(p, v[q]);
+                return st;
+            }
+        }
+        w.gc = static_cast<double *>(v[1]);
+        w.ym = static_cast<double *>(v[2]);
+        w.lx = static_cast<double *>(v[3]);
+        w.gr = static_cast<double *>(v[0]);  // set last: marks the workspace complete
     }
     *out = &w;
     return PAT_OK;
