@@ -5,9 +5,11 @@ On a 64-node ball the posterior is available in closed form,
     C_post = (G^T G / sigma^2 + L^T L)^-1,  mu_post = C_post G^T y / sigma^2,
 with G and L assembled densely by the oracle.  RTO samples solved to convergence
 (n_iter = N, float64 sweeps, device-drawn perturbations) must reproduce mu_post and
-diag(C_post) within their sampling error: |mean - mu| < 5 sqrt(C_ii / S) per node and
-|var / C_ii - 1| < 5 sqrt(2 / (S - 1)).  Both solvers and both priors-as-factors
-(a = 0.01 and a = 0, the paper's i.i.d. prior of eq. (iid-prior)) are covered.
+C_post within their sampling error: |mean - mu| < 5 sqrt(C_ii / S) per node,
+|var / C_ii - 1| < 5 sqrt(2 / (S - 1)), and the Frobenius error of the sample
+covariance below 3x its expected size sqrt((||C||_F^2 + (tr C)^2) / (S - 1)).
+Both solvers and both prior factors (a = 0.01 and a = 0, the paper's i.i.d. prior
+of eq. (iid-prior)) are covered.
 """
 import numpy as np
 import pytest
@@ -51,5 +53,10 @@ def test_samples_follow_exact_posterior(tiny, solver, a):
     d = np.diag(C)
     zm = np.abs(mean - mu) / np.sqrt(d / S)
     zv = np.abs(var / d - 1) / np.sqrt(2.0 / (S - 1))
-    print(f"{solver} a={a}: max |mean - mu| / se = {zm.max():.2f}, max |var/C_ii - 1| / se = {zv.max():.2f}")
-    assert zm.max() < 5 and zv.max() < 5
+    # whole covariance: for Gaussian samples E||C_hat - C||_F^2 = (||C||_F^2 + (tr C)^2) / (S - 1)
+    X = out["samples"].cpu().numpy()
+    Ch = np.cov(X, rowvar=False)
+    ec = np.linalg.norm(Ch - C) / np.sqrt((np.linalg.norm(C) ** 2 + np.trace(C) ** 2) / (S - 1))
+    print(f"{solver} a={a}: max |mean - mu| / se = {zm.max():.2f}, max |var/C_ii - 1| / se = {zv.max():.2f}, "
+          f"||C_hat - C||_F / its expected size = {ec:.2f}")
+    assert zm.max() < 5 and zv.max() < 5 and ec < 3
