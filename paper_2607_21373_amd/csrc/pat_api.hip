@@ -322,7 +322,7 @@ pat_status get_cgls(pat_problem *p, int RB, int64_t NX, int n_iter, bool reorth,
         dev_free(p, c.Q); dev_free(p, c.mpart); dev_free(p, c.coef);
         c.Q = c.mpart = c.coef = nullptr;
         c.cap_iter = 0;
-        PAT_TRY(alloc_group({{&c.Q, size_t(need) * nb}, {&c.mpart, size_t(need) * pat::kDotBlocks * RB * 8},
+        PAT_TRY(alloc_group({{&c.Q, size_t(need) * nb}, {&c.mpart, size_t(need) * pat::kMultiBlocks * RB * 8},
                              {&c.coef, size_t(need) * RB * 8}}));
         c.cap_iter = need;
     }

@@ -136,7 +136,10 @@ void launch_axpy_neg(double *y, const double *x, const double *alpha, int64_t ro
 // Q[k] = s * invn ; d = s + beta d
 void launch_append_dir(const double *sv, double *Qk, double *d, const double *invn, const double *beta, int first,
                        int64_t rows, int RB, hipStream_t s);
-// reorthogonalisation: coef[j][r] = sum_i Q[j][i][r] s[i][r] (j < k); s -= sum_j coef[j] Q[j]
+// reorthogonalisation: coef[j][r] = sum_i Q[j][i][r] s[i][r] (j < k); s -= sum_j coef[j] Q[j].
+// The multi-dot streams k basis vectors per call and needs more workgroups than the
+// plain dots (4 per CU); part holds kMultiBlocks x k x RB partial sums.
+constexpr int kMultiBlocks = 1024;
 void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *coef,
                      hipStream_t s);
 void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s);

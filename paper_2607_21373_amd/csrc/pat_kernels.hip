@@ -815,6 +815,7 @@ __global__ void __launch_bounds__(256) k_prior(const int32_t *rowptr, const int3
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
         const int i = int(e / RB), r = int(e % RB);
         double acc = 0.0;
+#pragma unroll 4
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc = __builtin_fma(k1[k], x[int64_t(col[k]) * RB + r], acc);
         y[e] = sqrtm[i] * x[e] + a * isqrtm[i] * acc;
     }
@@ -829,6 +830,7 @@ __global__ void __launch_bounds__(256) k_gext_t(const int32_t *rowptr, const int
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
         const int i = int(e / RB), r = int(e % RB);
         double acc = 0.0;
+#pragma unroll 4
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
             const int j = col[k];
             acc = __builtin_fma(k1[k], isqrtm[j] * rp[int64_t(j) * RB + r], acc);
@@ -845,6 +847,7 @@ __global__ void __launch_bounds__(256) k_prior_t(const int32_t *rowptr, const in
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
         const int i = int(e / RB), r = int(e % RB);
         double acc = 0.0;
+#pragma unroll 4
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
             const int j = col[k];
             acc = __builtin_fma(k1[k], isqrtm[j] * x[int64_t(j) * RB + r], acc);
@@ -1468,8 +1471,8 @@ void launch_append_dir(const double *sv, double *Qk, double *d, const double *in
 void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *coef,
                      hipStream_t s) {
     if (k <= 0) return;
-    hipLaunchKernelGGL(k_multidot_partial, dim3(kDotBlocks), dim3(256), 0, s, Q, sv, k, rows, RB, part);
-    hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(256), 0, s, part, kDotBlocks, k, RB, coef);
+    hipLaunchKernelGGL(k_multidot_partial, dim3(kMultiBlocks), dim3(256), 0, s, Q, sv, k, rows, RB, part);
+    hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(256), 0, s, part, kMultiBlocks, k, RB, coef);
 }
 
 void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s) {
