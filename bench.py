@@ -204,6 +204,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy a float32 buffer of this many MB three times (counter calibration)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="time a plain elementwise update over four state-sized float32 arrays (what streaming "
+                         "reaches for the step's working set) and over arrays 8x larger (past the 256 MB cache)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
     ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
     ap.add_argument("--uneven-modes", action="store_true", help="also time each launch mode of the uneven batch")
@@ -261,6 +264,32 @@ def main():
         del src, dst
         log(f"copy probe: {args.copy_probe_mb} MiB float32 copies at {copy_probe['GBs_read_plus_write']} GB/s "
             f"(read + write)")
+
+    stream_probe = None
+    if args.stream_probe:
+        # V' = V - c P, P' = P + c V' with torch's elementwise kernels on arrays of the
+        # step's state size (N x 64 float32): 6 array passes per update, no gathers
+        stream_probe = {}
+        for label, scale, reps in (("state_size", 1, 200), ("state_size_x8", 8, 25)):
+            n = scale * w.n_nodes * R
+            P, V = torch.ones(n, dtype=torch.float32, device=dev), torch.ones(n, dtype=torch.float32, device=dev)
+            P2, V2 = torch.empty_like(P), torch.empty_like(P)
+
+            def upd():
+                torch.add(V, P, alpha=-1e-3, out=V2)
+                torch.add(P, V2, alpha=1e-3, out=P2)
+
+            upd()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                upd()
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / reps / 1e3
+            stream_probe[label] = {"array_MB": round(n * 4 / 1e6, 1), "GBs": round(6 * n * 4 / sec / 1e9, 1)}
+            del P, V, P2, V2
+        log(f"stream probe: {stream_probe}")
 
     def run():
         return pat.rto_sample(G, yobs, eta, xi, sigma, w.prior_a, n_iter, sweep_prec="f32", rhs_block=64)
@@ -336,6 +365,8 @@ def main():
 
     if copy_probe:
         result["copy_probe"] = copy_probe
+    if stream_probe:
+        result["stream_probe"] = stream_probe
     if not args.no_uneven:
         names = tuple(args.uneven_set.split(","))
         result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter, modes=args.uneven_modes, names=names)
