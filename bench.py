@@ -193,6 +193,35 @@ def big_leg(pat, W, dev, n_iter):
     return res
 
 
+def wide_leg(pat, dev, G, info, w, yobs, sigma, n_iter):
+    """256 samples as one 256-RHS block on the same mesh: the float32 state of a step
+    (4 x N x 256 x 4 B = 800 MB) no longer fits the 256 MB Infinity Cache."""
+    import torch
+    S = RB = 256
+    args = (G, yobs, None, None, sigma, w.prior_a)
+    pat.rto_sample(*args, 2, sweep_prec="f32", rhs_block=RB, n_samples=S, seed=11)  # graphs and workspaces
+    G.profile_enable(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    pat.rto_sample(*args, n_iter, sweep_prec="f32", rhs_block=RB, n_samples=S, seed=11)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    prof = G.profile()
+    G.profile_enable(False)
+    # as in the main leg: sweep time over N_T step launches (the extra init/sampling launch is tiny)
+    fwd_s = prof["fwd_ms"] / max(prof["fwd_sweeps"], 1) / w.n_steps / 1e3
+    adj_s = prof["adj_ms"] / max(prof["adj_sweeps"], 1) / w.n_steps / 1e3
+    fb, ab = step_bytes(info, RB, 4, "fwd"), step_bytes(info, RB, 4, "adj")
+    res = {"samples": S, "rhs_block": RB, "iters": n_iter, "seconds": round(el, 3),
+           "value": round(S * 60.0 / el, 3), "unit": "samples/min",
+           "fwd_step_us": round(fwd_s * 1e6, 3), "fwd_step_GBs": round(fb / fwd_s / 1e9, 1),
+           "adj_step_us": round(adj_s * 1e6, 3), "adj_step_GBs": round(ab / adj_s / 1e9, 1),
+           "bytes_per_fwd_launch": fb}
+    log(f"wide block: {S} samples as one {RB}-RHS block in {el:.2f} s ({res['value']:.1f} samples/min); forward "
+        f"step {fwd_s * 1e6:.1f} us ({res['fwd_step_GBs']:.0f} GB/s), transpose {adj_s * 1e6:.1f} us")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +238,8 @@ def main():
                          "reaches for the step's working set) and over arrays 8x larger (past the 256 MB cache)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
     ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
+    ap.add_argument("--wide", action="store_true",
+                    help="also time 256 samples as one 256-RHS block (working set beyond the Infinity Cache)")
     ap.add_argument("--uneven-modes", action="store_true", help="also time each launch mode of the uneven batch")
     ap.add_argument("--uneven-set", default="cube40,ball60,slab120",
                     help="workloads of the uneven batch (equal step counts), comma-separated")
@@ -370,6 +401,8 @@ def main():
     if not args.no_uneven:
         names = tuple(args.uneven_set.split(","))
         result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter, modes=args.uneven_modes, names=names)
+    if args.wide:
+        result["wide_block"] = wide_leg(pat, dev, G, info, w, yobs, sigma, n_iter)
     if args.big:
         result["ball100_single_sample"] = big_leg(pat, W, dev, n_iter)
 

@@ -126,9 +126,13 @@ typedef struct {
     int32_t n_iter;            /* solver iterations (fixed; >= 1) */
     int32_t reorth;            /* 1: full reorthogonalisation (default); see pat_solver */
     pat_precision sweep_prec;  /* precision of the wave sweeps; solver vectors and scalars are always float64 */
-    int32_t rhs_block;         /* samples per multi-RHS block: 1, 2, 4, ..., 64, or 0 = the autotuned block for
-                                  (S, sweep_prec) if pat_autotune / pat_batch_autotune ran, else the
-                                  smallest power of two >= S (at most 64) */
+    int32_t rhs_block;         /* samples per multi-RHS block: a power of two up to 256 (float32 sweeps) or 128
+                                  (float64 sweeps; a row of the block spans at most one wave), or 0 = the
+                                  autotuned block for (S, sweep_prec) if pat_autotune / pat_batch_autotune
+                                  ran, else the smallest power of two >= S (at most 64).  One block's
+                                  sweep state, N x block x element size, must stay below 4 GiB: automatic
+                                  choices halve the block until it does, an explicit larger block is
+                                  PAT_ERR_INVALID_ARG */
     const double *eta;         /* device [S][N_T][N_obs] standard-normal data perturbations, or NULL */
     const double *xi;          /* device [S][N] standard-normal prior perturbations, or NULL (both or neither) */
     int32_t solver;            /* pat_solver; 0 (CGLS) when the struct is zero-initialised */
@@ -180,8 +184,9 @@ pat_status pat_spectral_prior_set(pat_problem *p, const pat_spectral_desc *d);
  * transpose = 1: y = P^T x, x device [R][N] -> y device [R][n^3].  float64. */
 pat_status pat_spectral_apply(pat_problem *p, int64_t R, int transpose, const double *x, double *y, void *stream);
 
-/* Autotuner of the RHS block.  For each candidate block RB (powers of two from
- * 1/16 of the smallest block holding S up to it) it times 8 forward and 8
+/* Autotuner of the RHS block.  With B the smallest power of two >= S (at most 256
+ * for float32 and 128 for float64 sweeps), for each candidate block RB (powers of
+ * two from max(1, min(B, 64) / 16) up to B) it times 8 forward and 8
  * transpose steps, captured in graphs as the sweeps are, with HIP events after a
  * warm-up, prices S samples as
  * ceil(S/RB) * (forward + transpose step) and records the cheapest RB for

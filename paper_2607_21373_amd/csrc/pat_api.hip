@@ -66,9 +66,30 @@ int choose_rb(int64_t R) {
     return rb;
 }
 
-bool valid_rb(int rb) { return rb == 1 || rb == 2 || rb == 4 || rb == 8 || rb == 16 || rb == 32 || rb == 64; }
+// an explicit RHS block: a power of two up to the step kernels' limit for the sweep precision
+bool valid_rb(int rb, pat::Prec pr) { return rb >= 1 && rb <= pat::max_rhs_block(pr) && (rb & (rb - 1)) == 0; }
 
 size_t tsize(pat::Prec p) { return p == pat::Prec::F64 ? 8 : 4; }
+
+// The vector-lane step kernels (rows of >= 16 bytes) address one block's state
+// (N x block x element size) with 32-bit byte offsets, so it must stay below 4 GiB;
+// the scalar-lane kernels use 64-bit indices.
+bool block_fits(int64_t n, pat::Prec pr, int rb) {
+    const uint64_t row = uint64_t(rb) * tsize(pr);
+    return row < 16 || uint64_t(n) * row < (uint64_t(1) << 32);
+}
+
+// the largest block <= rb (halving) whose state fits the step kernels' addressing
+int fit_rb(int64_t n, pat::Prec pr, int rb) {
+    while (rb > 1 && !block_fits(n, pr, rb)) rb >>= 1;
+    return rb;
+}
+
+pat_status check_block(int64_t n, pat::Prec pr, int rb) {
+    if (block_fits(n, pr, rb)) return PAT_OK;
+    return fail(PAT_ERR_INVALID_ARG, "RHS block of " + std::to_string(rb) + " too large for a mesh of " +
+                                         std::to_string(n) + " nodes: one block's state must stay below 4 GiB");
+}
 
 }  // namespace
 
@@ -353,9 +374,9 @@ pat_status get_spec(pat_problem *p, int RB, SpecWS **out) {
     return PAT_OK;
 }
 
-int auto_rb(const std::map<std::pair<int64_t, int>, int> &tuned, int64_t S, pat::Prec pr) {
+int auto_rb(const std::map<std::pair<int64_t, int>, int> &tuned, int64_t n, int64_t S, pat::Prec pr) {
     auto it = tuned.find({S, int(pr)});
-    return it != tuned.end() ? it->second : choose_rb(S);
+    return it != tuned.end() ? it->second : fit_rb(n, pr, choose_rb(S));
 }
 
 // ---- several meshes per sweep launch ------------------------------------
@@ -437,8 +458,13 @@ void enqueue_adjoint_multi(const std::vector<pat_problem *> &P, const std::vecto
 // launch per mesh, and the faster is kept (*mf, *ma).
 pat_status tune_rb(const std::vector<pat_problem *> &P, hipStream_t cap, int64_t S, pat::Prec pr, hipStream_t s,
                    int *best, double *best_us, int *mf = nullptr, int *ma = nullptr) {
-    const int top = choose_rb(S);
-    const int lo = std::max(1, top / 16);
+    // candidates: up to the smallest block holding all S samples (beyond 64 only when S needs it)
+    int top = 1;
+    while (top < S && top < pat::max_rhs_block(pr)) top <<= 1;
+    int64_t nmax = 0;
+    for (const pat_problem *q : P) nmax = std::max<int64_t>(nmax, q->ops.n);
+    top = fit_rb(nmax, pr, top);
+    const int lo = std::max(1, std::min(top, 64) / 16);
     const int reps = 8;
     hipEvent_t ev[5];
     for (auto &e : ev) PAT_HIP(hipEventCreate(&e));
@@ -806,8 +832,10 @@ pat_status check_rto_params(const pat_rto_params *prm, int64_t S, bool want_std)
     if (!(prm->prior_a >= 0.0) || !std::isfinite(prm->prior_a)) return fail(PAT_ERR_INVALID_ARG, "prior_a must be >= 0");
     if (prm->n_iter < 1) return fail(PAT_ERR_INVALID_ARG, "n_iter must be >= 1");
     if (want_std && S < 2) return fail(PAT_ERR_INVALID_ARG, "std needs S >= 2");
-    if (prm->rhs_block != 0 && !valid_rb(prm->rhs_block))
-        return fail(PAT_ERR_INVALID_ARG, "rhs_block must be 0 or a power of two <= 64");
+    if (prm->rhs_block != 0 &&
+        !valid_rb(prm->rhs_block, prm->sweep_prec == PAT_F64 ? pat::Prec::F64 : pat::Prec::F32))
+        return fail(PAT_ERR_INVALID_ARG,
+                    "rhs_block must be 0 or a power of two <= 256 (float32 sweeps) or <= 128 (float64 sweeps)");
     if (prm->solver != PAT_CGLS && prm->solver != PAT_LSQR)
         return fail(PAT_ERR_INVALID_ARG, "solver must be PAT_CGLS or PAT_LSQR");
     if (prm->prior != PAT_PRIOR_FE && prm->prior != PAT_PRIOR_SPECTRAL)
@@ -993,7 +1021,8 @@ pat_status pat_forward(pat_problem *p, int64_t R, const void *p0, void *y, pat_p
     DeviceGuard guard(p->device);
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int RB = choose_rb(R);
+    const int RB = fit_rb(p->ops.n, pr, choose_rb(R));
+    PAT_TRY(check_block(p->ops.n, pr, RB));
     SweepWS *w;
     PAT_TRY(get_sweep(p, pr, RB, true, &w));
     if (!w->g_fwd_user)
@@ -1018,7 +1047,8 @@ pat_status pat_adjoint(pat_problem *p, int64_t R, const void *yhat, void *p_out,
     DeviceGuard guard(p->device);
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int RB = choose_rb(R);
+    const int RB = fit_rb(p->ops.n, pr, choose_rb(R));
+    PAT_TRY(check_block(p->ops.n, pr, RB));
     SweepWS *w;
     PAT_TRY(get_sweep(p, pr, RB, true, &w));
     const bool f64 = pr == pat::Prec::F64;
@@ -1046,7 +1076,8 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    const int RB = prm->rhs_block ? prm->rhs_block : auto_rb(p->tuned, S, pr);
+    const int RB = prm->rhs_block ? prm->rhs_block : auto_rb(p->tuned, p->ops.n, S, pr);
+    PAT_TRY(check_block(p->ops.n, pr, RB));
     PAT_TRY(check_spectral(p, prm, RB));
     const int n_iter = prm->n_iter;
     const bool lsqr = prm->solver == PAT_LSQR;
@@ -1192,7 +1223,9 @@ pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_
     DeviceGuard guard(b->device);
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int RB = prm[0].rhs_block ? prm[0].rhs_block : choose_rb(smax);
+    int64_t nmax = 0;
+    for (size_t m = 0; m < n; ++m) nmax = std::max<int64_t>(nmax, b->probs[m]->ops.n);
+    int RB = prm[0].rhs_block ? prm[0].rhs_block : fit_rb(nmax, pr, choose_rb(smax));
     int mf = 1, ma = 1;
     {
         auto it = b->tune.find({smax, int(pr)});
@@ -1204,6 +1237,7 @@ pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_
         if (b->force_mf >= 0) mf = b->force_mf;
         if (b->force_ma >= 0) ma = b->force_ma;
     }
+    PAT_TRY(check_block(nmax, pr, RB));
     const int n_iter = prm[0].n_iter;
     const bool lsqr = prm[0].solver == PAT_LSQR;
 

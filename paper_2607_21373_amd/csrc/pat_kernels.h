@@ -67,6 +67,9 @@ struct AdjStep {
     double yscale;
 };
 bool multi_step_supported(Prec prec, int RB);
+// largest RHS block of the step kernels: a row of the block spans at most one
+// wave of 16-byte lanes (256 float32 or 128 float64 values)
+int max_rhs_block(Prec prec);
 void launch_fwd_multi(Prec prec, int RB, bool y_is_f64, const FwdStep *st, int n, hipStream_t s);
 void launch_adj_multi(Prec prec, int RB, bool y_is_f64, const AdjStep *st, int n, hipStream_t s);
 

@@ -650,43 +650,52 @@ __global__ void __launch_bounds__(256) k_adj_init(const AdjArgs<T> a) {
 // Layout conversions (LDS-tiled transposes)
 // ---------------------------------------------------------------------------
 
-// out[c][r] = in[rb0 + r][perm(c)] (zero for rb0 + r >= R), tile of 64 columns
+// out[c][r] = in[rb0 + r][perm(c)] (zero for rb0 + r >= R), tile of 64 columns x 64 RHS,
+// the block's RHS in chunks of 64
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) k_pack(const TI *in, int64_t R, int64_t rb0, int RB, int64_t cols,
                                               const int32_t *perm, TO *out) {
     __shared__ double tile[64][65];
     const int64_t c0 = int64_t(blockIdx.x) * 64;
-    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
-        const int r = e / 64, c = e % 64;
-        const int64_t cc = c0 + c, rr = rb0 + r;
-        double v = 0.0;
-        if (cc < cols && rr < R) v = static_cast<double>(in[rr * cols + (perm ? perm[cc] : cc)]);
-        tile[r][c] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
-        const int c = e / RB, r = e % RB;
-        const int64_t cc = c0 + c;
-        if (cc < cols) out[cc * RB + r] = static_cast<TO>(tile[r][c]);
+    for (int r0 = 0; r0 < RB; r0 += 64) {
+        const int rn = RB - r0 < 64 ? RB - r0 : 64;
+        for (int e = threadIdx.x; e < 64 * rn; e += 256) {
+            const int r = e / 64, c = e % 64;
+            const int64_t cc = c0 + c, rr = rb0 + r0 + r;
+            double v = 0.0;
+            if (cc < cols && rr < R) v = static_cast<double>(in[rr * cols + (perm ? perm[cc] : cc)]);
+            tile[r][c] = v;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * rn; e += 256) {
+            const int c = e / rn, r = e % rn;
+            const int64_t cc = c0 + c;
+            if (cc < cols) out[cc * RB + r0 + r] = static_cast<TO>(tile[r][c]);
+        }
+        __syncthreads();
     }
 }
 
-// out[rb0 + r][perm(c)] = in[c][r] for rb0 + r < R
+// out[rb0 + r][perm(c)] = in[c][r] for rb0 + r < R (same tiling as k_pack)
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) k_unpack(const TI *in, int64_t R, int64_t rb0, int RB, int64_t cols,
                                                 const int32_t *perm, TO *out) {
     __shared__ double tile[64][65];
     const int64_t c0 = int64_t(blockIdx.x) * 64;
-    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
-        const int c = e / RB, r = e % RB;
-        const int64_t cc = c0 + c;
-        tile[r][c] = cc < cols ? static_cast<double>(in[cc * RB + r]) : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
-        const int r = e / 64, c = e % 64;
-        const int64_t cc = c0 + c, rr = rb0 + r;
-        if (cc < cols && rr < R) out[rr * cols + (perm ? perm[cc] : cc)] = static_cast<TO>(tile[r][c]);
+    for (int r0 = 0; r0 < RB; r0 += 64) {
+        const int rn = RB - r0 < 64 ? RB - r0 : 64;
+        for (int e = threadIdx.x; e < 64 * rn; e += 256) {
+            const int c = e / rn, r = e % rn;
+            const int64_t cc = c0 + c;
+            tile[r][c] = cc < cols ? static_cast<double>(in[cc * RB + r0 + r]) : 0.0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * rn; e += 256) {
+            const int r = e / 64, c = e % 64;
+            const int64_t cc = c0 + c, rr = rb0 + r0 + r;
+            if (cc < cols && rr < R) out[rr * cols + (perm ? perm[cc] : cc)] = static_cast<TO>(tile[r][c]);
+        }
+        __syncthreads();
     }
 }
 
@@ -775,21 +784,25 @@ __global__ void __launch_bounds__(256) k_xi_rng(uint64_t seed, int64_t k0, int64
     }
 }
 
-// bd[m][r] = yobs[m] * isig + eta[rb0 + r][m]  (zero rows past S)
+// bd[m][r] = yobs[m] * isig + eta[rb0 + r][m]  (zero rows past S); RHS in chunks of 64
 __global__ void __launch_bounds__(256) k_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t rb0,
                                                    int RB, int64_t M, double isig, double *bd) {
     __shared__ double tile[64][65];
     const int64_t c0 = int64_t(blockIdx.x) * 64;
-    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
-        const int r = e / 64, c = e % 64;
-        const int64_t cc = c0 + c, rr = rb0 + r;
-        tile[r][c] = (cc < M && rr < S) ? eta[rr * M + cc] : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * RB; e += 256) {
-        const int c = e / RB, r = e % RB;
-        const int64_t cc = c0 + c;
-        if (cc < M) bd[cc * RB + r] = (rb0 + r < S) ? yobs[cc] * isig + tile[r][c] : 0.0;
+    for (int r0 = 0; r0 < RB; r0 += 64) {
+        const int rn = RB - r0 < 64 ? RB - r0 : 64;
+        for (int e = threadIdx.x; e < 64 * rn; e += 256) {
+            const int r = e / 64, c = e % 64;
+            const int64_t cc = c0 + c, rr = rb0 + r0 + r;
+            tile[r][c] = (cc < M && rr < S) ? eta[rr * M + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * rn; e += 256) {
+            const int c = e / rn, r = e % rn;
+            const int64_t cc = c0 + c;
+            if (cc < M) bd[cc * RB + r0 + r] = (rb0 + r0 + r < S) ? yobs[cc] * isig + tile[r][c] : 0.0;
+        }
+        __syncthreads();
     }
 }
 
@@ -1214,29 +1227,31 @@ template <typename T, typename OT, int RB>
 void fwd_impl(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
               int t, void *y, double yscale, hipStream_t s) {
     if constexpr (RB * sizeof(T) >= 16) {
-        fwd_impl_v<T, OT, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s);
-        return;
+        // a row of the RHS block fits one wave (64 lanes x 16 bytes): up to 256 float / 128 double
+        if constexpr (RB * sizeof(T) <= 1024) fwd_impl_v<T, OT, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s);
+    } else {
+        using G = Geo<RB>;
+        FwdArgs<T> a;
+        a.o = row_ops<T>(op);
+        a.snode = op.snode;
+        a.sw = sw_of<T>(op);
+        a.P = static_cast<const T *>(P); a.V = static_cast<const T *>(V);
+        a.Pn = static_cast<T *>(Pn); a.Vn = static_cast<T *>(Vn);
+        a.y = y; a.yscale = yscale;
+        a.n = op.n; a.n_obs = op.n_obs;
+        a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
+        a.first = first; a.sample = sample; a.t = t;
+        a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
+        const int grid = rows ? persistent_grid(a.n_tiles) : 8 * ((op.n_obs + 8 * 4 * G::RPW - 1) / (8 * 4 * G::RPW));
+        hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
     }
-    using G = Geo<RB>;
-    FwdArgs<T> a;
-    a.o = row_ops<T>(op);
-    a.snode = op.snode;
-    a.sw = sw_of<T>(op);
-    a.P = static_cast<const T *>(P); a.V = static_cast<const T *>(V);
-    a.Pn = static_cast<T *>(Pn); a.Vn = static_cast<T *>(Vn);
-    a.y = y; a.yscale = yscale;
-    a.n = op.n; a.n_obs = op.n_obs;
-    a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
-    a.first = first; a.sample = sample; a.t = t;
-    a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
-    const int grid = rows ? persistent_grid(a.n_tiles) : 8 * ((op.n_obs + 8 * 4 * G::RPW - 1) / (8 * 4 * G::RPW));
-    hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
 }
 
 template <typename T, typename YT, int RB>
 void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bool last, int tm1, const void *yh,
               double yscale, hipStream_t s) {
-    using G = Geo<RB>;
+    constexpr bool vec = RB * sizeof(T) >= 16;
+    using G = Geo<vec ? 1 : RB>;  // the scalar-lane geometry, used only below 16 bytes per row
     AdjArgs<T> a;
     a.o = row_ops<T>(op);
     a.injptr = op.injptr; a.injs = op.injs;
@@ -1246,14 +1261,10 @@ void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bo
     a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
     a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
     a.dt = T(op.dt);
-    if constexpr (RB * sizeof(T) >= 16) {
-        if (!init) {
-            adj_impl_v<T, YT, RB>(op, PH, Q, Qn, last, tm1, yh, yscale, s);
-            return;
-        }
-    }
     if (init) {
         hipLaunchKernelGGL((k_adj_init<T, YT, RB>), dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, a);
+    } else if constexpr (vec) {
+        if constexpr (RB * sizeof(T) <= 1024) adj_impl_v<T, YT, RB>(op, PH, Q, Qn, last, tm1, yh, yscale, s);
     } else {
         hipLaunchKernelGGL((k_adj<T, YT, RB>), dim3(persistent_grid(a.n_tiles)), dim3(256), 0, s, a);
     }
@@ -1261,11 +1272,11 @@ void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bo
 
 template <typename T, typename OT, int RB>
 void fwd_multi(const FwdStep *st, int n, hipStream_t s) {
-    if constexpr (RB * sizeof(T) >= 16) fwd_impl_vm<T, OT, RB>(st, n, s);
+    if constexpr (RB * sizeof(T) >= 16 && RB * sizeof(T) <= 1024) fwd_impl_vm<T, OT, RB>(st, n, s);
 }
 template <typename T, typename YT, int RB>
 void adj_multi(const AdjStep *st, int n, hipStream_t s) {
-    if constexpr (RB * sizeof(T) >= 16) adj_impl_vm<T, YT, RB>(st, n, s);
+    if constexpr (RB * sizeof(T) >= 16 && RB * sizeof(T) <= 1024) adj_impl_vm<T, YT, RB>(st, n, s);
 }
 
 #define PAT_RB_SWITCH(RBV, CALL)               \
@@ -1276,7 +1287,10 @@ void adj_multi(const AdjStep *st, int n, hipStream_t s) {
         case 8: { constexpr int RB_ = 8; CALL; break; }   \
         case 16: { constexpr int RB_ = 16; CALL; break; } \
         case 32: { constexpr int RB_ = 32; CALL; break; } \
-        default: { constexpr int RB_ = 64; CALL; break; } \
+        case 64: { constexpr int RB_ = 64; CALL; break; } \
+        case 128: { constexpr int RB_ = 128; CALL; break; } \
+        case 256: { constexpr int RB_ = 256; CALL; break; } \
+        default: break;                                   \
     }
 
 }  // namespace
@@ -1316,6 +1330,8 @@ void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *
 }
 
 bool multi_step_supported(Prec prec, int RB) { return RB * (prec == Prec::F64 ? 8 : 4) >= 16; }
+
+int max_rhs_block(Prec prec) { return prec == Prec::F64 ? 128 : 256; }
 
 void launch_fwd_multi(Prec prec, int RB, bool y_is_f64, const FwdStep *st, int n, hipStream_t s) {
     if (prec == Prec::F64) {
@@ -1421,22 +1437,22 @@ void launch_dot_final(const double *partA, const double *partB, int RB, double *
 }
 
 void launch_scalar_alpha(const double *gamma, const double *delta, double *alpha, int RB, hipStream_t s) {
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, s, gamma, delta, alpha, RB);
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(256), 0, s, gamma, delta, alpha, RB);
 }
 
 void launch_scalar_gamma(double *gamma, const double *gnew, double *beta, double *invn, int first, int RB,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(64), 0, s, gamma, gnew, beta, invn, first, RB);
+    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(256), 0, s, gamma, gnew, beta, invn, first, RB);
 }
 
 void launch_resid(const double *a, const double *b, double *hist, double *diag, int64_t ld, int64_t col, int64_t rb0,
                   int64_t R, int RB, hipStream_t s) {
-    hipLaunchKernelGGL(k_resid, dim3(1), dim3(64), 0, s, a, b, hist, diag, ld, col, rb0, R, RB);
+    hipLaunchKernelGGL(k_resid, dim3(1), dim3(256), 0, s, a, b, hist, diag, ld, col, rb0, R, RB);
 }
 
 void launch_lsqr_scalar(LsqrStage st, const LsqrScalars &c, const double *n1, const double *n2, int RB,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_lsqr_scalar, dim3(1), dim3(64), 0, s, st, c, n1, n2, RB);
+    hipLaunchKernelGGL(k_lsqr_scalar, dim3(1), dim3(256), 0, s, st, c, n1, n2, RB);
 }
 
 void launch_lincomb(double *out, const double *a, const double *ca, double sa, const double *b, const double *cb,

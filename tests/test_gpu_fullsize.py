@@ -8,7 +8,8 @@
   with the inputs regenerated here from the same seeds and the oracle's own
   forward map, and checked against the stored checksums first.
   Bars: 1e-10 relative L2 for the float64 path, 1e-4 for float32 sweeps with
-  float64 CGLS.
+  float64 CGLS.  The float32 case runs in a 64-RHS block (the benchmark's) and
+  again inside 128- and 256-RHS blocks.
 """
 import json
 import os
@@ -109,7 +110,10 @@ def _regenerate(name, O, gold):
     return w, yobs, sigma, eta, xi
 
 
-@pytest.mark.parametrize("name,prec,tol,rb", [("ball58_fp64", "f64", 1e-10, 16), ("ball58_batched", "f32", 1e-4, 64)])
+# the 64 stored samples also inside one 128- and one 256-RHS block (64 and 192 idle RHS)
+@pytest.mark.parametrize("name,prec,tol,rb", [("ball58_fp64", "f64", 1e-10, 16), ("ball58_batched", "f32", 1e-4, 64),
+                                              ("ball58_batched", "f32", 1e-4, 128),
+                                              ("ball58_batched", "f32", 1e-4, 256)])
 def test_rto_fullsize_vs_stored_oracle(ball, name, prec, tol, rb):
     _, O, G = ball
     gold, meta = _golden(name)

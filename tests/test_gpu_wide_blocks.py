@@ -1,0 +1,91 @@
+"""RHS blocks wider than 64: 128 and 256 right-hand sides per sweep.
+
+A row of a float32 block of 256 RHS fills one wave (64 lanes x 16 bytes); 128
+float32 RHS, or 128 float64 RHS, take half a wave or a whole one.  Checked:
+
+* ball16: 130 samples (one ragged 256-block, or a full and a ragged 128-block)
+  with float32 sweeps against the oracle on the same draws (1e-4 relative L2 on
+  mean and std), and float64 sweeps with 128-blocks (1e-10 on the samples);
+* blocks the step kernels cannot hold are rejected before any launch;
+* the autotuner considers blocks beyond 64 only when S needs them.
+The full-size check (ball58, the 64 stored oracle samples inside one 128- and
+one 256-RHS block) is part of the stored-oracle test of test_gpu_fullsize.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pat = pytest.importorskip("paper_2607_21373_amd.pat")
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def ball16_130():
+    w = W.make_workload("ball16")
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    S, n_iter = 130, 10
+    eta, xi = W.rto_draws(S, w.n_steps, w.n_obs, w.n_nodes, w.rto_seed)
+    ref, rres = O.rto(yobs, sigma, w.prior_a, n_iter, eta, xi)
+    return w, G, (yobs, sigma, eta, xi, n_iter), ref, rres
+
+
+@pytest.mark.parametrize("prec,rb,tol", [("f32", 256, 1e-4), ("f32", 128, 1e-4), ("f64", 128, 1e-10)])
+def test_wide_blocks_match_oracle(ball16_130, prec, rb, tol):
+    w, G, (yobs, sigma, eta, xi, n_iter), ref, rres = ball16_130
+    print(f"ball16 S=130 {prec} rhs_block={rb}", flush=True)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, n_iter, sweep_prec=prec,
+                         rhs_block=rb, resid=True)
+    rmean, rstd = oracle.stats(ref)
+    em = _rel_l2(out["mean"].cpu().numpy(), rmean)
+    es = _rel_l2(out["std"].cpu().numpy(), rstd)
+    ex = _rel_l2(out["samples"].cpu().numpy(), ref)
+    print(f"  mean {em:.2e} std {es:.2e} samples {ex:.2e}")
+    assert em < tol and es < tol
+    if prec == "f64":
+        assert ex < tol
+        assert float(np.abs(out["resid"].cpu().numpy() - rres).max() / np.abs(rres).max()) < tol
+
+
+def test_wide_blocks_equal_narrow_sweeps(ball16_130):
+    """One float64 iteration with 128-blocks and with 64-blocks: the sweeps compute each RHS the
+    same way in any block; only the solver's dot products are summed in another order."""
+    w, G, (yobs, sigma, eta, xi, _), ref, _ = ball16_130
+    a = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, 1, sweep_prec="f64", rhs_block=128)
+    b = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, 1, sweep_prec="f64", rhs_block=64)
+    d = _rel_l2(a["samples"].cpu().numpy(), b["samples"].cpu().numpy())
+    print(f"one iteration, 128- vs 64-blocks: {d:.2e}")
+    assert d < 1e-14
+
+
+def test_wide_block_errors(ball16_130):
+    w, G, (yobs, sigma, eta, xi, n_iter), _, _ = ball16_130
+    args = (G, _dev(yobs), _dev(eta[:3]), _dev(xi[:3]), sigma, w.prior_a, 2)
+    for prec, rb in (("f64", 256), ("f32", 512), ("f32", 96)):
+        with pytest.raises(pat.PatError) as ei:
+            pat.rto_sample(*args, sweep_prec=prec, rhs_block=rb)
+        assert ei.value.name == "PAT_ERR_INVALID_ARG"
+
+
+def test_autotune_wide_candidates(ball16_130):
+    _, G, _, _, _ = ball16_130
+    rb, us = pat.autotune(G, 200, "f32")
+    print(f"autotune ball16 S=200 f32: rb={rb}, {us:.1f} us per step pair")
+    assert rb in (4, 8, 16, 32, 64, 128, 256) and us > 0
+    rb64, _ = pat.autotune(G, 200, "f64")
+    assert rb64 in (4, 8, 16, 32, 64, 128)
+    rbs, _ = pat.autotune(G, 40, "f32")
+    assert rbs <= 64
