@@ -216,7 +216,7 @@ def wide_leg(pat, dev, G, info, w, yobs, sigma, n_iter):
            "value": round(S * 60.0 / el, 3), "unit": "samples/min",
            "fwd_step_us": round(fwd_s * 1e6, 3), "fwd_step_GBs": round(fb / fwd_s / 1e9, 1),
            "adj_step_us": round(adj_s * 1e6, 3), "adj_step_GBs": round(ab / adj_s / 1e9, 1),
-           "bytes_per_fwd_launch": fb}
+           "bytes_per_fwd_launch": fb, "traffic_per_fwd_launch": stored_traffic("k_fwd_f32_rb256", w.name)}
     log(f"wide block: {S} samples as one {RB}-RHS block in {el:.2f} s ({res['value']:.1f} samples/min); forward "
         f"step {fwd_s * 1e6:.1f} us ({res['fwd_step_GBs']:.0f} GB/s), transpose {adj_s * 1e6:.1f} us")
     return res
