@@ -13,6 +13,10 @@ import os
 from typing import Optional
 
 import numpy as np
+# Imported before libpat makes its first HIP call: a process whose first HIP user is
+# libpat (a problem created before anything imported torch) later fails to
+# initialise torch's GPU context ("No HIP GPUs are available").
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # PAT_LIB selects an alternative build of the same library (e.g. a tuning variant)

@@ -165,3 +165,21 @@ def test_runtime_errors():
     with pytest.raises(pat.PatError) as ei:
         pat.rto_sample(G, bad, eta, xi, 1.0, 0.01, 2)
     assert ei.value.name == "PAT_ERR_NONFINITE"
+
+
+def test_binding_works_when_torch_is_not_imported_first():
+    """A fresh process that creates a problem before importing torch itself, then makes
+    calls that need torch's stream (regression: torch failed to find the GPU when libpat
+    had initialised HIP first)."""
+    import os
+    import subprocess
+    import sys
+    code = ("import workloads as W\n"
+            "from paper_2607_21373_amd import pat\n"
+            "G = pat.Problem.from_workload(W.make_workload('cube8_tiny'))\n"
+            "rb, us = pat.autotune(G, 8, 'f32')\n"
+            "print('ok', rb)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    print(r.stdout[-500:], r.stderr[-2000:])
+    assert r.returncode == 0 and "ok" in r.stdout
