@@ -222,6 +222,64 @@ def wide_leg(pat, dev, G, info, w, yobs, sigma, n_iter):
     return res
 
 
+def spectral_leg(pat, dev, G, w, yobs, sigma, n_iter):
+    """RTO with the Whittle-Matern spectral prior (latent-space solve, Sec. 6.4 construction) on the same
+    mesh: 128^3 grid on [-1.25, 1.25)^3, ell = 0.075, prior sigma 3, 64 samples as one 64-RHS block."""
+    import torch
+    n, lo, side, ell, psig = 128, -1.25, 2.5, 0.075, 3.0
+    pat.spectral_prior_set(G, n, lo, side, ell, psig)
+    try:
+        S = RB = 64
+        args = (G, yobs, None, None, sigma, 0.0)
+        pat.rto_sample(*args, 2, sweep_prec="f32", rhs_block=RB, n_samples=S, seed=21, prior="spectral")
+        # P and P^T alone on 64 RHS (including the binding's layout conversion in and out)
+        x = torch.randn(RB, n ** 3, dtype=torch.float64, device=dev)
+        v = torch.randn(RB, w.n_nodes, dtype=torch.float64, device=dev)
+        pat.spectral_apply(G, x)
+        pat.spectral_apply(G, v, transpose=True)
+        times = {}
+        for name, fn in (("P", lambda: pat.spectral_apply(G, x)), ("PT", lambda: pat.spectral_apply(G, v, True))):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) / 3
+        del x, v
+        # five FFT passes per application: real in / complex out, three complex passes, complex in / real out
+        fft_bytes = (24 + 32 + 32 + 32 + 24) * n ** 3 * RB
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = pat.rto_sample(*args, n_iter, sweep_prec="f32", rhs_block=RB, n_samples=S, seed=21, prior="spectral")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ok = bool(torch.isfinite(out["samples"]).all())
+    finally:
+        pat.spectral_prior_set(G, None, 0, 0, 0, 0)
+    res = {"grid": n, "samples": S, "rhs_block": RB, "iters": n_iter, "seconds": round(el, 3),
+           "value": round(S * 60.0 / el, 3), "unit": "samples/min", "finite": ok,
+           "P_ms": round(times["P"], 3), "PT_ms": round(times["PT"], 3), "fft_bytes_per_apply": fft_bytes,
+           "P_fft_GBs_upper": round(fft_bytes / (times["P"] * 1e-3) / 1e9, 1)}
+    log(f"spectral prior: {S} samples in {el:.2f} s ({res['value']:.1f} samples/min); P {times['P']:.2f} ms, "
+        f"P^T {times['PT']:.2f} ms per application on {RB} RHS ({fft_bytes / 1e9:.1f} GB of FFT passes)")
+    return res
+
+
+def lsqr_leg(pat, G, w, yobs, eta, xi, sigma, n_iter, R):
+    """The main workload solved with LSQR instead of CGLS (same iterates in exact arithmetic)."""
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    pat.rto_sample(G, yobs, eta, xi, sigma, w.prior_a, n_iter, sweep_prec="f32", rhs_block=64, solver="lsqr")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    res = {"samples": R, "iters": n_iter, "seconds": round(el, 3), "value": round(R * 60.0 / el, 3),
+           "unit": "samples/min"}
+    log(f"LSQR: {R} samples in {el:.2f} s ({res['value']:.1f} samples/min)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +296,9 @@ def main():
                          "reaches for the step's working set) and over arrays 8x larger (past the 256 MB cache)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
     ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
+    ap.add_argument("--spectral", action="store_true",
+                    help="also time 64 samples with the Whittle-Matern spectral prior (128^3 grid, latent solve)")
+    ap.add_argument("--lsqr", action="store_true", help="also time the main batch solved with LSQR")
     ap.add_argument("--wide", action="store_true",
                     help="also time 256 samples as one 256-RHS block (working set beyond the Infinity Cache)")
     ap.add_argument("--uneven-modes", action="store_true", help="also time each launch mode of the uneven batch")
@@ -401,8 +462,12 @@ def main():
     if not args.no_uneven:
         names = tuple(args.uneven_set.split(","))
         result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter, modes=args.uneven_modes, names=names)
+    if args.lsqr:
+        result["lsqr"] = lsqr_leg(pat, G, w, yobs, eta, xi, sigma, n_iter, R)
     if args.wide:
         result["wide_block"] = wide_leg(pat, dev, G, info, w, yobs, sigma, n_iter)
+    if args.spectral:
+        result["spectral_prior"] = spectral_leg(pat, dev, G, w, yobs, sigma, n_iter)
     if args.big:
         result["ball100_single_sample"] = big_leg(pat, W, dev, n_iter)
 

@@ -49,7 +49,9 @@ struct FftPass {
 // One length-n transform per (line, RHS) of the workgroup's line and RHS chunk.
 __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
     extern __shared__ double2 X[];  // [RC][n]
+    __shared__ double2 tws[64];     // the n/2 twiddles (n <= 128), read by every stage
     const int n = a.n, half_n = n >> 1;
+    for (int e = threadIdx.x; e < half_n; e += 256) tws[e] = a.tw[e];
     const int RC = a.RB < kRC ? a.RB : kRC;
     const int rc0 = blockIdx.y * RC;
     const int L = blockIdx.x;
@@ -79,7 +81,7 @@ __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
                 const int r = b / half_n, bi = b % half_n;
                 const int pos = bi % half, i1 = (bi / half) * m + pos, i2 = i1 + half;
                 double2 *x = X + r * n;
-                const double2 t = cmul(a.tw[pos * step], x[i2]), u = x[i1];
+                const double2 t = cmul(tws[pos * step], x[i2]), u = x[i1];
                 x[i1] = cadd(u, t);
                 x[i2] = csub(u, t);
             }
@@ -104,7 +106,7 @@ __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
                 double2 *x = X + r * n;
                 const double2 u = x[i1], v = x[i2];
                 x[i1] = cadd(u, v);
-                x[i2] = cmul(csub(u, v), conjg(a.tw[pos * step]));
+                x[i2] = cmul(csub(u, v), conjg(tws[pos * step]));
             }
             __syncthreads();
         }
