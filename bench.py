@@ -280,6 +280,25 @@ def lsqr_leg(pat, G, w, yobs, eta, xi, sigma, n_iter, R):
     return res
 
 
+def map_leg(G, w, dev, yobs, sigma, iters=50):
+    """MAP by gradient descent through the autograd operator (forward = G, backward = G^T) on the same mesh:
+    each iteration is one float64 forward and one transpose sweep plus the prior terms."""
+    import torch
+    from paper_2607_21373_amd import autograd as ag
+    y = yobs.contiguous()
+    lam = ag.hessian_lambda_max(G, sigma, w.prior_a, iters=5)
+    ag.map_gradient_descent(G, y, sigma, w.prior_a, n_iter=2, step=1.0 / (1.02 * lam))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, hist, _ = ag.map_gradient_descent(G, y, sigma, w.prior_a, n_iter=iters, step=1.0 / (1.02 * lam), history=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    res = {"iters": iters, "seconds": round(el, 3), "ms_per_iter": round(el / iters * 1e3, 3),
+           "objective_first_last": [hist[0], hist[-1]]}
+    log(f"MAP gradient descent through autograd: {iters} iterations in {el:.2f} s ({res['ms_per_iter']:.2f} ms each)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +318,7 @@ def main():
     ap.add_argument("--spectral", action="store_true",
                     help="also time 64 samples with the Whittle-Matern spectral prior (128^3 grid, latent solve)")
     ap.add_argument("--lsqr", action="store_true", help="also time the main batch solved with LSQR")
+    ap.add_argument("--map", action="store_true", help="also time MAP gradient descent through the autograd operator")
     ap.add_argument("--wide", action="store_true",
                     help="also time 256 samples as one 256-RHS block (working set beyond the Infinity Cache)")
     ap.add_argument("--uneven-modes", action="store_true", help="also time each launch mode of the uneven batch")
@@ -464,6 +484,8 @@ def main():
         result["uneven_batch"] = uneven_leg(pat, W, dev, n_iter, modes=args.uneven_modes, names=names)
     if args.lsqr:
         result["lsqr"] = lsqr_leg(pat, G, w, yobs, eta, xi, sigma, n_iter, R)
+    if args.map:
+        result["autograd_map"] = map_leg(G, w, dev, yobs, sigma)
     if args.wide:
         result["wide_block"] = wide_leg(pat, dev, G, info, w, yobs, sigma, n_iter)
     if args.spectral:
