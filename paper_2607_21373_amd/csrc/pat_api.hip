@@ -466,8 +466,13 @@ pat_status tune_rb(const std::vector<pat_problem *> &P, hipStream_t cap, int64_t
     top = fit_rb(nmax, pr, top);
     const int lo = std::max(1, std::min(top, 64) / 16);
     const int reps = 8;
-    hipEvent_t ev[5];
-    for (auto &e : ev) PAT_HIP(hipEventCreate(&e));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return fail(PAT_ERR_HIP, "autotune: hipEventCreate failed");
+        }
     *best = top;
     *best_us = 1e300;
     if (mf) *mf = 1;
