@@ -192,6 +192,24 @@ def big_leg(pat, W, dev, n_iter):
         res[prec] = {"seconds_per_sample": round(el, 3), "samples_per_min": round(60.0 / el, 3),
                      "fwd_step_us": round(fwd_s * 1e6, 3), "fwd_step_GBs": round(gbs, 1)}
         log(f"ball100 {prec}: {el:.2f} s per sample; forward step {fwd_s * 1e6:.1f} us ({gbs:.0f} GB/s)")
+    # 64 float32 RHS per sweep: the state of a step (1 GB) no longer fits the Infinity Cache
+    p0 = torch.randn(64, w.n_nodes, dtype=torch.float32, device=dev)
+    y = pat.pat_forward(G, p0)
+    a = pat.pat_adjoint(G, y)
+    r64 = {}
+    for name, fn, kind in (("fwd", lambda: pat.pat_forward(G, p0, y), "fwd"),
+                           ("adj", lambda: pat.pat_adjoint(G, y, a), "adj")):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 2 / w.n_steps * 1e3
+        r64[f"{name}_step_us"] = round(us, 2)
+        r64[f"{name}_step_GBs"] = round(step_bytes(info, 64, 4, kind) / us / 1e3, 1)
+    res["rhs64_sweeps"] = r64
+    log(f"ball100, 64 float32 RHS per sweep: {r64} (per step, including the layout conversion of the entry points)")
     return res
 
 
