@@ -7,12 +7,13 @@
 // and the RHS fastest; complex grid vectors interleave (re, im) per element.
 //
 // The 3D transform is five launches of one kernel, each a batch of length-n
-// radix-2 FFTs along one axis staged in LDS (one line and a chunk of up to 16
-// right-hand sides per workgroup): forward x, forward y, then forward z, the
+// FFTs along one axis (one line and a chunk of up to 16 right-hand sides per
+// workgroup, staged in LDS): forward x, forward y, then forward z, the
 // multiplication by a(k) and the inverse z in the same pass, then inverse y and
-// inverse x.  Forward transforms are decimation in time on bit-reversed input
-// (natural-order output); inverse ones are decimation in frequency (natural
-// input, bit-reversed output), so no separate reordering pass is needed.
+// inverse x.  Each length-n transform is a Stockham FFT (natural order in and
+// out, so no reordering pass) with 8 points per thread: radix-8 stages computed
+// in registers, exchanged through LDS between stages, then a radix-2 or radix-4
+// stage when n is not a power of 8 (n = 128: 8 x 8 x 2, three stages).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -29,8 +30,6 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 conjg(double2 a) { return make_double2(a.x, -a.y); }
 
-__device__ __forceinline__ int bitrev(int t, int logn) { return int(__brev(unsigned(t)) >> (32 - logn)); }
-
 constexpr int kRC = 16;  // right-hand sides per workgroup
 
 enum : int { kForward = 0, kInverse = 1, kCentre = 2 };
@@ -43,14 +42,120 @@ struct FftPass {
     const double *add;   // added to the real output, or null
     const double *amp;   // a(k) [G] for the centre pass
     const double2 *tw;   // tw[j] = exp(-2 pi i j / n), j < n/2
-    int n, logn, RB, axis, mode;
+    int n, RB, axis, mode;
 };
+
+// Radix-2 butterfly (u, t) -> (u + t, u - t).
+__device__ __forceinline__ void bfly(double2 &u, double2 &t) {
+    const double2 s = cadd(u, t);
+    t = csub(u, t);
+    u = s;
+}
+// multiplication by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 rot4(double2 a) { return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x); }
+
+// 8-point DFT in registers, natural order in and out, w = exp(-2 pi i / 8) (forward) or its conjugate.
+template <bool INV>
+__device__ __forceinline__ void dft8(double2 v[8]) {
+    constexpr double h = 0.70710678118654752440;
+    double2 a0 = v[0], a1 = v[4], a2 = v[2], a3 = v[6], a4 = v[1], a5 = v[5], a6 = v[3], a7 = v[7];
+    bfly(a0, a1); bfly(a2, a3); bfly(a4, a5); bfly(a6, a7);
+    a3 = rot4<INV>(a3); a7 = rot4<INV>(a7);
+    bfly(a0, a2); bfly(a1, a3); bfly(a4, a6); bfly(a5, a7);
+    // w8^1, w8^2, w8^3 on a5, a6, a7
+    a5 = INV ? make_double2(h * (a5.x - a5.y), h * (a5.x + a5.y)) : make_double2(h * (a5.x + a5.y), h * (a5.y - a5.x));
+    a6 = rot4<INV>(a6);
+    a7 = INV ? make_double2(-h * (a7.x + a7.y), h * (a7.x - a7.y)) : make_double2(h * (a7.y - a7.x), -h * (a7.x + a7.y));
+    bfly(a0, a4); bfly(a1, a5); bfly(a2, a6); bfly(a3, a7);
+    v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3; v[4] = a4; v[5] = a5; v[6] = a6; v[7] = a7;
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(double2 v[4]) {
+    double2 a0 = v[0], a1 = v[2], a2 = v[1], a3 = v[3];
+    bfly(a0, a1); bfly(a2, a3);
+    a3 = rot4<INV>(a3);
+    bfly(a0, a2); bfly(a1, a3);
+    v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3;
+}
+
+// LDS position of point t of a line: one pad element after every 8 points, so the
+// stride-8 writes of the first radix-8 stage spread over all LDS banks
+__device__ __forceinline__ int pidx(int t) { return t + (t >> 3); }
+
+// w^e, w = exp(-2 pi i / n), from the table of the first n/2 powers (conjugate for the inverse)
+template <bool INV>
+__device__ __forceinline__ double2 wpow(const double2 *tws, int e, int n) {
+    e &= n - 1;
+    const int h = n >> 1;
+    double2 w = e < h ? tws[e] : make_double2(-tws[e - h].x, -tws[e - h].y);
+    return INV ? conjg(w) : w;
+}
+
+// One length-n transform (Stockham, natural order in and out) of every line x of the
+// workgroup's LDS tile, 8 points per thread: radix-8 stages while 8^s divides n, then a
+// final radix-2 or radix-4 stage.  Threads past the tile's lines only take part in the
+// barriers.  Ends with a barrier.
+template <bool INV>
+__device__ __forceinline__ void line_fft(double2 *X, int stride, int n, int RC, const double2 *tws) {
+    const int tpl = n >> 3;  // threads per line
+    const int line = threadIdx.x / tpl, j = threadIdx.x % tpl;
+    const bool act = line < RC;
+    double2 *x = X + line * stride;
+    int ns = 1;
+    while (ns * 8 <= n) {
+        double2 v[8];
+        if (act) {
+            const int jm = j % ns;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[r] = x[pidx(j + r * tpl)];
+            if (ns > 1) {
+                const int f = n / (8 * ns);
+#pragma unroll
+                for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], wpow<INV>(tws, jm * r * f, n));
+            }
+            dft8<INV>(v);
+        }
+        __syncthreads();
+        if (act) {
+            const int jm = j % ns, base = (j / ns) * ns * 8 + jm;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[pidx(base + r * ns)] = v[r];
+        }
+        __syncthreads();
+        ns *= 8;
+    }
+    const int rf = n / ns;  // 1, 2 or 4 left; the stage is in place per thread
+    if (act && rf == 2) {
+        for (int q = 0; q < 4; ++q) {
+            const int b = j + q * tpl;  // butterfly b < ns = n/2
+            double2 u = x[pidx(b)], t = cmul(x[pidx(b + ns)], wpow<INV>(tws, b, n));
+            bfly(u, t);
+            x[pidx(b)] = u;
+            x[pidx(b + ns)] = t;
+        }
+    } else if (act && rf == 4) {
+        for (int q = 0; q < 2; ++q) {
+            const int b = j + q * tpl;  // b < ns = n/4
+            double2 v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = x[pidx(b + r * ns)];
+#pragma unroll
+            for (int r = 1; r < 4; ++r) v[r] = cmul(v[r], wpow<INV>(tws, b * r, n));
+            dft4<INV>(v);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[pidx(b + r * ns)] = v[r];
+        }
+    }
+    __syncthreads();
+}
 
 // One length-n transform per (line, RHS) of the workgroup's line and RHS chunk.
 __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
-    extern __shared__ double2 X[];  // [RC][n]
-    __shared__ double2 tws[64];     // the n/2 twiddles (n <= 128), read by every stage
-    const int n = a.n, half_n = n >> 1;
+    extern __shared__ double2 X[];  // [RC][n + n/8 + 1], see pidx
+    __shared__ double2 tws[64];     // the n/2 twiddles (n <= 128)
+    const int n = a.n, half_n = n >> 1, stride = n + (n >> 3) + 1;
     for (int e = threadIdx.x; e < half_n; e += 256) tws[e] = a.tw[e];
     const int RC = a.RB < kRC ? a.RB : kRC;
     const int rc0 = blockIdx.y * RC;
@@ -69,53 +174,24 @@ __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
     for (int e = threadIdx.x; e < n * RC; e += 256) {
         const int t = e / RC, r = e % RC;
         const int64_t gi = (g0 + t * ls) * a.RB + rc0 + r;
-        const double2 v = a.rin ? make_double2(a.rin[gi], 0.0) : a.cin[gi];
-        X[r * n + (a.mode == kInverse ? t : bitrev(t, a.logn))] = v;
+        X[r * stride + pidx(t)] = a.rin ? make_double2(a.rin[gi], 0.0) : a.cin[gi];
     }
     __syncthreads();
-    if (a.mode != kInverse) {
-        // decimation in time, exp(-2 pi i ...) twiddles
-        for (int s = 1; s <= a.logn; ++s) {
-            const int m = 1 << s, half = m >> 1, step = n >> s;
-            for (int b = threadIdx.x; b < half_n * RC; b += 256) {
-                const int r = b / half_n, bi = b % half_n;
-                const int pos = bi % half, i1 = (bi / half) * m + pos, i2 = i1 + half;
-                double2 *x = X + r * n;
-                const double2 t = cmul(tws[pos * step], x[i2]), u = x[i1];
-                x[i1] = cadd(u, t);
-                x[i2] = csub(u, t);
-            }
-            __syncthreads();
-        }
-    }
+    if (a.mode != kInverse) line_fft<false>(X, stride, n, RC, tws);
     if (a.mode == kCentre) {
         for (int e = threadIdx.x; e < n * RC; e += 256) {
             const int r = e / n, t = e % n;
             const double w = a.amp[g0 + t * ls];
-            X[r * n + t] = make_double2(w * X[r * n + t].x, w * X[r * n + t].y);
+            X[r * stride + pidx(t)] = make_double2(w * X[r * stride + pidx(t)].x, w * X[r * stride + pidx(t)].y);
         }
         __syncthreads();
     }
-    if (a.mode != kForward) {
-        // decimation in frequency, exp(+2 pi i ...) twiddles; bit-reversed output
-        for (int s = a.logn; s >= 1; --s) {
-            const int m = 1 << s, half = m >> 1, step = n >> s;
-            for (int b = threadIdx.x; b < half_n * RC; b += 256) {
-                const int r = b / half_n, bi = b % half_n;
-                const int pos = bi % half, i1 = (bi / half) * m + pos, i2 = i1 + half;
-                double2 *x = X + r * n;
-                const double2 u = x[i1], v = x[i2];
-                x[i1] = cadd(u, v);
-                x[i2] = cmul(csub(u, v), conjg(tws[pos * step]));
-            }
-            __syncthreads();
-        }
-    }
+    if (a.mode != kForward) line_fft<true>(X, stride, n, RC, tws);
     const double sc = a.mode == kForward ? 1.0 : 1.0 / n;
     for (int e = threadIdx.x; e < n * RC; e += 256) {
         const int t = e / RC, r = e % RC;
         const int64_t gi = (g0 + t * ls) * a.RB + rc0 + r;
-        const double2 v = X[r * n + (a.mode == kForward ? t : bitrev(t, a.logn))];
+        const double2 v = X[r * stride + pidx(t)];
         if (a.rout) a.rout[gi] = sc * v.x + (a.add ? a.add[gi] : 0.0);
         else a.cout[gi] = make_double2(sc * v.x, sc * v.y);
     }
@@ -168,12 +244,11 @@ void fft_pass(const SpecOps &sp, int RB, int axis, int mode, const double *rin, 
     a.amp = sp.amp;
     a.tw = reinterpret_cast<const double2 *>(sp.tw);
     a.n = sp.n;
-    a.logn = sp.logn;
     a.RB = RB;
     a.axis = axis;
     a.mode = mode;
     const int RC = RB < kRC ? RB : kRC;
-    const size_t lds = size_t(sp.n) * RC * sizeof(double2);
+    const size_t lds = size_t(sp.n + sp.n / 8 + 1) * RC * sizeof(double2);
     hipLaunchKernelGGL(k_fft_axis, dim3(unsigned(sp.n) * unsigned(sp.n), unsigned(RB / RC)), dim3(256), lds, s, a);
 }
 
