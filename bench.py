@@ -72,7 +72,7 @@ def stored_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(w, eta, xi, yobs, sigma, n_iter, R, n_steps_sample=250, iters_sample=3):
+def cpu_baseline(w, eta, xi, yobs, sigma, n_iter, R, n_steps_sample=350, iters_sample=3):
     """Oracle (plain CPU FP64) on a bounded sample of the same workload (about 10 s of CPU work), scaled
     to samples/min by sweep-steps.  Linear scaling leaves out the reorthogonalisation's growth with the
     iteration count, so it flatters the oracle."""
