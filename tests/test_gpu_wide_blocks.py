@@ -7,7 +7,9 @@ float32 RHS, or 128 float64 RHS, take half a wave or a whole one.  Checked:
   with float32 sweeps against the oracle on the same draws (1e-4 relative L2 on
   mean and std), and float64 sweeps with 128-blocks (1e-10 on the samples);
 * blocks the step kernels cannot hold are rejected before any launch;
-* the autotuner considers blocks beyond 64 only when S needs them.
+* the autotuner considers blocks beyond 64 only when S needs them;
+* maximum sizes: on a 4.25M-node ball a 256-RHS float32 block exceeds the
+  step kernels' 4 GiB state limit and is rejected; the tuner stops at 128.
 The full-size check (ball58, the 64 stored oracle samples inside one 128- and
 one 256-RHS block) is part of the stored-oracle test of test_gpu_fullsize.py.
 """
@@ -89,3 +91,26 @@ def test_autotune_wide_candidates(ball16_130):
     assert rb64 in (4, 8, 16, 32, 64, 128)
     rbs, _ = pat.autotune(G, 40, "f32")
     assert rbs <= 64
+
+
+def test_block_state_limit_on_a_4m_node_mesh():
+    """Maximum sizes: on a 4,251,528-node ball one 256-RHS float32 block's sweep state
+    (N x 256 x 4 B = 4.35 GB) is beyond what the step kernels address, so an explicit
+    rhs_block = 256 is rejected before any work; 128 runs; the autotuner asked for 256
+    samples considers blocks up to 128 only."""
+    X, T = W.ball_mesh(161)
+    N = X.shape[0]
+    assert N * 256 * 4 >= 1 << 32 > N * 128 * 4
+    sensors = np.linspace(0, N - 1, 16).astype(np.int32)
+    G = pat.Problem(X, T, None, True, 0.2 * 2.0 / 161, 4, sensor_nodes=sensors, check_dt=False)
+    print(f"ball161: {N} nodes", flush=True)
+    y = torch.zeros((4, 16), dtype=torch.float64, device="cuda")
+    args = (G, y, None, None, 1.0, 0.01, 1)
+    with pytest.raises(pat.PatError) as ei:
+        pat.rto_sample(*args, sweep_prec="f32", rhs_block=256, n_samples=2, seed=1)
+    assert ei.value.name == "PAT_ERR_INVALID_ARG" and "4 GiB" in str(ei.value)
+    out = pat.rto_sample(*args, sweep_prec="f32", rhs_block=128, n_samples=2, seed=1)
+    assert torch.isfinite(out["samples"]).all()
+    rb, us = pat.autotune(G, 256, "f32")
+    print(f"autotune S=256 on {N} nodes: rhs_block {rb}", flush=True)
+    assert rb <= 128 and us > 0
