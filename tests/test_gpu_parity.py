@@ -165,6 +165,19 @@ def test_runtime_errors():
     with pytest.raises(pat.PatError) as ei:
         pat.rto_sample(G, bad, eta, xi, 1.0, 0.01, 2)
     assert ei.value.name == "PAT_ERR_NONFINITE"
+    # empty inputs: no right-hand sides, no samples, no iterations
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_forward(G, _dev(np.zeros((0, w.n_nodes))))
+    assert ei.value.name == "PAT_ERR_INVALID_ARG"
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_adjoint(G, _dev(np.zeros((0, w.n_steps, w.n_obs))))
+    assert ei.value.name == "PAT_ERR_INVALID_ARG"
+    with pytest.raises(pat.PatError) as ei:
+        pat.rto_sample(G, yobs, None, None, 1.0, 0.01, 2, n_samples=0, stats=False)
+    assert ei.value.name == "PAT_ERR_INVALID_ARG"
+    with pytest.raises(pat.PatError) as ei:
+        pat.rto_sample(G, yobs, eta, xi, 1.0, 0.01, 0)
+    assert ei.value.name == "PAT_ERR_INVALID_ARG"
 
 
 def test_binding_works_when_torch_is_not_imported_first():
