@@ -9,7 +9,9 @@ float32 RHS, or 128 float64 RHS, take half a wave or a whole one.  Checked:
 * blocks the step kernels cannot hold are rejected before any launch;
 * the autotuner considers blocks beyond 64 only when S needs them;
 * maximum sizes: on a 4.25M-node ball a 256-RHS float32 block exceeds the
-  step kernels' 4 GiB state limit and is rejected; the tuner stops at 128.
+  step kernels' 4 GiB state limit and is rejected; the tuner stops at 128;
+* the merged multi-mesh step kernels with 128- and 256-RHS blocks equal the
+  per-problem runs bit for bit.
 The full-size check (ball58, the 64 stored oracle samples inside one 128- and
 one 256-RHS block) is part of the stored-oracle test of test_gpu_fullsize.py.
 """
@@ -114,3 +116,25 @@ def test_block_state_limit_on_a_4m_node_mesh():
     rb, us = pat.autotune(G, 256, "f32")
     print(f"autotune S=256 on {N} nodes: rhs_block {rb}", flush=True)
     assert rb <= 128 and us > 0
+
+
+@pytest.mark.parametrize("rb", [128, 256])
+def test_wide_block_merged_batch_equals_single(rb):
+    """The merged multi-mesh step kernels with wide blocks: three small meshes in one
+    batch (one merged launch per step) equal each mesh's own rto_sample bit for bit."""
+    ws = [W.make_workload(n) for n in ("cube8_tiny", "ball16", "box12")]
+    probs = [pat.Problem.from_workload(w) for w in ws]
+    ys, sig = [], []
+    for w in ws:
+        O = oracle.Problem.from_workload(w)
+        Y, yobs, sigma = oracle.synthesize(O, w)
+        ys.append(_dev(yobs))
+        sig.append(sigma)
+    B = pat.Batch(probs)
+    B.merge(1, 1)
+    S = [rb // 2 + 3, rb - 5, 7]
+    outs = pat.rto_sample_batch(B, ys, None, None, sig, 0.01, 4, sweep_prec="f32", rhs_block=rb, n_samples=S,
+                                seed=[1, 2, 3])
+    for m, (G, y, s) in enumerate(zip(probs, ys, sig)):
+        ref = pat.rto_sample(G, y, None, None, s, 0.01, 4, sweep_prec="f32", rhs_block=rb, n_samples=S[m], seed=m + 1)
+        assert torch.equal(outs[m]["samples"], ref["samples"]), (rb, m)
