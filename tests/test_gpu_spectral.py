@@ -6,7 +6,8 @@
 * latent-space RTO (float64 sweeps) against the oracle's latent CGLS: 1e-10;
   LSQR against it (equal iterates in exact arithmetic): 1e-9; float32 sweeps:
   samples and mean within 1e-4, std within the Lipschitz bound of the sample
-  differences; device-drawn latent perturbations;
+  differences; also inside one 128-RHS (float64) and one 256-RHS (float32)
+  block; device-drawn latent perturbations;
 * argument errors;
 * the 195k-node ball with the 128^3 grid: sampled P / P^T against the oracle and
   a short latent solve whose samples are P of its latent samples.
@@ -58,8 +59,10 @@ def test_spectral_apply_matches_oracle(ball16, n, R, ell):
     assert np.all(np.abs(lhs - rhs) < 1e-13 * scale)
 
 
-@pytest.mark.parametrize("solver,prec,tol", [("cgls", "f64", 1e-10), ("lsqr", "f64", 1e-9), ("cgls", "f32", 1e-4)])
-def test_latent_rto_matches_oracle(ball16, solver, prec, tol):
+@pytest.mark.parametrize("solver,prec,tol,rb", [("cgls", "f64", 1e-10, 0), ("lsqr", "f64", 1e-9, 0),
+                                               ("cgls", "f32", 1e-4, 0), ("cgls", "f64", 1e-10, 128),
+                                               ("cgls", "f32", 1e-4, 256)])
+def test_latent_rto_matches_oracle(ball16, solver, prec, tol, rb):
     w, O, G = ball16
     n, ell = 16, 0.2
     pr = SpectralPrior(n, BOX["lo"], BOX["side"], ell, 3.0)
@@ -72,14 +75,14 @@ def test_latent_rto_matches_oracle(ball16, solver, prec, tol):
     xi = rng.standard_normal((S, pr.size))
     ref, lat, res = latent_rto(O, pr, I, yobs, sigma, n_iter, eta, xi)
     out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, 0.0, n_iter, sweep_prec=prec, solver=solver,
-                         prior="spectral", latent=True, resid=True)
+                         prior="spectral", latent=True, resid=True, rhs_block=rb)
     got, glat = out["samples"].cpu().numpy(), out["latent"].cpu().numpy()
     e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     el = float(np.linalg.norm(glat - lat) / np.linalg.norm(lat))
     rmean, rstd = oracle.stats(ref)
     em = float(np.linalg.norm(out["mean"].cpu().numpy() - rmean) / np.linalg.norm(rmean))
     es = float(np.linalg.norm(out["std"].cpu().numpy() - rstd) / np.linalg.norm(rstd))
-    print(f"latent RTO {solver} {prec}: samples {e:.2e} latent {el:.2e} mean {em:.2e} std {es:.2e}")
+    print(f"latent RTO {solver} {prec} rb={rb}: samples {e:.2e} latent {el:.2e} mean {em:.2e} std {es:.2e}")
     assert e < tol and el < tol and em < tol
     # The pointwise std is 1-Lipschitz in the centred samples: per node
     # |std(a) - std(b)| <= ||a - b|| / sqrt(S - 1).  With few samples whose spread is
