@@ -47,12 +47,14 @@ def ball16_130():
     return w, G, (yobs, sigma, eta, xi, n_iter), ref, rres
 
 
-@pytest.mark.parametrize("prec,rb,tol", [("f32", 256, 1e-4), ("f32", 128, 1e-4), ("f64", 128, 1e-10)])
-def test_wide_blocks_match_oracle(ball16_130, prec, rb, tol):
+@pytest.mark.parametrize("prec,rb,tol,solver", [("f32", 256, 1e-4, "cgls"), ("f32", 128, 1e-4, "cgls"),
+                                              ("f64", 128, 1e-10, "cgls"), ("f64", 128, 1e-9, "lsqr")])
+def test_wide_blocks_match_oracle(ball16_130, prec, rb, tol, solver):
+    """Against the oracle's CGLS; LSQR has the same iterates in exact arithmetic (1e-9)."""
     w, G, (yobs, sigma, eta, xi, n_iter), ref, rres = ball16_130
-    print(f"ball16 S=130 {prec} rhs_block={rb}", flush=True)
+    print(f"ball16 S=130 {prec} rhs_block={rb} {solver}", flush=True)
     out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, n_iter, sweep_prec=prec,
-                         rhs_block=rb, resid=True)
+                         rhs_block=rb, resid=True, solver=solver)
     rmean, rstd = oracle.stats(ref)
     em = _rel_l2(out["mean"].cpu().numpy(), rmean)
     es = _rel_l2(out["std"].cpu().numpy(), rstd)
