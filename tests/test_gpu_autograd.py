@@ -86,7 +86,7 @@ def test_transpose_through_autograd(small, dtype):
     assert y.dtype == dtype
     s = torch.sum(y * yh)
     (gp,) = torch.autograd.grad(s, p)
-    lhs = float(s)
+    lhs = float(s.detach())
     rhs = float(torch.sum(p.detach().double() * gp.double()))
     tol = 1e-13 if dtype == torch.float64 else 1e-5
     assert abs(lhs - rhs) <= tol * abs(lhs)
