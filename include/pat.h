@@ -194,7 +194,9 @@ pat_status pat_spectral_apply(pat_problem *p, int64_t R, int transpose, const do
  *   rhs_block  host int32 or NULL: the chosen block
  *   step_us    host double or NULL: its priced cost of one forward plus one
  *              transpose step for all S samples, in microseconds
- * Synchronises `stream`; overwrites the handle's sweep workspaces. */
+ * Synchronises `stream`.  The sweep workspaces it allocates for candidate blocks
+ * other than the chosen one are freed again (those that existed before are kept,
+ * with their contents overwritten). */
 pat_status pat_autotune(pat_problem *p, int64_t S, pat_precision prec, int32_t *rhs_block, double *step_us,
                         void *stream);
 

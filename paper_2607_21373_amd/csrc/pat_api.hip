@@ -127,6 +127,7 @@ struct pat_problem {
     pat_problem_info info{};
     bool perm_identity = true;
     std::vector<void *> allocs;
+    std::vector<size_t> alloc_bytes;  // size of allocs[k]
     std::map<std::pair<int, int>, SweepWS> sweeps;
     std::map<std::pair<int, int64_t>, CglsWS> cgls;  // by (RB, unknowns per RHS)
     hipStream_t cap = nullptr;
@@ -179,14 +180,18 @@ pat_status dev_alloc(pat_problem *p, void **ptr, size_t bytes) {
                     "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
     }
     p->allocs.push_back(*ptr);
+    p->alloc_bytes.push_back(bytes);
     p->bytes += int64_t(bytes);
     return PAT_OK;
 }
 
 void dev_free(pat_problem *p, void *ptr) {
     if (!ptr) return;
-    for (auto &a : p->allocs)
-        if (a == ptr) a = nullptr;
+    for (size_t k = 0; k < p->allocs.size(); ++k)
+        if (p->allocs[k] == ptr) {
+            p->allocs[k] = nullptr;
+            p->bytes -= int64_t(p->alloc_bytes[k]);
+        }
     (void)hipFree(ptr);
 }
 
@@ -373,6 +378,43 @@ pat_status get_spec(pat_problem *p, int RB, SpecWS **out) {
     *out = &w;
     return PAT_OK;
 }
+
+// Free one sweep workspace and its graphs (the device is idle for it: callers
+// synchronise first).
+void release_sweep(pat_problem *p, pat::Prec prec, int RB) {
+    auto it = p->sweeps.find({int(prec), RB});
+    if (it == p->sweeps.end()) return;
+    SweepWS &w = it->second;
+    hipGraphExec_t *gs[] = {&w.g_fwd_user, &w.g_adj_user, &w.g_fwd_cgls, &w.g_adj_cgls};
+    for (auto *g : gs)
+        if (*g) (void)hipGraphExecDestroy(*g);
+    void *bufs[] = {w.P[0], w.P[1], w.V[0], w.V[1], w.Y};
+    for (void *b : bufs) dev_free(p, b);
+    p->sweeps.erase(it);
+}
+
+// Sweep workspaces the autotuner creates for the candidate blocks it does not
+// choose are released again; those that existed before it ran are kept.
+struct TuneScope {
+    std::vector<pat_problem *> probs;
+    pat::Prec prec;
+    std::vector<std::vector<int>> had;
+    TuneScope(const std::vector<pat_problem *> &P, pat::Prec pr) : probs(P), prec(pr), had(P.size()) {
+        for (size_t m = 0; m < P.size(); ++m)
+            for (auto &kv : P[m]->sweeps)
+                if (kv.first.first == int(pr)) had[m].push_back(kv.first.second);
+    }
+    void release_except(int keep) {
+        for (size_t m = 0; m < probs.size(); ++m) {
+            std::vector<int> made;
+            for (auto &kv : probs[m]->sweeps)
+                if (kv.first.first == int(prec) && kv.first.second != keep &&
+                    std::find(had[m].begin(), had[m].end(), kv.first.second) == had[m].end())
+                    made.push_back(kv.first.second);
+            for (int rb : made) release_sweep(probs[m], prec, rb);
+        }
+    }
+};
 
 int auto_rb(const std::map<std::pair<int64_t, int>, int> &tuned, int64_t n, int64_t S, pat::Prec pr) {
     auto it = tuned.find({S, int(pr)});
@@ -934,6 +976,7 @@ pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out) {
         for (void *a : p->allocs)
             if (a) (void)hipFree(a);
         p->allocs.clear();
+        p->alloc_bytes.clear();
         return s;
     };
 #define UP(vec, field)                                   \
@@ -1134,7 +1177,11 @@ pat_status pat_autotune(pat_problem *p, int64_t S, pat_precision prec, int32_t *
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
     int rb = 0;
     double us = 0.0;
-    PAT_TRY(tune_rb({p}, p->cap, S, pr, static_cast<hipStream_t>(stream), &rb, &us));
+    TuneScope scope({p}, pr);
+    const pat_status st = tune_rb({p}, p->cap, S, pr, static_cast<hipStream_t>(stream), &rb, &us);
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    scope.release_except(st == PAT_OK ? rb : -1);
+    PAT_TRY(st);
     p->tuned[{S, int(pr)}] = rb;
     if (rhs_block) *rhs_block = rb;
     if (step_us) *step_us = us;
@@ -1197,7 +1244,11 @@ pat_status pat_batch_autotune(pat_batch *b, int64_t S, pat_precision prec, int32
     int rb = 0;
     double us = 0.0;
     int mf = 1, ma = 1;
-    PAT_TRY(tune_rb(b->probs, b->cap, S, pr, static_cast<hipStream_t>(stream), &rb, &us, &mf, &ma));
+    TuneScope scope(b->probs, pr);
+    const pat_status st = tune_rb(b->probs, b->cap, S, pr, static_cast<hipStream_t>(stream), &rb, &us, &mf, &ma);
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    scope.release_except(st == PAT_OK ? rb : -1);
+    PAT_TRY(st);
     b->tune[{S, int(pr)}] = pat_batch::Tune{rb, mf, ma};
     if (rhs_block) *rhs_block = rb;
     if (step_us) *step_us = us;

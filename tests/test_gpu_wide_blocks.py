@@ -87,8 +87,19 @@ def test_wide_block_errors(ball16_130):
 
 
 def test_autotune_wide_candidates(ball16_130):
-    _, G, _, _, _ = ball16_130
+    w, G, _, _, _ = ball16_130
+    before = G.info()["device_bytes"]
     rb, us = pat.autotune(G, 200, "f32")
+    # the workspaces of the candidates not chosen are released again: the handle grows by at
+    # most the chosen block's sweep state and staging, and a second identical call adds nothing
+    def ws(b):  # sweep state (P, V, ping-pong) and the data staging of one block
+        return 4 * w.n_nodes * b * 4 + w.n_steps * w.n_obs * b * 4
+
+    grown = G.info()["device_bytes"] - before
+    assert grown <= ws(rb), (grown, rb)
+    after = G.info()["device_bytes"]
+    rb2, _ = pat.autotune(G, 200, "f32")
+    assert G.info()["device_bytes"] - after <= (0 if rb2 == rb else ws(rb2)), (rb, rb2)
     print(f"autotune ball16 S=200 f32: rb={rb}, {us:.1f} us per step pair")
     assert rb in (4, 8, 16, 32, 64, 128, 256) and us > 0
     rb64, _ = pat.autotune(G, 200, "f64")
