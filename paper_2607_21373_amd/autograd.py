@@ -114,7 +114,7 @@ def map_gradient_descent(problem, y_obs, sigma, prior_a, n_iter=200, step=None, 
         p.requires_grad_(True)
         f = map_objective(problem, p, y_obs, sigma, prior_a)
         (grad,) = torch.autograd.grad(f, p)
-        hist.append(float(f))
+        hist.append(float(f.detach()))
         with torch.no_grad():
             p = p - step * grad
     p = p.detach()
