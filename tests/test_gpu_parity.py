@@ -137,6 +137,23 @@ def test_rto_f32_sweeps_match_oracle(name, S):
     assert em < 1e-4 and es < 1e-4
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_rto_iid_prior_matches_oracle(prec, tol):
+    """a = 0: the paper's independent prior with precision M_L, L = M_L^{1/2} (Sec. 3.3)."""
+    w, O, G = _case("ball16")
+    yobs, sigma, eta, xi, n_iter = _rto_inputs(w, O, 12)
+    ref, rres = O.rto(yobs, sigma, 0.0, n_iter, eta, xi)
+    rmean, rstd = oracle.stats(ref)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, 0.0, n_iter, sweep_prec=prec, resid=True)
+    em = _rel_l2(out["mean"].cpu().numpy(), rmean)
+    es = _rel_l2(out["std"].cpu().numpy(), rstd)
+    print(f"a = 0, {prec} sweeps: mean rel L2 {em:.3e}, std rel L2 {es:.3e}")
+    assert em < tol and es < tol
+    if prec == "f64":
+        assert _rel_l2(out["samples"].cpu().numpy(), ref) < tol
+        assert _rel_max(out["resid"].cpu().numpy(), rres) < tol
+
+
 def test_rto_edge_cases():
     """One iteration, one sample (no std), no reorthogonalisation."""
     w, O, G = _case("ball16")

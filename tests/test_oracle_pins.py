@@ -375,22 +375,31 @@ def test_cgls_converges_to_least_squares(tiny):
         assert np.linalg.norm(x[r] - xs) < 1e-8 * np.linalg.norm(xs)
 
 
-def test_rto_sample_is_closed_form(tiny):
-    """Converged RTO sample = C_post [G^T y / sigma^2 + G^T eta / sigma + L^T L p_prior] (App. A)."""
+@pytest.mark.parametrize("a", [0.02, 0.0])
+def test_rto_sample_is_closed_form(tiny, a):
+    """Converged RTO sample = C_post [G^T y / sigma^2 + G^T eta / sigma + Q p_prior] (App. A), with the
+    prior precision Q = L^T L.  At a = 0 the prior is the paper's independent one, precision M_L
+    (Sec. 3.3, eq. iid-prior), written here from the lumped masses alone, and p_prior = M_L^{-1/2} xi."""
     P = tiny[0]
-    sigma, a = 0.05, 0.02
+    sigma = 0.05
     G, L, _ = _gext_dense(P, sigma, a)
     N = P.n_nodes
+    if a == 0.0:
+        m = P.lumped_mass()
+        Q = np.diag(m)
+        prior_mean = lambda x: x / np.sqrt(m)
+    else:
+        Q = L.T @ L
+        prior_mean = lambda x: np.linalg.solve(L, x)
     rng = np.random.default_rng(6)
     yobs = G @ rng.standard_normal(N) + sigma * rng.standard_normal(G.shape[0])
     S = 3
     eta = rng.standard_normal((S, P.n_steps, P.n_obs))
     xi = rng.standard_normal((S, N))
     samples, _ = P.rto(yobs.reshape(P.n_steps, P.n_obs), sigma, a, 2 * N, eta, xi)
-    Cpost = np.linalg.inv(G.T @ G / sigma ** 2 + L.T @ L)
+    Cpost = np.linalg.inv(G.T @ G / sigma ** 2 + Q)
     for s in range(S):
-        p_prior = np.linalg.solve(L, xi[s])
-        ref = Cpost @ (G.T @ yobs / sigma ** 2 + G.T @ eta[s].ravel() / sigma + L.T @ L @ p_prior)
+        ref = Cpost @ (G.T @ yobs / sigma ** 2 + G.T @ eta[s].ravel() / sigma + Q @ prior_mean(xi[s]))
         assert np.linalg.norm(samples[s] - ref) < 1e-8 * np.linalg.norm(ref)
 
 
