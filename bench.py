@@ -485,15 +485,29 @@ def main():
         # plain float64 path: one sample at a time, float64 everywhere
         e1, x1 = eta[:1].contiguous(), xi[:1].contiguous()
         pat.rto_sample(G, yobs, e1, x1, sigma, w.prior_a, 2, sweep_prec="f64", rhs_block=1, stats=False)
+        G.profile_enable(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         pat.rto_sample(G, yobs, e1, x1, sigma, w.prior_a, n_iter, sweep_prec="f64", rhs_block=1, stats=False)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t
+        pprof = G.profile()
+        G.profile_enable(False)
         plain = 60.0 / tp
+        # the single-RHS step is the plain SpMV: its rate against the HBM peak, as for the batched step
+        pf_s = pprof["fwd_ms"] / max(pprof["fwd_sweeps"], 1) / w.n_steps / 1e3
+        pa_s = pprof["adj_ms"] / max(pprof["adj_sweeps"], 1) / w.n_steps / 1e3
+        pfb, pab = step_bytes(info, 1, 8, "fwd"), step_bytes(info, 1, 8, "adj")
         result["plain_fp64"] = {"value": round(plain, 3), "unit": "samples/min", "rhs_block": 1,
-                                "seconds_per_sample": round(tp, 3), "speedup_batched_f32": round(value / plain, 2)}
-        log(f"plain f64 (1 sample, R=1): {tp:.2f} s -> {plain:.2f} samples/min; speed-up {value / plain:.1f}x")
+                                "seconds_per_sample": round(tp, 3), "speedup_batched_f32": round(value / plain, 2),
+                                "fwd_step": {"avg_launch_us": round(pf_s * 1e6, 3), "bytes_per_launch": pfb,
+                                             "achieved_GBs": round(pfb / pf_s / 1e9, 1),
+                                             "frac": round(pfb / pf_s / 1e9 / HBM_PEAK_GBS, 4)},
+                                "adj_step": {"avg_launch_us": round(pa_s * 1e6, 3), "bytes_per_launch": pab,
+                                             "achieved_GBs": round(pab / pa_s / 1e9, 1)},
+                                "sweep_time_share": round((pprof["fwd_ms"] + pprof["adj_ms"]) / (tp * 1e3), 4)}
+        log(f"plain f64 (1 sample, R=1): {tp:.2f} s -> {plain:.2f} samples/min; speed-up {value / plain:.1f}x; "
+            f"forward step {pf_s * 1e6:.2f} us ({pfb / pf_s / 1e9:.0f} GB/s), transpose {pa_s * 1e6:.2f} us")
 
     if copy_probe:
         result["copy_probe"] = copy_probe

@@ -2,10 +2,10 @@
 //
 // Data layout: a block of RB right-hand sides is stored node-major with the RHS
 // fastest, x[i*RB + r], so the RB values a row gathers from one neighbour are
-// one contiguous RB*sizeof(T) segment.  For RB >= 8 one wave64 covers 64/RB
-// rows with one lane per RHS (RB = 64: one row per wave, its CSR indices and
-// values are wave-uniform scalar loads).  For RB < 8, 8/RB lanes per RHS split
-// a row's nonzeros and combine their sums with cross-lane shuffles.
+// one contiguous RB*sizeof(T) segment.  Blocks of at least 16 bytes per row use
+// the vector-lane kernels (16 bytes per lane, further down).  Below that (one
+// RHS, or two floats) the scalar-lane kernels split a row's padded slots over
+// 4 lanes per RHS and combine their sums with cross-lane shuffles.
 //
 // Paper: "3D Uncertainty Quantification for Photoacoustic Tomography"
 // (arXiv 2607.21373).  The time stepping is Sec. 3 eq. (fully-discrete) with
@@ -23,7 +23,7 @@ __device__ __forceinline__ double mad(double a, double b, double c) { return __b
 
 template <int RB>
 struct Geo {
-    static constexpr int SPLIT = RB >= 8 ? 1 : 8 / RB;  // lanes sharing one RHS of a row
+    static constexpr int SPLIT = RB >= 8 ? 1 : RB == 1 ? 4 : 8 / RB;  // lanes sharing one RHS of a row
     static constexpr int LPR = RB * SPLIT;              // lanes per row
     static constexpr int RPW = 64 / LPR;                // rows per wave
     static constexpr int RPB = 4 * RPW;                 // rows per 256-thread workgroup
@@ -52,7 +52,8 @@ struct RowOps {
     const int32_t *bnum;  // boundary rows: slots with a nonzero B come first, bnum of them
 };
 
-// Operands of one row, loaded one row ahead of their use.
+// Operands of one row as seen by one lane: its padded slots' columns and
+// weights, the boundary-slot offset, the overflow range and dt/m.
 template <typename T, int RB>
 struct RowMeta {
     int c[Geo<RB>::PER];
@@ -113,19 +114,31 @@ __device__ __forceinline__ void row_sums(const RowOps<T> &o, const RowMeta<T, RB
     }
 }
 
-// Persistent row schedule: the grid has 8*gx workgroups; workgroup b runs on XCD
-// (b % 8) and takes tiles (RPB rows each) tx0 + (b / 8) + k*gx of that XCD's
-// contiguous tile range [tx0, tx1), so each XCD sweeps one contiguous part of
-// the rows and all its workgroups advance through it together.
-struct TileRange {
-    int first, end, stride;
-};
-__device__ __forceinline__ TileRange xcd_tiles(int ntile) {
-    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, gx = gridDim.x >> 3;
-    const int q = ntile >> 3, rem = ntile & 7;
-    const int tx0 = x * q + (x < rem ? x : rem);
-    const int tx1 = tx0 + q + (x < rem ? 1 : 0);
-    return TileRange{tx0 + j, tx1, gx};
+// Workgroup b is dispatched to XCD (b % 8); map it to a logical tile so that
+// each XCD walks one contiguous range of rows.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
+}
+
+// The logical tiles [0, T), T = n_rows + n_samp, of a forward step come in
+// eight contiguous shares, one per XCD (share x: floor(T/8) tiles, one more
+// for x < T % 8).  Each share starts with its part of the sensor-sampling
+// blocks (floor(n_samp/8), one more for x < n_samp % 8), which are short and
+// so are dispatched first, then its row tiles in order.  Returns the row tile,
+// or n_rows + j for sampling block j.
+__device__ __forceinline__ int fwd_work(int l, int n_rows, int n_samp) {
+    if (n_samp == 0) return l;
+    const int T = n_rows + n_samp;
+    const int q = T >> 3, r = T & 7;
+    const int x = l < r * (q + 1) ? l / (q + 1) : r + (l - r * (q + 1)) / q;
+    const int k = l - (x * q + (x < r ? x : r));
+    const int sq = n_samp >> 3, sr = n_samp & 7;
+    const int before = x * sq + (x < sr ? x : sr);  // sampling blocks of the shares before x
+    const int mine = sq + (x < sr ? 1 : 0);
+    if (k < mine) return n_rows + before + k;
+    return l - before - mine;
 }
 
 template <typename T>
@@ -137,67 +150,50 @@ struct FwdArgs {
     T *Pn, *Vn;
     void *y;
     double yscale;
-    int n, n_obs, n_tiles, first, sample, t;
+    int n, n_obs, n_tiles, n_samp, first, sample, t;
     T dt, half_dt;
 };
 
 // Forward step.  State (P, V) = (p^{n+1/2}, v^n):
 //   V' = V - (dt/m) (K P + B V),  P' = P + dt V'
-// which is the three-substep Stormer-Verlet update with lumped mass.  The same
-// workgroups then write the samples y^n = Pi (P - dt/2 V) of the incoming state.
+// which is the three-substep Stormer-Verlet update with lumped mass.  One tile
+// of RPB rows per workgroup; the sampling blocks placed among them write
+// the samples y^n = Pi (P - dt/2 V) of the incoming state, one (sensor, RHS)
+// pair per thread.
 template <typename T, typename OT, int RB>
 __global__ void __launch_bounds__(256) k_fwd(const FwdArgs<T> a) {
     using G = Geo<RB>;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = lane / G::LPR, part = (lane / RB) % G::SPLIT, r = lane % RB;
-    const TileRange tr = xcd_tiles(a.n_tiles);
-    const int off = wave * G::RPW + slot;
-    int tile = tr.first;
-    if (tile < tr.end) {
-        int row = tile * G::RPB + off;
-        if constexpr (RB == 64) row = __builtin_amdgcn_readfirstlane(row);
+    const int tile = fwd_work(xcd_tile(blockIdx.x, gridDim.x), a.n_tiles, a.n_samp);
+    if (tile < a.n_tiles) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int part = (lane / RB) % G::SPLIT, r = lane % RB;
+        const int row = tile * G::RPB + wave * G::RPW + lane / G::LPR;
+        if (row >= a.n) return;
         RowMeta<T, RB> m;
-        load_meta<T, RB>(a.o, row < a.n ? row : a.n - 1, part, m);
-        for (;;) {
-            const int ntile = tile + tr.stride;
-            const bool more = ntile < tr.end;
-            int nrow = ntile * G::RPB + off;
-            if constexpr (RB == 64) nrow = __builtin_amdgcn_readfirstlane(nrow);
-            RowMeta<T, RB> mn;
-            if (more) load_meta<T, RB>(a.o, nrow < a.n ? nrow : a.n - 1, part, mn);
-            if (row < a.n) {
-                const int64_t id = int64_t(row) * RB + r;
-                const T v0 = a.first ? T(0) : a.V[id];
-                T acc = T(0), bacc = T(0);
-                row_sums<T, RB, false>(a.o, m, part, r, a.P, a.V, !a.first && m.bo >= 0, acc, bacc);
-                acc = lane_sum<RB, G::LPR>(acc + bacc);
-                if (part == 0) {
-                    const T v = v0 - m.dm * acc;
-                    a.Vn[id] = v;
-                    a.Pn[id] = a.P[id] + a.dt * v;
-                }
-            }
-            if (!more) break;
-            tile = ntile;
-            row = nrow;
-            m = mn;
+        load_meta<T, RB>(a.o, row, part, m);
+        const int64_t id = int64_t(row) * RB + r;
+        const T v0 = a.first ? T(0) : a.V[id];
+        T acc = T(0), bacc = T(0);
+        row_sums<T, RB, false>(a.o, m, part, r, a.P, a.V, !a.first && m.bo >= 0, acc, bacc);
+        acc = lane_sum<RB, G::LPR>(acc + bacc);
+        if (part == 0) {
+            const T v = v0 - m.dm * acc;
+            a.Vn[id] = v;
+            a.Pn[id] = a.P[id] + a.dt * v;
         }
+        return;
     }
-    if (a.sample) {
-        // sensors spread over all workgroups: lane group g of the grid takes s = g, g + groups, ...
-        const int groups = gridDim.x * 4 * G::RPW;
-        for (int s = blockIdx.x * 4 * G::RPW + off; s < a.n_obs; s += groups) {
-            if (part != 0) continue;
-            T y = T(0);
-            for (int k = 0; k < 4; ++k) {
-                const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
-                const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
-                y = mad(a.sw[4 * s + k], pk, y);
-            }
-            OT *yo = static_cast<OT *>(a.y);
-            yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
-        }
+    const int64_t e = int64_t(tile - a.n_tiles) * 256 + threadIdx.x;
+    if (e >= int64_t(a.n_obs) * RB) return;
+    const int s = int(e / RB), r = int(e % RB);
+    T y = T(0);
+    for (int k = 0; k < 4; ++k) {
+        const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
+        const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
+        y = mad(a.sw[4 * s + k], pk, y);
     }
+    OT *yo = static_cast<OT *>(a.y);
+    yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
 }
 
 template <typename T>
@@ -228,48 +224,30 @@ __device__ __forceinline__ T inject(const AdjArgs<T> &a, int row, int r, int t) 
 //   PH -= dt K Q ;  unless last:  Q' = Q - (dt/m) B Q + (dt/m)(PH + inj/2),  PH += inj
 // with inj = Pi^T yhat^{n-1}.  Algebraically identical to applying the five
 // transposed substeps and then adding Pi^T yhat^{n-1}.  K Q and B Q share the
-// gathers of Q.  Same persistent schedule as the forward step.
+// gathers of Q.  One tile of RPB rows per workgroup.
 template <typename T, typename YT, int RB>
 __global__ void __launch_bounds__(256) k_adj(const AdjArgs<T> a) {
     using G = Geo<RB>;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = lane / G::LPR, part = (lane / RB) % G::SPLIT, r = lane % RB;
-    const TileRange tr = xcd_tiles(a.n_tiles);
-    const int off = wave * G::RPW + slot;
-    int tile = tr.first;
-    if (tile >= tr.end) return;
-    int row = tile * G::RPB + off;
-    if constexpr (RB == 64) row = __builtin_amdgcn_readfirstlane(row);
+    const int part = (lane / RB) % G::SPLIT, r = lane % RB;
+    const int row = xcd_tile(blockIdx.x, gridDim.x) * G::RPB + wave * G::RPW + lane / G::LPR;
+    if (row >= a.n) return;
     RowMeta<T, RB> m;
-    load_meta<T, RB>(a.o, row < a.n ? row : a.n - 1, part, m);
-    for (;;) {
-        const int ntile = tile + tr.stride;
-        const bool more = ntile < tr.end;
-        int nrow = ntile * G::RPB + off;
-        if constexpr (RB == 64) nrow = __builtin_amdgcn_readfirstlane(nrow);
-        RowMeta<T, RB> mn;
-        if (more) load_meta<T, RB>(a.o, nrow < a.n ? nrow : a.n - 1, part, mn);
-        if (row < a.n) {
-            const int64_t id = int64_t(row) * RB + r;
-            const T ph0 = a.PH[id];
-            T kq = T(0), bq = T(0);
-            row_sums<T, RB, true>(a.o, m, part, r, a.Q, a.Q, !a.last && m.bo >= 0, kq, bq);
-            kq = lane_sum<RB, G::LPR>(kq);
-            bq = lane_sum<RB, G::LPR>(bq);
-            if (part == 0) {
-                T ph = ph0 - a.dt * kq;
-                if (!a.last) {
-                    const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
-                    a.Qn[id] = a.Q[id] - m.dm * bq + m.dm * (ph + T(0.5) * inj);
-                    ph += inj;
-                }
-                a.PH[id] = ph;
-            }
+    load_meta<T, RB>(a.o, row, part, m);
+    const int64_t id = int64_t(row) * RB + r;
+    const T ph0 = a.PH[id];
+    T kq = T(0), bq = T(0);
+    row_sums<T, RB, true>(a.o, m, part, r, a.Q, a.Q, !a.last && m.bo >= 0, kq, bq);
+    kq = lane_sum<RB, G::LPR>(kq);
+    bq = lane_sum<RB, G::LPR>(bq);
+    if (part == 0) {
+        T ph = ph0 - a.dt * kq;
+        if (!a.last) {
+            const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
+            a.Qn[id] = a.Q[id] - m.dm * bq + m.dm * (ph + T(0.5) * inj);
+            ph += inj;
         }
-        if (!more) break;
-        tile = ntile;
-        row = nrow;
-        m = mn;
+        a.PH[id] = ph;
     }
 }
 
@@ -334,14 +312,6 @@ struct VGeo {
     static constexpr int RPB = 4 * RPW;      // rows per 256-thread workgroup (one tile)
     static constexpr int W = 16;             // padded slots per row
 };
-
-// Workgroup b is dispatched to XCD (b % 8); map it to a logical tile so that
-// each XCD walks one contiguous range of rows.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int q = nb >> 3, rem = nb & 7;
-    const int x = b & 7, k = b >> 3;
-    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
-}
 
 // LDS image of one tile's row operands.
 template <typename T, int RB>
@@ -466,7 +436,7 @@ struct VFwdArgs {
     T *Pn, *Vn;
     void *y;
     double yscale;
-    int n, n_obs, n_tiles, first, sample, t;
+    int n, n_obs, n_tiles, n_samp, first, sample, t;
     T dt, half_dt;
 };
 
@@ -518,7 +488,7 @@ __device__ __forceinline__ void fwd_tile(const VFwdArgs<T> &a, int tile, TileOps
 template <typename T, typename OT, int RB>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_v(const VFwdArgs<T> a) {
     __shared__ TileOps<T, RB> L;
-    fwd_tile<T, OT, RB>(a, xcd_tile(blockIdx.x, gridDim.x), L);
+    fwd_tile<T, OT, RB>(a, fwd_work(xcd_tile(blockIdx.x, gridDim.x), a.n_tiles, a.n_samp), L);
 }
 
 // Several meshes in one launch; mesh m has tiles[m] logical tiles.  Every XCD
@@ -562,7 +532,7 @@ __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_vm(const Multi<VFwd
     __shared__ TileOps<T, RB> L;
     int m, local;
     if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
-    fwd_tile<T, OT, RB>(mm.a[m], local, L);
+    fwd_tile<T, OT, RB>(mm.a[m], fwd_work(local, mm.a[m].n_tiles, mm.a[m].n_samp), L);
 }
 
 template <typename T>
@@ -1103,20 +1073,6 @@ __global__ void k_stats(const double *x, int64_t S, int64_t N, double *mean, dou
     }
 }
 
-// Workgroups of a persistent step launch: a multiple of 8 (one share per XCD),
-// PAT_WG_PER_CU resident 256-thread workgroups on each of the 256 CUs, and no
-// more than there are tiles.
-#ifndef PAT_WG_PER_CU
-#define PAT_WG_PER_CU 8
-#endif
-int persistent_grid(int ntiles) {
-    const int per_xcd = 32 * PAT_WG_PER_CU;
-    int gx = (ntiles + 7) / 8;
-    if (gx > per_xcd) gx = per_xcd;
-    if (gx < 1) gx = 1;
-    return 8 * gx;
-}
-
 int grid_for(int64_t total, int per_block = 256, int cap = 65536) {
     int64_t g = (total + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -1163,8 +1119,8 @@ VFwdArgs<T> fwd_args_v(const DevOps &op, const void *P, const void *V, void *Pn,
     a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
     a.first = first; a.sample = sample; a.t = t;
     a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
-    const int sblocks = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
-    *blocks = a.n_tiles + sblocks;
+    a.n_samp = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
+    *blocks = a.n_tiles + a.n_samp;
     return a;
 }
 
@@ -1242,8 +1198,9 @@ void fwd_impl(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn
         a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
         a.first = first; a.sample = sample; a.t = t;
         a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
-        const int grid = rows ? persistent_grid(a.n_tiles) : 8 * ((op.n_obs + 8 * 4 * G::RPW - 1) / (8 * 4 * G::RPW));
-        hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
+        a.n_samp = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
+        const int grid = a.n_tiles + a.n_samp;
+        if (grid > 0) hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
     }
 }
 
@@ -1266,7 +1223,7 @@ void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bo
     } else if constexpr (vec) {
         if constexpr (RB * sizeof(T) <= 1024) adj_impl_v<T, YT, RB>(op, PH, Q, Qn, last, tm1, yh, yscale, s);
     } else {
-        hipLaunchKernelGGL((k_adj<T, YT, RB>), dim3(persistent_grid(a.n_tiles)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adj<T, YT, RB>), dim3(a.n_tiles), dim3(256), 0, s, a);
     }
 }
 
