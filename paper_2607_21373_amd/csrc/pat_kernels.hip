@@ -210,6 +210,16 @@ struct AdjArgs {
     T dt;
 };
 
+// Rows with sensor weights are few (four per sensor at most): one wave-uniform
+// test of the injection range of the wave's rows [r0, r0 + nrows) lets waves
+// without any skip the per-row range loads.
+__device__ __forceinline__ bool wave_injects(const int32_t *injptr, int r0, int nrows, int n, int last) {
+    const int w0 = __builtin_amdgcn_readfirstlane(r0);
+    if (last || w0 >= n) return false;
+    const int w1 = w0 + nrows < n ? w0 + nrows : n;
+    return injptr[w0] != injptr[w1];
+}
+
 template <typename T, typename YT, int RB>
 __device__ __forceinline__ T inject(const AdjArgs<T> &a, int row, int r, int t) {
     const YT *yh = static_cast<const YT *>(a.yh);
@@ -230,7 +240,9 @@ __global__ void __launch_bounds__(256) k_adj(const AdjArgs<T> a) {
     using G = Geo<RB>;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int part = (lane / RB) % G::SPLIT, r = lane % RB;
-    const int row = xcd_tile(blockIdx.x, gridDim.x) * G::RPB + wave * G::RPW + lane / G::LPR;
+    const int wrow0 = xcd_tile(blockIdx.x, gridDim.x) * G::RPB + wave * G::RPW;
+    const bool winj = wave_injects(a.injptr, wrow0, G::RPW, a.n, a.last);
+    const int row = wrow0 + lane / G::LPR;
     if (row >= a.n) return;
     RowMeta<T, RB> m;
     load_meta<T, RB>(a.o, row, part, m);
@@ -243,7 +255,7 @@ __global__ void __launch_bounds__(256) k_adj(const AdjArgs<T> a) {
     if (part == 0) {
         T ph = ph0 - a.dt * kq;
         if (!a.last) {
-            const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
+            const T inj = winj ? inject<T, YT, RB>(a, row, r, a.tm1) : T(0);
             a.Qn[id] = a.Q[id] - m.dm * bq + m.dm * (ph + T(0.5) * inj);
             ph += inj;
         }
@@ -556,8 +568,9 @@ __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps
     using VT = typename Vec16<T>::t;
     if (tile >= a.n_tiles) return;
     const int row0 = tile * G::RPB;
-    stage_tile<T, RB>(a.o, a.n, row0, !a.last, L);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool winj = wave_injects(a.injptr, row0 + wave * G::RPW, G::RPW, a.n, a.last);
+    stage_tile<T, RB>(a.o, a.n, row0, !a.last, L);
     const int lr = wave * G::RPW + lane / G::LPR, q = lane % G::LPR;
     const int row = row0 + lr;
     if (row >= a.n) return;
@@ -572,13 +585,14 @@ __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps
         const T dm = L.dm[lr];
         VT inj = {};
         const YT *yh = static_cast<const YT *>(a.yh);
-        for (int e = a.injptr[row]; e < a.injptr[row + 1]; ++e) {
-            const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + q * G::VEC;
-            const T w = a.injw[e];
+        if (winj)
+            for (int e = a.injptr[row]; e < a.injptr[row + 1]; ++e) {
+                const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + q * G::VEC;
+                const T w = a.injw[e];
 #pragma unroll
-            for (int i = 0; i < G::VEC; ++i)
-                inj[i] = mad(w, static_cast<T>(static_cast<double>(yh[src + i]) * a.yscale), inj[i]);
-        }
+                for (int i = 0; i < G::VEC; ++i)
+                    inj[i] = mad(w, static_cast<T>(static_cast<double>(yh[src + i]) * a.yscale), inj[i]);
+            }
         VT qn;
 #pragma unroll
         for (int i = 0; i < G::VEC; ++i) {
