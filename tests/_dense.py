@@ -48,3 +48,33 @@ def forward_matrix(A, Pi, n_steps):
         An = A @ An
         rows.append(Pi @ An[:N, :N])
     return np.vstack(rows)
+
+
+def aperture_posteriors(oracle, W, n=6, n_steps=40, n_sens=160):
+    """Exact pointwise posterior std for three nested measurement apertures.
+
+    A ball of n cells per axis (absorbing, c = 1, dt = 0.2 h) with sensors on the
+    sphere r = 0.7: all of them, the half z > 0, and the quarter z > 0, x > 0.  The
+    prior precision is M_L (the paper's independent prior, eq. (iid-prior)); one
+    noise level sigma = 0.01 max|G_full| serves all three.  Returns the node
+    coordinates, {name: (std, sensor positions)} and sigma.
+    """
+    coords, tets = W.ball_mesh(n)
+    allpos = W.fibonacci_sphere(n_sens, 0.7)
+    sets = {"full": allpos, "half": allpos[allpos[:, 2] > 0],
+            "quarter": allpos[(allpos[:, 2] > 0) & (allpos[:, 0] > 0)]}
+    out, sigma = {}, None
+    for name, pos in sets.items():
+        P = oracle.Problem(coords, tets, None, True, 0.2 * 2.0 / n, n_steps, sensor_pos=pos)
+        N = P.n_nodes
+        G = P.forward(np.eye(N)).reshape(N, -1).T
+        if sigma is None:
+            sigma = 0.01 * float(np.abs(G).max())
+        H = G.T @ G / sigma ** 2 + np.diag(P.lumped_mass())
+        out[name] = (np.sqrt(np.diag(np.linalg.inv(H))), pos)
+    return coords, out, sigma
+
+
+def distance_to_sensors(coords, pos):
+    """Distance of each node to its nearest sensor."""
+    return np.min(np.linalg.norm(coords[:, None, :] - pos[None, :, :], axis=2), axis=1)

@@ -16,6 +16,7 @@ import pytest
 
 import oracle
 import workloads as W
+from tests import _dense
 
 pytestmark = pytest.mark.gpu
 
@@ -60,3 +61,27 @@ def test_samples_follow_exact_posterior(tiny, solver, a):
     print(f"{solver} a={a}: max |mean - mu| / se = {zm.max():.2f}, max |var/C_ii - 1| / se = {zv.max():.2f}, "
           f"||C_hat - C||_F / its expected size = {ec:.2f}")
     assert zm.max() < 5 and zv.max() < 5 and ec < 3
+
+
+def test_sampled_std_follows_the_aperture():
+    """The sampler's std on the quarter aperture (Sec. 6.2): it matches the exact posterior std node by node
+    within its sampling error and, like it, grows with distance from the sensors."""
+    from scipy.stats import spearmanr
+    coords, post, sigma = _dense.aperture_posteriors(oracle, W)
+    exact, pos = post["quarter"]
+    coords_, tets = W.ball_mesh(6)
+    w = W.Workload(name="quarter", coords=coords_, tets=tets, c_tet=None, absorbing=True, dt=0.2 * 2 / 6,
+                   n_steps=40, sensor_pos=pos, p0_true=W.smooth_bump(coords_, 0.8), prior_a=0.0)
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    N = w.n_nodes
+    y = O.forward(w.p0_true) + sigma * np.random.default_rng(9).standard_normal((w.n_steps, w.n_obs))
+    S = 1024
+    out = pat.rto_sample(G, torch.as_tensor(y, device="cuda"), None, None, sigma, 0.0, N, sweep_prec="f64",
+                         rhs_block=64, n_samples=S, seed=12)
+    std = out["std"].cpu().numpy()
+    zv = np.abs(std ** 2 / exact ** 2 - 1) / np.sqrt(2.0 / (S - 1))
+    inside = np.linalg.norm(coords, axis=1) <= 0.7
+    rho = spearmanr(_dense.distance_to_sensors(coords, pos)[inside], std[inside]).correlation
+    print(f"quarter aperture: max |var / C_ii - 1| / se = {zv.max():.2f}; rank correlation with distance {rho:.3f}")
+    assert zv.max() < 5 and rho > 0.6

@@ -426,6 +426,27 @@ def test_rto_distribution_matches_posterior():
     assert np.linalg.norm(C - Cpost) / np.linalg.norm(Cpost) < 6 / math.sqrt(S)
 
 
+def test_posterior_std_follows_the_aperture():
+    """Sec. 6.1 and 6.2: the pointwise posterior uncertainty falls as the measurement aperture grows and,
+    for a partial aperture, grows with distance from it.  The first is exact for nested sensor sets at
+    one noise level: each added sensor adds a positive semidefinite term to the posterior precision, so no
+    diagonal entry of C_post can grow.  The second is a trend, checked by the rank correlation between
+    a node's std and its distance to the nearest sensor over the nodes inside the sensor sphere."""
+    from scipy.stats import spearmanr
+    coords, post, _ = _dense.aperture_posteriors(oracle, W)
+    sd = {k: v[0] for k, v in post.items()}
+    assert np.all(sd["full"] <= sd["half"] * (1 + 1e-12))
+    assert np.all(sd["half"] <= sd["quarter"] * (1 + 1e-12))
+    assert sd["half"].mean() > 2 * sd["full"].mean() and sd["quarter"].mean() > 2 * sd["half"].mean()
+    inside = np.linalg.norm(coords, axis=1) <= 0.7
+    for name in ("half", "quarter"):
+        std, pos = post[name]
+        dist = _dense.distance_to_sensors(coords, pos)
+        rho = spearmanr(dist[inside], std[inside]).correlation
+        print(f"{name} aperture: rank correlation of std with distance to the sensors {rho:.3f}")
+        assert rho > 0.6, (name, rho)
+
+
 def test_stats_match_numpy():
     rng = np.random.default_rng(8)
     s = rng.standard_normal((7, 40)) * 3 + 1
