@@ -104,7 +104,7 @@ double barycentric(const Shape &s, const double *x, double lam[4]) {
 // level keeps spatially close nodes close in the numbering, so a tile of
 // consecutive rows touches few distinct neighbour rows and an XCD's L2 holds the
 // neighbourhood of the rows it is processing.  Stable sorts keep it deterministic.
-void locality_order(const double *X, int32_t N, std::vector<int32_t> &perm) {
+void locality_order(const double *X, int32_t N, const std::vector<char> &first, std::vector<int32_t> &perm) {
     perm.resize(size_t(N));
     for (int32_t i = 0; i < N; ++i) perm[size_t(i)] = i;
     std::vector<std::pair<size_t, size_t>> stack = {{0, size_t(N)}};
@@ -127,6 +127,28 @@ void locality_order(const double *X, int32_t N, std::vector<int32_t> &perm) {
         stack.push_back({m, b});
         stack.push_back({a, m});
     }
+    // Within each of the eight top-level parts (one per XCD), the nodes flagged in
+    // `first` (rows with a sensor weight) go to the front, each group keeping its
+    // k-d order.  Those rows are few, but in plain k-d order they sit in about a
+    // fifth of the tiles, and each such tile waits on the longer injection chain of
+    // the transposed step; at the front of their part they fill few tiles, which are
+    // also the first of that part to be dispatched.
+    std::vector<std::pair<size_t, size_t>> parts = {{0, size_t(N)}};
+    for (int level = 0; level < 3; ++level) {
+        std::vector<std::pair<size_t, size_t>> next;
+        for (const auto &[a, b] : parts) {
+            if (b - a <= 64) {
+                next.push_back({a, b});
+                continue;
+            }
+            const size_t m = a + (b - a) / 2;
+            next.push_back({a, m});
+            next.push_back({m, b});
+        }
+        parts.swap(next);
+    }
+    for (const auto &[a, b] : parts)
+        std::stable_partition(perm.begin() + a, perm.begin() + b, [&](int32_t u) { return first[size_t(u)] != 0; });
 }
 
 int local_index(const int32_t *t, int32_t node) {
@@ -174,8 +196,105 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
     hp.n_steps = d.n_steps;
     hp.n_tets = E;
     hp.dt = d.dt;
+    // Sensors (user numbering; mapped to the internal one further down).
+    const int32_t S = d.n_obs;
+    hp.snode.assign(size_t(4) * S, 0);
+    hp.sw.assign(size_t(4) * S, 0.0);
+    if (d.sensor_nodes) {
+        for (int32_t s = 0; s < S; ++s) {
+            const int32_t v = d.sensor_nodes[s];
+            if (v < 0 || v >= N) {
+                err = "sensor node id out of range";
+                return PAT_ERR_INVALID_ARG;
+            }
+            for (int k = 0; k < 4; ++k) hp.snode[4 * s + k] = v;
+            hp.sw[4 * s] = 1.0;
+        }
+    } else {
+        // bucket grid over the mesh bounding box; each tetrahedron is listed in
+        // every cell its bounding box touches
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int32_t i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], d.coords[3 * i + k]);
+                hi[k] = std::max(hi[k], d.coords[3 * i + k]);
+            }
+        const int G = std::max(1, std::min(256, int(std::cbrt(double(E) / 4.0))));
+        auto cell = [&](double x, int k) {
+            const double w = (hi[k] - lo[k]) > 0 ? (hi[k] - lo[k]) : 1.0;
+            int c = int((x - lo[k]) / w * G);
+            return std::min(G - 1, std::max(0, c));
+        };
+        std::vector<int64_t> cptr(size_t(G) * G * G + 1, 0);
+        auto for_cells = [&](int64_t e, auto &&fn) {
+            const int32_t *t = d.tets + 4 * e;
+            int c0[3], c1[3];
+            for (int k = 0; k < 3; ++k) {
+                double a = 1e300, b = -1e300;
+                for (int v = 0; v < 4; ++v) {
+                    a = std::min(a, d.coords[3 * int64_t(t[v]) + k]);
+                    b = std::max(b, d.coords[3 * int64_t(t[v]) + k]);
+                }
+                c0[k] = cell(a, k);
+                c1[k] = cell(b, k);
+            }
+            for (int z = c0[2]; z <= c1[2]; ++z)
+                for (int y = c0[1]; y <= c1[1]; ++y)
+                    for (int x = c0[0]; x <= c1[0]; ++x) fn((int64_t(z) * G + y) * G + x);
+        };
+        for (int64_t e = 0; e < E; ++e) for_cells(e, [&](int64_t c) { ++cptr[size_t(c) + 1]; });
+        for (size_t c = 0; c + 1 < cptr.size(); ++c) cptr[c + 1] += cptr[c];
+        std::vector<int64_t> clist(size_t(cptr.back()));
+        {
+            std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+            for (int64_t e = 0; e < E; ++e) for_cells(e, [&](int64_t c) { clist[size_t(fill[size_t(c)]++)] = e; });
+        }
+        int bad = -1;
+        for (int32_t s = 0; s < S; ++s) {
+            const double *x = d.sensor_pos + 3 * int64_t(s);
+            if (!std::isfinite(x[0]) || !std::isfinite(x[1]) || !std::isfinite(x[2])) {
+                bad = s;
+                break;
+            }
+            const int64_t c = (int64_t(cell(x[2], 2)) * G + cell(x[1], 1)) * G + cell(x[0], 0);
+            double best = -std::numeric_limits<double>::infinity();
+            int64_t best_e = -1;
+            double best_lam[4] = {0, 0, 0, 0};
+            // candidates in ascending tetrahedron index; the tetrahedron whose
+            // smallest barycentric coordinate is largest wins (first on ties)
+            for (int64_t q = cptr[size_t(c)]; q < cptr[size_t(c) + 1]; ++q) {
+                const int64_t e = clist[size_t(q)];
+                Shape sh;
+                tet_shape(d.coords, d.tets + 4 * e, sh);
+                double lam[4];
+                const double m = barycentric(sh, x, lam);
+                if (m > best) {
+                    best = m;
+                    best_e = e;
+                    std::memcpy(best_lam, lam, sizeof(lam));
+                }
+            }
+            if (best_e < 0 || best < -1e-10) {
+                bad = s;
+                break;
+            }
+            for (int k = 0; k < 4; ++k) {
+                hp.snode[4 * s + k] = d.tets[4 * best_e + k];
+                hp.sw[4 * s + k] = best_lam[k];
+            }
+        }
+        if (bad >= 0) {
+            err = "sensor " + std::to_string(bad) + " is not inside the mesh";
+            return PAT_ERR_INVALID_ARG;
+        }
+    }
+    // nodes that carry a sensor weight: their rows take the injection of the transposed step
+    std::vector<char> sensor_row(size_t(N), 0);
+    for (size_t q = 0; q < hp.sw.size(); ++q)
+        if (hp.sw[q] != 0.0) sensor_row[size_t(hp.snode[q])] = 1;
+
     // Internal numbering (see locality_order): perm[internal] = user node.
-    locality_order(d.coords, N, hp.perm);
+    locality_order(d.coords, N, sensor_row, hp.perm);
     hp.iperm.resize(N);
     for (int32_t i = 0; i < N; ++i) hp.iperm[hp.perm[i]] = i;
 
@@ -335,98 +454,6 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
     for (double v : hp.bval)
         if (v != 0.0) ++hp.nnz_b;
 
-    // Sensors.
-    const int32_t S = d.n_obs;
-    hp.snode.assign(size_t(4) * S, 0);
-    hp.sw.assign(size_t(4) * S, 0.0);
-    if (d.sensor_nodes) {
-        for (int32_t s = 0; s < S; ++s) {
-            const int32_t v = d.sensor_nodes[s];
-            if (v < 0 || v >= N) {
-                err = "sensor node id out of range";
-                return PAT_ERR_INVALID_ARG;
-            }
-            for (int k = 0; k < 4; ++k) hp.snode[4 * s + k] = v;
-            hp.sw[4 * s] = 1.0;
-        }
-    } else {
-        // bucket grid over the mesh bounding box; each tetrahedron is listed in
-        // every cell its bounding box touches
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (int32_t i = 0; i < N; ++i)
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = std::min(lo[k], d.coords[3 * i + k]);
-                hi[k] = std::max(hi[k], d.coords[3 * i + k]);
-            }
-        const int G = std::max(1, std::min(256, int(std::cbrt(double(E) / 4.0))));
-        auto cell = [&](double x, int k) {
-            const double w = (hi[k] - lo[k]) > 0 ? (hi[k] - lo[k]) : 1.0;
-            int c = int((x - lo[k]) / w * G);
-            return std::min(G - 1, std::max(0, c));
-        };
-        std::vector<int64_t> cptr(size_t(G) * G * G + 1, 0);
-        auto for_cells = [&](int64_t e, auto &&fn) {
-            const int32_t *t = d.tets + 4 * e;
-            int c0[3], c1[3];
-            for (int k = 0; k < 3; ++k) {
-                double a = 1e300, b = -1e300;
-                for (int v = 0; v < 4; ++v) {
-                    a = std::min(a, d.coords[3 * int64_t(t[v]) + k]);
-                    b = std::max(b, d.coords[3 * int64_t(t[v]) + k]);
-                }
-                c0[k] = cell(a, k);
-                c1[k] = cell(b, k);
-            }
-            for (int z = c0[2]; z <= c1[2]; ++z)
-                for (int y = c0[1]; y <= c1[1]; ++y)
-                    for (int x = c0[0]; x <= c1[0]; ++x) fn((int64_t(z) * G + y) * G + x);
-        };
-        for (int64_t e = 0; e < E; ++e) for_cells(e, [&](int64_t c) { ++cptr[size_t(c) + 1]; });
-        for (size_t c = 0; c + 1 < cptr.size(); ++c) cptr[c + 1] += cptr[c];
-        std::vector<int64_t> clist(size_t(cptr.back()));
-        {
-            std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
-            for (int64_t e = 0; e < E; ++e) for_cells(e, [&](int64_t c) { clist[size_t(fill[size_t(c)]++)] = e; });
-        }
-        int bad = -1;
-        for (int32_t s = 0; s < S; ++s) {
-            const double *x = d.sensor_pos + 3 * int64_t(s);
-            if (!std::isfinite(x[0]) || !std::isfinite(x[1]) || !std::isfinite(x[2])) {
-                bad = s;
-                break;
-            }
-            const int64_t c = (int64_t(cell(x[2], 2)) * G + cell(x[1], 1)) * G + cell(x[0], 0);
-            double best = -std::numeric_limits<double>::infinity();
-            int64_t best_e = -1;
-            double best_lam[4] = {0, 0, 0, 0};
-            // candidates in ascending tetrahedron index; the tetrahedron whose
-            // smallest barycentric coordinate is largest wins (first on ties)
-            for (int64_t q = cptr[size_t(c)]; q < cptr[size_t(c) + 1]; ++q) {
-                const int64_t e = clist[size_t(q)];
-                Shape sh;
-                tet_shape(d.coords, d.tets + 4 * e, sh);
-                double lam[4];
-                const double m = barycentric(sh, x, lam);
-                if (m > best) {
-                    best = m;
-                    best_e = e;
-                    std::memcpy(best_lam, lam, sizeof(lam));
-                }
-            }
-            if (best_e < 0 || best < -1e-10) {
-                bad = s;
-                break;
-            }
-            for (int k = 0; k < 4; ++k) {
-                hp.snode[4 * s + k] = d.tets[4 * best_e + k];
-                hp.sw[4 * s + k] = best_lam[k];
-            }
-        }
-        if (bad >= 0) {
-            err = "sensor " + std::to_string(bad) + " is not inside the mesh";
-            return PAT_ERR_INVALID_ARG;
-        }
-    }
     // map sensor nodes to the internal numbering
     for (auto &v : hp.snode) v = hp.iperm[size_t(v)];
 
