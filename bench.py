@@ -51,9 +51,12 @@ def step_bytes(info, RB, tsize, kind):
 
 
 def kernel_source_sha():
+    """Hash of what decides the step kernels' memory traffic: their source and the host setup that
+    lays out and orders the rows."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2607_21373_amd", "csrc", "pat_kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("pat_kernels.hip", "pat_setup.cpp"):
+        with open(os.path.join(ROOT, "paper_2607_21373_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
