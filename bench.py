@@ -216,6 +216,59 @@ def big_leg(pat, W, dev, n_iter):
     return res
 
 
+def roofline_record(fwd_s, adj_s, fb, ab, survey_bytes, sweep_share, wname, RB):
+    """Roofline of the two step kernels, which share the sweep time almost equally: the one with the
+    longer average launch leads the record, the other follows with its own fraction of the HBM peak."""
+    kern = {"fwd": (f"k_fwd_v<float,double,{RB}> (forward leapfrog step)", fwd_s, fb, f"k_fwd_f32_rb{RB}"),
+            "adj": (f"k_adj_v<float,double,{RB}> (transpose leapfrog step)", adj_s, ab, f"k_adj_f32_rb{RB}")}
+
+    def rec(k):
+        name, sec, b, key = kern[k]
+        gbs = b / sec / 1e9
+        r = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(key, wname),
+             "bytes_per_launch": b, "avg_launch_us": round(sec * 1e6, 3)}
+        if survey_bytes:
+            r["frac_survey_bytes"] = round(survey_bytes / sec / 1e9 / HBM_PEAK_GBS, 4)
+        return r
+
+    lead, other = ("adj", "fwd") if adj_s >= fwd_s else ("fwd", "adj")
+    out = rec(lead)
+    out["co_dominant"] = rec(other)
+    out["sweep_time_share"] = round(sweep_share, 4)
+    if survey_bytes:
+        out["survey_bytes_per_sweep_step"] = survey_bytes
+    return out
+
+
+def wide_probe(pat, G, info, w, yobs, sigma, iters=4):
+    """The step kernels with 256 samples as one 256-RHS block on the same mesh: the float32 state of a
+    step (4 x N x 256 x 4 B = 800 MB) no longer fits the 256 MB Infinity Cache.  A short solve
+    (a few iterations) gives the average launch of both steps."""
+    import torch
+    RB = 256
+    args = (G, yobs, None, None, sigma, w.prior_a)
+    pat.rto_sample(*args, 1, sweep_prec="f32", rhs_block=RB, n_samples=RB, seed=11, stats=False)
+    G.profile_enable(True)
+    torch.cuda.synchronize()
+    pat.rto_sample(*args, iters, sweep_prec="f32", rhs_block=RB, n_samples=RB, seed=11, stats=False)
+    torch.cuda.synchronize()
+    prof = G.profile()
+    G.profile_enable(False)
+    fwd_s = prof["fwd_ms"] / max(prof["fwd_sweeps"], 1) / w.n_steps / 1e3
+    adj_s = prof["adj_ms"] / max(prof["adj_sweeps"], 1) / w.n_steps / 1e3
+    fb, ab = step_bytes(info, RB, 4, "fwd"), step_bytes(info, RB, 4, "adj")
+    res = {"rhs_block": RB, "state_MB": round(4 * w.n_nodes * RB * 4 / 1e6, 1)}
+    for k, sec, b in (("fwd", fwd_s, fb), ("adj", adj_s, ab)):
+        gbs = b / sec / 1e9
+        res[k] = {"avg_launch_us": round(sec * 1e6, 3), "bytes_per_launch": b, "achieved": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "traffic": stored_traffic(f"k_{k}_f32_rb{RB}", w.name)}
+    log(f"256-RHS block steps: forward {fwd_s * 1e6:.1f} us ({res['fwd']['achieved']:.0f} GB/s), transpose "
+        f"{adj_s * 1e6:.1f} us ({res['adj']['achieved']:.0f} GB/s)")
+    return res
+
+
 def wide_leg(pat, dev, G, info, w, yobs, sigma, n_iter):
     """256 samples as one 256-RHS block on the same mesh: the float32 state of a step
     (4 x N x 256 x 4 B = 800 MB) no longer fits the 256 MB Infinity Cache."""
@@ -337,6 +390,8 @@ def main():
                     help="time a plain elementwise update over four state-sized float32 arrays (what streaming "
                          "reaches for the step's working set) and over arrays 8x larger (past the 256 MB cache)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
+    ap.add_argument("--no-wide-probe", action="store_true",
+                    help="skip the short 256-RHS solve that times the step kernels beyond the Infinity Cache")
     ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
     ap.add_argument("--spectral", action="store_true",
                     help="also time 64 samples with the Whittle-Matern spectral prior (128^3 grid, latent solve)")
@@ -427,7 +482,10 @@ def main():
         log(f"stream probe: {stream_probe}")
 
     def run():
-        return pat.rto_sample(G, yobs, eta, xi, sigma, w.prior_a, n_iter, sweep_prec="f32", rhs_block=64)
+        # final=True: the float64 recomputation of ||b - G_ext p|| of every sample (one float64
+        # forward sweep per block) is part of the timed step
+        return pat.rto_sample(G, yobs, eta, xi, sigma, w.prior_a, n_iter, sweep_prec="f32", rhs_block=64,
+                              final=True)
 
     for k in range(args.warmup):
         t = time.time()
@@ -446,7 +504,12 @@ def main():
     ms_per_step = el / args.steps * 1e3
     value = R * args.steps / el * 60.0
     mean_norm = float(torch.linalg.norm(out["mean"]))
-    log(f"batched f32: {ms_per_step:.1f} ms per batch of {R} -> {value:.1f} samples/min (|mean|={mean_norm:.4e})")
+    fres = out["final_resid"]
+    # ||b - G_ext p|| of each sample recomputed in float64; sqrt(N_T N_obs + N) is the size of b's noise
+    final = {"max": float(fres.max()), "min": float(fres.min()), "finite": bool(torch.isfinite(fres).all()),
+             "noise_level": round(math.sqrt(w.n_steps * w.n_obs + w.n_nodes), 3)}
+    log(f"batched f32: {ms_per_step:.1f} ms per batch of {R} -> {value:.1f} samples/min (|mean|={mean_norm:.4e}); "
+        f"float64 final residuals {final['min']:.2f} .. {final['max']:.2f}")
 
     # roofline of the dominant kernels: each sweep = N_T step launches (+1 tiny sampling/init launch)
     fwd_avg_s = prof["fwd_ms"] / max(prof["fwd_sweeps"], 1) / w.n_steps / 1e3
@@ -455,6 +518,9 @@ def main():
     ab = step_bytes(info, 64, 4, "adj")
     fwd_gbs = fb / fwd_avg_s / 1e9
     adj_gbs = ab / adj_avg_s / 1e9
+    # the estimate of the method's bytes per sweep-step of either direction, from the survey of the
+    # path (ball58, 64 float32 RHS: matrix 22.8 + rowptr 0.8 + B 1.1 + dt/m 0.8 + state 199.8 + sensors 0.26 MB)
+    survey_step_bytes = 225.5e6 if w.n_nodes == 195112 and R == 64 else None
     sweep_share = (prof["fwd_ms"] + prof["adj_ms"]) / (el * 1e3)
     log(f"forward step: {fwd_avg_s * 1e6:.2f} us, {fb / 1e6:.1f} MB -> {fwd_gbs:.0f} GB/s; transpose step: "
         f"{adj_avg_s * 1e6:.2f} us, {ab / 1e6:.1f} MB -> {adj_gbs:.0f} GB/s; sweeps = {100 * sweep_share:.1f}% of time")
@@ -472,17 +538,11 @@ def main():
             "n_nodes": w.n_nodes, "n_steps": w.n_steps, "n_obs": w.n_obs, "samples_per_step": R,
             "cgls_iters": n_iter, "rhs_block": 64, "cgls_dtype": "f64",
         },
-        "roofline": {
-            "kernel": "k_fwd_v<float,double,64> (forward leapfrog step)", "bound": "hbm",
-            "achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic("k_fwd_f32_rb64", w.name),
-            "bytes_per_launch": fb, "avg_launch_us": round(fwd_avg_s * 1e6, 3),
-            "transpose_step": {"achieved": round(adj_gbs, 1), "bytes_per_launch": ab,
-                               "avg_launch_us": round(adj_avg_s * 1e6, 3)},
-            "sweep_time_share": round(sweep_share, 4),
-        },
+        "roofline": roofline_record(fwd_avg_s, adj_avg_s, fb, ab, survey_step_bytes, sweep_share, w.name, 64),
+        "final_residual_f64": final,
     }
+    if not args.no_wide_probe:
+        result["roofline"]["beyond_cache"] = wide_probe(pat, G, info, w, yobs, sigma)
 
     if not args.no_plain:
         # plain float64 path: one sample at a time, float64 everywhere

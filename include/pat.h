@@ -10,8 +10,10 @@
  *    beyond the call's stream order.  Host arrays in pat_problem_desc are copied
  *    during pat_problem_create.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
- *    device work is enqueued on it asynchronously; results are ready when the
- *    stream has reached the point of the call.
+ *    device work is enqueued on it; results are ready when the stream has reached
+ *    the point of the call.  Calls return without waiting for the device, except
+ *    those whose comment says that they synchronise (rto_sample,
+ *    rto_sample_batch, the autotuners, pat_spectral_prior_set, pat_sync).
  *  - Node-indexed vectors use the caller's node numbering (the library reorders
  *    nodes internally and converts at the boundary).
  *  - Errors: validation failures return a negative pat_status before any device
@@ -106,7 +108,7 @@ pat_status pat_adjoint(pat_problem *p, int64_t R, const void *yhat, void *p_out,
 pat_status pat_prior_apply(pat_problem *p, int64_t R, double prior_a, int transpose, const double *x, double *y,
                            void *stream);
 
-/* Least-squares solver of each RTO sample (Sec. 5.2, App. A). */
+/* Least-squares solver of each RTO sample (Sec. 5, Algorithm 1, App. A). */
 typedef enum {
     PAT_CGLS = 0, /* CG on the normal equations; reorth acts on the normalised residuals s_j = G_ext^T r_j */
     PAT_LSQR = 1  /* Paige-Saunders Golub-Kahan bidiagonalisation; reorth acts on the right vectors v_j */
@@ -145,6 +147,11 @@ typedef struct {
                                   prior_a is ignored, the unknown of each solve is the latent vector w and the
                                   samples are p0 = P w */
     double *latent;            /* PAT_PRIOR_SPECTRAL: device [S][n^3] latent samples w, or NULL */
+    double *final_resid;       /* device [S] float64 or NULL: ||b_k - G_ext p_k||_2 of each returned sample
+                                  (Sec. 5 eq. (lsqr-residual)), recomputed after the solve from p_k with a
+                                  float64 forward sweep and the float64 prior factor, whatever sweep_prec
+                                  (resid_hist holds the residual the solver carries instead).  Costs one
+                                  float64 forward sweep per RHS block (per 128 RHS of wider blocks) */
 } pat_rto_params;
 
 /* S posterior samples by RTO.  Sample k solves
@@ -155,12 +162,29 @@ typedef struct {
  *   samples     device [S][N] float64 (required)
  *   mean, std   device [N] float64 or NULL: pointwise mean and standard deviation
  *               with 1/(S-1) normalisation (eq. (ergodic)); std needs S >= 2
- *   resid_hist  device [S][n_iter+1] float64 or NULL: ||b_k - G_ext p_k^{(j)}||_2 per iteration
- * Scratch memory is owned by the handle and grows to the largest block seen. */
+ *   resid_hist  device [S][n_iter+1] float64 or NULL: ||b_k - G_ext p_k^{(j)}||_2 per iteration, as
+ *               carried by the solver's recurrences
+ * Scratch memory is owned by the handle and grows to the largest block seen.
+ * Synchronises `stream` before it returns: it reads back one per-sample solver
+ * scalar (CGLS gamma, LSQR phi_bar) to report a breakdown.  PAT_ERR_NONFINITE
+ * then comes after every output has been written (the non-finite samples included). */
 pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params *prm, int64_t S,
                       double *samples, double *mean, double *std, double *resid_hist, void *stream);
 
-/* Whittle-Matern prior of Sec. 4.1 eq. (matern-cov-op), built as in Sec. 6.4: a
+/* Convergence diagnostics of Sec. 6.1 from a diag_hist of rto_sample (the normalised data
+ * misfit, prior contribution and extended residual per iteration, and the discrepancy
+ * principle).  diag: device [S][n_iter+1][2] float64, (||r_d||, ||r_p||) per iteration with
+ * r_d = y_obs/sigma + eta - G p/sigma (the whitened data residual) and r_p = xi - L p.
+ * n_data = N_T N_obs.  Outputs (device, each may be NULL):
+ *   data  [S][n_iter+1] float64: ||r_d|| / sqrt(n_data)  (1 at the discrepancy level sigma sqrt(N_T N_obs))
+ *   prior [S][n_iter+1] float64: ||r_p|| / ||b||, ||b|| the extended residual at iteration 0 (x = 0)
+ *   ext   [S][n_iter+1] float64: sqrt(||r_d||^2 + ||r_p||^2) / ||b||
+ *   first [S] int32: the first iteration j with ||r_d|| <= tau sqrt(n_data), or -1 if none
+ * A zero ||b|| leaves the ratios unscaled.  Runs on the current device; asynchronous. */
+pat_status pat_solver_diagnostics(const double *diag, int64_t S, int32_t n_iter, int64_t n_data, double tau,
+                                  double *data, double *prior, double *ext, int32_t *first, void *stream);
+
+/* Whittle-Matern prior of Sec. 4.1.2 eq. (matern-cov-op), built as in Sec. 6.4: a
  * latent white-noise vector w on a periodic grid of n^3 points over the cube
  * [lo, lo + side)^3 (index (k*n + j)*n + i for the point lo + h (i, j, k), h = side/n)
  * gives the field u = F^* diag(a) F w, F the unitary 3D DFT and
@@ -227,11 +251,12 @@ pat_status pat_batch_merge(pat_batch *b, int32_t forward, int32_t transpose);
 
 /* rto_sample for every problem m of the batch at once: arrays of n entries
  * (n = problems in the batch).  prm[m] gives problem m's sigma, prior_a,
- * perturbations (eta, xi or seed, sample0) and diag_hist; n_iter, reorth,
+ * perturbations (eta, xi or seed, sample0), diag_hist and final_resid; n_iter, reorth,
  * sweep_prec, rhs_block and solver must agree across m.  All problems use one RHS
  * block; with unequal S the smaller ones run zero right-hand sides in the later
  * blocks.  mean, std, resid_hist: arrays or NULL, entries may be NULL.  Results
- * equal rto_sample on each problem alone. */
+ * equal rto_sample on each problem alone.  Synchronises `stream` before it returns,
+ * and reports PAT_ERR_NONFINITE as rto_sample does (outputs already written). */
 pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_rto_params *prm, const int64_t *S,
                             double *const *samples, double *const *mean, double *const *std,
                             double *const *resid_hist, void *stream);

@@ -13,6 +13,7 @@ Layouts at this interface follow the GPU library's user-facing conventions:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional
@@ -27,6 +28,7 @@ _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 _lp = ctypes.POINTER(ctypes.c_int64)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 
 def build() -> str:
@@ -55,6 +57,8 @@ def _load():
     lib.orc_get_mass.argtypes = [ctypes.c_void_p, _dp]
     lib.orc_get_sensors.argtypes = [ctypes.c_void_p, _ip, _dp]
     lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+    lib.orc_forward_f32.argtypes = [ctypes.c_void_p, ctypes.c_int, _fp, _fp]
+    lib.orc_adjoint_f32.argtypes = [ctypes.c_void_p, ctypes.c_int, _fp, _fp]
     lib.orc_step_transpose.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
     lib.orc_forward.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     lib.orc_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
@@ -183,6 +187,24 @@ class Problem:
         out = np.moveaxis(y, 2, 0)
         return np.ascontiguousarray(out[0] if single else out)
 
+    def forward_f32(self, p0: np.ndarray) -> np.ndarray:
+        """forward() with float32 state and arithmetic (rounding-floor studies only); returns float64."""
+        p0 = np.atleast_2d(p0)
+        R = p0.shape[0]
+        x = np.ascontiguousarray(p0.T, dtype=np.float32)
+        y = np.empty((self.n_steps, self.n_obs, R), dtype=np.float32)
+        _load().orc_forward_f32(self._h, R, x.ctypes.data_as(_fp), y.ctypes.data_as(_fp))
+        return np.ascontiguousarray(np.moveaxis(y, 2, 0)).astype(np.float64)
+
+    def adjoint_f32(self, yhat: np.ndarray) -> np.ndarray:
+        """adjoint() with float32 state and arithmetic (rounding-floor studies only); returns float64."""
+        yh = yhat[None] if np.ndim(yhat) == 2 else yhat
+        R = yh.shape[0]
+        a = np.ascontiguousarray(np.moveaxis(yh, 0, 2), dtype=np.float32)
+        p = np.empty((self.n_nodes, R), dtype=np.float32)
+        _load().orc_adjoint_f32(self._h, R, a.ctypes.data_as(_fp), p.ctypes.data_as(_fp))
+        return np.ascontiguousarray(p.T).astype(np.float64)
+
     def adjoint(self, yhat: np.ndarray) -> np.ndarray:
         """p = G^T yhat for yhat [R][N_T][N_obs] (or [N_T][N_obs]); returns [R][N] (or [N])."""
         single = np.ndim(yhat) == 2
@@ -204,6 +226,16 @@ class Problem:
         f = _load().orc_prior_apply_transpose if transpose else _load().orc_prior_apply
         f(self._h, R, float(a), _ptr(xi), _ptr(y))
         return np.ascontiguousarray(y.T[0] if single else y.T)
+
+    def extended_residual(self, p: np.ndarray, yobs: np.ndarray, sigma: float, prior_a: float, eta: np.ndarray,
+                          xi: np.ndarray) -> np.ndarray:
+        """||G_ext p - b||_2 per sample (Sec. 5 eq. (lsqr-residual)), b = (yobs/sigma + eta, xi):
+        data part (G p - yobs - sigma eta)/sigma from the float64 forward map, prior part
+        L p - xi (L p_prior = xi).  p [S][N], eta [S][N_T][N_obs], xi [S][N]; returns [S]."""
+        p = np.atleast_2d(p)
+        rd = (self.forward(p) - yobs[None] - sigma * np.reshape(eta, (p.shape[0],) + yobs.shape)) / sigma
+        rp = self.prior_apply(p, prior_a) - np.reshape(xi, p.shape)
+        return np.sqrt(np.sum(rd.reshape(p.shape[0], -1) ** 2, axis=1) + np.sum(rp ** 2, axis=1))
 
     # -- least squares and sampling ----------------------------------------
     def cgls(self, bd: np.ndarray, bp: np.ndarray, sigma: float, prior_a: float, n_iter: int,
@@ -300,3 +332,30 @@ def synthesize(problem: Problem, w, eta0: Optional[np.ndarray] = None):
         eta0 = workloads.noise_draw(problem.n_steps, problem.n_obs, w.noise_seed)
     sigma = noise_sigma(Y, eta0, w.d_noise, w.noise_rule)
     return Y, Y + sigma * eta0, sigma
+
+
+def diagnostics(diag: np.ndarray, n_data: int, tau: float = 1.0) -> dict:
+    """Convergence diagnostics of Sec. 6.1 from a history diag [S][n_iter+1][2] of
+    (||r_d||, ||r_p||), r_d the whitened data residual: per iteration the normalised data
+    misfit ||r_d|| / sqrt(N_T N_obs) (1 at the discrepancy level), the prior part
+    ||r_p|| / ||b|| and the extended residual ||r|| / ||b|| (||b|| = the residual at x = 0),
+    and the first iteration meeting the discrepancy principle ||r_d|| <= tau sqrt(N_T N_obs)
+    (-1 if none)."""
+    d = np.asarray(diag, dtype=np.float64)
+    if d.ndim != 3 or d.shape[2] != 2:
+        raise ValueError("diag must have shape [S][n_iter+1][2]")
+    S, n1 = d.shape[0], d.shape[1]
+    out = {"data": np.empty((S, n1)), "prior": np.empty((S, n1)), "extended": np.empty((S, n1)),
+           "discrepancy": np.full(S, -1, dtype=np.int32)}
+    level = tau * math.sqrt(n_data)
+    for k in range(S):
+        b = math.sqrt(d[k, 0, 0] ** 2 + d[k, 0, 1] ** 2)
+        ib = 1.0 / b if b > 0 else 1.0
+        for j in range(n1):
+            nd, npr = d[k, j, 0], d[k, j, 1]
+            out["data"][k, j] = nd / math.sqrt(n_data)
+            out["prior"][k, j] = npr * ib
+            out["extended"][k, j] = math.sqrt(nd * nd + npr * npr) * ib
+            if out["discrepancy"][k] < 0 and nd <= level:
+                out["discrepancy"][k] = j
+    return out

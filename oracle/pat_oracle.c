@@ -26,7 +26,7 @@
  *   CGLS                least-squares solve of eq. (normal-equations), with full
  *                       reorthogonalisation of the normal-equation residuals
  *   LSQR                the same least squares by Paige and Saunders' Golub-Kahan
- *                       bidiagonalisation, the solver named in Sec. 5.2
+ *                       bidiagonalisation, the solver named in Sec. 5 and Algorithm 1
  *   RTO sample          Sec. 5, eq. (optimization); Algorithm 1
  *   mean / std          Sec. 6.2, eq. (ergodic)
  *   perturbations       the standard-normal draws eta, xi of Algorithm 1 when the
@@ -470,6 +470,107 @@ void orc_adjoint(const oproblem *P, int R, const double *yhat, double *p) {
         orc_step_transpose(P, R, p, vh, w);
     }
     free(vh); free(w);
+}
+
+/* ------------------------------------------------------------------ */
+/* The same sweeps with float32 state and arithmetic (test use only)   */
+/* ------------------------------------------------------------------ */
+
+/* These repeat orc_forward / orc_adjoint with every stored value (state, matrix
+ * entries, masses, dt) rounded to float32 and float32 arithmetic.  They measure
+ * the rounding floor of a float32-state implementation of the method, against
+ * which a float32 GPU path can be judged where the float64 results are poorly
+ * conditioned; they are not used to produce any expected value. */
+static inline void row_product_f32(const ocsr *A, int i, int R, const float *restrict x, float *restrict acc) {
+    for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+        const float a = (float)A->val[k];
+        const float *xj = x + (size_t)A->col[k] * R;
+        for (int r = 0; r < R; ++r) acc[r] += a * xj[r];
+    }
+}
+
+static void step_f32(const oproblem *P, int R, float *p, float *v, float *ph, float *vn) {
+    const int N = P->n_nodes;
+    const float dt = (float)P->dt, hdt = (float)(0.5 * P->dt);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r) ph[(size_t)i * R + r] = p[(size_t)i * R + r] + hdt * v[(size_t)i * R + r];
+#pragma omp parallel
+    {
+        float *kp = malloc(sizeof(float) * (size_t)R), *bv = malloc(sizeof(float) * (size_t)R);
+#pragma omp for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            const float m = (float)P->mL[i];
+            row_product_f32(&P->K, i, R, ph, kp);
+            row_product_f32(&P->B, i, R, v, bv);
+            for (int r = 0; r < R; ++r) vn[(size_t)i * R + r] = (m * v[(size_t)i * R + r] - dt * kp[r] - dt * bv[r]) / m;
+        }
+        free(kp); free(bv);
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r) {
+            v[(size_t)i * R + r] = vn[(size_t)i * R + r];
+            p[(size_t)i * R + r] = ph[(size_t)i * R + r] + hdt * vn[(size_t)i * R + r];
+        }
+}
+
+void orc_forward_f32(const oproblem *P, int R, const float *p0, float *y) {
+    const size_t NR = (size_t)P->n_nodes * R;
+    float *p = malloc(sizeof(float) * NR), *v = calloc(NR, sizeof(float));
+    float *ph = malloc(sizeof(float) * NR), *vn = malloc(sizeof(float) * NR);
+    memcpy(p, p0, sizeof(float) * NR);
+    for (int n = 1; n <= P->n_steps; ++n) {
+        step_f32(P, R, p, v, ph, vn);
+        float *yn = y + (size_t)(n - 1) * P->n_obs * R;
+        for (int s = 0; s < P->n_obs; ++s)
+            for (int r = 0; r < R; ++r) {
+                float acc = 0.0f;
+                for (int k = 0; k < 4; ++k) acc += (float)P->sw[4 * s + k] * p[(size_t)P->snode[4 * s + k] * R + r];
+                yn[(size_t)s * R + r] = acc;
+            }
+    }
+    free(p); free(v); free(ph); free(vn);
+}
+
+static void step_transpose_f32(const oproblem *P, int R, float *ph, float *vh, float *q) {
+    const int N = P->n_nodes;
+    const float dt = (float)P->dt, hdt = (float)(0.5 * P->dt);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r)
+            q[(size_t)i * R + r] = (vh[(size_t)i * R + r] + hdt * ph[(size_t)i * R + r]) / (float)P->mL[i];
+#pragma omp parallel
+    {
+        float *kq = malloc(sizeof(float) * (size_t)R), *bq = malloc(sizeof(float) * (size_t)R);
+#pragma omp for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            row_product_f32(&P->K, i, R, q, kq);
+            row_product_f32(&P->B, i, R, q, bq);
+            for (int r = 0; r < R; ++r) {
+                const float pn = ph[(size_t)i * R + r] - dt * kq[r];
+                ph[(size_t)i * R + r] = pn;
+                vh[(size_t)i * R + r] = ((float)P->mL[i] * q[(size_t)i * R + r] - dt * bq[r]) + hdt * pn;
+            }
+        }
+        free(kq); free(bq);
+    }
+}
+
+void orc_adjoint_f32(const oproblem *P, int R, const float *yhat, float *p) {
+    const size_t NR = (size_t)P->n_nodes * R;
+    float *vh = calloc(NR, sizeof(float)), *q = malloc(sizeof(float) * NR);
+    memset(p, 0, sizeof(float) * NR);
+    for (int n = P->n_steps; n >= 1; --n) {
+        const float *yh = yhat + (size_t)(n - 1) * P->n_obs * R;
+        for (int s = 0; s < P->n_obs; ++s)
+            for (int k = 0; k < 4; ++k)
+                for (int r = 0; r < R; ++r)
+                    p[(size_t)P->snode[4 * s + k] * R + r] += (float)P->sw[4 * s + k] * yh[(size_t)s * R + r];
+        step_transpose_f32(P, R, p, vh, q);
+    }
+    free(vh); free(q);
 }
 
 /* ------------------------------------------------------------------ */

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py): plain, slow float64 numpy;
 shares no code with the GPU library.
 
-Prior (Sec. 4.1, eq. (matern-cov-op); set-up of Sec. 6.4).  On a periodic box
+Prior (Sec. 4.1.2, eq. (matern-cov-op); set-up of Sec. 6.4).  On a periodic box
 [lo, lo + side)^3 with n points per axis (spacing h = side/n) a latent white-noise
 vector w ~ N(0, I) of length n^3 defines the grid field
 
@@ -88,18 +88,21 @@ class SpectralPrior:
 
 
 def latent_rto(problem, prior: SpectralPrior, I: sp.csr_matrix, yobs: np.ndarray, sigma: float, n_iter: int,
-               eta: np.ndarray, xi: np.ndarray, reorth: bool = True):
+               eta: np.ndarray, xi: np.ndarray, reorth: bool = True, sweeps: str = "f64"):
     """Latent-space RTO samples: returns (p0 samples [S][N], latent samples [S][n^3], resid [S][n_iter+1]).
 
-    eta [S][N_T][N_obs], xi [S][n^3].  CGLS on G_ext = [G P / sigma ; I] from w = 0."""
+    eta [S][N_T][N_obs], xi [S][n^3].  CGLS on G_ext = [G P / sigma ; I] from w = 0.
+    sweeps = "f32" runs the wave sweeps with float32 state and arithmetic (their inputs rounded
+    to float32), everything else in float64: the rounding floor of a float32-sweep solver."""
     S = xi.shape[0]
     isig = 1.0 / sigma
+    fwd, adj = (problem.forward, problem.adjoint) if sweeps == "f64" else (problem.forward_f32, problem.adjoint_f32)
 
     def gext(d):
-        return isig * problem.forward(prior.apply(d, I)), d.copy()
+        return isig * fwd(prior.apply(d, I)), d.copy()
 
     def gext_t(rd, rp):
-        return isig * prior.apply_t(problem.adjoint(rd), I) + rp
+        return isig * prior.apply_t(adj(rd), I) + rp
 
     def sq(a):
         return np.sum(a.reshape(a.shape[0], -1) ** 2, axis=1)
@@ -136,3 +139,13 @@ def latent_rto(problem, prior: SpectralPrior, I: sp.csr_matrix, yobs: np.ndarray
         d = s + beta[:, None] * d
         gamma = gnew
     return prior.apply(x, I), x, resid
+
+
+def latent_residual(problem, prior: SpectralPrior, I: sp.csr_matrix, w: np.ndarray, yobs: np.ndarray, sigma: float,
+                    eta: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """||G_ext w - b||_2 per latent sample w [S][n^3] (Sec. 5 eq. (lsqr-residual) with G_ext = [G P / sigma ; I],
+    b = [y/sigma + eta ; xi]): data part from the float64 forward map of p0 = P w, prior part w - xi."""
+    w = np.atleast_2d(w)
+    rd = problem.forward(prior.apply(w, I)) / sigma - yobs[None] / sigma - np.reshape(eta, (w.shape[0],) + yobs.shape)
+    rp = w - np.reshape(xi, w.shape)
+    return np.sqrt(np.sum(rd.reshape(w.shape[0], -1) ** 2, axis=1) + np.sum(rp ** 2, axis=1))

@@ -48,7 +48,7 @@ class PatPrior(torch.autograd.Function):
 
 class PatSpectral(torch.autograd.Function):
     """p0 = P w for latent w [R][n^3] (float64) with the handle's spectral prior
-    (Sec. 4.1 eq. (matern-cov-op), Sec. 6.4); backward: P^T."""
+    (Sec. 4.1.2 eq. (matern-cov-op), Sec. 6.4); backward: P^T."""
 
     @staticmethod
     def forward(ctx, w, problem):

@@ -25,15 +25,15 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, defines=(), out: str = LIB, bdir: str = "") -> str:
-    """Compile the sources; `defines` are extra -D tuning macros, `out` the library path."""
+def build(verbose: bool = False, out: str = LIB, bdir: str = "") -> str:
+    """Compile the sources into `out` (object files in `bdir`)."""
     objs = []
     bdir = bdir or os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         if src.endswith(".hip"):
-            cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         else:  # host-only C++
             cmd = [CXX, "-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-I", os.path.join(ROOT, "include"),
                    "-c", os.path.join(CSRC, src), "-o", obj]

@@ -103,6 +103,10 @@ struct SweepWS {
     hipGraphExec_t g_fwd_cgls = nullptr, g_adj_cgls = nullptr;
     double g_fwd_cgls_scale = 0.0;
     const void *g_fwd_cgls_out = nullptr, *g_adj_cgls_in = nullptr;
+    // float64 forward sweep of the final residual check (float64 workspaces only)
+    hipGraphExec_t g_fwd_chk = nullptr;
+    double g_fwd_chk_scale = 0.0;
+    const void *g_fwd_chk_out = nullptr;
 };
 
 // Work buffers of the spectral prior for one RHS block.
@@ -385,7 +389,7 @@ void release_sweep(pat_problem *p, pat::Prec prec, int RB) {
     auto it = p->sweeps.find({int(prec), RB});
     if (it == p->sweeps.end()) return;
     SweepWS &w = it->second;
-    hipGraphExec_t *gs[] = {&w.g_fwd_user, &w.g_adj_user, &w.g_fwd_cgls, &w.g_adj_cgls};
+    hipGraphExec_t *gs[] = {&w.g_fwd_user, &w.g_adj_user, &w.g_fwd_cgls, &w.g_adj_cgls, &w.g_fwd_chk};
     for (auto *g : gs)
         if (*g) (void)hipGraphExecDestroy(*g);
     void *bufs[] = {w.P[0], w.P[1], w.V[0], w.V[1], w.Y};
@@ -705,7 +709,7 @@ void cgls_post_fwd(Solve &v, int k) {
     record(v, c->rd, c->rp, k);
 }
 
-// ---- LSQR (Paige and Saunders' bidiagonalisation, the solver of Sec. 5.2):
+// ---- LSQR (Paige and Saunders' bidiagonalisation, the solver of Sec. 5 and Algorithm 1):
 // b in (rd, rp) and x = 0 on entry.  The left vector u lives in (rd, rp), so
 // the transpose graph reads it where CGLS keeps its residual; the search
 // direction w lives in d.  The residual b - G_ext x is carried (through
@@ -825,7 +829,7 @@ pat_status drive(std::vector<Solve> &blocks, int n_iter, Fwd &&fwd, Adj &&adj) {
 }
 
 // b = (y_obs/sigma + eta, xi) of block rb0 in (rd, rp), from the caller's draws or the device streams.
-void build_rhs(Solve &v, const double *y_obs, const pat_rto_params *prm) {
+void build_b(Solve &v, const double *y_obs, const pat_rto_params *prm) {
     const pat::DevOps &op = v.p->ops;
     // latent grid vectors keep the caller's (grid) order
     const int32_t *perm = (v.sw || v.p->perm_identity) ? nullptr : op.perm;
@@ -836,7 +840,53 @@ void build_rhs(Solve &v, const double *y_obs, const pat_rto_params *prm) {
         pat::launch_build_rhs_rng(y_obs, prm->seed, prm->sample0, v.S, v.rb0, v.RB, v.M, v.isig, v.c->rd, v.s);
         pat::launch_xi_rng(prm->seed, prm->sample0, v.S, v.rb0, v.RB, v.NX, perm, v.c->rp, v.s);
     }
+}
+
+// b in (rd, rp) and the starting point x = 0 of block rb0.
+void build_rhs(Solve &v, const double *y_obs, const pat_rto_params *prm) {
+    build_b(v, y_obs, prm);
     pat::launch_fill(v.c->x, v.NX * v.RB, 0.0, v.s);
+}
+
+// Float64 check of a finished block: out[rb0 + r] = ||b - G_ext x||_2 of its samples
+// (Sec. 5 eq. (lsqr-residual)), recomputed from x with a float64 forward sweep and the
+// float64 prior factor whatever the solver's sweep precision, unlike the residual the
+// solver carries.  rd, rp, qd and qp are free once the solve has ended, so b is rebuilt
+// in (rd, rp).  Blocks wider than the float64 step kernels take (one float64 sweep per
+// slice of at most 128 right-hand sides).
+pat_status final_check(Solve &v, const double *y_obs, const pat_rto_params *prm, double *out) {
+    if (!out) return PAT_OK;
+    pat_problem *p = v.p;
+    CglsWS *c = v.c;
+    const int RB = v.RB;
+    double *pA = c->part, *pB = c->part + pat::kDotBlocks * RB;
+    double *t1 = c->scal + 14 * RB, *t2 = c->scal + 15 * RB;
+    build_b(v, y_obs, prm);
+    prior_part(v, c->x);  // qp = L x (latent prior: x)
+    pat::launch_lincomb(c->rp, c->rp, nullptr, 1.0, c->qp, nullptr, -1.0, v.NX, RB, v.s);
+    pat::launch_dot_partial(c->rp, c->rp, v.NX, RB, pB, v.s);
+    pat::launch_dot_final(pB, nullptr, RB, t2, v.s);
+    const int RBf = fit_rb(v.N, pat::Prec::F64, std::min(RB, pat::max_rhs_block(pat::Prec::F64)));
+    SweepWS *w64;
+    PAT_TRY(get_sweep(p, pat::Prec::F64, RBf, false, &w64));
+    if (!w64->g_fwd_chk || w64->g_fwd_chk_out != c->qd || w64->g_fwd_chk_scale != v.isig) {
+        PAT_TRY(capture(p, &w64->g_fwd_chk, [&](hipStream_t cs) { enqueue_forward(p, *w64, c->qd, true, v.isig, cs); }));
+        w64->g_fwd_chk_out = c->qd;
+        w64->g_fwd_chk_scale = v.isig;
+    }
+    const double *src = c->x;
+    if (v.sw) {  // the sample p0 = P w of the latent solution
+        pat::launch_spectral(p->sops, RB, c->x, v.sw->gr, v.sw->gc, pat::Prec::F64, v.sw->ym, v.N, v.s);
+        src = v.sw->ym;
+    }
+    for (int h = 0; h < RB; h += RBf) {
+        pat::launch_cols(src, RB, h, static_cast<double *>(w64->P[0]), v.N, RBf, v.s);
+        PAT_HIP(hipGraphLaunch(w64->g_fwd_chk, v.s));  // qd [M][RBf] = G p / sigma
+        pat::launch_diff_sq_partial(c->rd, RB, h, c->qd, v.M, RBf, pA, v.s);
+        pat::launch_dot_final(pA, nullptr, RBf, t1 + h, v.s);
+    }
+    pat::launch_resid(t1, t2, out, nullptr, 1, 0, v.rb0, v.S, RB, v.s);
+    return PAT_OK;
 }
 
 // Samples of the finished block in the caller's layout: p0 = x (FE prior) or p0 = P x
@@ -1042,7 +1092,7 @@ pat_status pat_problem_destroy(pat_problem *p) {
     (void)hipDeviceSynchronize();
     for (auto &kv : p->sweeps) {
         SweepWS &w = kv.second;
-        hipGraphExec_t *gs[] = {&w.g_fwd_user, &w.g_adj_user, &w.g_fwd_cgls, &w.g_adj_cgls};
+        hipGraphExec_t *gs[] = {&w.g_fwd_user, &w.g_adj_user, &w.g_fwd_cgls, &w.g_adj_cgls, &w.g_fwd_chk};
         for (auto *g : gs)
             if (*g) (void)hipGraphExecDestroy(*g);
     }
@@ -1155,6 +1205,7 @@ pat_status rto_sample(pat_problem *p, const double *y_obs, const pat_rto_params 
         PAT_TRY(drive(blk, n_iter, fwd, adj));
         finish_block(blk[0], prm, samples);
         PAT_HIP(hipMemcpyAsync(chk_host.data() + rb0, ph_check(blk[0]), RB * sizeof(double), hipMemcpyDeviceToHost, s));
+        PAT_TRY(final_check(blk[0], y_obs, prm, prm->final_resid));
     }
     if (mean || std) pat::launch_stats(samples, S, N, mean, std, s);
     PAT_HIP(hipGetLastError());
@@ -1359,6 +1410,7 @@ pat_status rto_sample_batch(pat_batch *b, const double *const *y_obs, const pat_
         for (size_t m = 0; m < n; ++m) {
             if (rb0 < S[m]) finish_block(blk[m], &prm[m], samples[m]);
             PAT_HIP(hipMemcpyAsync(chk[m].data() + rb0, ph_check(blk[m]), RB * sizeof(double), hipMemcpyDeviceToHost, s));
+            if (rb0 < S[m]) PAT_TRY(final_check(blk[m], y_obs[m], &prm[m], prm[m].final_resid));
         }
     }
     for (size_t m = 0; m < n; ++m) {
@@ -1534,6 +1586,18 @@ pat_status pat_draw_normals(uint64_t seed, int32_t kind, int64_t k0, int64_t S, 
     if (S == 0 || len == 0) return PAT_OK;
     if (!out) return fail(PAT_ERR_INVALID_ARG, "pat_draw_normals: NULL output");
     pat::launch_normals(seed, kind, k0, S, len, out, static_cast<hipStream_t>(stream));
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
+pat_status pat_solver_diagnostics(const double *diag, int64_t S, int32_t n_iter, int64_t n_data, double tau,
+                                  double *data, double *prior, double *ext, int32_t *first, void *stream) {
+    g_err.clear();
+    if (!diag || S < 0 || n_iter < 0 || n_data < 1)
+        return fail(PAT_ERR_INVALID_ARG, "pat_solver_diagnostics: NULL history, negative sizes or n_data < 1");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(PAT_ERR_INVALID_ARG, "pat_solver_diagnostics: tau must be >= 0");
+    if (S == 0) return PAT_OK;
+    pat::launch_diagnostics(diag, S, n_iter + 1, n_data, tau, data, prior, ext, first, static_cast<hipStream_t>(stream));
     PAT_HIP(hipGetLastError());
     return PAT_OK;
 }

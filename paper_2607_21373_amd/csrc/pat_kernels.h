@@ -125,6 +125,12 @@ constexpr int kDotBlocks = 512;
 void launch_dot_partial(const double *x, const double *y, int64_t rows, int RB, double *part, hipStream_t s);
 // finalize: mode 0: out[r] = sum partA (+ sum partB if non-null)
 void launch_dot_final(const double *partA, const double *partB, int RB, double *out, hipStream_t s);
+// part[b][r] = sum over rows of block b of (a[row*lda + aoff + r] - y[row*RB + r])^2, r < RB
+// (kDotBlocks partial blocks; finish with launch_dot_final)
+void launch_diff_sq_partial(const double *a, int lda, int aoff, const double *y, int64_t rows, int RB, double *part,
+                            hipStream_t s);
+// out[row*RB + r] = in[row*ldin + c0 + r]: columns [c0, c0 + RB) of a wider block
+void launch_cols(const double *in, int ldin, int c0, double *out, int64_t rows, int RB, hipStream_t s);
 // scalar stages of CGLS, on device arrays of length RB
 void launch_scalar_alpha(const double *gamma, const double *delta, double *alpha, int RB, hipStream_t s);
 void launch_scalar_gamma(double *gamma, const double *gnew, double *beta, double *invn, int first, int RB,
@@ -163,6 +169,9 @@ void launch_lincomb(double *out, const double *a, const double *ca, double sa, c
 // v = inv*sv ; w = v - zfac*w (first: w = v) ; Qk = v if non-null
 void launch_lsqr_vw(const double *sv, const double *inv, const double *zfac, double *v, double *w, double *Qk,
                     int first, int64_t rows, int RB, hipStream_t s);
+// diagnostics of diag [S][n_it][2] (see pat_solver_diagnostics); outputs may be null
+void launch_diagnostics(const double *diag, int64_t S, int n_it, int64_t n_data, double tau, double *data,
+                        double *prior, double *ext, int32_t *first, hipStream_t s);
 // pointwise mean and std (1/(S-1)) of samples [S][N]
 void launch_stats(const double *samples, int64_t S, int64_t N, double *mean, double *std, hipStream_t s);
 

@@ -286,25 +286,14 @@ struct Vec16<double> {
     static constexpr int n = 2;
 };
 
-// Vector-kernel tuning (same arithmetic for every setting):
-//   PAT_VCH  gathers in flight per lane before they are consumed (16 or 8)
-//   PAT_NTS  1: non-temporal stores of the new state (written once, read next step)
-#ifndef PAT_VCH
-#define PAT_VCH 8
-#endif
-#ifndef PAT_NTS
-#define PAT_NTS 0
-#endif
-//   PAT_VWPE waves per SIMD the register allocation of the float32 step kernels must
-//            allow (float64 ones: at most 5); 0 leaves it to the compiler
-#ifndef PAT_VWPE
-#define PAT_VWPE 8
-#endif
-// waves per SIMD to ask for: the setting above, capped by what the tile's LDS image
-// allows (160 KiB per CU; one 4-wave workgroup per tile, one wave per SIMD)
+// Gathers in flight per lane before they are consumed.
+constexpr int kGatherChunk = 8;
+// Waves per SIMD the register allocation of the step kernels must allow: 8 for
+// float32 state, 5 for float64; capped by what the tile's LDS image allows
+// (160 KiB per CU; one 4-wave workgroup per tile, one wave per SIMD).
 template <typename T, int RB, typename Ops>
 constexpr int vwaves() {
-    const int want = PAT_VWPE == 0 ? 1 : sizeof(T) == 4 ? PAT_VWPE : (PAT_VWPE < 5 ? PAT_VWPE : 5);
+    const int want = sizeof(T) == 4 ? 8 : 5;
     const int lds = int(163840 / sizeof(Ops));
     return want < lds ? want : (lds > 0 ? lds : 1);
 }
@@ -312,8 +301,7 @@ constexpr int vwaves() {
 
 template <typename VT, typename T>
 __device__ __forceinline__ void vstore(T *p, VT v) {
-    if constexpr (PAT_NTS) __builtin_nontemporal_store(v, reinterpret_cast<VT *>(p));
-    else *reinterpret_cast<VT *>(p) = v;
+    *reinterpret_cast<VT *>(p) = v;
 }
 
 template <typename T, int RB>
@@ -389,7 +377,7 @@ __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, R
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
     const int base = lr * G::W;
-    constexpr int CH = PAT_VCH;
+    constexpr int CH = kGatherChunk;
     // 32-bit byte offsets from the uniform bases (state arrays are < 4 GiB)
     const char *Xc = reinterpret_cast<const char *>(X);
     const char *Yc = reinterpret_cast<const char *>(Y);
@@ -875,6 +863,35 @@ __global__ void __launch_bounds__(256) k_dot_partial(const double *x, const doub
     if (threadIdx.x < RB) part[int64_t(blockIdx.x) * RB + threadIdx.x] = red[threadIdx.x];
 }
 
+// part[b][r] = sum over rows of block b of (a[row][aoff + r] - y[row][r])^2, a with row
+// stride lda, y with row stride RB (same reduction shape as k_dot_partial)
+__global__ void __launch_bounds__(256) k_diff_sq_partial(const double *a, int lda, int aoff, const double *y,
+                                                         int64_t rows, int RB, double *part) {
+    __shared__ double red[256];
+    const int G = 256 / RB;
+    const int r = threadIdx.x % RB, g = threadIdx.x / RB;
+    const int64_t chunk = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t a0 = int64_t(blockIdx.x) * chunk, a1 = a0 + chunk < rows ? a0 + chunk : rows;
+    double acc = 0.0;
+    for (int64_t row = a0 + g; row < a1; row += G) {
+        const double d = a[row * lda + aoff + r] - y[row * RB + r];
+        acc = __builtin_fma(d, d, acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s >= RB; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < RB) part[int64_t(blockIdx.x) * RB + threadIdx.x] = red[threadIdx.x];
+}
+
+// out[row][r] = in[row][c0 + r], r < RB (in with row stride ldin)
+__global__ void k_cols(const double *in, int ldin, int c0, double *out, int64_t total, int RB) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x)
+        out[e] = in[(e / RB) * ldin + c0 + e % RB];
+}
+
 // out[r] = sum_b partA[b][r] (+ sum_b partB[b][r]), nb partial blocks each
 __global__ void __launch_bounds__(256) k_dot_final(const double *partA, const double *partB, int nb, int RB,
                                                    double *out) {
@@ -1085,6 +1102,25 @@ __global__ void k_stats(const double *x, int64_t S, int64_t N, double *mean, dou
         if (mean) mean[i] = m;
         if (std) std[i] = S > 1 ? sqrt(v / double(S - 1)) : 0.0;
     }
+}
+
+// Convergence diagnostics of one sample per thread from its (||r_d||, ||r_p||) history.
+__global__ void k_diagnostics(const double *diag, int64_t S, int n_it, double sqrt_nd, double tau, double *data,
+                              double *prior, double *ext, int32_t *first) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= S) return;
+    const double *h = diag + k * int64_t(n_it) * 2;
+    const double b0 = sqrt(h[0] * h[0] + h[1] * h[1]);
+    const double ib = b0 > 0.0 ? 1.0 / b0 : 1.0;
+    int32_t hit = -1;
+    for (int j = 0; j < n_it; ++j) {
+        const double nd = h[2 * j], np = h[2 * j + 1];
+        if (data) data[k * n_it + j] = nd / sqrt_nd;
+        if (prior) prior[k * n_it + j] = np * ib;
+        if (ext) ext[k * n_it + j] = sqrt(nd * nd + np * np) * ib;
+        if (hit < 0 && nd <= tau * sqrt_nd) hit = j;
+    }
+    if (first) first[k] = hit;
 }
 
 int grid_for(int64_t total, int per_block = 256, int cap = 65536) {
@@ -1403,6 +1439,15 @@ void launch_dot_partial(const double *x, const double *y, int64_t rows, int RB, 
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, x, y, rows, RB, part);
 }
 
+void launch_diff_sq_partial(const double *a, int lda, int aoff, const double *y, int64_t rows, int RB, double *part,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_diff_sq_partial, dim3(kDotBlocks), dim3(256), 0, s, a, lda, aoff, y, rows, RB, part);
+}
+
+void launch_cols(const double *in, int ldin, int c0, double *out, int64_t rows, int RB, hipStream_t s) {
+    hipLaunchKernelGGL(k_cols, dim3(grid_for(rows * RB)), dim3(256), 0, s, in, ldin, c0, out, rows * RB, RB);
+}
+
 void launch_dot_final(const double *partA, const double *partB, int RB, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, partA, partB, kDotBlocks, RB, out);
 }
@@ -1465,6 +1510,12 @@ void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int
 void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s) {
     if (k <= 0) return;
     hipLaunchKernelGGL(k_project, dim3(grid_for(rows * RB)), dim3(256), 0, s, Q, sv, coef, k, rows, RB);
+}
+
+void launch_diagnostics(const double *diag, int64_t S, int n_it, int64_t n_data, double tau, double *data,
+                        double *prior, double *ext, int32_t *first, hipStream_t s) {
+    hipLaunchKernelGGL(k_diagnostics, dim3(grid_for(S)), dim3(256), 0, s, diag, S, n_it, sqrt(double(n_data)), tau,
+                       data, prior, ext, first);
 }
 
 void launch_stats(const double *samples, int64_t S, int64_t N, double *mean, double *std, hipStream_t s) {

@@ -1,4 +1,4 @@
-// Whittle-Matern Fourier-spectral prior on the GPU (Sec. 4.1 eq. (matern-cov-op);
+// Whittle-Matern Fourier-spectral prior on the GPU (Sec. 4.1.2 eq. (matern-cov-op);
 // the construction of Sec. 6.4): p0 = P w with P = I_h F^* diag(a) F, w a latent
 // white-noise grid vector, F the 3D DFT on a periodic n^3 box, a(k) the
 // square-root spectrum, I_h trilinear interpolation to the mesh nodes.

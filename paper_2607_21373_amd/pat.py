@@ -68,7 +68,7 @@ class RtoParams(ctypes.Structure):
         ("reorth", ctypes.c_int32), ("sweep_prec", ctypes.c_int), ("rhs_block", ctypes.c_int32),
         ("eta", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("solver", ctypes.c_int32), ("diag_hist", ctypes.c_void_p),
         ("seed", ctypes.c_uint64), ("sample0", ctypes.c_int64), ("prior", ctypes.c_int32),
-        ("latent", ctypes.c_void_p),
+        ("latent", ctypes.c_void_p), ("final_resid", ctypes.c_void_p),
     ]
 
 
@@ -85,7 +85,8 @@ class SpectralDesc(ctypes.Structure):
 EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
            "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_spectral_prior_set", "pat_spectral_apply",
            "pat_autotune", "pat_batch_create", "pat_batch_destroy", "pat_batch_autotune", "pat_batch_merge",
-           "rto_sample_batch", "pat_host_assemble", "pat_profile_enable", "pat_profile_get", "pat_sync",
+           "rto_sample_batch", "pat_solver_diagnostics", "pat_host_assemble", "pat_profile_enable",
+           "pat_profile_get", "pat_sync",
            "pat_last_error", "pat_version")
 
 _lib = None
@@ -124,6 +125,8 @@ def load() -> ctypes.CDLL:
     lib.pat_batch_autotune.argtypes = [vp, ctypes.c_int64, ctypes.c_int, i32p, f64p, vp]
     lib.rto_sample_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(RtoParams), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.pat_solver_diagnostics.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                           vp, vp, vp, vp, vp]
     lib.pat_last_error.restype = ctypes.c_char_p
     lib.pat_version.restype = ctypes.c_char_p
     for f in EXPORTS:
@@ -335,7 +338,7 @@ def spectral_apply(problem: Problem, x, transpose: bool = False):
 
 
 def _rto_call(problem, y_obs, eta, xi, sigma, prior_a, n_iter, reorth, sweep_prec, rhs_block, stats, resid, samples,
-              solver, diag, n_samples, seed, sample0, prior="fe", latent=False):
+              solver, diag, n_samples, seed, sample0, prior="fe", latent=False, final=False):
     """Allocate outputs and fill RtoParams for one problem; returns (prm, S, outputs, pointers)."""
     import torch
     f64 = torch.float64
@@ -362,7 +365,8 @@ def _rto_call(problem, y_obs, eta, xi, sigma, prior_a, n_iter, reorth, sweep_pre
            "mean": torch.empty(N, dtype=f64, device=dev) if stats else None,
            "std": torch.empty(N, dtype=f64, device=dev) if stats and S >= 2 else None,
            "resid": torch.empty((S, n_iter + 1), dtype=f64, device=dev) if resid else None,
-           "diag": torch.empty((S, n_iter + 1, 2), dtype=f64, device=dev) if diag else None}
+           "diag": torch.empty((S, n_iter + 1, 2), dtype=f64, device=dev) if diag else None,
+           "final_resid": torch.empty(S, dtype=f64, device=dev) if final else None}
     prm = RtoParams()
     prm.solver = {"cgls": PAT_CGLS, "lsqr": PAT_LSQR}[solver]
     prm.diag_hist = out["diag"].data_ptr() if diag else None
@@ -376,6 +380,7 @@ def _rto_call(problem, y_obs, eta, xi, sigma, prior_a, n_iter, reorth, sweep_pre
     prm.sample0 = int(sample0)
     prm.prior = {"fe": PAT_PRIOR_FE, "spectral": PAT_PRIOR_SPECTRAL}[prior]
     prm.latent = out["latent"].data_ptr() if out["latent"] is not None else None
+    prm.final_resid = out["final_resid"].data_ptr() if final else None
     if eta is not None:
         prm.eta = _dev_ptr(eta, f64, (S, T, O), "eta")
         prm.xi = _dev_ptr(xi, f64, (S, NX), "xi")
@@ -388,20 +393,22 @@ def _rto_call(problem, y_obs, eta, xi, sigma, prior_a, n_iter, reorth, sweep_pre
 def rto_sample(problem: Problem, y_obs, eta, xi, sigma: float, prior_a: float, n_iter: int, reorth: bool = True,
                sweep_prec: str = "f64", rhs_block: int = 0, stats: bool = True, resid: bool = False,
                samples=None, solver: str = "cgls", diag: bool = False, n_samples: int = None, seed: int = 0,
-               sample0: int = 0, prior: str = "fe", latent: bool = False):
+               sample0: int = 0, prior: str = "fe", latent: bool = False, final: bool = False):
     """RTO posterior samples (Algorithm 1) through libpat's rto_sample.
 
     y_obs [N_T][N_obs], eta [S][N_T][N_obs], xi [S][N]: float64 CUDA tensors.
     With eta = xi = None the library draws them itself (streams seed,
     sample0 + k; see draw_normals) and n_samples gives S.
-    solver: "cgls" or "lsqr" (Sec. 5.2, App. A).
+    solver: "cgls" or "lsqr" (Sec. 5, Algorithm 1, App. A).
     prior: "fe" (the factor L with prior_a) or "spectral" (the Whittle-Matern prior set
     with spectral_prior_set; xi is then [S][n^3] and latent=True also returns the
     latent samples).
     Returns a dict with samples [S][N] and, if requested, mean, std [N],
-    resid [S][n_iter+1] and diag [S][n_iter+1][2] (data and prior residual norms)."""
+    resid [S][n_iter+1] and diag [S][n_iter+1][2] (data and prior residual norms), and
+    with final=True final_resid [S]: ||b - G_ext p|| of each sample recomputed with
+    float64 sweeps after the solve."""
     prm, S, out, ptr = _rto_call(problem, y_obs, eta, xi, sigma, prior_a, n_iter, reorth, sweep_prec, rhs_block, stats,
-                                 resid, samples, solver, diag, n_samples, seed, sample0, prior, latent)
+                                 resid, samples, solver, diag, n_samples, seed, sample0, prior, latent, final)
     _check(load().rto_sample(problem._h, ptr["y"], ctypes.byref(prm), S, ptr["samples"], ptr["mean"], ptr["std"],
                              ptr["resid"], _stream()))
     return out
@@ -451,7 +458,8 @@ class Batch:
 
 def rto_sample_batch(batch: Batch, y_obs, eta, xi, sigma, prior_a, n_iter: int, reorth: bool = True,
                      sweep_prec: str = "f32", rhs_block: int = 0, stats: bool = True, resid: bool = False,
-                     solver: str = "cgls", diag: bool = False, n_samples=None, seed=0, sample0=0, prior="fe"):
+                     solver: str = "cgls", diag: bool = False, n_samples=None, seed=0, sample0=0, prior="fe",
+                     final: bool = False):
     """rto_sample for every problem of the batch in one call (shared sweep launches).
 
     Per-problem lists: y_obs, eta, xi (entries None for device draws), sigma,
@@ -472,7 +480,7 @@ def rto_sample_batch(batch: Batch, y_obs, eta, xi, sigma, prior_a, n_iter: int, 
     for m, p in enumerate(batch.problems):
         prm, S[m], out, ptr = _rto_call(p, y_obs[m], eta[m], xi[m], sigma[m], prior_a[m], n_iter, reorth, sweep_prec,
                                         rhs_block, stats, resid, None, solver, diag, n_samples[m], seed[m], sample0[m],
-                                        prior[m])
+                                        prior[m], final=final)
         prms[m] = prm
         ys[m], smp[m] = ptr["y"].value, ptr["samples"].value
         mn[m] = ptr["mean"].value if ptr["mean"] is not None else None
@@ -484,26 +492,21 @@ def rto_sample_batch(batch: Batch, y_obs, eta, xi, sigma, prior_a, n_iter: int, 
 
 
 def solver_diagnostics(diag, n_data: int, tau: float = 1.0):
-    """Per-iteration convergence diagnostics of Sec. 6.1 from a diag history.
-
-    diag [S][n_iter+1][2] holds (||r_d||, ||r_p||) with r_d = b_d - G p / sigma (whitened
-    data residual) and r_p = b_p - L p.  Returns a dict of [S][n_iter+1] arrays:
-      data      ||r_d|| / sqrt(n_data)   (1 at the discrepancy level sigma sqrt(N_T N_obs))
-      prior     ||r_p|| / ||b||
-      extended  ||r|| / ||b||            (residual of the extended system)
-    and "discrepancy" [S]: the first iteration with ||r_d|| <= tau sqrt(n_data), or -1
-    (the discrepancy principle, Sec. 6.1).  Accepts a torch tensor or a numpy array."""
-    import numpy as np
-    d = diag.detach().cpu().numpy() if hasattr(diag, "detach") else np.asarray(diag, dtype=np.float64)
-    if d.ndim != 3 or d.shape[2] != 2:
+    """Per-iteration convergence diagnostics of Sec. 6.1 (pat_solver_diagnostics) from a diag
+    history [S][n_iter+1][2] of (||r_d||, ||r_p||) (float64 CUDA tensor).  Returns a dict of
+    [S][n_iter+1] tensors data (||r_d|| / sqrt(n_data)), prior (||r_p|| / ||b||), extended
+    (||r|| / ||b||) and "discrepancy" [S] int32: the first iteration with
+    ||r_d|| <= tau sqrt(n_data), or -1."""
+    import torch
+    if diag.ndim != 3 or diag.shape[2] != 2:
         raise ValueError("diag must have shape [S][n_iter+1][2]")
-    nd, npr = d[..., 0], d[..., 1]
-    ext = np.hypot(nd, npr)
-    b = ext[:, :1]
-    b = np.where(b > 0, b, 1.0)
-    hit = nd <= tau * np.sqrt(n_data)
-    first = np.where(hit.any(axis=1), hit.argmax(axis=1), -1)
-    return {"data": nd / np.sqrt(n_data), "prior": npr / b, "extended": ext / b, "discrepancy": first}
+    S, n1 = diag.shape[0], diag.shape[1]
+    dp = _dev_ptr(diag, torch.float64, (S, n1, 2), "diag")
+    out = {k: torch.empty((S, n1), dtype=torch.float64, device=diag.device) for k in ("data", "prior", "extended")}
+    out["discrepancy"] = torch.empty(S, dtype=torch.int32, device=diag.device)
+    ptr = [ctypes.c_void_p(out[k].data_ptr()) for k in ("data", "prior", "extended", "discrepancy")]
+    _check(load().pat_solver_diagnostics(dp, S, n1 - 1, int(n_data), float(tau), *ptr, _stream()))
+    return out
 
 
 def draw_normals(seed: int, kind: int, k0: int, S: int, length: int, device="cuda"):

@@ -8,6 +8,7 @@ confirm it regenerated the same inputs.
 
     python tests/golden/make_golden.py ball58_fp64       # 16 samples  (~40 min, 8 cores)
     python tests/golden/make_golden.py ball58_batched    # 64 samples  (~3 h, 8 cores)
+    python tests/golden/make_golden.py ball100_forward   # forward map on the 10^6-node ball (~2 min)
 """
 import json
 import os
@@ -61,6 +62,31 @@ def main(name):
     log(f"wrote {out}")
 
 
+# sensors whose traces the 10^6-node forward map stores: every 128th of the 1024
+BALL100_SENSORS = tuple(range(0, 1024, 128))
+
+
+def ball100_forward():
+    """Forward map Y = G p0 (Sec. 3 eq. (discrete-wave-matrix)) of the inclusion phantom on the
+    10^6-node ball, traces of BALL100_SENSORS over all 1000 steps."""
+    w = W.make_workload("ball100")
+    log(f"ball100: N={w.n_nodes} E={w.tets.shape[0]} N_T={w.n_steps} N_obs={w.n_obs} threads={oracle.num_threads()}")
+    P = oracle.Problem.from_workload(w)
+    t0 = time.time()
+    Y = P.forward(w.p0_true)
+    el = time.time() - t0
+    sens = np.array(BALL100_SENSORS)
+    out = os.path.join(HERE, "ball100_forward.npz")
+    np.savez_compressed(out, sensors=sens, traces=Y[:, sens], y_max=np.abs(Y).max(), y_norm=np.linalg.norm(Y),
+                        p0_sum=w.p0_true.sum(), p0_norm=np.linalg.norm(w.p0_true))
+    meta = {"workload": "ball100", "n_nodes": w.n_nodes, "n_steps": w.n_steps, "n_obs": w.n_obs,
+            "sensors": list(BALL100_SENSORS), "oracle_seconds": el, "oracle_threads": oracle.num_threads(),
+            "command": "python tests/golden/make_golden.py ball100_forward"}
+    with open(os.path.join(HERE, "ball100_forward.json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    log(f"wrote {out} (forward map {el:.1f} s)")
+
+
 if __name__ == "__main__":
     for n in sys.argv[1:]:
-        main(n)
+        ball100_forward() if n == "ball100_forward" else main(n)

@@ -1,6 +1,6 @@
 """GPU LSQR and residual diagnostics against the CPU FP64 oracle.
 
-LSQR (Paige-Saunders bidiagonalisation, the least-squares solver of Sec. 5.2)
+LSQR (Paige-Saunders bidiagonalisation, the least-squares solver of Sec. 5 and Algorithm 1)
 runs on the same sweeps and reductions as CGLS.  Checks:
   * float64 sweeps: samples, mean, std, the residual history and the split
     (data, prior) residual norms against the oracle's LSQR, 1e-10;
@@ -80,6 +80,28 @@ def test_cgls_diag_matches_oracle():
     assert _rel_max(dg, rdg) < 1e-10
     # the split norms recombine to the total residual
     np.testing.assert_allclose(np.hypot(dg[..., 0], dg[..., 1]), out["resid"].cpu().numpy(), rtol=1e-13)
+
+
+@pytest.mark.parametrize("tau", [2.0, 6.0, 1e-9])
+def test_solver_diagnostics_match_oracle(tau):
+    """pat_solver_diagnostics (Sec. 6.1 diagnostics and the discrepancy principle, on the device) of
+    the GPU's LSQR history against the oracle's diagnostics of the oracle's history (MAP solve,
+    eta = xi = 0, as in the paper's convergence study, plus perturbed samples)."""
+    w, O, G = _case("ball16")
+    yobs, sigma, eta, xi = _inputs(w, O, 4)
+    eta[0], xi[0] = 0.0, 0.0
+    _, _, rdg = O.rto(yobs, sigma, w.prior_a, 30, eta, xi, solver="lsqr", diag=True)
+    out = pat.rto_sample(G, _dev(yobs), _dev(eta), _dev(xi), sigma, w.prior_a, 30, solver="lsqr", diag=True)
+    M = w.n_steps * w.n_obs
+    got = pat.solver_diagnostics(out["diag"], M, tau=tau)
+    ref = oracle.diagnostics(rdg, M, tau=tau)
+    for k in ("data", "prior", "extended"):
+        assert _rel_max(got[k].cpu().numpy(), ref[k]) < 1e-10
+    np.testing.assert_array_equal(got["discrepancy"].cpu().numpy(), ref["discrepancy"])
+    if tau > 1.0:  # reached after a few iterations (the misfit starts near 100 on this mesh)
+        assert np.all(ref["discrepancy"] >= 1)
+    if tau == 1e-9:
+        assert np.all(ref["discrepancy"] == -1)
 
 
 def test_lsqr_equals_cgls_on_gpu():

@@ -139,7 +139,7 @@ def test_rto_f32_sweeps_match_oracle(name, S):
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
 def test_rto_iid_prior_matches_oracle(prec, tol):
-    """a = 0: the paper's independent prior with precision M_L, L = M_L^{1/2} (Sec. 3.3)."""
+    """a = 0: the paper's independent prior with precision M_L, L = M_L^{1/2} (Sec. 4.1.1 eq. (iid-prior))."""
     w, O, G = _case("ball16")
     yobs, sigma, eta, xi, n_iter = _rto_inputs(w, O, 12)
     ref, rres = O.rto(yobs, sigma, 0.0, n_iter, eta, xi)

@@ -170,14 +170,15 @@ def test_binding_structs_match_header(tmp_path):
 
 
 def test_solver_diagnostics_on_oracle_histories():
-    """Discrepancy principle on the whitened data residual of the MAP solve (eta = xi = 0)."""
+    """The oracle's diagnostics of Sec. 6.1: discrepancy principle on the whitened data residual of
+    the MAP solve (eta = xi = 0); the extended residual is the carried LSQR residual, normalised."""
     w = W.make_workload("cube8_tiny")
     O = oracle.Problem.from_workload(w)
     Y, yobs, sigma = oracle.synthesize(O, w)
     M = w.n_steps * w.n_obs
     zeros_d = np.zeros((1, w.n_steps, w.n_obs))
     x, res, dg = O.lsqr(yobs[None] / sigma + zeros_d, np.zeros((1, w.n_nodes)), sigma, w.prior_a, 30, diag=True)
-    out = pat.solver_diagnostics(dg, M)
+    out = oracle.diagnostics(dg, M)
     np.testing.assert_allclose(out["extended"][0], res[0] / res[0, 0], rtol=1e-14)
     assert out["extended"][0, 0] == 1.0 and out["prior"][0, 0] == 0.0
     # the LSQR residual of the extended system is non-increasing
@@ -185,7 +186,7 @@ def test_solver_diagnostics_on_oracle_histories():
     k = int(out["discrepancy"][0])
     assert k >= 1 and out["data"][0, k] <= 1.0 and np.all(out["data"][0, :k] > 1.0)
     # tau large enough: satisfied at iteration 0; tau tiny: never
-    assert pat.solver_diagnostics(dg, M, tau=1e9)["discrepancy"][0] == 0
-    assert pat.solver_diagnostics(dg, M, tau=1e-9)["discrepancy"][0] == -1
+    assert oracle.diagnostics(dg, M, tau=1e9)["discrepancy"][0] == 0
+    assert oracle.diagnostics(dg, M, tau=1e-9)["discrepancy"][0] == -1
     with pytest.raises(ValueError):
-        pat.solver_diagnostics(dg[..., 0], M)
+        oracle.diagnostics(dg[..., 0], M)

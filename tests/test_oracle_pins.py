@@ -336,6 +336,68 @@ def test_prior_factor_properties(tiny):
     np.testing.assert_allclose(P.prior_apply(x, 0.0), np.sqrt(m) * x, rtol=1e-15)
 
 
+def test_prior_factor_quadratic_on_kuhn_cube(cube8):
+    """L = M_L^{-1/2}(M_L + a K1) at a != 0 in closed form (reading of the prior (I - a Delta_FE)^2,
+    a -> 0 limit Sec. 4.1.1 eq. (iid-prior)).  On the Kuhn cube K1 is h times the 7-point stencil and
+    M_L = h^3 at interior nodes, so for u = |x|^2 the stencil gives K1 u = -6 h^3 there and
+    L u = h^{3/2} (u - 6 a): a wrong coefficient (a^2, 2a) or a dropped term moves every value.
+    Likewise L^T (h^{3/2} u) = h^3 (u - 6 a) at nodes whose whole stencil is interior."""
+    w, P = cube8
+    n, h, a = 8, 1.0 / 8, 0.01
+    idx = np.arange(n + 1)
+    ii, jj, kk = np.meshgrid(idx, idx, idx, indexing="ij")
+    node = (ii + (n + 1) * (jj + (n + 1) * kk)).ravel()
+    xyz = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1) * h
+    np.testing.assert_allclose(w.coords[node], xyz, atol=1e-15)   # lexicographic node numbering
+    u = np.sum(w.coords ** 2, axis=1)
+    inner = lambda lo, hi: node[((ii >= lo) & (ii <= hi) & (jj >= lo) & (jj <= hi) & (kk >= lo) & (kk <= hi)).ravel()]
+    interior, deep = inner(1, n - 1), inner(2, n - 2)
+    for aa in (a, 0.05):
+        Lu = P.prior_apply(u, aa)
+        np.testing.assert_allclose(Lu[interior], h ** 1.5 * (u[interior] - 6 * aa), rtol=1e-13, atol=1e-16)
+        Ltu = P.prior_apply(h ** 1.5 * u, aa, transpose=True)
+        np.testing.assert_allclose(Ltu[deep], h ** 3 * (u[deep] - 6 * aa), rtol=1e-13, atol=1e-17)
+    # power of the check: the a-term is not small against the rounding bar
+    assert np.abs(6 * a / u[interior]).min() > 1e-3
+
+
+def test_prior_factor_uses_unit_coefficient_stiffness():
+    """On a variable-speed ball, L (g . x) = M_L^{1/2} (g . x) at every interior node: the
+    unit-coefficient stiffness annihilates linear functions there (sum over the support of
+    vol_e grad(phi_i) is zero for an interior node), while the c^2-weighted K does not where c
+    varies.  So a K-for-K1 swap fails here, which L 1 = M_L^{1/2} 1 cannot detect."""
+    P, coords, tets, c = _tiny_ball(n=8, variable_c=True)
+    m = P.lumped_mass()
+    bnd = np.unique(_faces_numpy(tets))
+    interior = np.setdiff1d(np.arange(P.n_nodes), bnd)
+    g = np.array([0.3, -1.1, 0.7])
+    u = coords @ g + 0.25
+    for a in (0.01, 0.2):
+        Lu = P.prior_apply(u, a)
+        np.testing.assert_allclose(Lu[interior], np.sqrt(m[interior]) * u[interior], rtol=1e-12, atol=1e-14)
+        # the alternative with K in place of K1 would miss by a clear margin
+        Ku = P.matrix("K") @ u
+        alt = (m * u + a * Ku) / np.sqrt(m)
+        assert np.abs(alt[interior] - np.sqrt(m[interior]) * u[interior]).max() > 1e3 * 1e-12 * np.abs(Lu).max()
+    assert np.ptp(c) > 0.05
+
+
+def test_prior_factor_equals_assembled_matrices(tiny):
+    """L x and L^T y equal (M_L x + a K1 x)/sqrt(M_L) and (M_L + a K1)(y/sqrt(M_L)) written with the
+    assembled K1 (pinned by the stencil and identity tests) and the lumped masses."""
+    P = tiny[0]
+    N = P.n_nodes
+    m = P.lumped_mass()
+    K1 = P.matrix("K1")
+    x = np.random.default_rng(9).standard_normal(N)
+    for a in (0.01, 0.3):
+        np.testing.assert_allclose(P.prior_apply(x, a), (m * x + a * (K1 @ x)) / np.sqrt(m), rtol=1e-12,
+                                   atol=1e-14)
+        t = x / np.sqrt(m)
+        np.testing.assert_allclose(P.prior_apply(x, a, transpose=True), m * t + a * (K1 @ t), rtol=1e-12,
+                                   atol=1e-14)
+
+
 @pytest.mark.parametrize("reorth", [True, False])
 def test_cgls_iterates_are_krylov_minimisers(tiny, reorth):
     P = tiny[0]
@@ -375,11 +437,53 @@ def test_cgls_converges_to_least_squares(tiny):
         assert np.linalg.norm(x[r] - xs) < 1e-8 * np.linalg.norm(xs)
 
 
+def test_float32_sweeps_round_like_float32(tiny):
+    """The float32-state emulation of the sweeps (used only to measure the rounding floor of a
+    float32 implementation) agrees with the float64 maps to the accumulated float32 rounding
+    (between 1e-9 and 1e-5 relative over 20 steps), and keeps the transpose identity to that level."""
+    P = tiny[0]
+    rng = np.random.default_rng(13)
+    p = rng.standard_normal((2, P.n_nodes))
+    yh = rng.standard_normal((2, P.n_steps, P.n_obs))
+    y, y32 = P.forward(p), P.forward_f32(p)
+    a, a32 = P.adjoint(yh), P.adjoint_f32(yh)
+    for ref, got in ((y, y32), (a, a32)):
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert 1e-9 < e < 1e-5
+    lhs, rhs = np.sum(y32 * yh, axis=(1, 2)), np.sum(p * a32, axis=1)
+    scale = np.linalg.norm(y32, axis=(1, 2)) * np.linalg.norm(yh, axis=(1, 2)) + \
+        np.linalg.norm(p, axis=1) * np.linalg.norm(a32, axis=1)
+    assert np.all(np.abs(lhs - rhs) < 1e-5 * scale)
+
+
+def test_extended_residual_matches_least_squares(tiny):
+    """The oracle's ||G_ext p - b|| of given samples (Sec. 5 eq. (lsqr-residual)) equals, at the
+    least-squares solution, the residual numpy's lstsq reports, and at a fixed CGLS iterate the
+    residual norm CGLS carries (itself pinned against the dense b - G_ext x above)."""
+    P = tiny[0]
+    sigma, a = 0.05, 0.02
+    G, L, A = _gext_dense(P, sigma, a)
+    N = P.n_nodes
+    rng = np.random.default_rng(12)
+    yobs = (G @ rng.standard_normal(N) + sigma * rng.standard_normal(G.shape[0])).reshape(P.n_steps, P.n_obs)
+    S = 2
+    eta = rng.standard_normal((S, P.n_steps, P.n_obs))
+    xi = rng.standard_normal((S, N))
+    for s in range(S):
+        b = np.concatenate([yobs.ravel() / sigma + eta[s].ravel(), xi[s]])
+        xs, rss, *_ = np.linalg.lstsq(A, b, rcond=None)
+        got = P.extended_residual(xs[None], yobs, sigma, a, eta[s:s + 1], xi[s:s + 1])[0]
+        assert abs(got - np.sqrt(rss[0])) < 1e-10 * np.linalg.norm(b)
+    samples, res = P.rto(yobs, sigma, a, 7, eta, xi)
+    got = P.extended_residual(samples, yobs, sigma, a, eta, xi)
+    np.testing.assert_allclose(got, res[:, -1], rtol=1e-10)
+
+
 @pytest.mark.parametrize("a", [0.02, 0.0])
 def test_rto_sample_is_closed_form(tiny, a):
     """Converged RTO sample = C_post [G^T y / sigma^2 + G^T eta / sigma + Q p_prior] (App. A), with the
     prior precision Q = L^T L.  At a = 0 the prior is the paper's independent one, precision M_L
-    (Sec. 3.3, eq. iid-prior), written here from the lumped masses alone, and p_prior = M_L^{-1/2} xi."""
+    (Sec. 4.1.1 eq. (iid-prior)), written here from the lumped masses alone, and p_prior = M_L^{-1/2} xi."""
     P = tiny[0]
     sigma = 0.05
     G, L, _ = _gext_dense(P, sigma, a)

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import workloads as W
-from oracle.spectral import SpectralPrior, latent_rto
+from oracle.spectral import SpectralPrior, latent_residual, latent_rto
 
 
 @pytest.mark.parametrize("expo,shape", [(3.0, lambda x: (1 + x) * np.exp(-x)),
@@ -105,9 +105,16 @@ def test_latent_rto_krylov_and_converged():
             ref = Qk @ y
             assert np.linalg.norm(lat[r] - ref) < 1e-8 * np.linalg.norm(ref)
             assert abs(res[r, -1] - np.linalg.norm(b[r] - A @ lat[r])) < 1e-10 * np.linalg.norm(b[r])
+    # the recomputed residual of given latent samples equals the dense one
+    p0, lat, res = latent_rto(O, pr, I, yobs, sigma, 4, eta, xi)
+    got = latent_residual(O, pr, I, lat, yobs, sigma, eta, xi)
+    for r in range(2):
+        assert abs(got[r] - np.linalg.norm(b[r] - A @ lat[r])) < 1e-12 * np.linalg.norm(b[r])
     # converged
     p0, lat, res = latent_rto(O, pr, I, yobs, sigma, n, eta, xi)
     for r in range(2):
-        ref, *_ = np.linalg.lstsq(A, b[r], rcond=None)
+        ref, rss, *_ = np.linalg.lstsq(A, b[r], rcond=None)
         assert np.linalg.norm(lat[r] - ref) < 1e-9 * np.linalg.norm(ref)
+        assert abs(latent_residual(O, pr, I, ref, yobs, sigma, eta[r], xi[r])[0] - np.sqrt(rss[0])) \
+            < 1e-10 * np.linalg.norm(b[r])
         np.testing.assert_allclose(p0[r], P @ lat[r], rtol=0, atol=1e-10 * np.abs(p0[r]).max())

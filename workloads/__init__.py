@@ -71,11 +71,14 @@ def _kuhn_cells(nx: int, ny: int, nz: int, mirror_centre: bool) -> np.ndarray:
 
 def _orient_positive(coords: np.ndarray, tets: np.ndarray) -> np.ndarray:
     """Reorder vertices so that every tetrahedron has positive orientation."""
-    x0 = coords[tets[:, 0]]
-    d1, d2, d3 = coords[tets[:, 1]] - x0, coords[tets[:, 2]] - x0, coords[tets[:, 3]] - x0
-    det = np.einsum("ij,ij->i", d1, np.cross(d2, d3))
+    neg = np.empty(tets.shape[0], dtype=bool)
+    for a in range(0, tets.shape[0], 1 << 20):  # in chunks: whole-mesh temporaries are slow at 10^6 nodes
+        t = tets[a:a + (1 << 20)]
+        x0 = coords[t[:, 0]]
+        d1, d2, d3 = coords[t[:, 1]] - x0, coords[t[:, 2]] - x0, coords[t[:, 3]] - x0
+        det = np.einsum("ij,ij->i", d1, np.cross(d2, d3))
+        neg[a:a + t.shape[0]] = det < 0
     tets = tets.copy()
-    neg = det < 0
     tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
     return tets
 
