@@ -96,6 +96,21 @@ pat_status pat_problem_get_info(const pat_problem *p, pat_problem_info *out);
  *   p0 device [R][N], y device [R][N_T][N_obs]; both of type `prec`. */
 pat_status pat_forward(pat_problem *p, int64_t R, const void *p0, void *y, pat_precision prec, void *stream);
 
+/* pat_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * layouts and result as pat_forward; the device work is launched directly on
+ * `stream` (no graph of its own, so a caller may capture it), and the sweep state
+ * and data staging live in a fixed device scratch array of 64 MiB per device
+ * (held from the library's first use on a device until the process ends).  No
+ * hipMalloc, hipFree or other allocating call is made.  Right-hand sides run in
+ * blocks of the largest power of two <= pat_forward's block whose state and
+ * staging, (4 N + N_T N_obs) x block x element size, fit the scratch; a problem
+ * for which one right-hand side does not fit is PAT_ERR_INVALID_ARG.  All calls
+ * on one device share its scratch: calls that overlap in time on one device (on
+ * different streams or threads) race and give undefined results.  Nothing in the
+ * scratch needs to start at zero: each block overwrites what it reads. */
+pat_status pat_forward_noalloc(pat_problem *p, int64_t R, const void *p0, void *y, pat_precision prec, void *stream);
+
 /* Transpose map p = G^T yhat of Sec. 5.1 eqs. (transpose-definition),
  * (backward-recursion) and (adjoint-verlet): exact transpose of pat_forward in
  * exact arithmetic.  yhat device [R][N_T][N_obs], p device [R][N]; type `prec`. */

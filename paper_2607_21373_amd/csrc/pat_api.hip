@@ -14,6 +14,7 @@
 #include <initializer_list>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -89,6 +90,38 @@ pat_status check_block(int64_t n, pat::Prec pr, int rb) {
     if (block_fits(n, pr, rb)) return PAT_OK;
     return fail(PAT_ERR_INVALID_ARG, "RHS block of " + std::to_string(rb) + " too large for a mesh of " +
                                          std::to_string(n) + " nodes: one block's state must stay below 4 GiB");
+}
+
+}  // namespace
+
+// Device scratch of pat_forward_noalloc, for callers that cannot allocate: one RHS
+// block's sweep state (P, V ping-pong) and its data staging.  Each device holds its
+// own copy from the library's first use on it until the process ends.  Host code
+// never passes `scratch` itself to a kernel (on the host it only names the
+// symbol): pat_problem_create looks up each device's copy with
+// hipGetSymbolAddress and the entry point uses that address.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};  // device ordinal -> address of its copy of `scratch`
+
+// Look up the current device's copy of `scratch` once (the device must be current).
+pat_status scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(PAT_ERR_INVALID_ARG, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return PAT_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(PAT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+    return PAT_OK;
 }
 
 }  // namespace
@@ -1007,6 +1040,7 @@ pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out) {
     DeviceGuard guard(dev);
     if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
 
+    PAT_TRY(scratch_init(dev));
     auto p = std::make_unique<pat_problem>();
     p->device = dev;
     pat::DevOps &op = p->ops;
@@ -1132,6 +1166,47 @@ pat_status pat_forward(pat_problem *p, int64_t R, const void *p0, void *y, pat_p
         pat::launch_pack(f64, f64, p0, R, rb0, RB, p->ops.n, perm, w->P[0], s);
         PAT_HIP(hipGraphLaunch(w->g_fwd_user, s));
         pat::launch_unpack(f64, f64, w->Y, R, rb0, RB, M, nullptr, y, s);
+    }
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
+pat_status pat_forward_noalloc(pat_problem *p, int64_t R, const void *p0, void *y, pat_precision prec,
+                               void *stream) {
+    g_err.clear();
+    if (!p || !p0 || !y || R < 1) return fail(PAT_ERR_INVALID_ARG, "pat_forward_noalloc: NULL pointer or R < 1");
+    pat::Prec pr;
+    PAT_TRY(check_prec(prec, &pr));
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(PAT_ERR_HIP, "cannot select the device");
+    char *base = static_cast<char *>(p->device < kMaxDevices ? g_scratch_ptr[p->device] : nullptr);
+    if (!base) return fail(PAT_ERR_INTERNAL, "pat_forward_noalloc: no scratch address for the device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = int64_t(p->ops.n_steps) * p->ops.n_obs;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    // the block of pat_forward, halved until four state vectors and the staging fit the scratch
+    auto need = [&](int rb) { return 4 * up(size_t(p->ops.n) * rb * tsize(pr)) + up(size_t(M) * rb * tsize(pr)); };
+    int RB = fit_rb(p->ops.n, pr, choose_rb(R));
+    while (RB > 1 && need(RB) > kScratchBytes) RB >>= 1;
+    if (need(RB) > kScratchBytes)
+        return fail(PAT_ERR_INVALID_ARG, "pat_forward_noalloc: one right-hand side needs " + std::to_string(need(1)) +
+                                             " bytes of scratch, more than its " + std::to_string(kScratchBytes));
+    PAT_TRY(check_block(p->ops.n, pr, RB));
+    SweepWS w;  // a view of the scratch: nothing is allocated
+    w.prec = pr;
+    w.RB = RB;
+    const size_t nb = up(size_t(p->ops.n) * RB * tsize(pr));
+    w.P[0] = base;
+    w.P[1] = base + nb;
+    w.V[0] = base + 2 * nb;
+    w.V[1] = base + 3 * nb;
+    w.Y = base + 4 * nb;
+    const bool f64 = pr == pat::Prec::F64;
+    const int32_t *perm = p->perm_identity ? nullptr : p->ops.perm;
+    for (int64_t rb0 = 0; rb0 < R; rb0 += RB) {
+        pat::launch_pack(f64, f64, p0, R, rb0, RB, p->ops.n, perm, w.P[0], s);
+        enqueue_forward(p, w, w.Y, false, 1.0, s);
+        pat::launch_unpack(f64, f64, w.Y, R, rb0, RB, M, nullptr, y, s);
     }
     PAT_HIP(hipGetLastError());
     return PAT_OK;

@@ -82,7 +82,8 @@ class SpectralDesc(ctypes.Structure):
 
 
 # names exported by libpat (the C ABI in include/pat.h)
-EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_adjoint",
+EXPORTS = ("pat_problem_create", "pat_problem_destroy", "pat_problem_get_info", "pat_forward", "pat_forward_noalloc",
+           "pat_adjoint",
            "rto_sample", "pat_prior_apply", "pat_draw_normals", "pat_spectral_prior_set", "pat_spectral_apply",
            "pat_autotune", "pat_batch_create", "pat_batch_destroy", "pat_batch_autotune", "pat_batch_merge",
            "rto_sample_batch", "pat_solver_diagnostics", "pat_host_assemble", "pat_profile_enable",
@@ -106,6 +107,7 @@ def load() -> ctypes.CDLL:
     lib.pat_problem_destroy.argtypes = [vp]
     lib.pat_problem_get_info.argtypes = [vp, ctypes.POINTER(ProblemInfo)]
     lib.pat_forward.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
+    lib.pat_forward_noalloc.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
     lib.pat_adjoint.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
     lib.rto_sample.argtypes = [vp, vp, ctypes.POINTER(RtoParams), ctypes.c_int64, vp, vp, vp, vp, vp]
     lib.pat_sync.argtypes = [vp]
@@ -281,6 +283,16 @@ def pat_forward(problem: Problem, p0, y=None):
     pp = _dev_ptr(p0, p0.dtype, (R, problem.n_nodes), "p0")
     yp = _dev_ptr(y, p0.dtype, (R, problem.n_steps, problem.n_obs), "y")
     _check(load().pat_forward(problem._h, R, pp, yp, _prec(p0.dtype), _stream()))
+    return y
+
+
+def pat_forward_noalloc(problem: Problem, p0, y):
+    """pat_forward_noalloc: Y = G p0 into the caller's y [R][N_T][N_obs] with the library's
+    fixed device scratch (no device allocation by the library)."""
+    R = p0.shape[0]
+    pp = _dev_ptr(p0, p0.dtype, (R, problem.n_nodes), "p0")
+    yp = _dev_ptr(y, p0.dtype, (R, problem.n_steps, problem.n_obs), "y")
+    _check(load().pat_forward_noalloc(problem._h, R, pp, yp, _prec(p0.dtype), _stream()))
     return y
 
 
