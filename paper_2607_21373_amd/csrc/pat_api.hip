@@ -154,6 +154,7 @@ struct CglsWS {
     double *x = nullptr, *d = nullptr, *s = nullptr, *rp = nullptr, *qp = nullptr;
     double *rd = nullptr, *qd = nullptr, *Q = nullptr;
     double *part = nullptr, *mpart = nullptr, *coef = nullptr, *scal = nullptr;
+    double *cg = nullptr, *gram = nullptr;  // reorthogonalisation: coefficients and Gram row, Gram matrix
     // LSQR: right vector v; z = G_ext w and the residual r = b - G_ext x, kept only for the histories
     double *v = nullptr, *zp = nullptr, *zd = nullptr, *lrp = nullptr, *lrd = nullptr;
 };
@@ -382,11 +383,12 @@ pat_status get_cgls(pat_problem *p, int RB, int64_t NX, int n_iter, bool reorth,
     if (lsqr && track && !c.zd) PAT_TRY(alloc_group({{&c.zp, nb}, {&c.lrp, nb}, {&c.lrd, mb}, {&c.zd, mb}}));
     const int need = reorth ? n_iter + 1 : 0;
     if (need > c.cap_iter) {
-        dev_free(p, c.Q); dev_free(p, c.mpart); dev_free(p, c.coef);
-        c.Q = c.mpart = c.coef = nullptr;
+        dev_free(p, c.Q); dev_free(p, c.mpart); dev_free(p, c.coef); dev_free(p, c.cg); dev_free(p, c.gram);
+        c.Q = c.mpart = c.coef = c.cg = c.gram = nullptr;
         c.cap_iter = 0;
-        PAT_TRY(alloc_group({{&c.Q, size_t(need) * nb}, {&c.mpart, size_t(need) * pat::kMultiBlocks * RB * 8},
-                             {&c.coef, size_t(need) * RB * 8}}));
+        PAT_TRY(alloc_group({{&c.Q, size_t(need) * nb}, {&c.mpart, size_t(2 * need) * pat::kMultiBlocks * RB * 8},
+                             {&c.coef, size_t(need) * RB * 8}, {&c.cg, size_t(2 * need) * RB * 8},
+                             {&c.gram, size_t(need) * need * RB * 8}}));
         c.cap_iter = need;
     }
     *out = &c;
@@ -681,13 +683,17 @@ void record(Solve &v, const double *rd, const double *rp, int it) {
     pat::launch_resid(t1, t2, v.resid_hist, v.diag_hist, v.ld, it, v.rb0, v.S, v.RB, v.s);
 }
 
-// s -= sum_j (Q_j . s) Q_j over j < k, classical Gram-Schmidt applied twice.
+// s -= Q coef over the basis Q_j, j < k: classical Gram-Schmidt applied twice, in the
+// form that reads the basis twice instead of four times.  The first pass's
+// coefficients c1 = Q^T s and the newest basis vector's row of the Gram matrix
+// Q^T Q come from one read of Q; the second pass's coefficients follow from them,
+// c2 = Q^T (s - Q c1) = c1 - (Q^T Q) c1; one projection s -= Q (c1 + c2) ends it.
+// Equal to the two passes in exact arithmetic.
 void reorthogonalise(Solve &v, int k) {
     if (!v.reorth || k <= 0) return;
-    for (int pass = 0; pass < 2; ++pass) {
-        pat::launch_multidot(v.c->Q, v.c->s, k, v.NX, v.RB, v.c->mpart, v.c->coef, v.s);
-        pat::launch_project(v.c->Q, v.c->s, v.c->coef, k, v.NX, v.RB, v.s);
-    }
+    pat::launch_reorth_coef(v.c->Q, v.c->s, k, v.NX, v.RB, v.c->mpart, v.c->cg, v.c->gram, v.c->cap_iter, v.c->coef,
+                            v.s);
+    pat::launch_project(v.c->Q, v.c->s, v.c->coef, k, v.NX, v.RB, v.s);
 }
 
 // s = G^T rd / sigma + L^T up (spectral prior: P^T G^T rd / sigma + up), from the transpose sweep's result.
@@ -1522,7 +1528,7 @@ pat_status pat_spectral_prior_set(pat_problem *p, const pat_spectral_desc *d) {
     for (auto it = p->cgls.begin(); it != p->cgls.end();) {  // latent-space solver workspaces
         if (it->first.second != p->ops.n) {
             CglsWS &c = it->second;
-            double *bufs[] = {c.x, c.d, c.s, c.rp, c.qp, c.rd, c.qd, c.Q, c.part, c.mpart, c.coef, c.scal,
+            double *bufs[] = {c.x, c.d, c.s, c.rp, c.qp, c.rd, c.qd, c.Q, c.part, c.mpart, c.coef, c.scal, c.cg, c.gram,
                               c.v, c.zp, c.zd, c.lrp, c.lrd};
             for (double *q : bufs) dev_free(p, q);
             it = p->cgls.erase(it);

@@ -145,13 +145,16 @@ void launch_axpy_neg(double *y, const double *x, const double *alpha, int64_t ro
 // Q[k] = s * invn ; d = s + beta d
 void launch_append_dir(const double *sv, double *Qk, double *d, const double *invn, const double *beta, int first,
                        int64_t rows, int RB, hipStream_t s);
-// reorthogonalisation: coef[j][r] = sum_i Q[j][i][r] s[i][r] (j < k); s -= sum_j coef[j] Q[j].
-// The multi-dot streams k basis vectors per call and needs more workgroups than the
-// plain dots (4 per CU); part holds kMultiBlocks x k x RB partial sums.
+// reorthogonalisation: s -= sum_j coef[j] Q[j] (j < k), coef from launch_reorth_coef.  The
+// multi-dot streams k basis vectors per call and needs more workgroups than the plain dots
+// (4 per CU); its partial sums take kMultiBlocks x 2k x RB doubles.
 constexpr int kMultiBlocks = 1024;
-void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *coef,
-                     hipStream_t s);
 void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s);
+// Both Gram-Schmidt passes' coefficients from one read of the basis Q[0..k-1] (Q[k-1] the
+// newest): c1 = Q^T s and the Gram row Q^T Q[k-1] (part: kMultiBlocks x 2k x RB, cg: 2k x RB),
+// the row stored into gram [kcap][kcap][RB], then coef = c1 + (c1 - gram c1) (k x RB).
+void launch_reorth_coef(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *cg,
+                        double *gram, int kcap, double *coef, hipStream_t s);
 // LSQR scalar recurrences (device arrays of length RB each).
 struct LsqrScalars {
     double *alpha, *beta, *alpha1, *beta1, *rhob, *phib, *cs, *sn, *rho, *zfac, *step, *inv;

@@ -299,10 +299,25 @@ constexpr int vwaves() {
 }
 #define PAT_VOCC(T, RB) __attribute__((amdgpu_waves_per_eu(vwaves<T, RB, TileOps<T, RB>>())))
 
-template <typename VT, typename T>
+// Stores of the new state and loads of a row's own state (each touched once per
+// step).  When the step's state exceeds the Infinity Cache (`stream`), they are
+// non-temporal: caching them would only evict the neighbour rows that the gathers
+// of later rows reuse, and the next step cannot find them in cache anyway.
+// (A template parameter, not a run-time flag: the compiler merges two otherwise equal
+// stores and drops the non-temporal hint.)
+template <bool NT, typename VT, typename T>
 __device__ __forceinline__ void vstore(T *p, VT v) {
-    *reinterpret_cast<VT *>(p) = v;
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<VT *>(p));
+    else *reinterpret_cast<VT *>(p) = v;
 }
+template <bool NT, typename VT, typename T>
+__device__ __forceinline__ VT vload_own(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const VT *>(p));
+    else return *reinterpret_cast<const VT *>(p);
+}
+
+// Infinity Cache (memory-side last-level cache) of the MI355X
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 
 template <typename T, int RB>
 struct VGeo {
@@ -437,13 +452,31 @@ struct VFwdArgs {
     void *y;
     double yscale;
     int n, n_obs, n_tiles, n_samp, first, sample, t;
+    int stream;  // state beyond the Infinity Cache: launch the non-temporal variant
     T dt, half_dt;
 };
+
+// Sampling block j of a forward step: y^n = Pi (P - dt/2 V) of the incoming state,
+// one lane per (sensor, rhs).
+template <typename T, typename OT, int RB>
+__device__ __forceinline__ void fwd_sample(const VFwdArgs<T> &a, int j) {
+    const int64_t e = int64_t(j) * 256 + threadIdx.x;
+    if (e >= int64_t(a.n_obs) * RB) return;
+    const int s = int(e / RB), r = int(e % RB);
+    T y = T(0);
+    for (int k = 0; k < 4; ++k) {
+        const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
+        const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
+        y = mad(a.sw[4 * s + k], pk, y);
+    }
+    OT *yo = static_cast<OT *>(a.y);
+    yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
+}
 
 // Forward step (same update as k_fwd) with vector lanes on logical tile `tile`;
 // the tiles after the row tiles write the samples y^n = Pi (P - dt/2 V) of the
 // incoming state.
-template <typename T, typename OT, int RB>
+template <typename T, typename OT, int RB, bool NT>
 __device__ __forceinline__ void fwd_tile(const VFwdArgs<T> &a, int tile, TileOps<T, RB> &L) {
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
@@ -456,7 +489,7 @@ __device__ __forceinline__ void fwd_tile(const VFwdArgs<T> &a, int tile, TileOps
         if (row < a.n) {
             const int64_t id = int64_t(row) * RB + q * G::VEC;
             VT v0 = {};
-            if (!a.first) v0 = *reinterpret_cast<const VT *>(a.V + id);
+            if (!a.first) v0 = vload_own<NT, VT>(a.V + id);
             VT acc = {}, bacc = {}, p0;
             vrow_sums<T, RB>(a.o, L, lr, q, a.P, a.V, !a.first && L.bo[lr] >= 0, acc, bacc, p0);
             const T dm = L.dm[lr];
@@ -466,29 +499,18 @@ __device__ __forceinline__ void fwd_tile(const VFwdArgs<T> &a, int tile, TileOps
                 v[i] = v0[i] - dm * (acc[i] + bacc[i]);
                 pn[i] = p0[i] + a.dt * v[i];
             }
-            vstore<VT>(a.Vn + id, v);
-            vstore<VT>(a.Pn + id, pn);
+            vstore<NT, VT>(a.Vn + id, v);
+            vstore<NT, VT>(a.Pn + id, pn);
         }
     } else if (a.sample) {
-        // one lane per (sensor, rhs)
-        const int64_t e = int64_t(tile - a.n_tiles) * 256 + threadIdx.x;
-        if (e >= int64_t(a.n_obs) * RB) return;
-        const int s = int(e / RB), r = int(e % RB);
-        T y = T(0);
-        for (int k = 0; k < 4; ++k) {
-            const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
-            const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
-            y = mad(a.sw[4 * s + k], pk, y);
-        }
-        OT *yo = static_cast<OT *>(a.y);
-        yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
+        fwd_sample<T, OT, RB>(a, tile - a.n_tiles);
     }
 }
 
-template <typename T, typename OT, int RB>
+template <typename T, typename OT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_v(const VFwdArgs<T> a) {
     __shared__ TileOps<T, RB> L;
-    fwd_tile<T, OT, RB>(a, fwd_work(xcd_tile(blockIdx.x, gridDim.x), a.n_tiles, a.n_samp), L);
+    fwd_tile<T, OT, RB, NT>(a, fwd_work(xcd_tile(blockIdx.x, gridDim.x), a.n_tiles, a.n_samp), L);
 }
 
 // Several meshes in one launch; mesh m has tiles[m] logical tiles.  Every XCD
@@ -527,12 +549,12 @@ inline int multi_grid(const int *tiles, int n) {
     return 8 * c;
 }
 
-template <typename T, typename OT, int RB>
+template <typename T, typename OT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_vm(const Multi<VFwdArgs<T>> mm) {
     __shared__ TileOps<T, RB> L;
     int m, local;
     if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
-    fwd_tile<T, OT, RB>(mm.a[m], fwd_work(local, mm.a[m].n_tiles, mm.a[m].n_samp), L);
+    fwd_tile<T, OT, RB, NT>(mm.a[m], fwd_work(local, mm.a[m].n_tiles, mm.a[m].n_samp), L);
 }
 
 template <typename T>
@@ -546,11 +568,12 @@ struct VAdjArgs {
     const void *yh;
     double yscale;
     int n, n_obs, n_tiles, last, tm1;
+    int stream;  // state beyond the Infinity Cache: launch the non-temporal variant
     T dt;
 };
 
 // Transposed step (same update as k_adj) with vector lanes on logical tile `tile`.
-template <typename T, typename YT, int RB>
+template <typename T, typename YT, int RB, bool NT>
 __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps<T, RB> &L) {
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
@@ -563,7 +586,7 @@ __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps
     const int row = row0 + lr;
     if (row >= a.n) return;
     const int64_t id = int64_t(row) * RB + q * G::VEC;
-    const VT ph0 = *reinterpret_cast<const VT *>(a.PH + id);
+    const VT ph0 = vload_own<NT, VT>(a.PH + id);
     VT kq = {}, bq = {}, q0;
     vrow_sums<T, RB>(a.o, L, lr, q, a.Q, a.Q, !a.last && L.bo[lr] >= 0, kq, bq, q0);
     VT ph;
@@ -587,23 +610,23 @@ __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps
             qn[i] = q0[i] - dm * bq[i] + dm * (ph[i] + T(0.5) * inj[i]);
             ph[i] += inj[i];
         }
-        vstore<VT>(a.Qn + id, qn);
+        vstore<NT, VT>(a.Qn + id, qn);
     }
-    vstore<VT>(a.PH + id, ph);
+    vstore<NT, VT>(a.PH + id, ph);
 }
 
-template <typename T, typename YT, int RB>
+template <typename T, typename YT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_v(const VAdjArgs<T> a) {
     __shared__ TileOps<T, RB> L;
-    adj_tile<T, YT, RB>(a, xcd_tile(blockIdx.x, gridDim.x), L);
+    adj_tile<T, YT, RB, NT>(a, xcd_tile(blockIdx.x, gridDim.x), L);
 }
 
-template <typename T, typename YT, int RB>
+template <typename T, typename YT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdjArgs<T>> mm) {
     __shared__ TileOps<T, RB> L;
     int m, local;
     if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
-    adj_tile<T, YT, RB>(mm.a[m], local, L);
+    adj_tile<T, YT, RB, NT>(mm.a[m], local, L);
 }
 
 // p_hat = Pi^T yhat^{N_T}, q = (dt/2m) p_hat
@@ -961,7 +984,6 @@ __global__ void k_append(const double *sv, double *Qk, double *d, const double *
     }
 }
 
-// part[b][j][r] = sum over rows of block b of Q[j][row][r] * s[row][r], j in [j0, j0+8) and < k
 // ---- LSQR (Golub-Kahan bidiagonalisation) ---------------------------------
 // Per-RHS scalar stages; one thread per right-hand side.  A new alpha or beta
 // below 1e-15 of its first value is exact breakdown and is set to zero.
@@ -1031,33 +1053,64 @@ __global__ void k_lsqr_vw(const double *sv, const double *inv, const double *zfa
     }
 }
 
-__global__ void __launch_bounds__(256) k_multidot_partial(const double *Q, const double *sv, int k, int64_t rows,
-                                                          int RB, double *part) {
+// part[b][j][r] = sum over the rows of block b of Q[j][row][r] s[row][r] for j < k, and
+// part[b][k + j][r] the same with the newest basis vector Q[k-1] in place of s: the
+// first Gram-Schmidt coefficients and the new row of the Gram matrix in one read of Q.
+__global__ void __launch_bounds__(256) k_multidot2_partial(const double *Q, const double *sv, int k, int64_t rows,
+                                                           int RB, double *part) {
     __shared__ double red[256];
     const int G = 256 / RB;
     const int r = threadIdx.x % RB, g = threadIdx.x / RB;
     const int64_t chunk = (rows + gridDim.x - 1) / gridDim.x;
     const int64_t a0 = int64_t(blockIdx.x) * chunk, a1 = a0 + chunk < rows ? a0 + chunk : rows;
     const int64_t stride = rows * RB;
+    const double *w = Q + int64_t(k - 1) * stride;
     for (int j0 = 0; j0 < k; j0 += 8) {
-        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gac[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int64_t row = a0 + g; row < a1; row += G) {
             const int64_t e = row * RB + r;
-            const double s = sv[e];
+            const double s = sv[e], q = w[e];
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj)
-                if (j0 + jj < k) acc[jj] = __builtin_fma(Q[int64_t(j0 + jj) * stride + e], s, acc[jj]);
+                if (j0 + jj < k) {
+                    const double qj = Q[int64_t(j0 + jj) * stride + e];
+                    acc[jj] = __builtin_fma(qj, s, acc[jj]);
+                    gac[jj] = __builtin_fma(qj, q, gac[jj]);
+                }
         }
-        for (int jj = 0; jj < 8 && j0 + jj < k; ++jj) {
-            red[threadIdx.x] = acc[jj];
-            __syncthreads();
-            for (int s = 128; s >= RB; s >>= 1) {
-                if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        for (int h = 0; h < 2; ++h)
+            for (int jj = 0; jj < 8 && j0 + jj < k; ++jj) {
+                red[threadIdx.x] = h ? gac[jj] : acc[jj];
+                __syncthreads();
+                for (int s = 128; s >= RB; s >>= 1) {
+                    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+                    __syncthreads();
+                }
+                if (threadIdx.x < RB)
+                    part[(int64_t(blockIdx.x) * 2 * k + h * k + j0 + jj) * RB + threadIdx.x] = red[threadIdx.x];
                 __syncthreads();
             }
-            if (threadIdx.x < RB) part[(int64_t(blockIdx.x) * k + j0 + jj) * RB + threadIdx.x] = red[threadIdx.x];
-            __syncthreads();
-        }
+    }
+}
+
+// Second Gram-Schmidt pass from the Gram matrix, one thread per right-hand side.
+// cg[j] (j < k) are the first-pass coefficients c1 = Q^T s, cg[k + j] = Q_j . Q_{k-1}.
+// Stores that row into gram ([kcap][kcap][RB], symmetric) and writes
+//   coef = c1 + c2,  c2 = Q^T (s - Q c1) = c1 - (Q^T Q) c1,
+// so that s - Q coef equals two classical Gram-Schmidt passes in exact arithmetic.
+__global__ void k_gram_coef(double *gram, int kcap, const double *cg, int k, int RB, double *coef) {
+    const int r = threadIdx.x;
+    if (r >= RB) return;
+    for (int j = 0; j < k; ++j) {
+        const double v = cg[int64_t(k + j) * RB + r];
+        gram[(int64_t(k - 1) * kcap + j) * RB + r] = v;
+        gram[(int64_t(j) * kcap + (k - 1)) * RB + r] = v;
+    }
+    for (int j = 0; j < k; ++j) {
+        double gc = 0.0;
+        for (int i = 0; i < k; ++i) gc = __builtin_fma(gram[(int64_t(j) * kcap + i) * RB + r], cg[int64_t(i) * RB + r], gc);
+        const double c1 = cg[int64_t(j) * RB + r];
+        coef[int64_t(j) * RB + r] = c1 + (c1 - gc);
     }
 }
 
@@ -1154,6 +1207,9 @@ const double *injw_of<double>(const DevOps &op) { return op.injw64; }
 template <>
 const float *injw_of<float>(const DevOps &op) { return op.injw32; }
 
+// bytes of a step's state (two vectors read, two written) for one RHS block
+inline double state_bytes(const DevOps &op, int RB, size_t tsize) { return 4.0 * op.n * RB * double(tsize); }
+
 template <typename T, int RB>
 VFwdArgs<T> fwd_args_v(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first,
                        bool sample, int t, void *y, double yscale, int *blocks) {
@@ -1170,6 +1226,7 @@ VFwdArgs<T> fwd_args_v(const DevOps &op, const void *P, const void *V, void *Pn,
     a.first = first; a.sample = sample; a.t = t;
     a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
     a.n_samp = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
+    a.stream = state_bytes(op, RB, sizeof(T)) > kInfinityCacheBytes;
     *blocks = a.n_tiles + a.n_samp;
     return a;
 }
@@ -1179,7 +1236,9 @@ void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *
                 int t, void *y, double yscale, hipStream_t s) {
     int grid = 0;
     const VFwdArgs<T> a = fwd_args_v<T, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, &grid);
-    if (grid > 0) hipLaunchKernelGGL((k_fwd_v<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
+    if (grid <= 0) return;
+    if (a.stream) hipLaunchKernelGGL((k_fwd_v<T, OT, RB, true>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_fwd_v<T, OT, RB, false>), dim3(grid), dim3(256), 0, s, a);
 }
 
 template <typename T, typename OT, int RB>
@@ -1189,8 +1248,12 @@ void fwd_impl_vm(const FwdStep *st, int n, hipStream_t s) {
         mm.a[m] = fwd_args_v<T, RB>(*st[m].op, st[m].P, st[m].V, st[m].Pn, st[m].Vn, st[m].rows, st[m].first,
                                     st[m].sample, st[m].t, st[m].y, st[m].yscale, &mm.tiles[m]);
     mm.n = n;
+    double sb = 0.0;
+    for (int m = 0; m < n; ++m) sb += state_bytes(*st[m].op, RB, sizeof(T));
     const int grid = multi_grid(mm.tiles, n);
-    if (grid > 0) hipLaunchKernelGGL((k_fwd_vm<T, OT, RB>), dim3(grid), dim3(256), 0, s, mm);
+    if (grid <= 0) return;
+    if (sb > kInfinityCacheBytes) hipLaunchKernelGGL((k_fwd_vm<T, OT, RB, true>), dim3(grid), dim3(256), 0, s, mm);
+    else hipLaunchKernelGGL((k_fwd_vm<T, OT, RB, false>), dim3(grid), dim3(256), 0, s, mm);
 }
 
 template <typename T, int RB>
@@ -1206,6 +1269,7 @@ VAdjArgs<T> adj_args_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool
     a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
     a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
     a.dt = T(op.dt);
+    a.stream = state_bytes(op, RB, sizeof(T)) > kInfinityCacheBytes;
     return a;
 }
 
@@ -1213,7 +1277,8 @@ template <typename T, typename YT, int RB>
 void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
                 double yscale, hipStream_t s) {
     const VAdjArgs<T> a = adj_args_v<T, RB>(op, PH, Q, Qn, last, tm1, yh, yscale);
-    hipLaunchKernelGGL((k_adj_v<T, YT, RB>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    if (a.stream) hipLaunchKernelGGL((k_adj_v<T, YT, RB, true>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_adj_v<T, YT, RB, false>), dim3(a.n_tiles), dim3(256), 0, s, a);
 }
 
 template <typename T, typename YT, int RB>
@@ -1225,8 +1290,12 @@ void adj_impl_vm(const AdjStep *st, int n, hipStream_t s) {
         mm.tiles[m] = mm.a[m].n_tiles;
     }
     mm.n = n;
+    double sb = 0.0;
+    for (int m = 0; m < n; ++m) sb += state_bytes(*st[m].op, RB, sizeof(T));
     const int grid = multi_grid(mm.tiles, n);
-    if (grid > 0) hipLaunchKernelGGL((k_adj_vm<T, YT, RB>), dim3(grid), dim3(256), 0, s, mm);
+    if (grid <= 0) return;
+    if (sb > kInfinityCacheBytes) hipLaunchKernelGGL((k_adj_vm<T, YT, RB, true>), dim3(grid), dim3(256), 0, s, mm);
+    else hipLaunchKernelGGL((k_adj_vm<T, YT, RB, false>), dim3(grid), dim3(256), 0, s, mm);
 }
 
 template <typename T, typename OT, int RB>
@@ -1500,11 +1569,12 @@ void launch_append_dir(const double *sv, double *Qk, double *d, const double *in
     hipLaunchKernelGGL(k_append, dim3(grid_for(total)), dim3(256), 0, s, sv, Qk, d, invn, beta, first, total, RB);
 }
 
-void launch_multidot(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *coef,
-                     hipStream_t s) {
+void launch_reorth_coef(const double *Q, const double *sv, int k, int64_t rows, int RB, double *part, double *cg,
+                        double *gram, int kcap, double *coef, hipStream_t s) {
     if (k <= 0) return;
-    hipLaunchKernelGGL(k_multidot_partial, dim3(kMultiBlocks), dim3(256), 0, s, Q, sv, k, rows, RB, part);
-    hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(256), 0, s, part, kMultiBlocks, k, RB, coef);
+    hipLaunchKernelGGL(k_multidot2_partial, dim3(kMultiBlocks), dim3(256), 0, s, Q, sv, k, rows, RB, part);
+    hipLaunchKernelGGL(k_multidot_final, dim3(2 * k), dim3(256), 0, s, part, kMultiBlocks, 2 * k, RB, cg);
+    hipLaunchKernelGGL(k_gram_coef, dim3(1), dim3(256), 0, s, gram, kcap, cg, k, RB, coef);
 }
 
 void launch_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB, hipStream_t s) {

@@ -3,11 +3,15 @@
 * P and P^T (pat_spectral_apply) against oracle/spectral.py (numpy FFT), several
   grid sizes and ragged RHS counts: 1e-12 of the largest output;
 * the transpose identity on the GPU;
-* latent-space RTO (float64 sweeps) against the oracle's latent CGLS: 1e-10;
-  LSQR against it (equal iterates in exact arithmetic): 1e-9; float32 sweeps:
-  samples and mean within 1e-4, std within the Lipschitz bound of the sample
-  differences; also inside one 128-RHS (float64) and one 256-RHS (float32)
-  block; device-drawn latent perturbations;
+* latent-space RTO (float64 sweeps) against the oracle's latent CGLS, 40
+  iterations: 1e-10; LSQR against it (equal iterates in exact arithmetic): 1e-9;
+  float32 sweeps with 64 samples (as in the benchmark): samples, mean and std
+  within 1e-4; also inside one 128-RHS (float64) and one 256-RHS (float32)
+  block; device-drawn latent perturbations.  (After only 20 iterations the
+  float32 std error of this problem is 1.04e-4, and a CPU emulation of the same
+  float32 arithmetic gives the same figure: that point sits on the rounding floor
+  of the float32 step, so the comparison runs at 40 iterations, where the floor
+  is 1.5e-5.);
 * argument errors;
 * the 195k-node ball with the 128^3 grid: sampled P / P^T against the oracle and
   a short latent solve whose samples are P of its latent samples.
@@ -59,17 +63,17 @@ def test_spectral_apply_matches_oracle(ball16, n, R, ell):
     assert np.all(np.abs(lhs - rhs) < 1e-13 * scale)
 
 
-@pytest.mark.parametrize("solver,prec,tol,rb", [("cgls", "f64", 1e-10, 0), ("lsqr", "f64", 1e-9, 0),
-                                               ("cgls", "f32", 1e-4, 0), ("cgls", "f64", 1e-10, 128),
-                                               ("cgls", "f32", 1e-4, 256)])
-def test_latent_rto_matches_oracle(ball16, solver, prec, tol, rb):
+@pytest.mark.parametrize("solver,prec,tol,rb,S", [("cgls", "f64", 1e-10, 0, 6), ("lsqr", "f64", 1e-9, 0, 6),
+                                                 ("cgls", "f32", 1e-4, 0, 64), ("cgls", "f64", 1e-10, 128, 6),
+                                                 ("cgls", "f32", 1e-4, 256, 64)])
+def test_latent_rto_matches_oracle(ball16, solver, prec, tol, rb, S):
     w, O, G = ball16
     n, ell = 16, 0.2
     pr = SpectralPrior(n, BOX["lo"], BOX["side"], ell, 3.0)
     I = pr.interp_matrix(w.coords)
     pat.spectral_prior_set(G, n, BOX["lo"], BOX["side"], ell, 3.0)
     Y, yobs, sigma = oracle.synthesize(O, w)
-    S, n_iter = 6, 20
+    n_iter = 40
     rng = np.random.default_rng(41)
     eta = rng.standard_normal((S, w.n_steps, w.n_obs))
     xi = rng.standard_normal((S, pr.size))
@@ -82,17 +86,9 @@ def test_latent_rto_matches_oracle(ball16, solver, prec, tol, rb):
     rmean, rstd = oracle.stats(ref)
     em = float(np.linalg.norm(out["mean"].cpu().numpy() - rmean) / np.linalg.norm(rmean))
     es = float(np.linalg.norm(out["std"].cpu().numpy() - rstd) / np.linalg.norm(rstd))
-    print(f"latent RTO {solver} {prec} rb={rb}: samples {e:.2e} latent {el:.2e} mean {em:.2e} std {es:.2e}")
-    assert e < tol and el < tol and em < tol
-    # The pointwise std is 1-Lipschitz in the centred samples: per node
-    # |std(a) - std(b)| <= ||a - b|| / sqrt(S - 1).  With few samples whose spread is
-    # small against their size this amplifies the sample error, so bound it by that.
-    dstd = np.abs(out["std"].cpu().numpy() - rstd)
-    bound = np.linalg.norm(got - ref, axis=0) / np.sqrt(S - 1)
-    assert np.all(dstd <= bound * (1 + 1e-6) + 1e-12 * rstd.max())
-    if prec == "f64":
-        assert es < tol
-        assert np.abs(out["resid"].cpu().numpy() - res).max() < tol * res.max()
+    print(f"latent RTO {solver} {prec} rb={rb} S={S}: samples {e:.2e} latent {el:.2e} mean {em:.2e} std {es:.2e}")
+    assert e < tol and el < tol and em < tol and es < tol
+    assert np.abs(out["resid"].cpu().numpy() - res).max() < tol * res.max()
 
 
 def test_latent_rto_device_draws(ball16):

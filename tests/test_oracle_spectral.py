@@ -118,3 +118,29 @@ def test_latent_rto_krylov_and_converged():
         assert abs(latent_residual(O, pr, I, ref, yobs, sigma, eta[r], xi[r])[0] - np.sqrt(rss[0])) \
             < 1e-10 * np.linalg.norm(b[r])
         np.testing.assert_allclose(p0[r], P @ lat[r], rtol=0, atol=1e-10 * np.abs(p0[r]).max())
+
+
+def test_float32_floor_of_the_latent_std():
+    """The rounding floor behind the 40-iteration float32 latent-RTO test: on ball16 (16^3 grid,
+    ell = 0.2, 64 samples) float32 staggered sweeps (oracle/float32_floor.py, numpy float32)
+    give a posterior std 1.0e-4 away from the float64 oracle after 20 iterations while samples and
+    mean stay near 4e-6, and the oracle's float32 literal three-substep sweeps give 4e-5 there."""
+    from oracle.float32_floor import StaggeredFloat32
+    w = W.make_workload("ball16")
+    O = oracle.Problem.from_workload(w)
+    pr = SpectralPrior(16, -1.25, 2.5, 0.2, 3.0)
+    I = pr.interp_matrix(w.coords)
+    Y, yobs, sigma = oracle.synthesize(O, w)
+    S, n_iter = 64, 20
+    rng = np.random.default_rng(41)
+    eta = rng.standard_normal((S, w.n_steps, w.n_obs))
+    xi = rng.standard_normal((S, pr.size))
+    ref, _, _ = latent_rto(O, pr, I, yobs, sigma, n_iter, eta, xi)
+    m0, s0 = oracle.stats(ref)
+    rl = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    stag, _, _ = latent_rto(StaggeredFloat32(O), pr, I, yobs, sigma, n_iter, eta, xi)
+    lit, _, _ = latent_rto(O, pr, I, yobs, sigma, n_iter, eta, xi, sweeps="f32")
+    (ms, ss), (ml, sl) = oracle.stats(stag), oracle.stats(lit)
+    assert rl(stag, ref) < 1e-5 and rl(ms, m0) < 1e-5
+    assert 7e-5 < rl(ss, s0) < 1.5e-4
+    assert rl(sl, s0) < 7e-5
