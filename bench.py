@@ -323,8 +323,9 @@ def spectral_leg(pat, dev, G, w, yobs, sigma, n_iter):
             torch.cuda.synchronize()
             times[name] = e0.elapsed_time(e1) / 3
         del x, v
-        # five FFT passes per application: real in / complex out, three complex passes, complex in / real out
-        fft_bytes = (24 + 32 + 32 + 32 + 24) * n ** 3 * RB
+        # five passes per application on the half spectrum (n/2 + 1 x frequencies): real in / half complex
+        # out, three half-complex passes, half complex in / real out
+        fft_bytes = int((8 + 16 * (n // 2 + 1) / n + 3 * 32 * (n // 2 + 1) / n + 16 * (n // 2 + 1) / n + 8) * n ** 3 * RB)
         torch.cuda.synchronize()
         t = time.perf_counter()
         out = pat.rto_sample(*args, n_iter, sweep_prec="f32", rhs_block=RB, n_samples=S, seed=21, prior="spectral")
@@ -392,6 +393,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-mesh uneven batch")
     ap.add_argument("--no-wide-probe", action="store_true",
                     help="skip the short 256-RHS solve that times the step kernels beyond the Infinity Cache")
+    ap.add_argument("--wide-iters", type=int, default=4, help="solver iterations of that 256-RHS solve")
     ap.add_argument("--big", action="store_true", help="also time one sample on the 10^6-node ball")
     ap.add_argument("--spectral", action="store_true",
                     help="also time 64 samples with the Whittle-Matern spectral prior (128^3 grid, latent solve)")
@@ -542,7 +544,7 @@ def main():
         "final_residual_f64": final,
     }
     if not args.no_wide_probe:
-        result["roofline"]["beyond_cache"] = wide_probe(pat, G, info, w, yobs, sigma)
+        result["roofline"]["beyond_cache"] = wide_probe(pat, G, info, w, yobs, sigma, iters=args.wide_iters)
 
     if not args.no_plain:
         # plain float64 path: one sample at a time, float64 everywhere

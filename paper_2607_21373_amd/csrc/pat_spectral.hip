@@ -4,16 +4,22 @@
 // square-root spectrum, I_h trilinear interpolation to the mesh nodes.
 //
 // Layouts: grid vectors [n^3][RB] with grid index g = (k*n + j)*n + i (x fastest)
-// and the RHS fastest; complex grid vectors interleave (re, im) per element.
+// and the RHS fastest.  The filtered field is real, so its spectrum is kept only
+// for the nh = n/2 + 1 non-negative x frequencies (the others are the complex
+// conjugates): complex half-spectrum vectors [n][n][nh][RB], (re, im) per element.
 //
-// The 3D transform is five launches of one kernel, each a batch of length-n
-// FFTs along one axis (one line and a chunk of up to 16 right-hand sides per
-// workgroup, staged in LDS): forward x, forward y, then forward z, the
-// multiplication by a(k) and the inverse z in the same pass, then inverse y and
-// inverse x.  Each length-n transform is a Stockham FFT (natural order in and
-// out, so no reordering pass) with 8 points per thread: radix-8 stages computed
-// in registers, exchanged through LDS between stages, then a radix-2 or radix-4
-// stage when n is not a power of 8 (n = 128: 8 x 8 x 2, three stages).
+// The 3D transform is five launches, each a batch of one-dimensional transforms
+// along one axis (one line and a chunk of up to 16 right-hand sides per
+// workgroup, staged in LDS): the real-to-complex x pass, forward y, then forward
+// z, the multiplication by a(k) and the inverse z in the same pass, inverse y, and
+// the complex-to-real x pass.  The x passes pack the n real points of a line as
+// n/2 complex points (even samples real, odd samples imaginary), transform those
+// with one length-n/2 FFT and split the result into the n/2 + 1 spectrum values
+// (and back), which halves the bytes of every pass after the first.  Each complex
+// transform is a Stockham FFT (natural order in and out, so no reordering pass)
+// with 8 points per thread: radix-8 stages computed in registers, exchanged
+// through LDS between stages, then a radix-2 or radix-4 stage when the length is
+// not a power of 8 (n = 128: 8 x 8 x 2 along y and z, 8 x 8 along x).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -35,12 +41,12 @@ constexpr int kRC = 16;  // right-hand sides per workgroup
 enum : int { kForward = 0, kInverse = 1, kCentre = 2 };
 
 struct FftPass {
-    const double *rin;   // real input [G][RB], or null
-    const double2 *cin;  // complex input [G][RB], or null
-    double2 *cout;       // complex output, or null
-    double *rout;        // real output (the real part), or null
+    const double *rin;   // real input [G][RB] (x pass, forward), or null
+    const double2 *cin;  // complex half-spectrum input, or null
+    double2 *cout;       // complex half-spectrum output, or null
+    double *rout;        // real output (x pass, inverse), or null
     const double *add;   // added to the real output, or null
-    const double *amp;   // a(k) [G] for the centre pass
+    const double *amp;   // a(k) [G] (full grid index) for the centre pass
     const double2 *tw;   // tw[j] = exp(-2 pi i j / n), j < n/2
     int n, RB, axis, mode;
 };
@@ -99,6 +105,23 @@ __device__ __forceinline__ double2 wpow(const double2 *tws, int e, int n) {
 // barriers.  Ends with a barrier.
 template <bool INV>
 __device__ __forceinline__ void line_fft(double2 *X, int stride, int n, int RC, const double2 *tws) {
+    if (n < 8) {  // n = 2 or 4 (the x passes of a grid of 4 or 8): one thread per line
+        if (threadIdx.x < RC) {
+            double2 *x = X + threadIdx.x * stride;
+            if (n == 4) {
+                double2 v[4] = {x[pidx(0)], x[pidx(1)], x[pidx(2)], x[pidx(3)]};
+                dft4<INV>(v);
+                for (int r = 0; r < 4; ++r) x[pidx(r)] = v[r];
+            } else {
+                double2 u = x[pidx(0)], t = x[pidx(1)];
+                bfly(u, t);
+                x[pidx(0)] = u;
+                x[pidx(1)] = t;
+            }
+        }
+        __syncthreads();
+        return;
+    }
     const int tpl = n >> 3;  // threads per line
     const int line = threadIdx.x / tpl, j = threadIdx.x % tpl;
     const bool act = line < RC;
@@ -151,37 +174,31 @@ __device__ __forceinline__ void line_fft(double2 *X, int stride, int n, int RC, 
     __syncthreads();
 }
 
-// One length-n transform per (line, RHS) of the workgroup's line and RHS chunk.
+// One length-n transform along y (axis 1) or z (axis 2) per (line, RHS) of the
+// workgroup's line and RHS chunk, on the half spectrum (x extent nh = n/2 + 1);
+// the z pass of the centre mode multiplies by a(k) between its forward and inverse
+// transforms.
 __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
     extern __shared__ double2 X[];  // [RC][n + n/8 + 1], see pidx
     __shared__ double2 tws[64];     // the n/2 twiddles (n <= 128)
-    const int n = a.n, half_n = n >> 1, stride = n + (n >> 3) + 1;
+    const int n = a.n, nh = n / 2 + 1, half_n = n >> 1, stride = n + (n >> 3) + 1;
     for (int e = threadIdx.x; e < half_n; e += 256) tws[e] = a.tw[e];
     const int RC = a.RB < kRC ? a.RB : kRC;
     const int rc0 = blockIdx.y * RC;
-    const int L = blockIdx.x;
-    int64_t g0, ls;
-    if (a.axis == 0) {
-        g0 = int64_t(L) * n;
-        ls = 1;
-    } else if (a.axis == 1) {
-        g0 = int64_t(L / n) * n * n + L % n;
-        ls = n;
-    } else {
-        g0 = L;
-        ls = int64_t(n) * n;
-    }
+    const int L = blockIdx.x, i = L % nh, q = L / nh;  // line (q, i): q = k (axis 1) or j (axis 2)
+    const int64_t g0 = a.axis == 1 ? int64_t(q) * n * nh + i : int64_t(q) * nh + i;
+    const int64_t ls = a.axis == 1 ? nh : int64_t(n) * nh;
     for (int e = threadIdx.x; e < n * RC; e += 256) {
         const int t = e / RC, r = e % RC;
-        const int64_t gi = (g0 + t * ls) * a.RB + rc0 + r;
-        X[r * stride + pidx(t)] = a.rin ? make_double2(a.rin[gi], 0.0) : a.cin[gi];
+        X[r * stride + pidx(t)] = a.cin[(g0 + t * ls) * a.RB + rc0 + r];
     }
     __syncthreads();
     if (a.mode != kInverse) line_fft<false>(X, stride, n, RC, tws);
     if (a.mode == kCentre) {
+        // a(k) at (kx, ky, kz) = (i, q, t) of the full n^3 grid
         for (int e = threadIdx.x; e < n * RC; e += 256) {
             const int r = e / n, t = e % n;
-            const double w = a.amp[g0 + t * ls];
+            const double w = a.amp[(int64_t(t) * n + q) * n + i];
             X[r * stride + pidx(t)] = make_double2(w * X[r * stride + pidx(t)].x, w * X[r * stride + pidx(t)].y);
         }
         __syncthreads();
@@ -190,10 +207,61 @@ __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
     const double sc = a.mode == kForward ? 1.0 : 1.0 / n;
     for (int e = threadIdx.x; e < n * RC; e += 256) {
         const int t = e / RC, r = e % RC;
-        const int64_t gi = (g0 + t * ls) * a.RB + rc0 + r;
         const double2 v = X[r * stride + pidx(t)];
-        if (a.rout) a.rout[gi] = sc * v.x + (a.add ? a.add[gi] : 0.0);
-        else a.cout[gi] = make_double2(sc * v.x, sc * v.y);
+        a.cout[(g0 + t * ls) * a.RB + rc0 + r] = make_double2(sc * v.x, sc * v.y);
+    }
+}
+
+// The x passes: real lines of n points <-> their n/2 + 1 spectrum values, through one
+// complex transform of length m = n/2 of z[p] = x[2p] + i x[2p+1].  With Z = DFT_m(z),
+// w = exp(-2 pi i / n) and k = 0..m (Z[m] = Z[0]):
+//   X[k] = E[k] + w^k O[k],  E[k] = (Z[k] + conj Z[m-k]) / 2,  O[k] = -i (Z[k] - conj Z[m-k]) / 2,
+// and back: Z[k] = E[k] + i O[k] with E[k] = (X[k] + conj X[m-k]) / 2 and
+// O[k] = w^-k (X[k] - conj X[m-k]) / 2, z = IDFT_m(Z) / m (the inverse's 1/n included).
+__global__ void __launch_bounds__(256) k_fft_x(const FftPass a) {
+    extern __shared__ double2 X[];  // [RC][m + m/8 + 1], see pidx
+    __shared__ double2 tws[64], twh[32];  // the n/2 twiddles of length n, the m/2 of length m
+    const int n = a.n, m = n >> 1, nh = m + 1, stride = m + (m >> 3) + 1;
+    for (int e = threadIdx.x; e < m; e += 256) tws[e] = a.tw[e];
+    for (int e = threadIdx.x; e < m / 2; e += 256) twh[e] = a.tw[2 * e];
+    __syncthreads();
+    const int RC = a.RB < kRC ? a.RB : kRC;
+    const int rc0 = blockIdx.y * RC;
+    const int64_t L = blockIdx.x;  // line (k, j): real points g = L*n + t, spectrum h = L*nh + k
+    if (a.mode == kForward) {
+        for (int e = threadIdx.x; e < m * RC; e += 256) {
+            const int p = e / RC, r = e % RC;
+            const int64_t g = (L * n + 2 * p) * a.RB + rc0 + r;
+            X[r * stride + pidx(p)] = make_double2(a.rin[g], a.rin[g + a.RB]);
+        }
+        __syncthreads();
+        line_fft<false>(X, stride, m, RC, twh);
+        for (int e = threadIdx.x; e < nh * RC; e += 256) {
+            const int k = e / RC, r = e % RC;
+            const double2 zk = X[r * stride + pidx(k % m)], zc = conjg(X[r * stride + pidx((m - k) % m)]);
+            const double2 ev = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+            const double2 od = make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x));  // -i (zk - zc) / 2
+            a.cout[(L * nh + k) * a.RB + rc0 + r] = cadd(ev, cmul(wpow<false>(tws, k, n), od));
+        }
+    } else {
+        for (int e = threadIdx.x; e < m * RC; e += 256) {
+            const int k = e / RC, r = e % RC;
+            const double2 xk = a.cin[(L * nh + k) * a.RB + rc0 + r];
+            const double2 xc = conjg(a.cin[(L * nh + m - k) * a.RB + rc0 + r]);
+            const double2 ev = make_double2(0.5 * (xk.x + xc.x), 0.5 * (xk.y + xc.y));
+            const double2 od = cmul(wpow<true>(tws, k, n), make_double2(0.5 * (xk.x - xc.x), 0.5 * (xk.y - xc.y)));
+            X[r * stride + pidx(k)] = make_double2(ev.x - od.y, ev.y + od.x);  // E + i O
+        }
+        __syncthreads();
+        line_fft<true>(X, stride, m, RC, twh);
+        const double sc = 1.0 / m;
+        for (int e = threadIdx.x; e < m * RC; e += 256) {
+            const int p = e / RC, r = e % RC;
+            const double2 v = X[r * stride + pidx(p)];
+            const int64_t g = (L * n + 2 * p) * a.RB + rc0 + r;
+            a.rout[g] = sc * v.x + (a.add ? a.add[g] : 0.0);
+            a.rout[g + a.RB] = sc * v.y + (a.add ? a.add[g + a.RB] : 0.0);
+        }
     }
 }
 
@@ -248,11 +316,17 @@ void fft_pass(const SpecOps &sp, int RB, int axis, int mode, const double *rin, 
     a.axis = axis;
     a.mode = mode;
     const int RC = RB < kRC ? RB : kRC;
-    const size_t lds = size_t(sp.n + sp.n / 8 + 1) * RC * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_axis, dim3(unsigned(sp.n) * unsigned(sp.n), unsigned(RB / RC)), dim3(256), lds, s, a);
+    const unsigned n = unsigned(sp.n), nh = n / 2 + 1;
+    if (axis == 0) {
+        const size_t lds = size_t(n / 2 + n / 16 + 1) * RC * sizeof(double2);
+        hipLaunchKernelGGL(k_fft_x, dim3(n * n, unsigned(RB / RC)), dim3(256), lds, s, a);
+    } else {
+        const size_t lds = size_t(n + n / 8 + 1) * RC * sizeof(double2);
+        hipLaunchKernelGGL(k_fft_axis, dim3(n * nh, unsigned(RB / RC)), dim3(256), lds, s, a);
+    }
 }
 
-// g (real [G][RB]) -> filtered real field, written to rout (+ add)
+// g (real [G][RB]) -> filtered real field, written to rout (+ add); gc holds the half spectrum
 void filter(const SpecOps &sp, int RB, const double *g, double *gc, double *rout, const double *add, hipStream_t s) {
     fft_pass(sp, RB, 0, kForward, g, nullptr, gc, nullptr, nullptr, s);
     fft_pass(sp, RB, 1, kForward, nullptr, gc, gc, nullptr, nullptr, s);
