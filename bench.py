@@ -219,8 +219,11 @@ def big_leg(pat, W, dev, n_iter):
 def roofline_record(fwd_s, adj_s, fb, ab, survey_bytes, sweep_share, wname, RB):
     """Roofline of the two step kernels, which share the sweep time almost equally: the one with the
     longer average launch leads the record, the other follows with its own fraction of the HBM peak."""
-    kern = {"fwd": (f"k_fwd_v<float,double,{RB}> (forward leapfrog step)", fwd_s, fb, f"k_fwd_f32_rb{RB}"),
-            "adj": (f"k_adj_v<float,double,{RB}> (transpose leapfrog step)", adj_s, ab, f"k_adj_f32_rb{RB}")}
+    # float32 blocks of 64, 128 or 256 RHS run the halo-tile step kernels, narrower ones the vector-lane ones
+    fk, ak = (f"k_fwd_h<double,{RB}>", f"k_adj_h<double,{RB}>") if RB >= 64 else \
+        (f"k_fwd_v<float,double,{RB}>", f"k_adj_v<float,double,{RB}>")
+    kern = {"fwd": (f"{fk} (forward leapfrog step)", fwd_s, fb, f"k_fwd_f32_rb{RB}"),
+            "adj": (f"{ak} (transpose leapfrog step)", adj_s, ab, f"k_adj_f32_rb{RB}")}
 
     def rec(k):
         name, sec, b, key = kern[k]

@@ -1100,6 +1100,18 @@ pat_status pat_problem_create(const pat_problem_desc *desc, pat_problem **out) {
     UP(to_f32(hp.ell_val), ell_val32);
     UP(to_f32(hp.xval), xval32);
     UP(to_f32(hp.bslot), bslot32);
+    {
+        pat::HaloTiles ht;
+        pat::build_halo_tiles(hp, ht);
+        UP(ht.desc, ht_desc);
+        UP(ht.hrow, ht_hrow);
+        UP(ht.meta, ht_meta);
+        op.n_ht = ht.n_tiles;
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return cleanup(fail(PAT_ERR_HIP, "hipDeviceGetAttribute failed"));
+        op.n_cu = ncu;
+    }
 #undef UP
     p->perm_identity = true;
     for (int32_t i = 0; i < hp.n; ++i)

@@ -56,6 +56,32 @@ pat_status build_host_problem(const pat_problem_desc &d, HostProblem &hp, std::s
 // Build the padded row layout (ell_*, x*, bs*) from the CSR arrays.
 void build_padded_rows(HostProblem &hp);
 
+// Halo tiles of the float32 step kernels whose RHS block rows are 256-byte
+// multiples.  Consecutive rows (a compact cluster of the node order) are cut
+// greedily into tiles of at most kRows rows whose halo, the distinct rows that
+// the tile's padded slots refer to (K rows) plus the distinct rows its boundary
+// slots refer to (B rows), each padded to a multiple of 4, holds at most kMax
+// rows.  Per tile: a descriptor, the halo's row list and one metadata block
+// that the kernels copy into LDS with the halo:
+//   loc[nr][16]  uint16: K-local index | B-local index << 8 of each slot
+//   info[nr][8]  int32:  dt/m (float bits), bw row | bnum << 16, xptr[i], xptr[i+1],
+//                        injptr[i], injptr[i+1], 0, 0
+//   kv[nr][16]   float:  the slot values of K
+//   bw[nbr][16]  float:  the slot values of B of the tile's boundary rows
+struct HaloTiles {
+    static constexpr int kRows = 32;
+    static constexpr int kMax = 132;
+    static constexpr int kMetaBytes = kRows * (32 + 32 + 64 + 64);
+    int32_t n_tiles = 0;
+    // [n_tiles][4]: first row, first halo entry, metadata offset (16-byte units),
+    // rows | K rows << 6 | B rows << 14 | boundary rows << 22 (metadata bytes:
+    // 128 per row + 64 per boundary row)
+    std::vector<int32_t> desc;
+    std::vector<int32_t> hrow;
+    std::vector<uint32_t> meta;
+};
+void build_halo_tiles(const HostProblem &hp, HaloTiles &ht);
+
 
 // Largest eigenvalue of M_L^{-1} K by power iteration on M^{-1/2} K M^{-1/2}.
 double estimate_lambda_max(const HostProblem &hp, int iters);

@@ -21,6 +21,11 @@ struct DevOps {
     const int32_t *ell_col = nullptr, *xptr = nullptr, *xcol = nullptr, *bsoff = nullptr, *bnum = nullptr;
     const double *ell_val64 = nullptr, *xval64 = nullptr, *bslot64 = nullptr;
     const float *ell_val32 = nullptr, *xval32 = nullptr, *bslot32 = nullptr;
+    // halo tiles of the float32 step kernels (HaloTiles)
+    const int32_t *ht_desc = nullptr, *ht_hrow = nullptr;
+    const uint32_t *ht_meta = nullptr;
+    int32_t n_ht = 0;
+    int32_t n_cu = 0;  // compute units of the device (the halo kernels keep two workgroups on each)
     double dt = 0.0;
 };
 

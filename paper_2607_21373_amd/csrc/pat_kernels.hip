@@ -13,6 +13,9 @@
 // Sec. 5.1 eq. (adjoint-verlet) with the recursion (backward-recursion).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
+#include "pat_internal.h"
 #include "pat_kernels.h"
 
 namespace pat {
@@ -454,6 +457,10 @@ struct VFwdArgs {
     int n, n_obs, n_tiles, n_samp, first, sample, t;
     int stream;  // state beyond the Infinity Cache: launch the non-temporal variant
     T dt, half_dt;
+    // halo tiles (HaloTiles), float32 blocks of 256-byte row chunks
+    const int32_t *hdesc, *hrow;
+    const uint32_t *hmeta;
+    int n_ht;
 };
 
 // Sampling block j of a forward step: y^n = Pi (P - dt/2 V) of the incoming state,
@@ -570,6 +577,9 @@ struct VAdjArgs {
     int n, n_obs, n_tiles, last, tm1;
     int stream;  // state beyond the Infinity Cache: launch the non-temporal variant
     T dt;
+    const int32_t *hdesc, *hrow;
+    const uint32_t *hmeta;
+    int n_ht;
 };
 
 // Transposed step (same update as k_adj) with vector lanes on logical tile `tile`.
@@ -627,6 +637,385 @@ __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdj
     int m, local;
     if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
     adj_tile<T, YT, RB, NT>(mm.a[m], local, L);
+}
+
+// ---------------------------------------------------------------------------
+// Halo step kernels: float32 blocks whose rows are 64, 128 or 256 RHS (one to
+// four 256-byte chunks).
+//
+// The vector-lane kernels above gather 16 neighbour rows per row through the
+// CU's texture units, which keeps those units busy most of the step.  Here a
+// tile of consecutive rows (HaloTiles: at most 32 rows whose distinct neighbour
+// rows, the halo, fit 132 LDS rows; on the 195,112-node ball 4.3 halo rows per
+// row) copies its halo and its row operands from memory straight into LDS
+// (global_load_lds_dwordx4, 64 lanes x 16 bytes per instruction, no registers
+// in between), and every slot reads its neighbour from there.  Each workgroup
+// (512 threads: 32 rows x 16 lanes of 16 bytes) walks its tiles in a loop with
+// two LDS buffers: while it computes one tile, the copies of the next are in
+// flight, and the stores of the previous one drain.  Work item = (row chunk,
+// tile); XCD x takes the x-th eighth of the tiles, its workgroups interleaved
+// over them, so the tiles in flight on one XCD are neighbours and share their
+// halo rows in that XCD's L2.  The forward step also copies the rows of V
+// that its boundary slots refer to (the B part of the halo).  Sums run in the
+// slot order of the vector-lane kernels, with the same operations, so both
+// give the same bits.
+// ---------------------------------------------------------------------------
+
+using F4 = Vec16<float>::t;  // 16 bytes of float32
+constexpr int kHRows = HaloTiles::kRows;
+constexpr int kHMax = HaloTiles::kMax;
+constexpr int kHMetaWords = HaloTiles::kMetaBytes / 4;
+constexpr int kHThreads = kHRows * 16;
+constexpr int kHWaves = kHThreads / 64;
+constexpr int kHPerWave = (kHMax / 4 + kHWaves - 1) / kHWaves;  // halo copy instructions per wave at most
+constexpr int kHChunk = 4;  // LDS reads in flight per lane before they are consumed
+static_assert(kHThreads == 512 && kHMetaWords / 256 <= kHWaves, "halo tile geometry");
+
+// LDS image of one tile
+struct HaloBuf {
+    F4 rows[kHMax * 16];      // halo rows (256-byte chunks): K part, then B part
+    uint32_t meta[kHMetaWords];   // the tile's metadata block (HaloTiles)
+};
+// LDS of a workgroup: two tile images and two halo row lists, each its own
+// __shared__ variable, so that the compiler can tell the copies into one buffer
+// from the reads of the other and does not wait for the former before the latter
+struct HaloList {
+    int32_t r[kHMax];
+};
+static_assert(2 * (sizeof(HaloBuf) + sizeof(HaloList)) <= 81920, "two workgroups per CU");
+
+struct HDesc {
+    int r0, nr, h0, nk4, nb4, moff, mbytes, nbr;
+};
+
+// unpack a tile descriptor (HaloTiles::desc) into wave-uniform values
+__device__ __forceinline__ HDesc desc_uniform(const int4 u) {
+    const int r0 = __builtin_amdgcn_readfirstlane(u.x), h0 = __builtin_amdgcn_readfirstlane(u.y);
+    const int moff = __builtin_amdgcn_readfirstlane(u.z), f = __builtin_amdgcn_readfirstlane(u.w);
+    const int nr = f & 63, nk4 = (f >> 6) & 255, nb4 = (f >> 14) & 255, nbr = (f >> 22) & 63;
+    return {r0, nr, h0, nk4, nb4, moff, nr * 128 + nbr * 64, nbr};
+}
+
+// Work items of this workgroup: (chunk c, tile t), t = t_lo + k + j * G8.
+struct HWork {
+    int t_lo, k, G8, per_c, n;
+    __device__ HWork(int n_ht, int NC) {
+        G8 = int(gridDim.x >> 3);
+        const int x = int(blockIdx.x & 7);
+        k = int(blockIdx.x >> 3);
+        t_lo = int(int64_t(n_ht) * x / 8);
+        const int t_hi = int(int64_t(n_ht) * (x + 1) / 8);
+        per_c = t_hi - t_lo > k ? (t_hi - t_lo - k + G8 - 1) / G8 : 0;
+        n = per_c * NC;
+    }
+    __device__ int chunk(int it) const { return it / per_c; }
+    __device__ int tile(int it) const { return t_lo + k + (it - chunk(it) * per_c) * G8; }
+};
+
+__device__ __forceinline__ void lds_copy16(const void *src, void *lds) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+
+// Start the copy of a tile's halo row list (nh entries, a multiple of 4 from a
+// 16-byte aligned start) into list; one wave issues it.
+__device__ __forceinline__ void halo_list_issue(const int32_t *hrow, const HDesc &d, int nh, int32_t *list, int wave,
+                                                int lane) {
+    if (wave == 1 && 4 * lane < nh) lds_copy16(hrow + d.h0 + 4 * lane, list);
+}
+
+// Start the copies of a tile into Lb: its nh halo rows (row numbers from list; the
+// first nk4 from X, the rest from Y) at byte offset coff of each row, and its
+// metadata block.  Copy instruction h (halo rows 4h .. 4h+3) is issued by wave h % 8.
+template <uint32_t RS>
+__device__ __forceinline__ void halo_issue(const char *X, const char *Y, uint32_t coff, const uint32_t *hmeta,
+                                           const HDesc &d, int nh, const int32_t *list, HaloBuf &Lb, int wave,
+                                           int lane) {
+    int hr[kHPerWave];
+#pragma unroll
+    for (int m = 0; m < kHPerWave; ++m) {
+        const int h = wave + kHWaves * m;
+        hr[m] = 4 * h < nh ? list[4 * h + (lane >> 4)] : 0;
+    }
+#pragma unroll
+    for (int m = 0; m < kHPerWave; ++m) {
+        const int h = wave + kHWaves * m;
+        if (4 * h < nh) {
+            const char *base = 4 * h < d.nk4 ? X : Y;
+            lds_copy16(base + (uint32_t(hr[m]) * RS + coff + uint32_t(lane & 15) * 16u), &Lb.rows[h * 64]);
+        }
+    }
+    const int nu = d.mbytes >> 4, u = kHWaves - 1 - wave;  // metadata: 16-byte units, 64 per instruction
+    if (u * 64 < nu && u * 64 + lane < nu)
+        lds_copy16(hmeta + 4 * (int64_t(d.moff) + u * 64 + lane), &Lb.meta[u * 256]);
+}
+
+// 16-bit slot entry j of a row's loc words
+__device__ __forceinline__ int hloc(const uint32_t (&lw)[8], int j) { return int((lw[j >> 1] >> (16 * (j & 1))) & 0xFFFFu); }
+
+// acc += sum_slots K(row, slot) X[col] from the halo, slot order as vrow_sums, then
+// the entries beyond 16 from memory; own = slot 0 (the row's diagonal).
+__device__ __forceinline__ void halo_ksums(const HaloBuf &Lb, const uint32_t (&lw)[8], const float *kv, int q,
+                                           const float *__restrict__ xval, const int32_t *__restrict__ xcol, int x0,
+                                           int x1, const char *Xc, uint32_t RS, uint32_t coff, F4 &acc,
+                                           F4 &own) {
+    constexpr int CH = kHChunk;
+#pragma unroll
+    for (int j0 = 0; j0 < 16; j0 += CH) {
+        F4 x[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) x[j] = Lb.rows[(hloc(lw, j0 + j) & 0xFF) * 16 + q];
+        if (j0 == 0) own = x[0];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) acc = vfma(kv[j0 + j], x[j], acc);
+    }
+    for (int k = x0; k < x1; ++k) {
+        const F4 xv = *reinterpret_cast<const F4 *>(Xc + (uint32_t(xcol[k]) * RS + coff + uint32_t(q) * 16u));
+        acc = vfma(xval[k], xv, acc);
+    }
+}
+
+// bacc += sum over the first nb slots of B(row, slot) Y[col], as vrow_sums: rows from
+// halo rows base + (slot's index >> shift & 0xFF), entries beyond 16 from memory.
+__device__ __forceinline__ void halo_bsums(const HaloBuf &Lb, const uint32_t (&lw)[8], const float *bw, int nb, int q,
+                                           int base, int shift, const float *__restrict__ bslot, int bo,
+                                           const int32_t *__restrict__ xcol, int x0, const char *Yc, uint32_t RS,
+                                           uint32_t coff, F4 &bacc) {
+    constexpr int CH = kHChunk;
+    // re-read the rows from LDS instead of keeping the K sums' reads live (same
+    // addresses in the transposed step)
+    asm volatile("" : "+v"(base));
+#pragma unroll
+    for (int j0 = 0; j0 < 16; j0 += CH) {
+        if (j0 < nb) {
+            F4 y[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                y[j] = F4{};
+                if (j0 + j < nb) y[j] = Lb.rows[(base + ((hloc(lw, j0 + j) >> shift) & 0xFF)) * 16 + q];
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) bacc = vfma(bw[j0 + j], y[j], bacc);
+        }
+    }
+    for (int k = x0; k < x0 + nb - 16; ++k) {
+        const F4 yv = *reinterpret_cast<const F4 *>(Yc + (uint32_t(xcol[k]) * RS + coff + uint32_t(q) * 16u));
+        bacc = vfma(bslot[bo + 16 + (k - x0)], yv, bacc);
+    }
+}
+
+// Row g of the tile in Lb: its loc words, info words, K values and B values.
+struct HRow {
+    uint32_t lw[8];
+    uint4 i0, i1;
+    const float *kv, *bw;
+};
+__device__ __forceinline__ HRow halo_row(const HaloBuf &Lb, int nr, int g) {
+    HRow r;
+    const uint4 *L4 = reinterpret_cast<const uint4 *>(Lb.meta + g * 8);
+    const uint4 a = L4[0], b = L4[1];
+    r.lw[0] = a.x; r.lw[1] = a.y; r.lw[2] = a.z; r.lw[3] = a.w;
+    r.lw[4] = b.x; r.lw[5] = b.y; r.lw[6] = b.z; r.lw[7] = b.w;
+    const uint4 *I4 = reinterpret_cast<const uint4 *>(Lb.meta + nr * 8 + g * 8);
+    r.i0 = I4[0];
+    r.i1 = I4[1];
+    r.kv = reinterpret_cast<const float *>(Lb.meta + nr * 16 + g * 16);
+    const int bwr = int(r.i0.y & 0xFFFFu);
+    r.bw = reinterpret_cast<const float *>(Lb.meta + nr * 32 + (bwr == 0xFFFF ? 0 : bwr) * 16);
+    return r;
+}
+
+// Pipeline of one workgroup over its work items: fn_list(d, list) starts the copy
+// of an item's halo row list, fn_issue(it, d, list, buffer) the copies of its halo
+// and metadata, fn_pre(it, d) loads its own rows into the "next" registers and
+// fn_rot moves them to the "current" ones, fn_compute(it, d, buffer) computes
+// item it into registers and fn_store() writes the last computed item.  While
+// item it is computed, the copies of item it + 1, the row list of item it + 2 and
+// the descriptor of item it + 4 are in flight, and item it - 1's stores drain.
+// Even items use (B0, L0), odd items (B1, L1); the loop is unrolled by two so
+// that each access names its buffer at compile time.
+template <typename List, typename Issue, typename Pre, typename Rot, typename Compute, typename Store>
+__device__ __forceinline__ void halo_loop(const HWork &wk, const int32_t *hdesc, HaloBuf &B0, HaloBuf &B1,
+                                          HaloList &L0, HaloList &L1, List fn_list, Issue fn_issue, Pre fn_pre,
+                                          Rot fn_rot, Compute fn_compute, Store fn_store) {
+    const int n = wk.n;
+    if (n == 0) return;
+    const int4 *D = reinterpret_cast<const int4 *>(hdesc);
+    auto raw = [&](int it) { return it < n ? D[wk.tile(it)] : int4{0, 0, 0, 0}; };
+    HDesc d0 = desc_uniform(raw(0)), d1 = desc_uniform(raw(1)), d2 = desc_uniform(raw(2));
+    fn_list(d0, L0.r);
+    if (1 < n) fn_list(d1, L1.r);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    fn_issue(0, d0, L0.r, B0);
+    fn_pre(0, d0);
+    int4 u3 = raw(3);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies of item 0 have landed
+    __syncthreads();
+    auto step = [&](int it, HaloBuf &Bc, HaloBuf &Bn, HaloList &Lc, HaloList &Ln) {
+        fn_rot();
+        if (it + 1 < n) fn_issue(it + 1, d1, Ln.r, Bn);
+        if (it + 2 < n) fn_list(d2, Lc.r);
+        if (it > 0) fn_store();
+        if (it + 1 < n) fn_pre(it + 1, d1);
+        const int4 u4 = raw(it + 4);
+        fn_compute(it, d0, Bc);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies of item it + 1 and list it + 2 have landed
+        __syncthreads();                     // ... for every wave, and item it's buffer is free
+        d0 = d1;
+        d1 = d2;
+        d2 = desc_uniform(u3);
+        u3 = u4;
+    };
+    for (int it = 0; it < n; it += 2) {
+        step(it, B0, B1, L0, L1);
+        if (it + 1 < n) step(it + 1, B1, B0, L1, L0);
+    }
+    fn_store();
+}
+
+template <typename OT, int RB, bool NT>
+__global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_fwd_h(const VFwdArgs<float> a) {
+    constexpr int NC = RB / 64;
+    constexpr uint32_t RS = uint32_t(RB) * 4u;
+    __shared__ HaloBuf B0, B1;
+    __shared__ HaloList L0, L1;
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63, g = tid >> 4, q = tid & 15;
+    const HWork wk(a.n_ht, NC);
+    const bool with_b = !a.first;
+    const char *Pc = reinterpret_cast<const char *>(a.P);
+    const char *Vc = reinterpret_cast<const char *>(a.V);
+    F4 v_cur = {}, v_nxt = {}, out_v = {}, out_p = {};
+    int64_t out_id = -1;
+    auto fn_list = [&](const HDesc &d, int32_t *list) {
+        halo_list_issue(a.hrow, d, d.nk4 + (with_b ? d.nb4 : 0), list, wave, lane);
+    };
+    auto fn_issue = [&](int it, const HDesc &d, const int32_t *list, HaloBuf &Bn) {
+        halo_issue<RS>(Pc, Vc, uint32_t(wk.chunk(it)) * 256u, a.hmeta, d, d.nk4 + (with_b ? d.nb4 : 0), list, Bn,
+                       wave, lane);
+    };
+    auto fn_pre = [&](int it, const HDesc &d) {
+        if (with_b && g < d.nr)
+            v_nxt = vload_own<NT, F4>(a.V + (int64_t(d.r0 + g) * RB + wk.chunk(it) * 64 + q * 4));
+    };
+    auto fn_rot = [&]() { v_cur = v_nxt; };
+    auto fn_store = [&]() {
+        if (out_id >= 0) {
+            vstore<NT, F4>(a.Vn + out_id, out_v);
+            vstore<NT, F4>(a.Pn + out_id, out_p);
+        }
+    };
+    auto fn_compute = [&](int it, const HDesc &d, const HaloBuf &Lb) {
+        out_id = -1;
+        if (g >= d.nr) return;
+        const uint32_t coff = uint32_t(wk.chunk(it)) * 256u;
+        const HRow r = halo_row(Lb, d.nr, g);
+        const int x0 = int(r.i0.z), x1 = int(r.i0.w);
+        F4 acc = {}, bacc = {}, p0;
+        halo_ksums(Lb, r.lw, r.kv, q, a.o.xval, a.o.xcol, x0, x1, Pc, RS, coff, acc, p0);
+        const int row = d.r0 + g;
+        if (with_b && (r.i0.y & 0xFFFFu) != 0xFFFFu) {
+            const int nb = int(r.i0.y >> 16);
+            const int bo = nb > 16 ? a.o.bsoff[row] : 0;
+            halo_bsums(Lb, r.lw, r.bw, nb, q, d.nk4, 8, a.o.bslot, bo, a.o.xcol, x0, Vc, RS, coff, bacc);
+        }
+        const float dm = __uint_as_float(r.i0.x);
+        const F4 v0 = with_b ? v_cur : F4{};
+        F4 v, pn;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[i] = v0[i] - dm * (acc[i] + bacc[i]);
+            pn[i] = p0[i] + a.dt * v[i];
+        }
+        out_v = v;
+        out_p = pn;
+        out_id = int64_t(row) * RB + wk.chunk(it) * 64 + q * 4;
+    };
+    halo_loop(wk, a.hdesc, B0, B1, L0, L1, fn_list, fn_issue, fn_pre, fn_rot, fn_compute, fn_store);
+    if (a.sample) {
+        // y^n = Pi (P - dt/2 V) of the incoming state, one lane per (sensor, rhs)
+        const int64_t total = int64_t(a.n_obs) * RB;
+        OT *yo = static_cast<OT *>(a.y);
+        for (int64_t e = int64_t(blockIdx.x) * kHThreads + tid; e < total; e += int64_t(gridDim.x) * kHThreads) {
+            const int s = int(e / RB), rr = int(e % RB);
+            float y = 0.0f;
+            for (int k = 0; k < 4; ++k) {
+                const int64_t id = int64_t(a.snode[4 * s + k]) * RB + rr;
+                const float pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
+                y = mad(a.sw[4 * s + k], pk, y);
+            }
+            yo[(int64_t(a.t) * a.n_obs + s) * RB + rr] = static_cast<OT>(static_cast<double>(y) * a.yscale);
+        }
+    }
+}
+
+template <typename YT, int RB, bool NT>
+__global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_adj_h(const VAdjArgs<float> a) {
+    constexpr int NC = RB / 64;
+    constexpr uint32_t RS = uint32_t(RB) * 4u;
+    __shared__ HaloBuf B0, B1;
+    __shared__ HaloList L0, L1;
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63, g = tid >> 4, q = tid & 15;
+    const HWork wk(a.n_ht, NC);
+    const char *Qc = reinterpret_cast<const char *>(a.Q);
+    F4 ph_cur = {}, ph_nxt = {}, out_ph = {}, out_q = {};
+    int64_t out_id = -1;
+    auto fn_list = [&](const HDesc &d, int32_t *list) { halo_list_issue(a.hrow, d, d.nk4, list, wave, lane); };
+    auto fn_issue = [&](int it, const HDesc &d, const int32_t *list, HaloBuf &Bn) {
+        halo_issue<RS>(Qc, Qc, uint32_t(wk.chunk(it)) * 256u, a.hmeta, d, d.nk4, list, Bn, wave, lane);
+    };
+    auto fn_pre = [&](int it, const HDesc &d) {
+        if (g < d.nr) ph_nxt = vload_own<NT, F4>(a.PH + (int64_t(d.r0 + g) * RB + wk.chunk(it) * 64 + q * 4));
+    };
+    auto fn_rot = [&]() { ph_cur = ph_nxt; };
+    auto fn_store = [&]() {
+        if (out_id >= 0) {
+            if (!a.last) vstore<NT, F4>(a.Qn + out_id, out_q);
+            vstore<NT, F4>(a.PH + out_id, out_ph);
+        }
+    };
+    auto fn_compute = [&](int it, const HDesc &d, const HaloBuf &Lb) {
+        out_id = -1;
+        if (g >= d.nr) return;
+        const int c = wk.chunk(it);
+        const uint32_t coff = uint32_t(c) * 256u;
+        const HRow r = halo_row(Lb, d.nr, g);
+        const int x0 = int(r.i0.z), x1 = int(r.i0.w);
+        F4 kq = {}, bq = {}, q0;
+        halo_ksums(Lb, r.lw, r.kv, q, a.o.xval, a.o.xcol, x0, x1, Qc, RS, coff, kq, q0);
+        const int row = d.r0 + g;
+        if (!a.last && (r.i0.y & 0xFFFFu) != 0xFFFFu) {
+            const int nb = int(r.i0.y >> 16);
+            const int bo = nb > 16 ? a.o.bsoff[row] : 0;
+            halo_bsums(Lb, r.lw, r.bw, nb, q, 0, 0, a.o.bslot, bo, a.o.xcol, x0, Qc, RS, coff, bq);
+        }
+        F4 ph;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ph[i] = ph_cur[i] - a.dt * kq[i];
+        if (!a.last) {
+            const float dm = __uint_as_float(r.i0.x);
+            F4 inj = {};
+            const YT *yh = static_cast<const YT *>(a.yh);
+            for (int e = int(r.i1.x); e < int(r.i1.y); ++e) {
+                const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + c * 64 + q * 4;
+                const float w = a.injw[e];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    inj[i] = mad(w, static_cast<float>(static_cast<double>(yh[src + i]) * a.yscale), inj[i]);
+            }
+            F4 qn;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                qn[i] = q0[i] - dm * bq[i] + dm * (ph[i] + 0.5f * inj[i]);
+                ph[i] += inj[i];
+            }
+            out_q = qn;
+        }
+        out_ph = ph;
+        out_id = int64_t(row) * RB + c * 64 + q * 4;
+    };
+    halo_loop(wk, a.hdesc, B0, B1, L0, L1, fn_list, fn_issue, fn_pre, fn_rot, fn_compute, fn_store);
 }
 
 // p_hat = Pi^T yhat^{N_T}, q = (dt/2m) p_hat
@@ -1227,8 +1616,19 @@ VFwdArgs<T> fwd_args_v(const DevOps &op, const void *P, const void *V, void *Pn,
     a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
     a.n_samp = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
     a.stream = state_bytes(op, RB, sizeof(T)) > kInfinityCacheBytes;
+    a.hdesc = op.ht_desc; a.hrow = op.ht_hrow; a.hmeta = op.ht_meta; a.n_ht = op.n_ht;
     *blocks = a.n_tiles + a.n_samp;
     return a;
+}
+
+// workgroups of a halo kernel launch: two per CU, a multiple of the 8 XCDs
+inline int halo_grid(const DevOps &op) { return (2 * op.n_cu + 7) / 8 * 8; }
+
+// the halo kernels take float32 blocks of 256-byte row chunks (rows == false:
+// a sampling-only launch stays with the vector-lane kernel)
+template <typename T, int RB>
+bool use_halo(const DevOps &op, bool rows) {
+    return std::is_same<T, float>::value && RB >= 64 && RB <= 256 && rows && op.n_ht > 0 && op.n_cu > 0;
 }
 
 template <typename T, typename OT, int RB>
@@ -1237,6 +1637,13 @@ void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *
     int grid = 0;
     const VFwdArgs<T> a = fwd_args_v<T, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, &grid);
     if (grid <= 0) return;
+    if constexpr (std::is_same<T, float>::value && RB >= 64 && RB <= 256) {
+        if (use_halo<T, RB>(op, rows)) {
+            if (a.stream) hipLaunchKernelGGL((k_fwd_h<OT, RB, true>), dim3(halo_grid(op)), dim3(kHThreads), 0, s, a);
+            else hipLaunchKernelGGL((k_fwd_h<OT, RB, false>), dim3(halo_grid(op)), dim3(kHThreads), 0, s, a);
+            return;
+        }
+    }
     if (a.stream) hipLaunchKernelGGL((k_fwd_v<T, OT, RB, true>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_fwd_v<T, OT, RB, false>), dim3(grid), dim3(256), 0, s, a);
 }
@@ -1270,6 +1677,7 @@ VAdjArgs<T> adj_args_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool
     a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
     a.dt = T(op.dt);
     a.stream = state_bytes(op, RB, sizeof(T)) > kInfinityCacheBytes;
+    a.hdesc = op.ht_desc; a.hrow = op.ht_hrow; a.hmeta = op.ht_meta; a.n_ht = op.n_ht;
     return a;
 }
 
@@ -1277,6 +1685,13 @@ template <typename T, typename YT, int RB>
 void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
                 double yscale, hipStream_t s) {
     const VAdjArgs<T> a = adj_args_v<T, RB>(op, PH, Q, Qn, last, tm1, yh, yscale);
+    if constexpr (std::is_same<T, float>::value && RB >= 64 && RB <= 256) {
+        if (use_halo<T, RB>(op, true)) {
+            if (a.stream) hipLaunchKernelGGL((k_adj_h<YT, RB, true>), dim3(halo_grid(op)), dim3(kHThreads), 0, s, a);
+            else hipLaunchKernelGGL((k_adj_h<YT, RB, false>), dim3(halo_grid(op)), dim3(kHThreads), 0, s, a);
+            return;
+        }
+    }
     if (a.stream) hipLaunchKernelGGL((k_adj_v<T, YT, RB, true>), dim3(a.n_tiles), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_adj_v<T, YT, RB, false>), dim3(a.n_tiles), dim3(256), 0, s, a);
 }

@@ -552,6 +552,81 @@ void build_padded_rows(HostProblem &hp) {
     }
 }
 
+void build_halo_tiles(const HostProblem &hp, HaloTiles &ht) {
+    const int W = HostProblem::kEll;
+    const int32_t N = hp.n;
+    ht.desc.clear();
+    ht.hrow.clear();
+    ht.meta.clear();
+    auto pad4 = [](size_t k) { return int32_t((k + 3) / 4 * 4); };
+    auto is_bnd = [&](int32_t i) { return hp.bsoff[size_t(i)] >= 0; };
+    // B slots of boundary row i: the first min(bnum, kEll) padded slots
+    auto nbs = [&](int32_t i) { return is_bnd(i) ? std::min(hp.bnum[size_t(i)], W) : 0; };
+    std::vector<int32_t> kc, bc, kt, bt;
+    int32_t r0 = 0;
+    while (r0 < N) {
+        kc.clear();
+        bc.clear();
+        int32_t r1 = r0;
+        while (r1 < N && r1 - r0 < HaloTiles::kRows) {
+            kt = kc;
+            bt = bc;
+            for (int j = 0; j < W; ++j) kt.push_back(hp.ell_col[size_t(r1) * W + j]);
+            for (int j = 0; j < nbs(r1); ++j) bt.push_back(hp.ell_col[size_t(r1) * W + j]);
+            std::sort(kt.begin(), kt.end());
+            kt.erase(std::unique(kt.begin(), kt.end()), kt.end());
+            std::sort(bt.begin(), bt.end());
+            bt.erase(std::unique(bt.begin(), bt.end()), bt.end());
+            if (pad4(kt.size()) + pad4(bt.size()) > HaloTiles::kMax) break;
+            kc.swap(kt);
+            bc.swap(bt);
+            ++r1;
+        }
+        const int32_t nr = r1 - r0, nk4 = pad4(kc.size()), nb4 = pad4(bc.size());
+        static_assert(HaloTiles::kRows < 64 && HaloTiles::kMax < 256, "descriptor fields");
+        const int32_t h0 = int32_t(ht.hrow.size());
+        for (int32_t k = 0; k < nk4; ++k) ht.hrow.push_back(kc[size_t(std::min<int32_t>(k, int32_t(kc.size()) - 1))]);
+        for (int32_t k = 0; k < nb4; ++k) ht.hrow.push_back(bc[size_t(std::min<int32_t>(k, int32_t(bc.size()) - 1))]);
+        int32_t nbr = 0;
+        for (int32_t i = r0; i < r1; ++i) nbr += is_bnd(i) ? 1 : 0;
+        const size_t m0 = ht.meta.size();
+        ht.meta.resize(m0 + size_t(nr) * (8 + 8 + 16) + size_t(nbr) * 16, 0u);
+        uint32_t *loc = ht.meta.data() + m0, *info = loc + size_t(nr) * 8, *kv = info + size_t(nr) * 8,
+                 *bw = kv + size_t(nr) * 16;
+        auto fbits = [](double v) {
+            const float f = float(v);
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            return u;
+        };
+        int32_t br = 0;
+        for (int32_t i = r0; i < r1; ++i) {
+            const size_t li = size_t(i - r0);
+            for (int j = 0; j < W; ++j) {
+                const int32_t c = hp.ell_col[size_t(i) * W + j];
+                uint32_t v = uint32_t(std::lower_bound(kc.begin(), kc.end(), c) - kc.begin());
+                if (j < nbs(i)) v |= uint32_t(std::lower_bound(bc.begin(), bc.end(), c) - bc.begin()) << 8;
+                loc[li * 8 + j / 2] |= v << (16 * (j % 2));
+                kv[li * 16 + j] = fbits(hp.ell_val[size_t(i) * W + j]);
+            }
+            info[li * 8 + 0] = fbits(hp.dt / hp.mass[size_t(i)]);
+            info[li * 8 + 1] = uint32_t(is_bnd(i) ? br : 0xFFFF) | (uint32_t(hp.bnum[size_t(i)]) << 16);
+            info[li * 8 + 2] = uint32_t(hp.xptr[size_t(i)]);
+            info[li * 8 + 3] = uint32_t(hp.xptr[size_t(i) + 1]);
+            info[li * 8 + 4] = uint32_t(hp.injptr[size_t(i)]);
+            info[li * 8 + 5] = uint32_t(hp.injptr[size_t(i) + 1]);
+            if (is_bnd(i)) {
+                for (int j = 0; j < W; ++j) bw[size_t(br) * 16 + j] = fbits(hp.bslot[size_t(hp.bsoff[size_t(i)]) + j]);
+                ++br;
+            }
+        }
+        const int32_t d[4] = {r0, h0, int32_t(m0 / 4), nr | (nk4 << 6) | (nb4 << 14) | (nbr << 22)};
+        ht.desc.insert(ht.desc.end(), d, d + 4);
+        r0 = r1;
+    }
+    ht.n_tiles = int32_t(ht.desc.size() / 4);
+}
+
 namespace {
 void spmv_host(const HostProblem &hp, const std::vector<double> &val, const std::vector<double> &x,
                std::vector<double> &y) {
