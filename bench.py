@@ -75,10 +75,14 @@ def stored_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(w, eta, xi, yobs, sigma, n_iter, R, n_steps_sample=350, iters_sample=3):
-    """Oracle (plain CPU FP64) on a bounded sample of the same workload (about 10 s of CPU work), scaled
-    to samples/min by sweep-steps.  Linear scaling leaves out the reorthogonalisation's growth with the
-    iteration count, so it flatters the oracle."""
+def cpu_baseline(w, eta, xi, yobs, sigma, n_iter, R, n_steps_sample=350, iters_sample=3, reorth_iters=6,
+                 reorth_steps=10):
+    """Oracle (plain CPU FP64) on a bounded sample of the same workload, extrapolated to the full batch.
+
+    The sweeps scale with sweep-steps; the reorthogonalisation of iteration j projects against j basis
+    vectors, so its cost grows with the iteration count.  It is measured on its own: two short runs
+    (reorth_iters iterations over reorth_steps steps, with and without reorthogonalisation) give the
+    cost of one basis-vector pass, and the full batch adds that cost times 1 + 2 + ... + n_iter."""
     import oracle
     t0 = time.time()
     P = oracle.Problem.from_workload(w, n_steps=n_steps_sample)
@@ -86,15 +90,31 @@ def cpu_baseline(w, eta, xi, yobs, sigma, n_iter, R, n_steps_sample=350, iters_s
     t0 = time.time()
     P.rto(yobs[:n_steps_sample], sigma, w.prior_a, iters_sample, eta[:R, :n_steps_sample], xi[:R])
     el = time.time() - t0
+    # the reorthogonalisation's cost per basis vector, from a short run with and without it
+    Pr = oracle.Problem.from_workload(w, n_steps=reorth_steps)
+    t0 = time.time()
+    Pr.rto(yobs[:reorth_steps], sigma, w.prior_a, reorth_iters, eta[:R, :reorth_steps], xi[:R], reorth=True)
+    t_on = time.time() - t0
+    t0 = time.time()
+    Pr.rto(yobs[:reorth_steps], sigma, w.prior_a, reorth_iters, eta[:R, :reorth_steps], xi[:R], reorth=False)
+    t_off = time.time() - t0
+    per_vec = max(t_on - t_off, 0.0) / (reorth_iters * (reorth_iters + 1) / 2)
     sweeps_sample = 2 * iters_sample
     sweeps_full = 2 * n_iter
-    t_batch = el * (sweeps_full / sweeps_sample) * (w.n_steps / n_steps_sample)
+    t_sweeps = (el - per_vec * iters_sample * (iters_sample + 1) / 2) * (sweeps_full / sweeps_sample) * \
+        (w.n_steps / n_steps_sample)
+    t_reorth = per_vec * n_iter * (n_iter + 1) / 2
+    t_batch = t_sweeps + t_reorth
     return {
         "value": round(R / t_batch * 60.0, 6), "unit": "samples/min", "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"oracle RTO on the same mesh with {R} RHS, {iters_sample} CGLS iterations x {n_steps_sample} steps "
-                   f"({el:.1f} s, setup {setup:.1f} s excluded), scaled by sweep-steps to {n_iter} iterations x "
-                   f"{w.n_steps} steps"),
+        "sample": (f"oracle RTO on the same mesh with {R} RHS: {iters_sample} CGLS iterations x {n_steps_sample} "
+                   f"steps ({el:.1f} s, setup {setup:.1f} s excluded) scaled by sweep-steps to {n_iter} iterations x "
+                   f"{w.n_steps} steps ({t_sweeps:.0f} s), plus the reorthogonalisation measured from "
+                   f"{reorth_iters}-iteration runs over {reorth_steps} steps with and without it "
+                   f"({t_on:.1f} / {t_off:.1f} s: {per_vec:.3f} s per basis-vector pass) grown to {n_iter} "
+                   f"iterations ({t_reorth:.0f} s)"),
+        "extrapolated_batch_s": round(t_batch, 1),
     }
 
 

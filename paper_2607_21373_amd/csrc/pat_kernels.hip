@@ -669,6 +669,7 @@ constexpr int kHThreads = kHRows * 16;
 constexpr int kHWaves = kHThreads / 64;
 constexpr int kHPerWave = (kHMax / 4 + kHWaves - 1) / kHWaves;  // halo copy instructions per wave at most
 constexpr int kHChunk = 4;  // LDS reads in flight per lane before they are consumed
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 static_assert(kHThreads == 512 && kHMetaWords / 256 <= kHWaves, "halo tile geometry");
 
 // LDS image of one tile
@@ -730,18 +731,21 @@ template <uint32_t RS>
 __device__ __forceinline__ void halo_issue(const char *X, const char *Y, uint32_t coff, const uint32_t *hmeta,
                                            const HDesc &d, int nh, const int32_t *list, HaloBuf &Lb, int wave,
                                            int lane) {
+    // wave is wave-uniform (callers pass it through readfirstlane), so the tests and
+    // the base select below are scalar; the list entries are read in one batch
     int hr[kHPerWave];
 #pragma unroll
     for (int m = 0; m < kHPerWave; ++m) {
         const int h = wave + kHWaves * m;
-        hr[m] = 4 * h < nh ? list[4 * h + (lane >> 4)] : 0;
+        hr[m] = list[min(4 * h, kHMax - 4) + (lane >> 4)];
     }
+    const uint32_t lo = coff + uint32_t(lane & 15) * 16u;
 #pragma unroll
     for (int m = 0; m < kHPerWave; ++m) {
         const int h = wave + kHWaves * m;
         if (4 * h < nh) {
             const char *base = 4 * h < d.nk4 ? X : Y;
-            lds_copy16(base + (uint32_t(hr[m]) * RS + coff + uint32_t(lane & 15) * 16u), &Lb.rows[h * 64]);
+            lds_copy16(base + (uint32_t(hr[m]) * RS + lo), &Lb.rows[h * 64]);
         }
     }
     const int nu = d.mbytes >> 4, u = kHWaves - 1 - wave;  // metadata: 16-byte units, 64 per instruction
@@ -749,79 +753,102 @@ __device__ __forceinline__ void halo_issue(const char *X, const char *Y, uint32_
         lds_copy16(hmeta + 4 * (int64_t(d.moff) + u * 64 + lane), &Lb.meta[u * 256]);
 }
 
-// 16-bit slot entry j of a row's loc words
-__device__ __forceinline__ int hloc(const uint32_t (&lw)[8], int j) { return int((lw[j >> 1] >> (16 * (j & 1))) & 0xFFFFu); }
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B, B + S, ... < E.
+template <int B, int E, int S = 1, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + S, E, S>(f);
+    }
+}
+
+// Lane J of this lane's row of 16 lanes (DPP row broadcast): the 16 lanes of a row
+// group each hold one slot's operands and hand them to the group slot by slot.
+template <int J>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t x) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x150 + J, 0xF, 0xF, true));
+}
+template <int J>
+__device__ __forceinline__ float row_bcast(float x) {
+    return __uint_as_float(row_bcast<J>(__float_as_uint(x)));
+}
+
+// The operands of row g of the tile in Lb as held by lane q of its row group:
+// slot q's K value and halo byte offsets, info word q % 8, and (boundary rows) slot
+// q's B value.  Per-row values come from the info words by row broadcast.
+struct HLane {
+    uint32_t koff, boff;  // byte offsets of slot q's neighbour in the K and B parts of the halo
+    float kv, bw;
+    uint32_t info;
+};
+__device__ __forceinline__ HLane halo_lane(const HaloBuf &Lb, int nr, int g, int q, int bbase) {
+    HLane h;
+    const uint32_t loc = reinterpret_cast<const uint16_t *>(Lb.meta + g * 8)[q];
+    h.koff = (loc & 0xFFu) * 256u;
+    h.boff = (uint32_t(bbase) + (loc >> 8)) * 256u;
+    h.kv = reinterpret_cast<const float *>(Lb.meta + nr * 16 + g * 16)[q];
+    h.info = Lb.meta[nr * 8 + g * 8 + (q & 7)];
+    h.bw = 0.0f;
+    return h;
+}
+// per-row values from the info words: dt/m, boundary word, overflow and injection ranges
+__device__ __forceinline__ float hl_dm(const HLane &h) { return __uint_as_float(row_bcast<0>(h.info)); }
+__device__ __forceinline__ uint32_t hl_bword(const HLane &h) { return row_bcast<1>(h.info); }
+__device__ __forceinline__ int hl_x0(const HLane &h) { return int(row_bcast<2>(h.info)); }
+__device__ __forceinline__ int hl_x1(const HLane &h) { return int(row_bcast<3>(h.info)); }
+__device__ __forceinline__ int hl_inj0(const HLane &h) { return int(row_bcast<4>(h.info)); }
+__device__ __forceinline__ int hl_inj1(const HLane &h) { return int(row_bcast<5>(h.info)); }
+
+__device__ __forceinline__ F4 lds_row(const HaloBuf &Lb, uint32_t off) {
+    return *reinterpret_cast<const F4 *>(reinterpret_cast<const char *>(Lb.rows) + off);
+}
 
 // acc += sum_slots K(row, slot) X[col] from the halo, slot order as vrow_sums, then
 // the entries beyond 16 from memory; own = slot 0 (the row's diagonal).
-__device__ __forceinline__ void halo_ksums(const HaloBuf &Lb, const uint32_t (&lw)[8], const float *kv, int q,
-                                           const float *__restrict__ xval, const int32_t *__restrict__ xcol, int x0,
-                                           int x1, const char *Xc, uint32_t RS, uint32_t coff, F4 &acc,
-                                           F4 &own) {
-    constexpr int CH = kHChunk;
-#pragma unroll
-    for (int j0 = 0; j0 < 16; j0 += CH) {
-        F4 x[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) x[j] = Lb.rows[(hloc(lw, j0 + j) & 0xFF) * 16 + q];
-        if (j0 == 0) own = x[0];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) acc = vfma(kv[j0 + j], x[j], acc);
-    }
+__device__ __forceinline__ void halo_ksums(const HaloBuf &Lb, const HLane &h, uint32_t q16, int x0, int x1,
+                                           const float *__restrict__ xval, const int32_t *__restrict__ xcol,
+                                           const char *Xc, uint32_t RS, uint32_t coff, F4 &acc, F4 &own) {
+    static_for<0, 16, kHChunk>([&](auto J0) {
+        constexpr int j0 = decltype(J0)::value;
+        F4 x[kHChunk];
+        static_for<0, kHChunk>([&](auto J) { x[J.value] = lds_row(Lb, row_bcast<j0 + J.value>(h.koff) + q16); });
+        if constexpr (j0 == 0) own = x[0];
+        static_for<0, kHChunk>([&](auto J) { acc = vfma(row_bcast<j0 + J.value>(h.kv), x[J.value], acc); });
+    });
     for (int k = x0; k < x1; ++k) {
-        const F4 xv = *reinterpret_cast<const F4 *>(Xc + (uint32_t(xcol[k]) * RS + coff + uint32_t(q) * 16u));
+        const F4 xv = *reinterpret_cast<const F4 *>(Xc + (uint32_t(xcol[k]) * RS + coff + q16));
         acc = vfma(xval[k], xv, acc);
     }
 }
 
-// bacc += sum over the first nb slots of B(row, slot) Y[col], as vrow_sums: rows from
-// halo rows base + (slot's index >> shift & 0xFF), entries beyond 16 from memory.
-__device__ __forceinline__ void halo_bsums(const HaloBuf &Lb, const uint32_t (&lw)[8], const float *bw, int nb, int q,
-                                           int base, int shift, const float *__restrict__ bslot, int bo,
-                                           const int32_t *__restrict__ xcol, int x0, const char *Yc, uint32_t RS,
-                                           uint32_t coff, F4 &bacc) {
-    constexpr int CH = kHChunk;
+// bacc += sum over the first nb slots of B(row, slot) Y[col], as vrow_sums: each slot's
+// row at byte offset off (this lane's slot: offq) of the halo, entries beyond 16 from
+// memory.  bwq: this lane's slot's B value.
+__device__ __forceinline__ void halo_bsums(const HaloBuf &Lb, uint32_t offq, float bwq, int nb, uint32_t q16,
+                                           const float *__restrict__ bslot, int bo, const int32_t *__restrict__ xcol,
+                                           int x0, const char *Yc, uint32_t RS, uint32_t coff, F4 &bacc) {
     // re-read the rows from LDS instead of keeping the K sums' reads live (same
     // addresses in the transposed step)
-    asm volatile("" : "+v"(base));
-#pragma unroll
-    for (int j0 = 0; j0 < 16; j0 += CH) {
+    asm volatile("" : "+v"(offq));
+    // slots j >= nb carry B = 0: the vector-lane kernels add 0 * 0 there, which leaves
+    // bacc unchanged (it starts at +0 and a sum that starts at +0 never becomes -0),
+    // so skipping them keeps the bits
+    static_for<0, 16, kHChunk>([&](auto J0) {
+        constexpr int j0 = decltype(J0)::value;
         if (j0 < nb) {
-            F4 y[CH];
-#pragma unroll
-            for (int j = 0; j < CH; ++j) {
-                y[j] = F4{};
-                if (j0 + j < nb) y[j] = Lb.rows[(base + ((hloc(lw, j0 + j) >> shift) & 0xFF)) * 16 + q];
-            }
-#pragma unroll
-            for (int j = 0; j < CH; ++j) bacc = vfma(bw[j0 + j], y[j], bacc);
+            F4 y[kHChunk];
+            static_for<0, kHChunk>([&](auto J) {
+                if (j0 + J.value < nb) y[J.value] = lds_row(Lb, row_bcast<j0 + J.value>(offq) + q16);
+            });
+            static_for<0, kHChunk>([&](auto J) {
+                if (j0 + J.value < nb) bacc = vfma(row_bcast<j0 + J.value>(bwq), y[J.value], bacc);
+            });
         }
-    }
+    });
     for (int k = x0; k < x0 + nb - 16; ++k) {
-        const F4 yv = *reinterpret_cast<const F4 *>(Yc + (uint32_t(xcol[k]) * RS + coff + uint32_t(q) * 16u));
+        const F4 yv = *reinterpret_cast<const F4 *>(Yc + (uint32_t(xcol[k]) * RS + coff + q16));
         bacc = vfma(bslot[bo + 16 + (k - x0)], yv, bacc);
     }
-}
-
-// Row g of the tile in Lb: its loc words, info words, K values and B values.
-struct HRow {
-    uint32_t lw[8];
-    uint4 i0, i1;
-    const float *kv, *bw;
-};
-__device__ __forceinline__ HRow halo_row(const HaloBuf &Lb, int nr, int g) {
-    HRow r;
-    const uint4 *L4 = reinterpret_cast<const uint4 *>(Lb.meta + g * 8);
-    const uint4 a = L4[0], b = L4[1];
-    r.lw[0] = a.x; r.lw[1] = a.y; r.lw[2] = a.z; r.lw[3] = a.w;
-    r.lw[4] = b.x; r.lw[5] = b.y; r.lw[6] = b.z; r.lw[7] = b.w;
-    const uint4 *I4 = reinterpret_cast<const uint4 *>(Lb.meta + nr * 8 + g * 8);
-    r.i0 = I4[0];
-    r.i1 = I4[1];
-    r.kv = reinterpret_cast<const float *>(Lb.meta + nr * 16 + g * 16);
-    const int bwr = int(r.i0.y & 0xFFFFu);
-    r.bw = reinterpret_cast<const float *>(Lb.meta + nr * 32 + (bwr == 0xFFFF ? 0 : bwr) * 16);
-    return r;
 }
 
 // Pipeline of one workgroup over its work items: fn_list(d, list) starts the copy
@@ -880,13 +907,14 @@ k_fwd_h(const VFwdArgs<float> a) {
     constexpr uint32_t RS = uint32_t(RB) * 4u;
     __shared__ HaloBuf B0, B1;
     __shared__ HaloList L0, L1;
-    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63, g = tid >> 4, q = tid & 15;
+    const int tid = int(threadIdx.x), wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, g = tid >> 4,
+              q = tid & 15;
     const HWork wk(a.n_ht, NC);
     const bool with_b = !a.first;
     const char *Pc = reinterpret_cast<const char *>(a.P);
     const char *Vc = reinterpret_cast<const char *>(a.V);
     F4 v_cur = {}, v_nxt = {}, out_v = {}, out_p = {};
-    int64_t out_id = -1;
+    uint32_t out_id = kNoRow;  // byte offset of the pending result, kNoRow: none
     auto fn_list = [&](const HDesc &d, int32_t *list) {
         halo_list_issue(a.hrow, d, d.nk4 + (with_b ? d.nb4 : 0), list, wave, lane);
     };
@@ -896,30 +924,33 @@ k_fwd_h(const VFwdArgs<float> a) {
     };
     auto fn_pre = [&](int it, const HDesc &d) {
         if (with_b && g < d.nr)
-            v_nxt = vload_own<NT, F4>(a.V + (int64_t(d.r0 + g) * RB + wk.chunk(it) * 64 + q * 4));
+            v_nxt = vload_own<NT, F4>(reinterpret_cast<const float *>(
+                Vc + (uint32_t(d.r0 + g) * RS + uint32_t(wk.chunk(it)) * 256u + uint32_t(q) * 16u)));
     };
     auto fn_rot = [&]() { v_cur = v_nxt; };
     auto fn_store = [&]() {
-        if (out_id >= 0) {
-            vstore<NT, F4>(a.Vn + out_id, out_v);
-            vstore<NT, F4>(a.Pn + out_id, out_p);
+        if (out_id != kNoRow) {
+            vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.Vn) + out_id), out_v);
+            vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.Pn) + out_id), out_p);
         }
     };
     auto fn_compute = [&](int it, const HDesc &d, const HaloBuf &Lb) {
-        out_id = -1;
+        out_id = kNoRow;
         if (g >= d.nr) return;
-        const uint32_t coff = uint32_t(wk.chunk(it)) * 256u;
-        const HRow r = halo_row(Lb, d.nr, g);
-        const int x0 = int(r.i0.z), x1 = int(r.i0.w);
+        const uint32_t coff = uint32_t(wk.chunk(it)) * 256u, q16 = uint32_t(q) * 16u;
+        HLane h = halo_lane(Lb, d.nr, g, q, d.nk4);
+        const int x0 = hl_x0(h), x1 = hl_x1(h);
         F4 acc = {}, bacc = {}, p0;
-        halo_ksums(Lb, r.lw, r.kv, q, a.o.xval, a.o.xcol, x0, x1, Pc, RS, coff, acc, p0);
+        halo_ksums(Lb, h, q16, x0, x1, a.o.xval, a.o.xcol, Pc, RS, coff, acc, p0);
         const int row = d.r0 + g;
-        if (with_b && (r.i0.y & 0xFFFFu) != 0xFFFFu) {
-            const int nb = int(r.i0.y >> 16);
+        const uint32_t bword = hl_bword(h);
+        if (with_b && (bword & 0xFFFFu) != 0xFFFFu) {
+            const int nb = int(bword >> 16);
             const int bo = nb > 16 ? a.o.bsoff[row] : 0;
-            halo_bsums(Lb, r.lw, r.bw, nb, q, d.nk4, 8, a.o.bslot, bo, a.o.xcol, x0, Vc, RS, coff, bacc);
+            const float bwq = reinterpret_cast<const float *>(Lb.meta + d.nr * 32 + int(bword & 0xFFFFu) * 16)[q];
+            halo_bsums(Lb, h.boff, bwq, nb, q16, a.o.bslot, bo, a.o.xcol, x0, Vc, RS, coff, bacc);
         }
-        const float dm = __uint_as_float(r.i0.x);
+        const float dm = hl_dm(h);
         const F4 v0 = with_b ? v_cur : F4{};
         F4 v, pn;
 #pragma unroll
@@ -929,7 +960,7 @@ k_fwd_h(const VFwdArgs<float> a) {
         }
         out_v = v;
         out_p = pn;
-        out_id = int64_t(row) * RB + wk.chunk(it) * 64 + q * 4;
+        out_id = uint32_t(row) * RS + coff + q16;
     };
     halo_loop(wk, a.hdesc, B0, B1, L0, L1, fn_list, fn_issue, fn_pre, fn_rot, fn_compute, fn_store);
     if (a.sample) {
@@ -956,48 +987,55 @@ k_adj_h(const VAdjArgs<float> a) {
     constexpr uint32_t RS = uint32_t(RB) * 4u;
     __shared__ HaloBuf B0, B1;
     __shared__ HaloList L0, L1;
-    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63, g = tid >> 4, q = tid & 15;
+    const int tid = int(threadIdx.x), wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, g = tid >> 4,
+              q = tid & 15;
     const HWork wk(a.n_ht, NC);
     const char *Qc = reinterpret_cast<const char *>(a.Q);
     F4 ph_cur = {}, ph_nxt = {}, out_ph = {}, out_q = {};
-    int64_t out_id = -1;
+    uint32_t out_id = kNoRow;  // byte offset of the pending result, kNoRow: none
     auto fn_list = [&](const HDesc &d, int32_t *list) { halo_list_issue(a.hrow, d, d.nk4, list, wave, lane); };
     auto fn_issue = [&](int it, const HDesc &d, const int32_t *list, HaloBuf &Bn) {
         halo_issue<RS>(Qc, Qc, uint32_t(wk.chunk(it)) * 256u, a.hmeta, d, d.nk4, list, Bn, wave, lane);
     };
     auto fn_pre = [&](int it, const HDesc &d) {
-        if (g < d.nr) ph_nxt = vload_own<NT, F4>(a.PH + (int64_t(d.r0 + g) * RB + wk.chunk(it) * 64 + q * 4));
+        if (g < d.nr)
+            ph_nxt = vload_own<NT, F4>(reinterpret_cast<const float *>(
+                reinterpret_cast<const char *>(a.PH) + (uint32_t(d.r0 + g) * RS + uint32_t(wk.chunk(it)) * 256u +
+                                                        uint32_t(q) * 16u)));
     };
     auto fn_rot = [&]() { ph_cur = ph_nxt; };
     auto fn_store = [&]() {
-        if (out_id >= 0) {
-            if (!a.last) vstore<NT, F4>(a.Qn + out_id, out_q);
-            vstore<NT, F4>(a.PH + out_id, out_ph);
+        if (out_id != kNoRow) {
+            if (!a.last) vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.Qn) + out_id), out_q);
+            vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.PH) + out_id), out_ph);
         }
     };
     auto fn_compute = [&](int it, const HDesc &d, const HaloBuf &Lb) {
-        out_id = -1;
+        out_id = kNoRow;
         if (g >= d.nr) return;
         const int c = wk.chunk(it);
-        const uint32_t coff = uint32_t(c) * 256u;
-        const HRow r = halo_row(Lb, d.nr, g);
-        const int x0 = int(r.i0.z), x1 = int(r.i0.w);
+        const uint32_t coff = uint32_t(c) * 256u, q16 = uint32_t(q) * 16u;
+        HLane h = halo_lane(Lb, d.nr, g, q, 0);
+        const int x0 = hl_x0(h), x1 = hl_x1(h);
         F4 kq = {}, bq = {}, q0;
-        halo_ksums(Lb, r.lw, r.kv, q, a.o.xval, a.o.xcol, x0, x1, Qc, RS, coff, kq, q0);
+        halo_ksums(Lb, h, q16, x0, x1, a.o.xval, a.o.xcol, Qc, RS, coff, kq, q0);
         const int row = d.r0 + g;
-        if (!a.last && (r.i0.y & 0xFFFFu) != 0xFFFFu) {
-            const int nb = int(r.i0.y >> 16);
+        const uint32_t bword = hl_bword(h);
+        if (!a.last && (bword & 0xFFFFu) != 0xFFFFu) {
+            const int nb = int(bword >> 16);
             const int bo = nb > 16 ? a.o.bsoff[row] : 0;
-            halo_bsums(Lb, r.lw, r.bw, nb, q, 0, 0, a.o.bslot, bo, a.o.xcol, x0, Qc, RS, coff, bq);
+            const float bwq = reinterpret_cast<const float *>(Lb.meta + d.nr * 32 + int(bword & 0xFFFFu) * 16)[q];
+            halo_bsums(Lb, h.koff, bwq, nb, q16, a.o.bslot, bo, a.o.xcol, x0, Qc, RS, coff, bq);
         }
         F4 ph;
 #pragma unroll
         for (int i = 0; i < 4; ++i) ph[i] = ph_cur[i] - a.dt * kq[i];
         if (!a.last) {
-            const float dm = __uint_as_float(r.i0.x);
+            const float dm = hl_dm(h);
             F4 inj = {};
             const YT *yh = static_cast<const YT *>(a.yh);
-            for (int e = int(r.i1.x); e < int(r.i1.y); ++e) {
+            const int e1 = hl_inj1(h);
+            for (int e = hl_inj0(h); e < e1; ++e) {
                 const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + c * 64 + q * 4;
                 const float w = a.injw[e];
 #pragma unroll
@@ -1013,7 +1051,7 @@ k_adj_h(const VAdjArgs<float> a) {
             out_q = qn;
         }
         out_ph = ph;
-        out_id = int64_t(row) * RB + c * 64 + q * 4;
+        out_id = uint32_t(row) * RS + coff + q16;
     };
     halo_loop(wk, a.hdesc, B0, B1, L0, L1, fn_list, fn_issue, fn_pre, fn_rot, fn_compute, fn_store);
 }

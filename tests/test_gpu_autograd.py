@@ -11,7 +11,9 @@ Checks:
     App. A with eta = xi = 0);
   * at full size, the objective decreases monotonically, and 200 CGLS steps
     reach a lower objective than 200 descent steps (CGLS minimises over the
-    Krylov space that contains the descent iterate).
+    Krylov space that contains the descent iterate);
+  * float32 autograd at full size: forward and gradient against the oracle's
+    maps of the same inputs, and the transpose identity through autograd.
 """
 import numpy as np
 import pytest
@@ -92,6 +94,44 @@ def test_transpose_through_autograd(small, dtype):
     assert abs(lhs - rhs) <= tol * abs(lhs)
     ref = O.adjoint(yh.double().cpu().numpy())
     assert np.abs(gp.double().cpu().numpy() - ref).max() <= (1e-11 if dtype == torch.float64 else 2e-5) * np.abs(ref).max()
+
+
+def test_autograd_float32_fullsize():
+    """Float32 autograd on the 195,112-node ball: y = G p through PatForward and the gradient of
+    <y, yhat> (the transpose sweep as backward) for two float32 RHS, against the oracle's float64 maps
+    of the same float32-rounded inputs on RHS 0 and 1 (1e-4 of the largest entry, the float32 sweep
+    bar; Sec. 3 eq. (discrete-wave-matrix), Sec. 5.1 eq. (adjoint-verlet)), and the transpose identity
+    through autograd within the bound the measured errors of the two maps imply."""
+    w = W.make_workload("ball58_fp64")
+    O = oracle.Problem.from_workload(w)
+    G = pat.Problem.from_workload(w)
+    rng = np.random.default_rng(34)
+    p = rng.standard_normal((2, w.n_nodes)).astype(np.float32)
+    yh = rng.standard_normal((2, w.n_steps, w.n_obs)).astype(np.float32)
+    pt = _dev(p, torch.float32).requires_grad_(True)
+    y = ag.PatForward.apply(pt, G)
+    assert y.dtype == torch.float32
+    s = torch.sum(y * _dev(yh, torch.float32))
+    (gp,) = torch.autograd.grad(s, pt)
+    y_np, g_np = y.detach().double().cpu().numpy(), gp.double().cpu().numpy()
+    ref_ys = O.forward(p.astype(np.float64))
+    ref_gs = O.adjoint(yh.astype(np.float64))
+    # <G p, yh> = <p, G^T yh> for the oracle's maps, so the GPU's defect is at most
+    # |<y - G p, yh>| + |<p, g - G^T yh>| <= ||y - G p|| ||yh|| + ||p|| ||g - G^T yh||
+    # (plus the float64 rounding of the two sums and of the oracle's own identity)
+    yh64, p64 = yh.astype(np.float64), p.astype(np.float64)
+    bound = (np.linalg.norm(y_np - ref_ys) * np.linalg.norm(yh64) + np.linalg.norm(p64) * np.linalg.norm(g_np - ref_gs)
+             + 1e-12 * (float(np.sum(np.abs(ref_ys * yh64))) + float(np.sum(np.abs(p64 * ref_gs)))))
+    for r in (0, 1):
+        ref_y, ref_g = ref_ys[r], ref_gs[r]
+        ey = np.abs(y_np[r] - ref_y).max() / np.abs(ref_y).max()
+        eg = np.abs(g_np[r] - ref_g).max() / np.abs(ref_g).max()
+        print(f"RHS {r}: forward {ey:.2e}, gradient {eg:.2e}")
+        assert ey < 1e-4 and eg < 1e-4
+    lhs = float(np.sum(y_np * yh.astype(np.float64)))
+    rhs = float(np.sum(p.astype(np.float64) * g_np))
+    print(f"transpose identity defect {abs(lhs - rhs):.3e}, bound {bound:.3e}")
+    assert abs(lhs - rhs) <= bound
 
 
 def test_map_descent_matches_oracle_iteration(small):
