@@ -1576,6 +1576,14 @@ pat_status pat_spectral_prior_set(pat_problem *p, const pat_spectral_desc *d) {
     }
     const double c = d->sigma * std::sqrt(double(G) / sum);
     for (double &v : amp) v *= c;
+    // the z pass reads a(k) line by line on the half spectrum: store it as
+    // [(ky * nh + kx) * n + kz] for kx < nh = n/2 + 1, so each line's n values are contiguous
+    const int nh = n / 2 + 1;
+    std::vector<double> ampz(size_t(n) * nh * n);
+    for (int ky = 0; ky < n; ++ky)
+        for (int kx = 0; kx < nh; ++kx)
+            for (int kz = 0; kz < n; ++kz)
+                ampz[(size_t(ky) * nh + kx) * n + kz] = amp[(size_t(kz) * n + ky) * n + kx];
     std::vector<double> tw(static_cast<size_t>(n));  // (re, im) pairs of exp(-2 pi i j / n), j < n/2
     for (int j = 0; j < n / 2; ++j) {
         tw[size_t(2 * j)] = std::cos(2.0 * M_PI * j / n);
@@ -1625,7 +1633,7 @@ pat_status pat_spectral_prior_set(pat_problem *p, const pat_spectral_desc *d) {
         return st;
     };
     pat_status st = PAT_OK;
-    if (st == PAT_OK) st = up(amp, &so.amp);
+    if (st == PAT_OK) st = up(ampz, &so.amp);
     if (st == PAT_OK) st = up(tw, &so.tw);
     if (st == PAT_OK) st = up(ig, &so.ig);
     if (st == PAT_OK) st = up(iw, &so.iw);

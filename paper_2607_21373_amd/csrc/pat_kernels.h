@@ -83,7 +83,7 @@ void launch_adj_multi(Prec prec, int RB, bool y_is_f64, const AdjStep *st, int n
 struct SpecOps {
     int n = 0, logn = 0;
     int64_t G = 0;
-    const double *amp = nullptr;                   // a(k) [G]
+    const double *amp = nullptr;                   // a(k) on the half spectrum, [ky][kx < n/2 + 1][kz]
     const double *tw = nullptr;                    // exp(-2 pi i j / n), j < n/2, as (re, im) pairs
     const int32_t *ig = nullptr;                   // [N][8] grid corners of each (internal) node
     const double *iw = nullptr;                    // [N][8] trilinear weights

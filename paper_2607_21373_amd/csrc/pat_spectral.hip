@@ -37,6 +37,9 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 conjg(double2 a) { return make_double2(a.x, -a.y); }
 
 constexpr int kRC = 16;  // right-hand sides per workgroup
+// elements a thread stages between global memory and LDS at most: n * RC / 256
+// (n <= 128 points per line, RC <= 16), all loads issued before any is consumed
+constexpr int kPer = 128 * kRC / 256;
 
 enum : int { kForward = 0, kInverse = 1, kCentre = 2 };
 
@@ -46,7 +49,7 @@ struct FftPass {
     double2 *cout;       // complex half-spectrum output, or null
     double *rout;        // real output (x pass, inverse), or null
     const double *add;   // added to the real output, or null
-    const double *amp;   // a(k) [G] (full grid index) for the centre pass
+    const double *amp;   // a(k) for the centre pass, [(ky * nh + kx) * n + kz]: z lines contiguous
     const double2 *tw;   // tw[j] = exp(-2 pi i j / n), j < n/2
     int n, RB, axis, mode;
 };
@@ -188,27 +191,52 @@ __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
     const int L = blockIdx.x, i = L % nh, q = L / nh;  // line (q, i): q = k (axis 1) or j (axis 2)
     const int64_t g0 = a.axis == 1 ? int64_t(q) * n * nh + i : int64_t(q) * nh + i;
     const int64_t ls = a.axis == 1 ? nh : int64_t(n) * nh;
-    for (int e = threadIdx.x; e < n * RC; e += 256) {
-        const int t = e / RC, r = e % RC;
-        X[r * stride + pidx(t)] = a.cin[(g0 + t * ls) * a.RB + rc0 + r];
+    {
+        double2 v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * 256, t = e / RC, r = e % RC;
+            double2 x = make_double2(0.0, 0.0);
+            if (e < n * RC) x = a.cin[(g0 + t * ls) * a.RB + rc0 + r];
+            v[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * 256, t = e / RC, r = e % RC;
+            if (e < n * RC) X[r * stride + pidx(t)] = v[u];
+        }
     }
     __syncthreads();
     if (a.mode != kInverse) line_fft<false>(X, stride, n, RC, tws);
     if (a.mode == kCentre) {
-        // a(k) at (kx, ky, kz) = (i, q, t) of the full n^3 grid
-        for (int e = threadIdx.x; e < n * RC; e += 256) {
-            const int r = e / n, t = e % n;
-            const double w = a.amp[(int64_t(t) * n + q) * n + i];
-            X[r * stride + pidx(t)] = make_double2(w * X[r * stride + pidx(t)].x, w * X[r * stride + pidx(t)].y);
+        // a(k) at (kx, ky, kz) = (i, q, t): line L = q * nh + i of the z-ordered table
+        double w[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * 256, t = e % n;
+            double x = 0.0;
+            if (e < n * RC) x = a.amp[int64_t(L) * n + t];
+            w[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * 256, r = e / n, t = e % n;
+            if (e < n * RC) {
+                const double2 x = X[r * stride + pidx(t)];
+                X[r * stride + pidx(t)] = make_double2(w[u] * x.x, w[u] * x.y);
+            }
         }
         __syncthreads();
     }
     if (a.mode != kForward) line_fft<true>(X, stride, n, RC, tws);
     const double sc = a.mode == kForward ? 1.0 : 1.0 / n;
-    for (int e = threadIdx.x; e < n * RC; e += 256) {
-        const int t = e / RC, r = e % RC;
-        const double2 v = X[r * stride + pidx(t)];
-        a.cout[(g0 + t * ls) * a.RB + rc0 + r] = make_double2(sc * v.x, sc * v.y);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * 256, t = e / RC, r = e % RC;
+        if (e < n * RC) {
+            const double2 v = X[r * stride + pidx(t)];
+            a.cout[(g0 + t * ls) * a.RB + rc0 + r] = make_double2(sc * v.x, sc * v.y);
+        }
     }
 }
 
@@ -228,11 +256,36 @@ __global__ void __launch_bounds__(256) k_fft_x(const FftPass a) {
     const int RC = a.RB < kRC ? a.RB : kRC;
     const int rc0 = blockIdx.y * RC;
     const int64_t L = blockIdx.x;  // line (k, j): real points g = L*n + t, spectrum h = L*nh + k
+    constexpr int kPerX = kPer / 2;  // m * RC / 256 elements per thread at most
+    // with an even RHS chunk a lane moves two neighbouring RHS of a real point as one
+    // 16-byte access (RC = 1 takes one RHS per lane)
+    const int rw = RC % 2 == 0 ? 2 : 1, nw = m * RC / rw;
     if (a.mode == kForward) {
-        for (int e = threadIdx.x; e < m * RC; e += 256) {
-            const int p = e / RC, r = e % RC;
+        double2 v0[kPerX], v1[kPerX];  // points 2p and 2p + 1 of RHS r (, r + 1)
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            const int e = threadIdx.x + u * 256, p = e / (RC / rw), r = (e % (RC / rw)) * rw;
             const int64_t g = (L * n + 2 * p) * a.RB + rc0 + r;
-            X[r * stride + pidx(p)] = make_double2(a.rin[g], a.rin[g + a.RB]);
+            double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+            if (e < nw) {
+                if (rw == 2) {
+                    x0 = *reinterpret_cast<const double2 *>(a.rin + g);
+                    x1 = *reinterpret_cast<const double2 *>(a.rin + g + a.RB);
+                } else {
+                    x0.x = a.rin[g];
+                    x1.x = a.rin[g + a.RB];
+                }
+            }
+            v0[u] = x0;
+            v1[u] = x1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            const int e = threadIdx.x + u * 256, p = e / (RC / rw), r = (e % (RC / rw)) * rw;
+            if (e < nw) {
+                X[r * stride + pidx(p)] = make_double2(v0[u].x, v1[u].x);
+                if (rw == 2) X[(r + 1) * stride + pidx(p)] = make_double2(v0[u].y, v1[u].y);
+            }
         }
         __syncthreads();
         line_fft<false>(X, stride, m, RC, twh);
@@ -244,23 +297,62 @@ __global__ void __launch_bounds__(256) k_fft_x(const FftPass a) {
             a.cout[(L * nh + k) * a.RB + rc0 + r] = cadd(ev, cmul(wpow<false>(tws, k, n), od));
         }
     } else {
-        for (int e = threadIdx.x; e < m * RC; e += 256) {
-            const int k = e / RC, r = e % RC;
-            const double2 xk = a.cin[(L * nh + k) * a.RB + rc0 + r];
-            const double2 xc = conjg(a.cin[(L * nh + m - k) * a.RB + rc0 + r]);
-            const double2 ev = make_double2(0.5 * (xk.x + xc.x), 0.5 * (xk.y + xc.y));
-            const double2 od = cmul(wpow<true>(tws, k, n), make_double2(0.5 * (xk.x - xc.x), 0.5 * (xk.y - xc.y)));
-            X[r * stride + pidx(k)] = make_double2(ev.x - od.y, ev.y + od.x);  // E + i O
+        double2 vk[kPerX], vc[kPerX];
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            const int e = threadIdx.x + u * 256, k = e / RC, r = e % RC;
+            if (e < m * RC) {
+                vk[u] = a.cin[(L * nh + k) * a.RB + rc0 + r];
+                vc[u] = a.cin[(L * nh + m - k) * a.RB + rc0 + r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            const int e = threadIdx.x + u * 256, k = e / RC, r = e % RC;
+            if (e < m * RC) {
+                const double2 xk = vk[u], xc = conjg(vc[u]);
+                const double2 ev = make_double2(0.5 * (xk.x + xc.x), 0.5 * (xk.y + xc.y));
+                const double2 od = cmul(wpow<true>(tws, k, n), make_double2(0.5 * (xk.x - xc.x), 0.5 * (xk.y - xc.y)));
+                X[r * stride + pidx(k)] = make_double2(ev.x - od.y, ev.y + od.x);  // E + i O
+            }
         }
         __syncthreads();
         line_fft<true>(X, stride, m, RC, twh);
         const double sc = 1.0 / m;
-        for (int e = threadIdx.x; e < m * RC; e += 256) {
-            const int p = e / RC, r = e % RC;
-            const double2 v = X[r * stride + pidx(p)];
+        double2 d0[kPerX], d1[kPerX];  // the added values at points 2p and 2p + 1 of RHS r (, r + 1)
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            const int e = threadIdx.x + u * 256, p = e / (RC / rw), r = (e % (RC / rw)) * rw;
             const int64_t g = (L * n + 2 * p) * a.RB + rc0 + r;
-            a.rout[g] = sc * v.x + (a.add ? a.add[g] : 0.0);
-            a.rout[g + a.RB] = sc * v.y + (a.add ? a.add[g + a.RB] : 0.0);
+            double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+            if (a.add && e < nw) {
+                if (rw == 2) {
+                    x0 = *reinterpret_cast<const double2 *>(a.add + g);
+                    x1 = *reinterpret_cast<const double2 *>(a.add + g + a.RB);
+                } else {
+                    x0.x = a.add[g];
+                    x1.x = a.add[g + a.RB];
+                }
+            }
+            d0[u] = x0;
+            d1[u] = x1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            const int e = threadIdx.x + u * 256, p = e / (RC / rw), r = (e % (RC / rw)) * rw;
+            if (e < nw) {
+                const int64_t g = (L * n + 2 * p) * a.RB + rc0 + r;
+                const double2 v = X[r * stride + pidx(p)];  // (point 2p, point 2p + 1) of RHS r
+                if (rw == 2) {
+                    const double2 w = X[(r + 1) * stride + pidx(p)];
+                    *reinterpret_cast<double2 *>(a.rout + g) = make_double2(sc * v.x + d0[u].x, sc * w.x + d0[u].y);
+                    *reinterpret_cast<double2 *>(a.rout + g + a.RB) =
+                        make_double2(sc * v.y + d1[u].x, sc * w.y + d1[u].y);
+                } else {
+                    a.rout[g] = sc * v.x + d0[u].x;
+                    a.rout[g + a.RB] = sc * v.y + d1[u].x;
+                }
+            }
         }
     }
 }
