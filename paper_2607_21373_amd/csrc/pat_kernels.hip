@@ -656,9 +656,10 @@ __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdj
 // tile); XCD x takes the x-th eighth of the tiles, its workgroups interleaved
 // over them, so the tiles in flight on one XCD are neighbours and share their
 // halo rows in that XCD's L2.  The forward step also copies the rows of V
-// that its boundary slots refer to (the B part of the halo).  Sums run in the
-// slot order of the vector-lane kernels, with the same operations, so both
-// give the same bits.
+// that its boundary slots refer to (the B part of the halo).  Each lane of a
+// row's 16 reads one slot's operands from the LDS image and hands them to the
+// others by DPP row broadcast.  Sums run in the slot order of the vector-lane
+// kernels, with the same operations, so both give the same bits.
 // ---------------------------------------------------------------------------
 
 using F4 = Vec16<float>::t;  // 16 bytes of float32
@@ -673,14 +674,14 @@ constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 static_assert(kHThreads == 512 && kHMetaWords / 256 <= kHWaves, "halo tile geometry");
 
 // LDS image of one tile
-struct HaloBuf {
+struct alignas(16) HaloBuf {
     F4 rows[kHMax * 16];      // halo rows (256-byte chunks): K part, then B part
     uint32_t meta[kHMetaWords];   // the tile's metadata block (HaloTiles)
 };
 // LDS of a workgroup: two tile images and two halo row lists, each its own
 // __shared__ variable, so that the compiler can tell the copies into one buffer
 // from the reads of the other and does not wait for the former before the latter
-struct HaloList {
+struct alignas(16) HaloList {  // copied into 16 bytes per lane
     int32_t r[kHMax];
 };
 static_assert(2 * (sizeof(HaloBuf) + sizeof(HaloList)) <= 81920, "two workgroups per CU");
