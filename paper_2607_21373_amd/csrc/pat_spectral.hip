@@ -102,42 +102,57 @@ __device__ __forceinline__ double2 wpow(const double2 *tws, int e, int n) {
     return INV ? conjg(w) : w;
 }
 
-// One length-n transform (Stockham, natural order in and out) of every line x of the
-// workgroup's LDS tile, 8 points per thread: radix-8 stages while 8^s divides n, then a
-// final radix-2 or radix-4 stage.  Threads past the tile's lines only take part in the
-// barriers.  Ends with a barrier.
-template <bool INV>
-__device__ __forceinline__ void line_fft(double2 *X, int stride, int n, int RC, const double2 *tws) {
+// One length-n transform (Stockham, natural order in and out) of each of the RC lines
+// of a workgroup, 8 points per thread: radix-8 stages while 8^s divides n, then a
+// final radix-2 or radix-4 stage.  The first stage takes its points from
+// load(line, t) and the last hands its results to store(line, t, value); the stages
+// in between exchange through the LDS tile X (line r at X + r * stride, see pidx).
+// So a pass reads its input once and writes its output once, with no staging copy
+// through LDS.  The first and last stages map thread -> (line = thread % RC,
+// j = thread / RC), so that consecutive threads touch consecutive right-hand sides
+// of a point in memory.  load may read X and store may write X: every stage reads
+// all its inputs and waits at a barrier before it writes.  Threads without a line
+// only take part in the barriers.  Ends with a barrier.
+template <bool INV, typename Load, typename Store>
+__device__ __forceinline__ void line_fft_io(double2 *X, int stride, int n, int RC, const double2 *tws, Load load,
+                                            Store store) {
+    const int tid = threadIdx.x;
     if (n < 8) {  // n = 2 or 4 (the x passes of a grid of 4 or 8): one thread per line
-        if (threadIdx.x < RC) {
-            double2 *x = X + threadIdx.x * stride;
-            if (n == 4) {
-                double2 v[4] = {x[pidx(0)], x[pidx(1)], x[pidx(2)], x[pidx(3)]};
-                dft4<INV>(v);
-                for (int r = 0; r < 4; ++r) x[pidx(r)] = v[r];
-            } else {
-                double2 u = x[pidx(0)], t = x[pidx(1)];
-                bfly(u, t);
-                x[pidx(0)] = u;
-                x[pidx(1)] = t;
-            }
+        double2 v[4];
+        const bool act = tid < RC;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            double2 x = make_double2(0.0, 0.0);
+            if (act && t < n) x = load(tid, t);
+            v[t] = x;
+        }
+        __syncthreads();
+        if (act) {
+            if (n == 4) dft4<INV>(v);
+            else bfly(v[0], v[1]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (t < n) store(tid, t, v[t]);
         }
         __syncthreads();
         return;
     }
     const int tpl = n >> 3;  // threads per line
-    const int line = threadIdx.x / tpl, j = threadIdx.x % tpl;
-    const bool act = line < RC;
-    double2 *x = X + line * stride;
-    int ns = 1;
-    while (ns * 8 <= n) {
+    int n8 = 1;              // the radix-8 part: 8^s dividing n
+    while (n8 * 8 <= n) n8 *= 8;
+    const int rf = n / n8;  // 1, 2 or 4 left for the final stage
+    for (int ns = 1; ns < n8; ns *= 8) {
+        const bool first = ns == 1, last = ns * 8 == n8 && rf == 1;
+        const bool io = first || last;
+        const int line = io ? tid % RC : tid / tpl, j = io ? tid / RC : tid % tpl;
+        const bool act = io ? tid < RC * tpl : line < RC;
         double2 v[8];
         if (act) {
-            const int jm = j % ns;
+            double2 *x = X + line * stride;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) v[r] = x[pidx(j + r * tpl)];
+            for (int r = 0; r < 8; ++r) v[r] = first ? load(line, j + r * tpl) : x[pidx(j + r * tpl)];
             if (ns > 1) {
-                const int f = n / (8 * ns);
+                const int jm = j % ns, f = n / (8 * ns);
 #pragma unroll
                 for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], wpow<INV>(tws, jm * r * f, n));
             }
@@ -145,98 +160,97 @@ __device__ __forceinline__ void line_fft(double2 *X, int stride, int n, int RC, 
         }
         __syncthreads();
         if (act) {
-            const int jm = j % ns, base = (j / ns) * ns * 8 + jm;
+            double2 *x = X + line * stride;
+            const int base = (j / ns) * ns * 8 + j % ns;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) x[pidx(base + r * ns)] = v[r];
+            for (int r = 0; r < 8; ++r) {
+                if (last) store(line, base + r * ns, v[r]);
+                else x[pidx(base + r * ns)] = v[r];
+            }
         }
         __syncthreads();
-        ns *= 8;
     }
-    const int rf = n / ns;  // 1, 2 or 4 left; the stage is in place per thread
-    if (act && rf == 2) {
-        for (int q = 0; q < 4; ++q) {
-            const int b = j + q * tpl;  // butterfly b < ns = n/2
-            double2 u = x[pidx(b)], t = cmul(x[pidx(b + ns)], wpow<INV>(tws, b, n));
-            bfly(u, t);
-            x[pidx(b)] = u;
-            x[pidx(b + ns)] = t;
+    if (rf > 1) {
+        const int ns = n8, line = tid % RC, j = tid / RC;
+        const bool act = tid < RC * tpl;
+        double2 v[8];  // rf = 2: four butterflies (u, t); rf = 4: two radix-4 groups
+        const double2 *x = X + line * stride;
+        if (act) {
+            if (rf == 2) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int b = j + q * tpl;  // butterfly b < ns = n/2
+                    v[2 * q] = x[pidx(b)];
+                    v[2 * q + 1] = cmul(x[pidx(b + ns)], wpow<INV>(tws, b, n));
+                    bfly(v[2 * q], v[2 * q + 1]);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int b = j + q * tpl;  // b < ns = n/4
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[4 * q + r] = x[pidx(b + r * ns)];
+#pragma unroll
+                    for (int r = 1; r < 4; ++r) v[4 * q + r] = cmul(v[4 * q + r], wpow<INV>(tws, b * r, n));
+                    dft4<INV>(v + 4 * q);
+                }
+            }
         }
-    } else if (act && rf == 4) {
-        for (int q = 0; q < 2; ++q) {
-            const int b = j + q * tpl;  // b < ns = n/4
-            double2 v[4];
+        __syncthreads();
+        if (act) {
+            if (rf == 2) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = x[pidx(b + r * ns)];
+                for (int q = 0; q < 4; ++q) {
+                    const int b = j + q * tpl;
+                    store(line, b, v[2 * q]);
+                    store(line, b + ns, v[2 * q + 1]);
+                }
+            } else {
 #pragma unroll
-            for (int r = 1; r < 4; ++r) v[r] = cmul(v[r], wpow<INV>(tws, b * r, n));
-            dft4<INV>(v);
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) x[pidx(b + r * ns)] = v[r];
+                    for (int r = 0; r < 4; ++r) store(line, j + q * tpl + r * ns, v[4 * q + r]);
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // One length-n transform along y (axis 1) or z (axis 2) per (line, RHS) of the
 // workgroup's line and RHS chunk, on the half spectrum (x extent nh = n/2 + 1);
 // the z pass of the centre mode multiplies by a(k) between its forward and inverse
-// transforms.
+// transforms (the forward transform's last stage writes the products to LDS, where
+// the inverse transform's first stage reads them).
 __global__ void __launch_bounds__(256) k_fft_axis(const FftPass a) {
     extern __shared__ double2 X[];  // [RC][n + n/8 + 1], see pidx
     __shared__ double2 tws[64];     // the n/2 twiddles (n <= 128)
     const int n = a.n, nh = n / 2 + 1, half_n = n >> 1, stride = n + (n >> 3) + 1;
     for (int e = threadIdx.x; e < half_n; e += 256) tws[e] = a.tw[e];
+    __syncthreads();
     const int RC = a.RB < kRC ? a.RB : kRC;
     const int rc0 = blockIdx.y * RC;
     const int L = blockIdx.x, i = L % nh, q = L / nh;  // line (q, i): q = k (axis 1) or j (axis 2)
     const int64_t g0 = a.axis == 1 ? int64_t(q) * n * nh + i : int64_t(q) * nh + i;
     const int64_t ls = a.axis == 1 ? nh : int64_t(n) * nh;
-    {
-        double2 v[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = threadIdx.x + u * 256, t = e / RC, r = e % RC;
-            double2 x = make_double2(0.0, 0.0);
-            if (e < n * RC) x = a.cin[(g0 + t * ls) * a.RB + rc0 + r];
-            v[u] = x;
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = threadIdx.x + u * 256, t = e / RC, r = e % RC;
-            if (e < n * RC) X[r * stride + pidx(t)] = v[u];
-        }
-    }
-    __syncthreads();
-    if (a.mode != kInverse) line_fft<false>(X, stride, n, RC, tws);
-    if (a.mode == kCentre) {
-        // a(k) at (kx, ky, kz) = (i, q, t): line L = q * nh + i of the z-ordered table
-        double w[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = threadIdx.x + u * 256, t = e % n;
-            double x = 0.0;
-            if (e < n * RC) x = a.amp[int64_t(L) * n + t];
-            w[u] = x;
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = threadIdx.x + u * 256, r = e / n, t = e % n;
-            if (e < n * RC) {
-                const double2 x = X[r * stride + pidx(t)];
-                X[r * stride + pidx(t)] = make_double2(w[u] * x.x, w[u] * x.y);
-            }
-        }
-        __syncthreads();
-    }
-    if (a.mode != kForward) line_fft<true>(X, stride, n, RC, tws);
+    auto gload = [&](int r, int t) { return a.cin[(g0 + t * ls) * a.RB + rc0 + r]; };
     const double sc = a.mode == kForward ? 1.0 : 1.0 / n;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = threadIdx.x + u * 256, t = e / RC, r = e % RC;
-        if (e < n * RC) {
-            const double2 v = X[r * stride + pidx(t)];
-            a.cout[(g0 + t * ls) * a.RB + rc0 + r] = make_double2(sc * v.x, sc * v.y);
-        }
+    auto gstore = [&](int r, int t, double2 v) {
+        a.cout[(g0 + t * ls) * a.RB + rc0 + r] = make_double2(sc * v.x, sc * v.y);
+    };
+    if (a.mode == kForward) {
+        line_fft_io<false>(X, stride, n, RC, tws, gload, gstore);
+    } else if (a.mode == kInverse) {
+        line_fft_io<true>(X, stride, n, RC, tws, gload, gstore);
+    } else {
+        // a(k) at (kx, ky, kz) = (i, q, t): line L = q * nh + i of the z-ordered table
+        const double *amp = a.amp + int64_t(L) * n;
+        auto lstore = [&](int r, int t, double2 v) {
+            const double w = amp[t];
+            X[r * stride + pidx(t)] = make_double2(w * v.x, w * v.y);
+        };
+        auto lload = [&](int r, int t) { return X[r * stride + pidx(t)]; };
+        line_fft_io<false>(X, stride, n, RC, tws, gload, lstore);
+        line_fft_io<true>(X, stride, n, RC, tws, lload, gstore);
     }
 }
 
@@ -256,39 +270,14 @@ __global__ void __launch_bounds__(256) k_fft_x(const FftPass a) {
     const int RC = a.RB < kRC ? a.RB : kRC;
     const int rc0 = blockIdx.y * RC;
     const int64_t L = blockIdx.x;  // line (k, j): real points g = L*n + t, spectrum h = L*nh + k
-    constexpr int kPerX = kPer / 2;  // m * RC / 256 elements per thread at most
-    // with an even RHS chunk a lane moves two neighbouring RHS of a real point as one
-    // 16-byte access (RC = 1 takes one RHS per lane)
-    const int rw = RC % 2 == 0 ? 2 : 1, nw = m * RC / rw;
+    auto lload = [&](int r, int t) { return X[r * stride + pidx(t)]; };
+    auto lstore = [&](int r, int t, double2 v) { X[r * stride + pidx(t)] = v; };
     if (a.mode == kForward) {
-        double2 v0[kPerX], v1[kPerX];  // points 2p and 2p + 1 of RHS r (, r + 1)
-#pragma unroll
-        for (int u = 0; u < kPerX; ++u) {
-            const int e = threadIdx.x + u * 256, p = e / (RC / rw), r = (e % (RC / rw)) * rw;
+        auto rload = [&](int r, int p) {
             const int64_t g = (L * n + 2 * p) * a.RB + rc0 + r;
-            double2 x0 = make_double2(0.0, 0.0), x1 = x0;
-            if (e < nw) {
-                if (rw == 2) {
-                    x0 = *reinterpret_cast<const double2 *>(a.rin + g);
-                    x1 = *reinterpret_cast<const double2 *>(a.rin + g + a.RB);
-                } else {
-                    x0.x = a.rin[g];
-                    x1.x = a.rin[g + a.RB];
-                }
-            }
-            v0[u] = x0;
-            v1[u] = x1;
-        }
-#pragma unroll
-        for (int u = 0; u < kPerX; ++u) {
-            const int e = threadIdx.x + u * 256, p = e / (RC / rw), r = (e % (RC / rw)) * rw;
-            if (e < nw) {
-                X[r * stride + pidx(p)] = make_double2(v0[u].x, v1[u].x);
-                if (rw == 2) X[(r + 1) * stride + pidx(p)] = make_double2(v0[u].y, v1[u].y);
-            }
-        }
-        __syncthreads();
-        line_fft<false>(X, stride, m, RC, twh);
+            return make_double2(a.rin[g], a.rin[g + a.RB]);
+        };
+        line_fft_io<false>(X, stride, m, RC, twh, rload, lstore);
         for (int e = threadIdx.x; e < nh * RC; e += 256) {
             const int k = e / RC, r = e % RC;
             const double2 zk = X[r * stride + pidx(k % m)], zc = conjg(X[r * stride + pidx((m - k) % m)]);
@@ -297,14 +286,18 @@ __global__ void __launch_bounds__(256) k_fft_x(const FftPass a) {
             a.cout[(L * nh + k) * a.RB + rc0 + r] = cadd(ev, cmul(wpow<false>(tws, k, n), od));
         }
     } else {
+        constexpr int kPerX = kPer / 2;  // m * RC / 256 elements per thread at most
         double2 vk[kPerX], vc[kPerX];
 #pragma unroll
         for (int u = 0; u < kPerX; ++u) {
             const int e = threadIdx.x + u * 256, k = e / RC, r = e % RC;
+            double2 xk = make_double2(0.0, 0.0), xc = xk;
             if (e < m * RC) {
-                vk[u] = a.cin[(L * nh + k) * a.RB + rc0 + r];
-                vc[u] = a.cin[(L * nh + m - k) * a.RB + rc0 + r];
+                xk = a.cin[(L * nh + k) * a.RB + rc0 + r];
+                xc = a.cin[(L * nh + m - k) * a.RB + rc0 + r];
             }
+            vk[u] = xk;
+            vc[u] = xc;
         }
 #pragma unroll
         for (int u = 0; u < kPerX; ++u) {
@@ -317,9 +310,12 @@ __global__ void __launch_bounds__(256) k_fft_x(const FftPass a) {
             }
         }
         __syncthreads();
-        line_fft<true>(X, stride, m, RC, twh);
+        line_fft_io<true>(X, stride, m, RC, twh, lload, lstore);
+        // the real points, two neighbouring RHS per 16-byte access when the chunk is even
+        // (RC = 1: one), with the added values loaded before any is used
         const double sc = 1.0 / m;
-        double2 d0[kPerX], d1[kPerX];  // the added values at points 2p and 2p + 1 of RHS r (, r + 1)
+        const int rw = RC % 2 == 0 ? 2 : 1, nw = m * RC / rw;
+        double2 d0[kPerX], d1[kPerX];  // added values at points 2p and 2p + 1 of RHS r (, r + 1)
 #pragma unroll
         for (int u = 0; u < kPerX; ++u) {
             const int e = threadIdx.x + u * 256, p = e / (RC / rw), r = (e % (RC / rw)) * rw;
