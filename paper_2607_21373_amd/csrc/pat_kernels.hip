@@ -646,7 +646,7 @@ __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdj
 // The vector-lane kernels above gather 16 neighbour rows per row through the
 // CU's texture units, which keeps those units busy most of the step.  Here a
 // tile of consecutive rows (HaloTiles: at most 32 rows whose distinct neighbour
-// rows, the halo, fit 132 LDS rows; on the 195,112-node ball 4.3 halo rows per
+// rows, the halo, fit 132 LDS rows; on the 195,112-node ball 4.7 halo rows per
 // row) copies its halo and its row operands from memory straight into LDS
 // (global_load_lds_dwordx4, 64 lanes x 16 bytes per instruction, no registers
 // in between), and every slot reads its neighbour from there.  Each workgroup
