@@ -62,20 +62,25 @@ void build_padded_rows(HostProblem &hp);
 // the tile's padded slots refer to (K rows) plus the distinct rows its boundary
 // slots refer to (B rows), each padded to a multiple of 4, holds at most kMax
 // rows.  Per tile: a descriptor, the halo's row list and one metadata block
-// that the kernels copy into LDS with the halo:
-//   loc[nr][16]  uint16: K-local index | B-local index << 8 of each slot
-//   info[nr][8]  int32:  dt/m (float bits), bw row | bnum << 16, xptr[i], xptr[i+1],
-//                        injptr[i], injptr[i+1], 0, 0
-//   kv[nr][16]   float:  the slot values of K
-//   bw[nbr][16]  float:  the slot values of B of the tile's boundary rows
+// that the kernels copy into LDS with the halo (96 B per row, 80 more per
+// boundary row):
+//   loc[nr][16]   uint8:  K-local index of each slot (kMax < 256)
+//   info[nr][4]   uint32: dt/m (float bits); boundary row (0xFF: none) | bnum << 8 |
+//                         (xptr[i+1] - xptr[i]) << 16 | (injptr[i+1] - injptr[i]) << 24;
+//                         xptr[i]; injptr[i]
+//   kv[nr][16]    float:  the slot values of K
+//   bw[nbr][16]   float:  the slot values of B of the tile's boundary rows
+//   bloc[nbr][16] uint8:  B-local index of each of their first min(bnum, 16) slots
+// A mesh with a count beyond its byte (bnum, overflow entries or injections of a
+// row above 255) gets no halo tiles and runs on the vector-lane kernels.
 struct HaloTiles {
     static constexpr int kRows = 32;
     static constexpr int kMax = 132;
-    static constexpr int kMetaBytes = kRows * (32 + 32 + 64 + 64);
+    static constexpr int kMetaBytes = kRows * (16 + 16 + 64 + 64 + 16);
     int32_t n_tiles = 0;
     // [n_tiles][4]: first row, first halo entry, metadata offset (16-byte units),
     // rows | K rows << 6 | B rows << 14 | boundary rows << 22 (metadata bytes:
-    // 128 per row + 64 per boundary row)
+    // 96 per row + 80 per boundary row)
     std::vector<int32_t> desc;
     std::vector<int32_t> hrow;
     std::vector<uint32_t> meta;

@@ -671,7 +671,7 @@ constexpr int kHWaves = kHThreads / 64;
 constexpr int kHPerWave = (kHMax / 4 + kHWaves - 1) / kHWaves;  // halo copy instructions per wave at most
 constexpr int kHChunk = 4;  // LDS reads in flight per lane before they are consumed
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
-static_assert(kHThreads == 512 && kHMetaWords / 256 <= kHWaves, "halo tile geometry");
+static_assert(kHThreads == 512 && (kHMetaWords + 255) / 256 <= kHWaves, "halo tile geometry");
 
 // LDS image of one tile
 struct alignas(16) HaloBuf {
@@ -695,7 +695,7 @@ __device__ __forceinline__ HDesc desc_uniform(const int4 u) {
     const int r0 = __builtin_amdgcn_readfirstlane(u.x), h0 = __builtin_amdgcn_readfirstlane(u.y);
     const int moff = __builtin_amdgcn_readfirstlane(u.z), f = __builtin_amdgcn_readfirstlane(u.w);
     const int nr = f & 63, nk4 = (f >> 6) & 255, nb4 = (f >> 14) & 255, nbr = (f >> 22) & 63;
-    return {r0, nr, h0, nk4, nb4, moff, nr * 128 + nbr * 64, nbr};
+    return {r0, nr, h0, nk4, nb4, moff, nr * 96 + nbr * 80, nbr};
 }
 
 // Work items of this workgroup: (chunk c, tile t), t = t_lo + k + j * G8.
@@ -774,31 +774,38 @@ __device__ __forceinline__ float row_bcast(float x) {
     return __uint_as_float(row_bcast<J>(__float_as_uint(x)));
 }
 
-// The operands of row g of the tile in Lb as held by lane q of its row group:
-// slot q's K value and halo byte offsets, info word q % 8, and (boundary rows) slot
-// q's B value.  Per-row values come from the info words by row broadcast.
+// The operands of row g of the tile in Lb (metadata layout of HaloTiles) as held by
+// lane q of its row group: slot q's K value and K-halo byte offset, and info word
+// q % 4.  Per-row values come from the info words by row broadcast.
 struct HLane {
-    uint32_t koff, boff;  // byte offsets of slot q's neighbour in the K and B parts of the halo
-    float kv, bw;
+    uint32_t koff;  // byte offset of slot q's neighbour in the K part of the halo
+    float kv;
     uint32_t info;
 };
-__device__ __forceinline__ HLane halo_lane(const HaloBuf &Lb, int nr, int g, int q, int bbase) {
+__device__ __forceinline__ HLane halo_lane(const HaloBuf &Lb, int nr, int g, int q) {
     HLane h;
-    const uint32_t loc = reinterpret_cast<const uint16_t *>(Lb.meta + g * 8)[q];
-    h.koff = (loc & 0xFFu) * 256u;
-    h.boff = (uint32_t(bbase) + (loc >> 8)) * 256u;
-    h.kv = reinterpret_cast<const float *>(Lb.meta + nr * 16 + g * 16)[q];
-    h.info = Lb.meta[nr * 8 + g * 8 + (q & 7)];
-    h.bw = 0.0f;
+    h.koff = uint32_t(reinterpret_cast<const uint8_t *>(Lb.meta + g * 4)[q]) * 256u;
+    h.info = Lb.meta[nr * 4 + g * 4 + (q & 3)];
+    h.kv = reinterpret_cast<const float *>(Lb.meta + nr * 8 + g * 16)[q];
     return h;
 }
-// per-row values from the info words: dt/m, boundary word, overflow and injection ranges
+// per-row values from the info words: dt/m, boundary row (0xFF: none), bnum, the
+// overflow range [x0, x0 + nx) and the injection range [inj0, inj0 + ninj)
 __device__ __forceinline__ float hl_dm(const HLane &h) { return __uint_as_float(row_bcast<0>(h.info)); }
-__device__ __forceinline__ uint32_t hl_bword(const HLane &h) { return row_bcast<1>(h.info); }
+__device__ __forceinline__ uint32_t hl_word(const HLane &h) { return row_bcast<1>(h.info); }
 __device__ __forceinline__ int hl_x0(const HLane &h) { return int(row_bcast<2>(h.info)); }
-__device__ __forceinline__ int hl_x1(const HLane &h) { return int(row_bcast<3>(h.info)); }
-__device__ __forceinline__ int hl_inj0(const HLane &h) { return int(row_bcast<4>(h.info)); }
-__device__ __forceinline__ int hl_inj1(const HLane &h) { return int(row_bcast<5>(h.info)); }
+__device__ __forceinline__ int hl_inj0(const HLane &h) { return int(row_bcast<3>(h.info)); }
+__device__ __forceinline__ int hw_brow(uint32_t w) { return int(w & 0xFFu); }
+__device__ __forceinline__ int hw_bnum(uint32_t w) { return int((w >> 8) & 0xFFu); }
+__device__ __forceinline__ int hw_nx(uint32_t w) { return int((w >> 16) & 0xFFu); }
+__device__ __forceinline__ int hw_ninj(uint32_t w) { return int(w >> 24); }
+// boundary row br's B value and B-halo byte offset (base: the B part's first row) of slot q
+__device__ __forceinline__ float hb_value(const HaloBuf &Lb, int nr, int br, int q) {
+    return reinterpret_cast<const float *>(Lb.meta + nr * 24 + br * 16)[q];
+}
+__device__ __forceinline__ uint32_t hb_offset(const HaloBuf &Lb, int nr, int nbr, int br, int q, int base) {
+    return (uint32_t(base) + reinterpret_cast<const uint8_t *>(Lb.meta + nr * 24 + nbr * 16 + br * 4)[q]) * 256u;
+}
 
 __device__ __forceinline__ F4 lds_row(const HaloBuf &Lb, uint32_t off) {
     return *reinterpret_cast<const F4 *>(reinterpret_cast<const char *>(Lb.rows) + off);
@@ -939,17 +946,17 @@ k_fwd_h(const VFwdArgs<float> a) {
         out_id = kNoRow;
         if (g >= d.nr) return;
         const uint32_t coff = uint32_t(wk.chunk(it)) * 256u, q16 = uint32_t(q) * 16u;
-        HLane h = halo_lane(Lb, d.nr, g, q, d.nk4);
-        const int x0 = hl_x0(h), x1 = hl_x1(h);
+        const HLane h = halo_lane(Lb, d.nr, g, q);
+        const uint32_t hw = hl_word(h);
+        const int x0 = hl_x0(h), x1 = x0 + hw_nx(hw);
         F4 acc = {}, bacc = {}, p0;
         halo_ksums(Lb, h, q16, x0, x1, a.o.xval, a.o.xcol, Pc, RS, coff, acc, p0);
         const int row = d.r0 + g;
-        const uint32_t bword = hl_bword(h);
-        if (with_b && (bword & 0xFFFFu) != 0xFFFFu) {
-            const int nb = int(bword >> 16);
+        if (with_b && hw_brow(hw) != 0xFF) {
+            const int nb = hw_bnum(hw), br = hw_brow(hw);
             const int bo = nb > 16 ? a.o.bsoff[row] : 0;
-            const float bwq = reinterpret_cast<const float *>(Lb.meta + d.nr * 32 + int(bword & 0xFFFFu) * 16)[q];
-            halo_bsums(Lb, h.boff, bwq, nb, q16, a.o.bslot, bo, a.o.xcol, x0, Vc, RS, coff, bacc);
+            halo_bsums(Lb, hb_offset(Lb, d.nr, d.nbr, br, q, d.nk4), hb_value(Lb, d.nr, br, q), nb, q16, a.o.bslot, bo,
+                       a.o.xcol, x0, Vc, RS, coff, bacc);
         }
         const float dm = hl_dm(h);
         const F4 v0 = with_b ? v_cur : F4{};
@@ -1016,17 +1023,17 @@ k_adj_h(const VAdjArgs<float> a) {
         if (g >= d.nr) return;
         const int c = wk.chunk(it);
         const uint32_t coff = uint32_t(c) * 256u, q16 = uint32_t(q) * 16u;
-        HLane h = halo_lane(Lb, d.nr, g, q, 0);
-        const int x0 = hl_x0(h), x1 = hl_x1(h);
+        const HLane h = halo_lane(Lb, d.nr, g, q);
+        const uint32_t hw = hl_word(h);
+        const int x0 = hl_x0(h), x1 = x0 + hw_nx(hw);
         F4 kq = {}, bq = {}, q0;
         halo_ksums(Lb, h, q16, x0, x1, a.o.xval, a.o.xcol, Qc, RS, coff, kq, q0);
         const int row = d.r0 + g;
-        const uint32_t bword = hl_bword(h);
-        if (!a.last && (bword & 0xFFFFu) != 0xFFFFu) {
-            const int nb = int(bword >> 16);
+        if (!a.last && hw_brow(hw) != 0xFF) {
+            const int nb = hw_bnum(hw), br = hw_brow(hw);
             const int bo = nb > 16 ? a.o.bsoff[row] : 0;
-            const float bwq = reinterpret_cast<const float *>(Lb.meta + d.nr * 32 + int(bword & 0xFFFFu) * 16)[q];
-            halo_bsums(Lb, h.koff, bwq, nb, q16, a.o.bslot, bo, a.o.xcol, x0, Qc, RS, coff, bq);
+            // B multiplies the same vector as K: the B slots read the K part of the halo
+            halo_bsums(Lb, h.koff, hb_value(Lb, d.nr, br, q), nb, q16, a.o.bslot, bo, a.o.xcol, x0, Qc, RS, coff, bq);
         }
         F4 ph;
 #pragma unroll
@@ -1035,8 +1042,8 @@ k_adj_h(const VAdjArgs<float> a) {
             const float dm = hl_dm(h);
             F4 inj = {};
             const YT *yh = static_cast<const YT *>(a.yh);
-            const int e1 = hl_inj1(h);
-            for (int e = hl_inj0(h); e < e1; ++e) {
+            const int e0 = hl_inj0(h), e1 = e0 + hw_ninj(hw);
+            for (int e = e0; e < e1; ++e) {
                 const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + c * 64 + q * 4;
                 const float w = a.injw[e];
 #pragma unroll

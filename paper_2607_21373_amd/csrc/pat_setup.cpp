@@ -590,9 +590,9 @@ void build_halo_tiles(const HostProblem &hp, HaloTiles &ht) {
         int32_t nbr = 0;
         for (int32_t i = r0; i < r1; ++i) nbr += is_bnd(i) ? 1 : 0;
         const size_t m0 = ht.meta.size();
-        ht.meta.resize(m0 + size_t(nr) * (8 + 8 + 16) + size_t(nbr) * 16, 0u);
-        uint32_t *loc = ht.meta.data() + m0, *info = loc + size_t(nr) * 8, *kv = info + size_t(nr) * 8,
-                 *bw = kv + size_t(nr) * 16;
+        ht.meta.resize(m0 + size_t(nr) * (4 + 4 + 16) + size_t(nbr) * (16 + 4), 0u);
+        uint32_t *loc = ht.meta.data() + m0, *info = loc + size_t(nr) * 4, *kv = info + size_t(nr) * 4,
+                 *bw = kv + size_t(nr) * 16, *bloc = bw + size_t(nbr) * 16;
         auto fbits = [](double v) {
             const float f = float(v);
             uint32_t u;
@@ -602,21 +602,32 @@ void build_halo_tiles(const HostProblem &hp, HaloTiles &ht) {
         int32_t br = 0;
         for (int32_t i = r0; i < r1; ++i) {
             const size_t li = size_t(i - r0);
+            const int32_t nx = hp.xptr[size_t(i) + 1] - hp.xptr[size_t(i)];
+            const int32_t ninj = hp.injptr[size_t(i) + 1] - hp.injptr[size_t(i)];
+            if (hp.bnum[size_t(i)] > 255 || nx > 255 || ninj > 255) {  // a count beyond its byte: no halo tiles
+                ht = HaloTiles{};
+                return;
+            }
             for (int j = 0; j < W; ++j) {
                 const int32_t c = hp.ell_col[size_t(i) * W + j];
-                uint32_t v = uint32_t(std::lower_bound(kc.begin(), kc.end(), c) - kc.begin());
-                if (j < nbs(i)) v |= uint32_t(std::lower_bound(bc.begin(), bc.end(), c) - bc.begin()) << 8;
-                loc[li * 8 + j / 2] |= v << (16 * (j % 2));
+                const uint32_t kl = uint32_t(std::lower_bound(kc.begin(), kc.end(), c) - kc.begin());
+                loc[li * 4 + j / 4] |= kl << (8 * (j % 4));
                 kv[li * 16 + j] = fbits(hp.ell_val[size_t(i) * W + j]);
             }
-            info[li * 8 + 0] = fbits(hp.dt / hp.mass[size_t(i)]);
-            info[li * 8 + 1] = uint32_t(is_bnd(i) ? br : 0xFFFF) | (uint32_t(hp.bnum[size_t(i)]) << 16);
-            info[li * 8 + 2] = uint32_t(hp.xptr[size_t(i)]);
-            info[li * 8 + 3] = uint32_t(hp.xptr[size_t(i) + 1]);
-            info[li * 8 + 4] = uint32_t(hp.injptr[size_t(i)]);
-            info[li * 8 + 5] = uint32_t(hp.injptr[size_t(i) + 1]);
+            info[li * 4 + 0] = fbits(hp.dt / hp.mass[size_t(i)]);
+            info[li * 4 + 1] = uint32_t(is_bnd(i) ? br : 0xFF) | (uint32_t(hp.bnum[size_t(i)]) << 8) |
+                               (uint32_t(nx) << 16) | (uint32_t(ninj) << 24);
+            info[li * 4 + 2] = uint32_t(hp.xptr[size_t(i)]);
+            info[li * 4 + 3] = uint32_t(hp.injptr[size_t(i)]);
             if (is_bnd(i)) {
-                for (int j = 0; j < W; ++j) bw[size_t(br) * 16 + j] = fbits(hp.bslot[size_t(hp.bsoff[size_t(i)]) + j]);
+                for (int j = 0; j < W; ++j) {
+                    bw[size_t(br) * 16 + j] = fbits(hp.bslot[size_t(hp.bsoff[size_t(i)]) + j]);
+                    if (j < nbs(i)) {
+                        const int32_t c = hp.ell_col[size_t(i) * W + j];
+                        const uint32_t bl = uint32_t(std::lower_bound(bc.begin(), bc.end(), c) - bc.begin());
+                        bloc[size_t(br) * 4 + j / 4] |= bl << (8 * (j % 4));
+                    }
+                }
                 ++br;
             }
         }

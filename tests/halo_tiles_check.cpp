@@ -90,34 +90,42 @@ int main(int argc, char **argv) {
             if (ht.hrow[size_t(h0 + nk4 + k)] != bc[std::min<size_t>(size_t(k), bc.size() - 1)]) return fail(at + ": B list");
         // metadata block
         const uint32_t *M = ht.meta.data() + next_m / 4;
-        const uint32_t *loc = M, *info = M + size_t(nr) * 8, *kv = M + size_t(nr) * 16, *bw = M + size_t(nr) * 32;
+        const uint32_t *loc = M, *info = M + size_t(nr) * 4, *kv = M + size_t(nr) * 8, *bw = M + size_t(nr) * 24,
+                       *bloc = bw + size_t(nbr) * 16;
         int32_t br = 0;
         for (int32_t g = 0; g < nr; ++g) {
             const int32_t i = r0 + g;
             const bool b = hp.bsoff[size_t(i)] >= 0;
             const std::string ar = at + " row " + std::to_string(i);
             for (int j = 0; j < W; ++j) {
-                const uint32_t e = (loc[size_t(g) * 8 + j / 2] >> (16 * (j % 2))) & 0xFFFFu;
+                const uint32_t e = (loc[size_t(g) * 4 + j / 4] >> (8 * (j % 4))) & 0xFFu;
                 const int32_t col = hp.ell_col[size_t(i) * W + j];
-                if (kc[e & 0xFFu] != col) return fail(ar + ": K index");
-                if (b && j < hp.bnum[size_t(i)] && bc[e >> 8] != col) return fail(ar + ": B index");
+                if (kc[e] != col) return fail(ar + ": K index");
                 if (kv[size_t(g) * 16 + j] != fbits(hp.ell_val[size_t(i) * W + j])) return fail(ar + ": K value");
             }
-            const uint32_t *in = info + size_t(g) * 8;
+            const uint32_t *in = info + size_t(g) * 4;
+            const int32_t nx = hp.xptr[size_t(i) + 1] - hp.xptr[size_t(i)];
+            const int32_t ninj = hp.injptr[size_t(i) + 1] - hp.injptr[size_t(i)];
             if (in[0] != fbits(hp.dt / hp.mass[size_t(i)])) return fail(ar + ": dt/m");
-            if ((in[1] & 0xFFFFu) != (b ? uint32_t(br) : 0xFFFFu) || int32_t(in[1] >> 16) != hp.bnum[size_t(i)])
-                return fail(ar + ": boundary word");
-            if (int32_t(in[2]) != hp.xptr[size_t(i)] || int32_t(in[3]) != hp.xptr[size_t(i) + 1]) return fail(ar + ": overflow range");
-            if (int32_t(in[4]) != hp.injptr[size_t(i)] || int32_t(in[5]) != hp.injptr[size_t(i) + 1]) return fail(ar + ": injection range");
+            if ((in[1] & 0xFFu) != (b ? uint32_t(br) : 0xFFu) || int32_t((in[1] >> 8) & 0xFFu) != hp.bnum[size_t(i)] ||
+                int32_t((in[1] >> 16) & 0xFFu) != nx || int32_t(in[1] >> 24) != ninj)
+                return fail(ar + ": count word");
+            if (int32_t(in[2]) != hp.xptr[size_t(i)]) return fail(ar + ": overflow start");
+            if (int32_t(in[3]) != hp.injptr[size_t(i)]) return fail(ar + ": injection start");
             if (b) {
-                for (int j = 0; j < W; ++j)
+                for (int j = 0; j < W; ++j) {
                     if (bw[size_t(br) * 16 + j] != fbits(hp.bslot[size_t(hp.bsoff[size_t(i)]) + j])) return fail(ar + ": B value");
+                    if (j < hp.bnum[size_t(i)]) {
+                        const uint32_t e = (bloc[size_t(br) * 4 + j / 4] >> (8 * (j % 4))) & 0xFFu;
+                        if (bc[e] != hp.ell_col[size_t(i) * W + j]) return fail(ar + ": B index");
+                    }
+                }
                 ++br;
             }
         }
         next_row = r0 + nr;
         next_h = h0 + nk4 + nb4;
-        next_m += int64_t(nr) * 128 + int64_t(nbr) * 64;
+        next_m += int64_t(nr) * 96 + int64_t(nbr) * 80;
     }
     if (next_row != N) return fail("tiles do not cover the rows");
     if (size_t(next_h) != ht.hrow.size() || size_t(next_m) != ht.meta.size() * 4) return fail("trailing data");
