@@ -35,18 +35,20 @@ def log(msg):
 def step_bytes(info, RB, tsize, kind):
     """Algorithmic HBM bytes of one step launch (each array element read or written once).
 
-    forward : CSR (col + value), rowptr, boundary offsets, dt/m, stored boundary values,
-              state P, V read and P', V' written, sensor rows and the float64 sample output.
-    transpose: same matrix data plus the injection CSR, state Q read, Q' written, p_hat read and written,
-              and the float64 data values injected at the sensor nodes.
+    Both steps carry the three-level state: S^n read (its rows also serve as the neighbours),
+    S^{n-1} read and S^{n+1} written.
+    forward : CSR (col + value), rowptr, boundary offsets, dt/m, stored boundary values, the
+              state, sensor rows and the float64 sample output.
+    transpose: same matrix data and state plus the injection CSR, and the float64 data values of
+              two sample times injected at the sensor nodes.
     """
     N, nnz, nobs = info["n_nodes"], info["nnz_k"], info["n_obs"]
     b = nnz * (4 + tsize) + (N + 1) * 4 + N * 4 + N * tsize + info["b_stored"] * tsize
-    b += 4 * N * RB * tsize
+    b += 3 * N * RB * tsize
     if kind == "fwd":
         b += nobs * 4 * (4 + tsize) + nobs * RB * 8
     else:
-        b += (N + 1) * 4 + 4 * nobs * (4 + tsize) + 4 * nobs * RB * 8
+        b += (N + 1) * 4 + 4 * nobs * (4 + tsize) + 2 * 4 * nobs * RB * 8
     return int(b)
 
 
@@ -281,7 +283,7 @@ def wide_probe(pat, G, info, w, yobs, sigma, iters=4):
     fwd_s = prof["fwd_ms"] / max(prof["fwd_sweeps"], 1) / w.n_steps / 1e3
     adj_s = prof["adj_ms"] / max(prof["adj_sweeps"], 1) / w.n_steps / 1e3
     fb, ab = step_bytes(info, RB, 4, "fwd"), step_bytes(info, RB, 4, "adj")
-    res = {"rhs_block": RB, "state_MB": round(4 * w.n_nodes * RB * 4 / 1e6, 1)}
+    res = {"rhs_block": RB, "state_MB": round(3 * w.n_nodes * RB * 4 / 1e6, 1)}
     for k, sec, b in (("fwd", fwd_s, fb), ("adj", adj_s, ab)):
         gbs = b / sec / 1e9
         res[k] = {"avg_launch_us": round(sec * 1e6, 3), "bytes_per_launch": b, "achieved": round(gbs, 1),

@@ -129,8 +129,9 @@ pat_status scratch_init(int dev) {
 struct SweepWS {
     pat::Prec prec = pat::Prec::F64;
     int RB = 0;
-    void *P[2] = {nullptr, nullptr};
-    void *V[2] = {nullptr, nullptr};
+    // state buffers of the three-level steps: S[0] holds a forward sweep's input and
+    // receives a transpose sweep's result
+    void *S[3] = {nullptr, nullptr, nullptr};
     void *Y = nullptr;  // [M][RB] staging of the user-facing calls
     hipGraphExec_t g_fwd_user = nullptr, g_adj_user = nullptr;
     hipGraphExec_t g_fwd_cgls = nullptr, g_adj_cgls = nullptr;
@@ -251,20 +252,17 @@ std::vector<float> to_f32(const std::vector<double> &v) {
 pat_status get_sweep(pat_problem *p, pat::Prec prec, int RB, bool need_y, SweepWS **out) {
     SweepWS &w = p->sweeps[{int(prec), RB}];
     if (w.RB == 0) {
-        // all four state buffers or none (a failed allocation leaves the workspace empty)
+        // all three state buffers or none (a failed allocation leaves the workspace empty)
         const size_t bytes = size_t(p->ops.n) * RB * tsize(prec);
-        void *v[4] = {nullptr, nullptr, nullptr, nullptr};
-        for (int k = 0; k < 4; ++k) {
+        void *v[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < 3; ++k) {
             pat_status st = dev_alloc(p, &v[k], bytes);
             if (st != PAT_OK) {
                 for (int q = 0; q < k; ++q) dev_free(p, v[q]);
                 return st;
             }
         }
-        w.P[0] = v[0];
-        w.P[1] = v[1];
-        w.V[0] = v[2];
-        w.V[1] = v[3];
+        for (int k = 0; k < 3; ++k) w.S[k] = v[k];
         w.prec = prec;
         w.RB = RB;
     }
@@ -297,31 +295,32 @@ pat_status capture(pat_problem *p, hipGraphExec_t *exec, F &&body) {
     return capture_on(p->cap, exec, std::forward<F>(body));
 }
 
-// Forward sweep: input state in w.P[0]; y^n (n = 1..N_T) written to y_out [N_T][N_obs][RB].
+// Forward sweep: input state in w.S[0]; y^n (n = 1..N_T) written to y_out [N_T][N_obs][RB].
+// Step k computes S^{k+1} from S^k and S^{k-1}, S^k in w.S[k % 3] (S^{-1} = S^0), and
+// samples y^k of the state it reads.
 void enqueue_forward(pat_problem *p, SweepWS &w, void *y_out, bool y_f64, double yscale, hipStream_t s) {
     const pat::DevOps &op = p->ops;
-    pat::launch_fwd_step(w.prec, w.RB, op, w.P[0], w.V[0], w.P[1], w.V[1], true, true, false, 0, y_out, y_f64,
-                         yscale, s);
-    int cur = 1;
-    for (int n = 2; n <= op.n_steps; ++n) {
-        pat::launch_fwd_step(w.prec, w.RB, op, w.P[cur], w.V[cur], w.P[1 - cur], w.V[1 - cur], true, false, true,
-                             n - 2, y_out, y_f64, yscale, s);
-        cur = 1 - cur;
-    }
-    pat::launch_fwd_step(w.prec, w.RB, op, w.P[cur], w.V[cur], nullptr, nullptr, false, false, true, op.n_steps - 1,
-                         y_out, y_f64, yscale, s);
+    const int NT = op.n_steps;
+    for (int k = 0; k < NT; ++k)
+        pat::launch_fwd_step(w.prec, w.RB, op, w.S[k % 3], w.S[k == 0 ? 0 : (k - 1) % 3], w.S[(k + 1) % 3], true,
+                             k > 0, k - 1, y_out, y_f64, yscale, s);
+    pat::launch_fwd_step(w.prec, w.RB, op, w.S[NT % 3], w.S[(NT - 1) % 3], nullptr, false, true, NT - 1, y_out,
+                         y_f64, yscale, s);
 }
 
-// Transpose sweep: data yhat [N_T][N_obs][RB]; result G^T yhat in w.P[0].
+// Buffer of q_j (j >= -1) in a transpose sweep of NT steps: chosen so that the
+// result, written where q_{NT} would go, lands in S[0].
+inline int adj_slot(int j, int NT) { return ((j - NT) % 3 + 3) % 3; }
+
+// Transpose sweep: data yhat [N_T][N_obs][RB]; result G^T yhat in w.S[0].
 void enqueue_adjoint(pat_problem *p, SweepWS &w, const void *yhat, bool y_f64, hipStream_t s) {
     const pat::DevOps &op = p->ops;
-    pat::launch_adj_init(w.prec, w.RB, op, w.P[0], w.V[0], yhat, y_f64, 1.0, s);
-    int cur = 0;
-    for (int n = op.n_steps; n >= 2; --n) {
-        pat::launch_adj_step(w.prec, w.RB, op, w.P[0], w.V[cur], w.V[1 - cur], false, n - 2, yhat, y_f64, 1.0, s);
-        cur = 1 - cur;
-    }
-    pat::launch_adj_step(w.prec, w.RB, op, w.P[0], w.V[cur], nullptr, true, 0, yhat, y_f64, 1.0, s);
+    const int NT = op.n_steps;
+    auto q = [&](int j) { return w.S[adj_slot(j, NT)]; };
+    pat::launch_adj_init(w.prec, w.RB, op, q(0), q(-1), yhat, y_f64, 1.0, s);
+    for (int k = 0; k + 1 < NT; ++k)
+        pat::launch_adj_step(w.prec, w.RB, op, q(k), q(k - 1), q(k + 1), false, NT - 2 - k, yhat, y_f64, 1.0, s);
+    pat::launch_adj_step(w.prec, w.RB, op, q(NT - 1), q(NT - 2), q(NT), true, 0, yhat, y_f64, 1.0, s);
 }
 
 // Launch a sweep graph; with profiling on, bracket it with two events from the pool.
@@ -427,7 +426,7 @@ void release_sweep(pat_problem *p, pat::Prec prec, int RB) {
     hipGraphExec_t *gs[] = {&w.g_fwd_user, &w.g_adj_user, &w.g_fwd_cgls, &w.g_adj_cgls, &w.g_fwd_chk};
     for (auto *g : gs)
         if (*g) (void)hipGraphExecDestroy(*g);
-    void *bufs[] = {w.P[0], w.P[1], w.V[0], w.V[1], w.Y};
+    void *bufs[] = {w.S[0], w.S[1], w.S[2], w.Y};
     for (void *b : bufs) dev_free(p, b);
     p->sweeps.erase(it);
 }
@@ -470,7 +469,7 @@ void fwd_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::FwdSte
         return;
     }
     for (const pat::FwdStep &f : st)
-        pat::launch_fwd_step(prec, RB, *f.op, f.P, f.V, f.Pn, f.Vn, f.rows, f.first, f.sample, f.t, f.y, y_f64,
+        pat::launch_fwd_step(prec, RB, *f.op, f.S, f.Sp, f.Sn, f.rows, f.sample, f.t, f.y, y_f64,
                              f.yscale, s);
 }
 
@@ -481,7 +480,7 @@ void adj_steps(pat::Prec prec, int RB, bool y_f64, const std::vector<pat::AdjSte
         return;
     }
     for (const pat::AdjStep &a : st)
-        pat::launch_adj_step(prec, RB, *a.op, a.PH, a.Q, a.Qn, a.last, a.tm1, a.yh, y_f64, a.yscale, s);
+        pat::launch_adj_step(prec, RB, *a.op, a.S, a.Sp, a.Sn, a.last, a.tb, a.yh, y_f64, a.yscale, s);
 }
 
 // enqueue_forward for several meshes with equal N_T: the same launches, merged per step.
@@ -493,20 +492,14 @@ void enqueue_forward_multi(const std::vector<pat_problem *> &P, const std::vecto
     const pat::Prec prec = W[0]->prec;
     const int RB = W[0]->RB;
     std::vector<pat::FwdStep> st(n);
-    for (size_t m = 0; m < n; ++m)
-        st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->P[1], W[m]->V[1], true, true, false, 0,
-                             yout[m], scale[m]};
-    fwd_steps(prec, RB, y_f64, st, s, merge);
-    int cur = 1;
-    for (int t = 2; t <= NT; ++t) {
+    for (int k = 0; k < NT; ++k) {
         for (size_t m = 0; m < n; ++m)
-            st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[cur], W[m]->V[cur], W[m]->P[1 - cur], W[m]->V[1 - cur], true,
-                                 false, true, t - 2, yout[m], scale[m]};
+            st[m] = pat::FwdStep{&P[m]->ops, W[m]->S[k % 3], W[m]->S[k == 0 ? 0 : (k - 1) % 3], W[m]->S[(k + 1) % 3],
+                                 true, k > 0, k - 1, yout[m], scale[m]};
         fwd_steps(prec, RB, y_f64, st, s, merge);
-        cur = 1 - cur;
     }
     for (size_t m = 0; m < n; ++m)
-        st[m] = pat::FwdStep{&P[m]->ops, W[m]->P[cur], W[m]->V[cur], nullptr, nullptr, false, false, true, NT - 1,
+        st[m] = pat::FwdStep{&P[m]->ops, W[m]->S[NT % 3], W[m]->S[(NT - 1) % 3], nullptr, false, true, NT - 1,
                              yout[m], scale[m]};
     fwd_steps(prec, RB, y_f64, st, s, merge);
 }
@@ -518,17 +511,16 @@ void enqueue_adjoint_multi(const std::vector<pat_problem *> &P, const std::vecto
     const int NT = P[0]->ops.n_steps;
     const pat::Prec prec = W[0]->prec;
     const int RB = W[0]->RB;
-    for (size_t m = 0; m < n; ++m) pat::launch_adj_init(prec, RB, P[m]->ops, W[m]->P[0], W[m]->V[0], yin[m], y_f64, 1.0, s);
+    auto q = [&](size_t m, int j) { return W[m]->S[adj_slot(j, NT)]; };
+    for (size_t m = 0; m < n; ++m) pat::launch_adj_init(prec, RB, P[m]->ops, q(m, 0), q(m, -1), yin[m], y_f64, 1.0, s);
     std::vector<pat::AdjStep> st(n);
-    int cur = 0;
-    for (int t = NT; t >= 2; --t) {
+    for (int k = 0; k + 1 < NT; ++k) {
         for (size_t m = 0; m < n; ++m)
-            st[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[cur], W[m]->V[1 - cur], false, t - 2, yin[m], 1.0};
+            st[m] = pat::AdjStep{&P[m]->ops, q(m, k), q(m, k - 1), q(m, k + 1), false, NT - 2 - k, yin[m], 1.0};
         adj_steps(prec, RB, y_f64, st, s, merge);
-        cur = 1 - cur;
     }
     for (size_t m = 0; m < n; ++m)
-        st[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[cur], nullptr, true, 0, yin[m], 1.0};
+        st[m] = pat::AdjStep{&P[m]->ops, q(m, NT - 1), q(m, NT - 2), q(m, NT), true, 0, yin[m], 1.0};
     adj_steps(prec, RB, y_f64, st, s, merge);
 }
 
@@ -568,8 +560,8 @@ pat_status tune_rb(const std::vector<pat_problem *> &P, hipStream_t cap, int64_t
             if (st != PAT_OK) break;
             const size_t nb = size_t(P[m]->ops.n) * RB * tsize(pr);
             const size_t yb = size_t(P[m]->ops.n_steps) * P[m]->ops.n_obs * RB * tsize(pr);
-            for (int k = 0; k < 2; ++k) {
-                if (hipMemsetAsync(W[m]->P[k], 0, nb, s) != hipSuccess || hipMemsetAsync(W[m]->V[k], 0, nb, s) != hipSuccess)
+            for (int k = 0; k < 3; ++k) {
+                if (hipMemsetAsync(W[m]->S[k], 0, nb, s) != hipSuccess)
                     st = fail(PAT_ERR_HIP, "autotune: hipMemsetAsync failed");
             }
             if (hipMemsetAsync(W[m]->Y, 0, yb, s) != hipSuccess) st = fail(PAT_ERR_HIP, "autotune: hipMemsetAsync failed");
@@ -580,9 +572,9 @@ pat_status tune_rb(const std::vector<pat_problem *> &P, hipStream_t cap, int64_t
         std::vector<pat::FwdStep> fs(P.size());
         std::vector<pat::AdjStep> as(P.size());
         for (size_t m = 0; m < P.size(); ++m) {
-            fs[m] = pat::FwdStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->P[1], W[m]->V[1], true, false, true, 0,
-                                 Y[m], 1.0};
-            as[m] = pat::AdjStep{&P[m]->ops, W[m]->P[0], W[m]->V[0], W[m]->V[1], false, 0, Y[m], 1.0};
+            fs[m] = pat::FwdStep{&P[m]->ops, W[m]->S[0], W[m]->S[1], W[m]->S[2], true, true, 0, Y[m], 1.0};
+            // a plain step reads the data of sample times 0 and 1; one-step problems time the closing launch
+            as[m] = pat::AdjStep{&P[m]->ops, W[m]->S[0], W[m]->S[1], W[m]->S[2], P[m]->ops.n_steps < 2, 0, Y[m], 1.0};
         }
         // The sweeps replay captured graphs, so time captured sequences of `reps` steps
         // (sequence q: direction q % 2).  Several meshes: q = 0, 1 merged launches per
@@ -651,8 +643,8 @@ pat_status tune_rb(const std::vector<pat_problem *> &P, hipStream_t cap, int64_t
 //   init, [transpose sweep], post_adj(0),
 //   then for k = 1..n_iter: pre_fwd(k), [forward sweep], post_fwd(k),
 //   and unless k = n_iter: [transpose sweep], post_adj(k).
-// The forward graph reads w->P[0] and writes qd = G x / sigma; the transpose
-// graph reads rd and leaves G^T rd in w->P[0].
+// The forward graph reads w->S[0] and writes qd = G x / sigma; the transpose
+// graph reads rd and leaves G^T rd in w->S[0].
 // With the spectral prior the unknowns are the latent grid vector (NX = n^3):
 // G_ext = [G P / sigma ; I], the forward input is P x and the transpose output
 // P^T (G^T r_d) / sigma + r_p.
@@ -699,9 +691,9 @@ void reorthogonalise(Solve &v, int k) {
 // s = G^T rd / sigma + L^T up (spectral prior: P^T G^T rd / sigma + up), from the transpose sweep's result.
 void combine_t(Solve &v, const double *up) {
     if (v.sw)
-        pat::launch_spectral_t(v.p->sops, v.RB, v.w->P[0], v.pr, v.isig, up, v.sw->gr, v.sw->gc, v.c->s, v.s);
+        pat::launch_spectral_t(v.p->sops, v.RB, v.w->S[0], v.pr, v.isig, up, v.sw->gr, v.sw->gc, v.c->s, v.s);
     else
-        pat::launch_gext_t_combine(v.pr, v.p->ops, v.RB, v.a, v.isig, v.w->P[0], up, v.c->s, v.s);
+        pat::launch_gext_t_combine(v.pr, v.p->ops, v.RB, v.a, v.isig, v.w->S[0], up, v.c->s, v.s);
 }
 
 // qp = L x (spectral prior: the identity on the latent vector).
@@ -841,10 +833,10 @@ void ph_init(Solve &v) {
 }
 void ph_post_adj(Solve &v, int k) { v.lsqr ? lsqr_post_adj(v, k) : cgls_post_adj(v, k); }
 void ph_pre_fwd(Solve &v, int) {
-    // the forward graph reads its input from P[0] in the sweep precision
+    // the forward graph reads its input from S[0] in the sweep precision
     const double *x = v.lsqr ? v.c->v : v.c->d;
-    if (v.sw) pat::launch_spectral(v.p->sops, v.RB, x, v.sw->gr, v.sw->gc, v.pr, v.w->P[0], v.N, v.s);
-    else pat::launch_cast_to_state(v.pr, x, v.w->P[0], v.N * v.RB, v.s);
+    if (v.sw) pat::launch_spectral(v.p->sops, v.RB, x, v.sw->gr, v.sw->gc, v.pr, v.w->S[0], v.N, v.s);
+    else pat::launch_cast_to_state(v.pr, x, v.w->S[0], v.N * v.RB, v.s);
 }
 void ph_post_fwd(Solve &v, int k) { v.lsqr ? lsqr_post_fwd(v, k) : cgls_post_fwd(v, k); }
 // per-RHS scalar that turns non-finite when the solve breaks down (CGLS gamma, LSQR phi_bar)
@@ -919,7 +911,7 @@ pat_status final_check(Solve &v, const double *y_obs, const pat_rto_params *prm,
         src = v.sw->ym;
     }
     for (int h = 0; h < RB; h += RBf) {
-        pat::launch_cols(src, RB, h, static_cast<double *>(w64->P[0]), v.N, RBf, v.s);
+        pat::launch_cols(src, RB, h, static_cast<double *>(w64->S[0]), v.N, RBf, v.s);
         PAT_HIP(hipGraphLaunch(w64->g_fwd_chk, v.s));  // qd [M][RBf] = G p / sigma
         pat::launch_diff_sq_partial(c->rd, RB, h, c->qd, v.M, RBf, pA, v.s);
         pat::launch_dot_final(pA, nullptr, RBf, t1 + h, v.s);
@@ -1181,7 +1173,7 @@ pat_status pat_forward(pat_problem *p, int64_t R, const void *p0, void *y, pat_p
     const int64_t M = int64_t(p->ops.n_steps) * p->ops.n_obs;
     const int32_t *perm = p->perm_identity ? nullptr : p->ops.perm;
     for (int64_t rb0 = 0; rb0 < R; rb0 += RB) {
-        pat::launch_pack(f64, f64, p0, R, rb0, RB, p->ops.n, perm, w->P[0], s);
+        pat::launch_pack(f64, f64, p0, R, rb0, RB, p->ops.n, perm, w->S[0], s);
         PAT_HIP(hipGraphLaunch(w->g_fwd_user, s));
         pat::launch_unpack(f64, f64, w->Y, R, rb0, RB, M, nullptr, y, s);
     }
@@ -1202,8 +1194,8 @@ pat_status pat_forward_noalloc(pat_problem *p, int64_t R, const void *p0, void *
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t M = int64_t(p->ops.n_steps) * p->ops.n_obs;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    // the block of pat_forward, halved until four state vectors and the staging fit the scratch
-    auto need = [&](int rb) { return 4 * up(size_t(p->ops.n) * rb * tsize(pr)) + up(size_t(M) * rb * tsize(pr)); };
+    // the block of pat_forward, halved until three state vectors and the staging fit the scratch
+    auto need = [&](int rb) { return 3 * up(size_t(p->ops.n) * rb * tsize(pr)) + up(size_t(M) * rb * tsize(pr)); };
     int RB = fit_rb(p->ops.n, pr, choose_rb(R));
     while (RB > 1 && need(RB) > kScratchBytes) RB >>= 1;
     if (need(RB) > kScratchBytes)
@@ -1214,15 +1206,14 @@ pat_status pat_forward_noalloc(pat_problem *p, int64_t R, const void *p0, void *
     w.prec = pr;
     w.RB = RB;
     const size_t nb = up(size_t(p->ops.n) * RB * tsize(pr));
-    w.P[0] = base;
-    w.P[1] = base + nb;
-    w.V[0] = base + 2 * nb;
-    w.V[1] = base + 3 * nb;
-    w.Y = base + 4 * nb;
+    w.S[0] = base;
+    w.S[1] = base + nb;
+    w.S[2] = base + 2 * nb;
+    w.Y = base + 3 * nb;
     const bool f64 = pr == pat::Prec::F64;
     const int32_t *perm = p->perm_identity ? nullptr : p->ops.perm;
     for (int64_t rb0 = 0; rb0 < R; rb0 += RB) {
-        pat::launch_pack(f64, f64, p0, R, rb0, RB, p->ops.n, perm, w.P[0], s);
+        pat::launch_pack(f64, f64, p0, R, rb0, RB, p->ops.n, perm, w.S[0], s);
         enqueue_forward(p, w, w.Y, false, 1.0, s);
         pat::launch_unpack(f64, f64, w.Y, R, rb0, RB, M, nullptr, y, s);
     }
@@ -1250,7 +1241,7 @@ pat_status pat_adjoint(pat_problem *p, int64_t R, const void *yhat, void *p_out,
     for (int64_t rb0 = 0; rb0 < R; rb0 += RB) {
         pat::launch_pack(f64, f64, yhat, R, rb0, RB, M, nullptr, w->Y, s);
         PAT_HIP(hipGraphLaunch(w->g_adj_user, s));
-        pat::launch_unpack(f64, f64, w->P[0], R, rb0, RB, p->ops.n, perm, p_out, s);
+        pat::launch_unpack(f64, f64, w->S[0], R, rb0, RB, p->ops.n, perm, p_out, s);
     }
     PAT_HIP(hipGetLastError());
     return PAT_OK;
@@ -1719,12 +1710,12 @@ pat_status pat_prior_apply(pat_problem *p, int64_t R, double prior_a, int transp
     const int32_t *perm = p->perm_identity ? nullptr : p->ops.perm;
     const int64_t N = p->ops.n;
     for (int64_t rb0 = 0; rb0 < R; rb0 += RB) {
-        pat::launch_pack(true, true, x, R, rb0, RB, N, perm, w->P[0], s);
+        pat::launch_pack(true, true, x, R, rb0, RB, N, perm, w->S[0], s);
         if (transpose)
-            pat::launch_prior_t(p->ops, RB, prior_a, static_cast<const double *>(w->P[0]), static_cast<double *>(w->P[1]), s);
+            pat::launch_prior_t(p->ops, RB, prior_a, static_cast<const double *>(w->S[0]), static_cast<double *>(w->S[1]), s);
         else
-            pat::launch_prior(p->ops, RB, prior_a, static_cast<const double *>(w->P[0]), static_cast<double *>(w->P[1]), s);
-        pat::launch_unpack(true, true, w->P[1], R, rb0, RB, N, perm, y, s);
+            pat::launch_prior(p->ops, RB, prior_a, static_cast<const double *>(w->S[0]), static_cast<double *>(w->S[1]), s);
+        pat::launch_unpack(true, true, w->S[1], R, rb0, RB, N, perm, y, s);
     }
     PAT_HIP(hipGetLastError());
     return PAT_OK;

@@ -32,20 +32,25 @@ struct DevOps {
 enum class Prec { F64, F32 };
 
 
-// One forward Stormer-Verlet step on the staggered state (P = p^{n+1/2}, V = v^n),
-// optionally sampling y^{k} = Pi (P - dt/2 V) of the incoming state into
-// y_out[(t*n_obs + s)*RB + r] * yscale.  first != 0 treats V as zero.
-// rows = 0 launches only the sampling part.
-void launch_fwd_step(Prec prec, int RB, const DevOps &op, const void *P, const void *V, void *Pn, void *Vn,
-                     bool rows, bool first, bool sample, int t, void *y_out, bool y_is_f64, double yscale,
-                     hipStream_t s);
+// One forward Stormer-Verlet step in the three-level form (Sec. 3 eq. (fully-discrete),
+// lumped mass, S^n = p^{n+1/2}):
+//   Sn = S + (S - Sp) - (dt/m)(dt K S + B (S - Sp)),
+// optionally sampling y = Pi (S + Sp)/2 (= Pi p^n) of the incoming state into
+// y_out[(t*n_obs + s)*RB + r] * yscale.  The first step of a sweep passes Sp == S
+// (v^0 = 0).  rows = 0 launches only the sampling part.  S, Sp and Sn are three
+// distinct buffers except for Sp == S.
+void launch_fwd_step(Prec prec, int RB, const DevOps &op, const void *S, const void *Sp, void *Sn, bool rows,
+                     bool sample, int t, void *y_out, bool y_is_f64, double yscale, hipStream_t s);
 
-// Transpose sweep: init (p = Pi^T yhat^{N_T}, q = dt/(2m) p) and one staggered
-// transpose step (p -= dt K q; unless last: q' = q - dt/m B q + dt/m (p + inj/2), p += inj,
-// inj = Pi^T yhat^{tm1}).  yhat[(t*n_obs + s)*RB + r] * yscale, f64 or the sweep type.
-void launch_adj_init(Prec prec, int RB, const DevOps &op, void *PH, void *Q, const void *yhat, bool y_is_f64,
+// Transpose sweep in the three-level form (Sec. 5.1 eq. (adjoint-verlet) within the
+// recursion (backward-recursion), q = M_L^{-1}(v_hat + dt/2 p_hat)).  init: q0 =
+// (dt/2m) Pi^T yhat^{N_T}, qm1 = 0.  step: Sn = S + (S - Sp) - (dt/m)(dt K S + B (S - Sp)
+// - Pi^T (yhat^{tb+1} + yhat^{tb})/2); last: Sn = the result G^T yhat = (S - Sp) m/dt -
+// (dt K S - B Sp - Pi^T yhat^{tb}/2) with tb = 0.  yhat[(t*n_obs + s)*RB + r] * yscale,
+// float64 or the sweep type (t = 0 .. N_T - 1 for yhat^1 .. yhat^{N_T}).
+void launch_adj_init(Prec prec, int RB, const DevOps &op, void *q0, void *qm1, const void *yhat, bool y_is_f64,
                      double yscale, hipStream_t s);
-void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1,
+void launch_adj_step(Prec prec, int RB, const DevOps &op, const void *S, const void *Sp, void *Sn, bool last, int tb,
                      const void *yhat, bool y_is_f64, double yscale, hipStream_t s);
 
 // Several meshes' steps in one launch (vector-lane kernels only: RB * sizeof(T) >= 16,
@@ -54,20 +59,19 @@ void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *
 constexpr int kMaxMeshes = 4;
 struct FwdStep {
     const DevOps *op;
-    const void *P, *V;
-    void *Pn, *Vn;
-    bool rows, first, sample;
+    const void *S, *Sp;
+    void *Sn;
+    bool rows, sample;
     int t;
     void *y;
     double yscale;
 };
 struct AdjStep {
     const DevOps *op;
-    void *PH;
-    const void *Q;
-    void *Qn;
+    const void *S, *Sp;
+    void *Sn;
     bool last;
-    int tm1;
+    int tb;
     const void *yh;
     double yscale;
 };

@@ -9,8 +9,23 @@
 //
 // Paper: "3D Uncertainty Quantification for Photoacoustic Tomography"
 // (arXiv 2607.21373).  The time stepping is Sec. 3 eq. (fully-discrete) with
-// M replaced by M_L, written in staggered form; the transposed stepping is
-// Sec. 5.1 eq. (adjoint-verlet) with the recursion (backward-recursion).
+// M replaced by M_L; the transposed stepping is Sec. 5.1 eq. (adjoint-verlet)
+// with the recursion (backward-recursion).
+//
+// Both are carried as three-level recurrences in one state vector, so that a
+// step reads two state vectors and writes one (the velocity form reads two and
+// writes two).  Forward: with S^n = p^{n+1/2} (p^{1/2} = p^0 since v^0 = 0),
+// the three substeps give dt v^n = S^n - S^{n-1} and
+//   S^{n+1} = S^n + (S^n - S^{n-1}) - (dt/m) (dt K S^n + B (S^n - S^{n-1})),
+//   p^n = (S^{n-1} + S^n) / 2  (the sampled pressure),
+// started from S^{-1} = S^0 = p^0.  Transposed: write inj_j = Pi^T yhat^{N_T - j}
+// and q_k = M_L^{-1}(v_hat + dt/2 p_hat) after k transposed steps.  Then
+// p_hat_{k+1} = (q_{k+1} - q_k) m/dt + B q_k + inj_{k+1}/2, and eliminating p_hat
+// leaves the same recurrence for q with a source:
+//   q_{k+1} = q_k + (q_k - q_{k-1}) - (dt/m) (dt K q_k + B (q_k - q_{k-1}) - (inj_k + inj_{k+1})/2)
+// for k = 0 .. N_T - 2, started from q_{-1} = 0, q_0 = (dt/2m) inj_0; the result is
+//   G^T yhat = (q_K - q_{K-1}) m/dt - (dt K q_K - B q_{K-1} - inj_K/2),  K = N_T - 1.
+// In exact arithmetic both forms give the same maps.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -80,13 +95,34 @@ __device__ __forceinline__ void load_meta(const RowOps<T> &o, int row, int part,
     m.dm = o.dtm[row];
 }
 
-// sum over the row's entries of K(row, k) X[col_k][r] into acc, and of B(row, k) Y[col_k][r]
-// into bacc for a boundary row (Y == X shares the gathers).  All PER gathers of the lane
-// are issued before any is consumed; sums run in slot order, then the entries beyond 16.
-template <typename T, int RB, bool Y_IS_X>
+// The value a boundary slot multiplies: S - S_prev in a step, -S_prev in the
+// transpose sweep's closing launch (only_prev).
+template <typename T>
+__device__ __forceinline__ T bdiff(T x, T y, bool only_prev) { return only_prev ? -y : x - y; }
+
+// One row of a three-level step: S' = S + ((S - Sp) - (dt/m)(dt K S + B (S - Sp) - src))
+// from acc = (K S)_row, bacc = (B (S - Sp))_row and the source src (0 forward).
+template <typename T>
+__device__ __forceinline__ T step_update(T cur, T prev, T acc, T bacc, T src, T dm, T dt) {
+    const T f = mad(dt, acc, bacc) - src;
+    return cur + mad(-dm, f, cur - prev);
+}
+// The transpose sweep's result, (q - q_prev) m/dt - (dt K q - B q_prev - src), from
+// acc = (K q)_row and bacc = -(B q_prev)_row.
+template <typename T>
+__device__ __forceinline__ T adj_result(T cur, T prev, T acc, T bacc, T src, T dm, T dt) {
+    const T f = mad(dt, acc, bacc) - src;
+    return (cur - prev) / dm - f;
+}
+
+// acc = sum over the row's entries of K(row, k) X[col_k][r], and for a boundary row
+// bacc = sum of B(row, k) bdiff(X[col_k][r], Y[col_k][r]).  All PER gathers of the
+// lane are issued before any is consumed; sums run in slot order, then the entries
+// beyond 16.
+template <typename T, int RB>
 __device__ __forceinline__ void row_sums(const RowOps<T> &o, const RowMeta<T, RB> &m, int part, int r,
-                                         const T *__restrict__ X, const T *__restrict__ Y, bool with_b, T &acc,
-                                         T &bacc) {
+                                         const T *__restrict__ X, const T *__restrict__ Y, bool with_b,
+                                         bool only_prev, T &acc, T &bacc) {
     using G = Geo<RB>;
     T x[G::PER];
 #pragma unroll
@@ -95,25 +131,19 @@ __device__ __forceinline__ void row_sums(const RowOps<T> &o, const RowMeta<T, RB
     for (int j = 0; j < G::PER; ++j) acc = mad(m.w[j], x[j], acc);
     if (with_b) {
         const T *Bv = o.bslot + m.bo;
-        T bw[G::PER];
+        T bw[G::PER], y[G::PER];
 #pragma unroll
         for (int j = 0; j < G::PER; ++j) bw[j] = Bv[part + j * G::SPLIT];
-        if constexpr (Y_IS_X) {
 #pragma unroll
-            for (int j = 0; j < G::PER; ++j) bacc = mad(bw[j], x[j], bacc);
-        } else {
-            T y[G::PER];
+        for (int j = 0; j < G::PER; ++j) y[j] = Y[int64_t(m.c[j]) * RB + r];
 #pragma unroll
-            for (int j = 0; j < G::PER; ++j) y[j] = Y[int64_t(m.c[j]) * RB + r];
-#pragma unroll
-            for (int j = 0; j < G::PER; ++j) bacc = mad(bw[j], y[j], bacc);
-        }
+        for (int j = 0; j < G::PER; ++j) bacc = mad(bw[j], bdiff(x[j], y[j], only_prev), bacc);
     }
     for (int k = m.x0 + part; k < m.x1; k += G::SPLIT) {
         const int64_t cj = int64_t(o.xcol[k]) * RB + r;
         const T xv = X[cj];
         acc = mad(o.xval[k], xv, acc);
-        if (with_b) bacc = mad(o.bslot[m.bo + G::W + (k - m.x0)], Y_IS_X ? xv : Y[cj], bacc);
+        if (with_b) bacc = mad(o.bslot[m.bo + G::W + (k - m.x0)], bdiff(xv, Y[cj], only_prev), bacc);
     }
 }
 
@@ -149,19 +179,18 @@ struct FwdArgs {
     RowOps<T> o;
     const int32_t *snode;
     const T *sw;
-    const T *P, *V;
-    T *Pn, *Vn;
+    const T *S, *Sp;  // S^n, S^{n-1}
+    T *Sn;            // S^{n+1}
     void *y;
     double yscale;
-    int n, n_obs, n_tiles, n_samp, first, sample, t;
-    T dt, half_dt;
+    int n, n_obs, n_tiles, n_samp, sample, t;
+    T dt;
 };
 
-// Forward step.  State (P, V) = (p^{n+1/2}, v^n):
-//   V' = V - (dt/m) (K P + B V),  P' = P + dt V'
-// which is the three-substep Stormer-Verlet update with lumped mass.  One tile
-// of RPB rows per workgroup; the sampling blocks placed among them write
-// the samples y^n = Pi (P - dt/2 V) of the incoming state, one (sensor, RHS)
+// Forward step S^{n+1} = S^n + (S^n - S^{n-1}) - (dt/m)(dt K S^n + B (S^n - S^{n-1})),
+// the three-substep Stormer-Verlet update with lumped mass in S^n = p^{n+1/2}.  One
+// tile of RPB rows per workgroup; the sampling blocks placed among them write the
+// samples y = Pi p^n = Pi (S^n + S^{n-1})/2 of the incoming state, one (sensor, RHS)
 // pair per thread.
 template <typename T, typename OT, int RB>
 __global__ void __launch_bounds__(256) k_fwd(const FwdArgs<T> a) {
@@ -175,15 +204,11 @@ __global__ void __launch_bounds__(256) k_fwd(const FwdArgs<T> a) {
         RowMeta<T, RB> m;
         load_meta<T, RB>(a.o, row, part, m);
         const int64_t id = int64_t(row) * RB + r;
-        const T v0 = a.first ? T(0) : a.V[id];
         T acc = T(0), bacc = T(0);
-        row_sums<T, RB, false>(a.o, m, part, r, a.P, a.V, !a.first && m.bo >= 0, acc, bacc);
-        acc = lane_sum<RB, G::LPR>(acc + bacc);
-        if (part == 0) {
-            const T v = v0 - m.dm * acc;
-            a.Vn[id] = v;
-            a.Pn[id] = a.P[id] + a.dt * v;
-        }
+        row_sums<T, RB>(a.o, m, part, r, a.S, a.Sp, m.bo >= 0, false, acc, bacc);
+        acc = lane_sum<RB, G::LPR>(acc);
+        bacc = lane_sum<RB, G::LPR>(bacc);
+        if (part == 0) a.Sn[id] = step_update(a.S[id], a.Sp[id], acc, bacc, T(0), m.dm, a.dt);
         return;
     }
     const int64_t e = int64_t(tile - a.n_tiles) * 256 + threadIdx.x;
@@ -192,8 +217,7 @@ __global__ void __launch_bounds__(256) k_fwd(const FwdArgs<T> a) {
     T y = T(0);
     for (int k = 0; k < 4; ++k) {
         const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
-        const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
-        y = mad(a.sw[4 * s + k], pk, y);
+        y = mad(a.sw[4 * s + k], T(0.5) * (a.S[id] + a.Sp[id]), y);
     }
     OT *yo = static_cast<OT *>(a.y);
     yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
@@ -204,65 +228,64 @@ struct AdjArgs {
     RowOps<T> o;
     const int32_t *injptr, *injs;
     const T *injw;
-    T *PH;
-    const T *Q;
-    T *Qn;
+    const T *S, *Sp;  // q_k, q_{k-1}
+    T *Sn;            // q_{k+1}, or the result after the last step
     const void *yh;
     double yscale;
-    int n, n_obs, n_tiles, last, tm1;
+    int n, n_obs, n_tiles, last;
+    int ta, tb;  // sources: Pi^T yhat at sample indices ta (if >= 0) and tb
     T dt;
 };
 
 // Rows with sensor weights are few (four per sensor at most): one wave-uniform
 // test of the injection range of the wave's rows [r0, r0 + nrows) lets waves
 // without any skip the per-row range loads.
-__device__ __forceinline__ bool wave_injects(const int32_t *injptr, int r0, int nrows, int n, int last) {
+__device__ __forceinline__ bool wave_injects(const int32_t *injptr, int r0, int nrows, int n) {
     const int w0 = __builtin_amdgcn_readfirstlane(r0);
-    if (last || w0 >= n) return false;
+    if (w0 >= n) return false;
     const int w1 = w0 + nrows < n ? w0 + nrows : n;
     return injptr[w0] != injptr[w1];
 }
 
+// (Pi^T (yhat^{ta} + yhat^{tb}))_row for RHS r (yhat^{ta} left out for ta < 0)
 template <typename T, typename YT, int RB>
-__device__ __forceinline__ T inject(const AdjArgs<T> &a, int row, int r, int t) {
+__device__ __forceinline__ T inject(const AdjArgs<T> &a, int row, int r) {
     const YT *yh = static_cast<const YT *>(a.yh);
     T inj = T(0);
-    for (int e = a.injptr[row]; e < a.injptr[row + 1]; ++e)
-        inj = mad(a.injw[e], static_cast<T>(static_cast<double>(yh[(int64_t(t) * a.n_obs + a.injs[e]) * RB + r]) * a.yscale),
-                  inj);
+    for (int e = a.injptr[row]; e < a.injptr[row + 1]; ++e) {
+        const int s = a.injs[e];
+        T v = static_cast<T>(static_cast<double>(yh[(int64_t(a.tb) * a.n_obs + s) * RB + r]) * a.yscale);
+        if (a.ta >= 0) v = static_cast<T>(static_cast<double>(yh[(int64_t(a.ta) * a.n_obs + s) * RB + r]) * a.yscale) + v;
+        inj = mad(a.injw[e], v, inj);
+    }
     return inj;
 }
 
-// Transposed step on the staggered state (PH = p_hat, Q = M_L^{-1}(v_hat + dt/2 p_hat)):
-//   PH -= dt K Q ;  unless last:  Q' = Q - (dt/m) B Q + (dt/m)(PH + inj/2),  PH += inj
-// with inj = Pi^T yhat^{n-1}.  Algebraically identical to applying the five
-// transposed substeps and then adding Pi^T yhat^{n-1}.  K Q and B Q share the
-// gathers of Q.  One tile of RPB rows per workgroup.
+// Transposed step q_{k+1} = q_k + (q_k - q_{k-1}) - (dt/m)(dt K q_k + B (q_k - q_{k-1})
+// - inj/2), inj = Pi^T (yhat^{ta} + yhat^{tb}); with `last`, the result
+// (q_k - q_{k-1}) m/dt - (dt K q_k - B q_{k-1} - inj/2), inj = Pi^T yhat^{tb}.
+// One tile of RPB rows per workgroup.
 template <typename T, typename YT, int RB>
 __global__ void __launch_bounds__(256) k_adj(const AdjArgs<T> a) {
     using G = Geo<RB>;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int part = (lane / RB) % G::SPLIT, r = lane % RB;
     const int wrow0 = xcd_tile(blockIdx.x, gridDim.x) * G::RPB + wave * G::RPW;
-    const bool winj = wave_injects(a.injptr, wrow0, G::RPW, a.n, a.last);
+    const bool winj = wave_injects(a.injptr, wrow0, G::RPW, a.n);
     const int row = wrow0 + lane / G::LPR;
     if (row >= a.n) return;
     RowMeta<T, RB> m;
     load_meta<T, RB>(a.o, row, part, m);
     const int64_t id = int64_t(row) * RB + r;
-    const T ph0 = a.PH[id];
     T kq = T(0), bq = T(0);
-    row_sums<T, RB, true>(a.o, m, part, r, a.Q, a.Q, !a.last && m.bo >= 0, kq, bq);
+    row_sums<T, RB>(a.o, m, part, r, a.S, a.Sp, m.bo >= 0, a.last, kq, bq);
     kq = lane_sum<RB, G::LPR>(kq);
     bq = lane_sum<RB, G::LPR>(bq);
     if (part == 0) {
-        T ph = ph0 - a.dt * kq;
-        if (!a.last) {
-            const T inj = winj ? inject<T, YT, RB>(a, row, r, a.tm1) : T(0);
-            a.Qn[id] = a.Q[id] - m.dm * bq + m.dm * (ph + T(0.5) * inj);
-            ph += inj;
-        }
-        a.PH[id] = ph;
+        const T src = winj ? T(0.5) * inject<T, YT, RB>(a, row, r) : T(0);
+        const T cur = a.S[id], prev = a.Sp[id];
+        a.Sn[id] = a.last ? adj_result(cur, prev, kq, bq, src, m.dm, a.dt)
+                          : step_update(cur, prev, kq, bq, src, m.dm, a.dt);
     }
 }
 
@@ -381,16 +404,16 @@ __device__ __forceinline__ VT vfma(T w, VT x, VT acc) {
     return o;
 }
 
-// acc += sum_slots K(row, slot) X[col][q-th vector]; with_b: bacc += B(row, slot) Y[col].
-// The B sums (boundary rows only) run after the K sums have been consumed, with
-// their own gathers, so the two sets of gathers are never live together and the
-// kernel keeps the register budget (and occupancy) of the interior rows.
-// Slot 0 of every row is its diagonal, so the first gather is the row's own X
-// value; it is returned in `own`.
+// acc += sum_slots K(row, slot) X[col][q-th vector]; with_b: bacc += B(row, slot)
+// bdiff(X[col], Y[col]).  The B sums (boundary rows only) run after the K sums have
+// been consumed, with their own gathers, so the two sets of gathers are never live
+// together and the kernel keeps the register budget (and occupancy) of the interior
+// rows.  Slot 0 of every row is its diagonal, so the first gather is the row's own
+// X value; it is returned in `own`.
 template <typename T, int RB>
 __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, RB> &L, int lr, int q,
                                           const T *__restrict__ X, const T *__restrict__ Y, bool with_b,
-                                          typename Vec16<T>::t &acc, typename Vec16<T>::t &bacc,
+                                          bool only_prev, typename Vec16<T>::t &acc, typename Vec16<T>::t &bacc,
                                           typename Vec16<T>::t &own) {
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
@@ -416,31 +439,40 @@ __device__ __forceinline__ void vrow_sums(const RowOps<T> &o, const TileOps<T, R
         const VT xv = *reinterpret_cast<const VT *>(Xc + (uint32_t(o.xcol[k]) * ROWB + qoff));
         acc = vfma(o.xval[k], xv, acc);
     }
-    {
-        if (with_b) {
-            // only the row's first bnum slots carry B; re-read the slot operands from LDS
-            // instead of keeping them live across the K sums
-            int bbase = base;
-            asm volatile("" : "+v"(bbase));
-            const int nb = L.bn[lr];
+    if (with_b) {
+        // only the row's first bnum slots carry B; re-read the slot operands from LDS
+        // instead of keeping them live across the K sums
+        int bbase = base;
+        asm volatile("" : "+v"(bbase));
+        const int nb = L.bn[lr];
+        constexpr int BCH = CH / 4;  // two gathers per slot
 #pragma unroll
-            for (int j0 = 0; j0 < G::W; j0 += CH) {
-                if (j0 < nb) {
-                    VT y[CH];
+        for (int j0 = 0; j0 < G::W; j0 += BCH) {
+            if (j0 < nb) {
+                VT y[BCH];
 #pragma unroll
-                    for (int j = 0; j < CH; ++j) {
-                        y[j] = VT{};
-                        if (j0 + j < nb)
-                            y[j] = *reinterpret_cast<const VT *>(Yc + (uint32_t(L.col[bbase + j0 + j]) * ROWB + qoff));
+                for (int j = 0; j < BCH; ++j) {
+                    y[j] = VT{};
+                    if (j0 + j < nb) {
+                        const uint32_t off = uint32_t(L.col[bbase + j0 + j]) * ROWB + qoff;
+                        const VT xv = *reinterpret_cast<const VT *>(Xc + off);
+                        const VT yv = *reinterpret_cast<const VT *>(Yc + off);
+#pragma unroll
+                        for (int i = 0; i < G::VEC; ++i) y[j][i] = bdiff(xv[i], yv[i], only_prev);
                     }
-#pragma unroll
-                    for (int j = 0; j < CH; ++j) bacc = vfma(L.bv[bbase + j0 + j], y[j], bacc);
                 }
+#pragma unroll
+                for (int j = 0; j < BCH; ++j) bacc = vfma(L.bv[bbase + j0 + j], y[j], bacc);
             }
-            for (int k = x0; k < x0 + nb - G::W; ++k) {
-                const VT yv = *reinterpret_cast<const VT *>(Yc + (uint32_t(o.xcol[k]) * ROWB + qoff));
-                bacc = vfma(o.bslot[L.bo[lr] + G::W + (k - x0)], yv, bacc);
-            }
+        }
+        for (int k = x0; k < x0 + nb - G::W; ++k) {
+            const uint32_t off = uint32_t(o.xcol[k]) * ROWB + qoff;
+            const VT xv = *reinterpret_cast<const VT *>(Xc + off);
+            const VT yv = *reinterpret_cast<const VT *>(Yc + off);
+            VT dv;
+#pragma unroll
+            for (int i = 0; i < G::VEC; ++i) dv[i] = bdiff(xv[i], yv[i], only_prev);
+            bacc = vfma(o.bslot[L.bo[lr] + G::W + (k - x0)], dv, bacc);
         }
     }
 }
@@ -450,21 +482,21 @@ struct VFwdArgs {
     RowOps<T> o;
     const int32_t *snode;
     const T *sw;
-    const T *P, *V;
-    T *Pn, *Vn;
+    const T *S, *Sp;  // S^n, S^{n-1}
+    T *Sn;            // S^{n+1}
     void *y;
     double yscale;
-    int n, n_obs, n_tiles, n_samp, first, sample, t;
+    int n, n_obs, n_tiles, n_samp, sample, t;
     int stream;  // state beyond the Infinity Cache: launch the non-temporal variant
-    T dt, half_dt;
+    T dt;
     // halo tiles (HaloTiles), float32 blocks of 256-byte row chunks
     const int32_t *hdesc, *hrow;
     const uint32_t *hmeta;
     int n_ht;
 };
 
-// Sampling block j of a forward step: y^n = Pi (P - dt/2 V) of the incoming state,
-// one lane per (sensor, rhs).
+// Sampling block j of a forward step: y = Pi (S^n + S^{n-1})/2 of the incoming
+// state, one lane per (sensor, rhs).
 template <typename T, typename OT, int RB>
 __device__ __forceinline__ void fwd_sample(const VFwdArgs<T> &a, int j) {
     const int64_t e = int64_t(j) * 256 + threadIdx.x;
@@ -473,41 +505,35 @@ __device__ __forceinline__ void fwd_sample(const VFwdArgs<T> &a, int j) {
     T y = T(0);
     for (int k = 0; k < 4; ++k) {
         const int64_t id = int64_t(a.snode[4 * s + k]) * RB + r;
-        const T pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
-        y = mad(a.sw[4 * s + k], pk, y);
+        y = mad(a.sw[4 * s + k], T(0.5) * (a.S[id] + a.Sp[id]), y);
     }
     OT *yo = static_cast<OT *>(a.y);
     yo[(int64_t(a.t) * a.n_obs + s) * RB + r] = static_cast<OT>(static_cast<double>(y) * a.yscale);
 }
 
 // Forward step (same update as k_fwd) with vector lanes on logical tile `tile`;
-// the tiles after the row tiles write the samples y^n = Pi (P - dt/2 V) of the
-// incoming state.
+// the tiles after the row tiles write the samples of the incoming state.
 template <typename T, typename OT, int RB, bool NT>
 __device__ __forceinline__ void fwd_tile(const VFwdArgs<T> &a, int tile, TileOps<T, RB> &L) {
     using G = VGeo<T, RB>;
     using VT = typename Vec16<T>::t;
     if (tile < a.n_tiles) {
         const int row0 = tile * G::RPB;
-        stage_tile<T, RB>(a.o, a.n, row0, !a.first, L);
+        stage_tile<T, RB>(a.o, a.n, row0, true, L);
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int lr = wave * G::RPW + lane / G::LPR, q = lane % G::LPR;
         const int row = row0 + lr;
         if (row < a.n) {
             const int64_t id = int64_t(row) * RB + q * G::VEC;
-            VT v0 = {};
-            if (!a.first) v0 = vload_own<NT, VT>(a.V + id);
-            VT acc = {}, bacc = {}, p0;
-            vrow_sums<T, RB>(a.o, L, lr, q, a.P, a.V, !a.first && L.bo[lr] >= 0, acc, bacc, p0);
+            VT acc = {}, bacc = {}, cur;
+            vrow_sums<T, RB>(a.o, L, lr, q, a.S, a.Sp, L.bo[lr] >= 0, false, acc, bacc, cur);
+            // loaded after the sums: the kernel has no register to spare for it before
+            const VT prev = vload_own<NT, VT>(a.Sp + id);
             const T dm = L.dm[lr];
-            VT v, pn;
+            VT sn;
 #pragma unroll
-            for (int i = 0; i < G::VEC; ++i) {
-                v[i] = v0[i] - dm * (acc[i] + bacc[i]);
-                pn[i] = p0[i] + a.dt * v[i];
-            }
-            vstore<NT, VT>(a.Vn + id, v);
-            vstore<NT, VT>(a.Pn + id, pn);
+            for (int i = 0; i < G::VEC; ++i) sn[i] = step_update(cur[i], prev[i], acc[i], bacc[i], T(0), dm, a.dt);
+            vstore<NT, VT>(a.Sn + id, sn);
         }
     } else if (a.sample) {
         fwd_sample<T, OT, RB>(a, tile - a.n_tiles);
@@ -569,18 +595,39 @@ struct VAdjArgs {
     RowOps<T> o;
     const int32_t *injptr, *injs;
     const T *injw;
-    T *PH;
-    const T *Q;
-    T *Qn;
+    const T *S, *Sp;  // q_k, q_{k-1}
+    T *Sn;            // q_{k+1}, or the result after the last step
     const void *yh;
     double yscale;
-    int n, n_obs, n_tiles, last, tm1;
+    int n, n_obs, n_tiles, last;
+    int ta, tb;  // sources: Pi^T yhat at sample indices ta (if >= 0) and tb
     int stream;  // state beyond the Infinity Cache: launch the non-temporal variant
     T dt;
     const int32_t *hdesc, *hrow;
     const uint32_t *hmeta;
     int n_ht;
 };
+
+// Pi^T (yhat^{ta} + yhat^{tb}) over the injection entries [e0, e1) of a row, for
+// the VEC right-hand sides from rhs0 (yhat^{ta} left out for ta < 0).
+template <typename T, typename YT, int RB, typename VT>
+__device__ __forceinline__ VT vinject(const VAdjArgs<T> &a, int e0, int e1, int rhs0) {
+    VT inj = {};
+    const YT *yh = static_cast<const YT *>(a.yh);
+    for (int e = e0; e < e1; ++e) {
+        const int s = a.injs[e];
+        const int64_t sb = (int64_t(a.tb) * a.n_obs + s) * RB + rhs0;
+        const int64_t sa = (int64_t(a.ta) * a.n_obs + s) * RB + rhs0;
+        const T w = a.injw[e];
+#pragma unroll
+        for (int i = 0; i < Vec16<T>::n; ++i) {
+            T v = static_cast<T>(static_cast<double>(yh[sb + i]) * a.yscale);
+            if (a.ta >= 0) v = static_cast<T>(static_cast<double>(yh[sa + i]) * a.yscale) + v;
+            inj[i] = mad(w, v, inj[i]);
+        }
+    }
+    return inj;
+}
 
 // Transposed step (same update as k_adj) with vector lanes on logical tile `tile`.
 template <typename T, typename YT, int RB, bool NT>
@@ -590,39 +637,27 @@ __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps
     if (tile >= a.n_tiles) return;
     const int row0 = tile * G::RPB;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool winj = wave_injects(a.injptr, row0 + wave * G::RPW, G::RPW, a.n, a.last);
-    stage_tile<T, RB>(a.o, a.n, row0, !a.last, L);
+    const bool winj = wave_injects(a.injptr, row0 + wave * G::RPW, G::RPW, a.n);
+    stage_tile<T, RB>(a.o, a.n, row0, true, L);
     const int lr = wave * G::RPW + lane / G::LPR, q = lane % G::LPR;
     const int row = row0 + lr;
     if (row >= a.n) return;
     const int64_t id = int64_t(row) * RB + q * G::VEC;
-    const VT ph0 = vload_own<NT, VT>(a.PH + id);
-    VT kq = {}, bq = {}, q0;
-    vrow_sums<T, RB>(a.o, L, lr, q, a.Q, a.Q, !a.last && L.bo[lr] >= 0, kq, bq, q0);
-    VT ph;
+    VT kq = {}, bq = {}, cur;
+    vrow_sums<T, RB>(a.o, L, lr, q, a.S, a.Sp, L.bo[lr] >= 0, a.last, kq, bq, cur);
+    // loaded after the sums: the kernel has no register to spare for it before
+    const VT prev = vload_own<NT, VT>(a.Sp + id);
+    const T dm = L.dm[lr];
+    VT inj = {};
+    if (winj) inj = vinject<T, YT, RB, VT>(a, a.injptr[row], a.injptr[row + 1], q * G::VEC);
+    VT out;
 #pragma unroll
-    for (int i = 0; i < G::VEC; ++i) ph[i] = ph0[i] - a.dt * kq[i];
-    if (!a.last) {
-        const T dm = L.dm[lr];
-        VT inj = {};
-        const YT *yh = static_cast<const YT *>(a.yh);
-        if (winj)
-            for (int e = a.injptr[row]; e < a.injptr[row + 1]; ++e) {
-                const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + q * G::VEC;
-                const T w = a.injw[e];
-#pragma unroll
-                for (int i = 0; i < G::VEC; ++i)
-                    inj[i] = mad(w, static_cast<T>(static_cast<double>(yh[src + i]) * a.yscale), inj[i]);
-            }
-        VT qn;
-#pragma unroll
-        for (int i = 0; i < G::VEC; ++i) {
-            qn[i] = q0[i] - dm * bq[i] + dm * (ph[i] + T(0.5) * inj[i]);
-            ph[i] += inj[i];
-        }
-        vstore<NT, VT>(a.Qn + id, qn);
+    for (int i = 0; i < G::VEC; ++i) {
+        const T src = T(0.5) * inj[i];
+        out[i] = a.last ? adj_result(cur[i], prev[i], kq[i], bq[i], src, dm, a.dt)
+                        : step_update(cur[i], prev[i], kq[i], bq[i], src, dm, a.dt);
     }
-    vstore<NT, VT>(a.PH + id, ph);
+    vstore<NT, VT>(a.Sn + id, out);
 }
 
 template <typename T, typename YT, int RB, bool NT>
@@ -829,15 +864,16 @@ __device__ __forceinline__ void halo_ksums(const HaloBuf &Lb, const HLane &h, ui
     }
 }
 
-// bacc += sum over the first nb slots of B(row, slot) Y[col], as vrow_sums: each slot's
-// row at byte offset off (this lane's slot: offq) of the halo, entries beyond 16 from
-// memory.  bwq: this lane's slot's B value.
-__device__ __forceinline__ void halo_bsums(const HaloBuf &Lb, uint32_t offq, float bwq, int nb, uint32_t q16,
-                                           const float *__restrict__ bslot, int bo, const int32_t *__restrict__ xcol,
-                                           int x0, const char *Yc, uint32_t RS, uint32_t coff, F4 &bacc) {
-    // re-read the rows from LDS instead of keeping the K sums' reads live (same
-    // addresses in the transposed step)
-    asm volatile("" : "+v"(offq));
+// bacc += sum over the first nb slots of B(row, slot) bdiff(X[col], Y[col]), as
+// vrow_sums: slot j's X row at the halo byte offset koffq of lane j (the K part), its
+// Y row at boffq of lane j (the B part), the entries beyond 16 from memory.  bwq:
+// this lane's slot's B value.
+__device__ __forceinline__ void halo_bsums(const HaloBuf &Lb, uint32_t koffq, uint32_t boffq, float bwq, int nb,
+                                           uint32_t q16, const float *__restrict__ bslot, int bo,
+                                           const int32_t *__restrict__ xcol, int x0, const char *Xc, const char *Yc,
+                                           uint32_t RS, uint32_t coff, bool only_prev, F4 &bacc) {
+    // re-read the K part's rows from LDS instead of keeping the K sums' reads live
+    asm volatile("" : "+v"(koffq));
     // slots j >= nb carry B = 0: the vector-lane kernels add 0 * 0 there, which leaves
     // bacc unchanged (it starts at +0 and a sum that starts at +0 never becomes -0),
     // so skipping them keeps the bits
@@ -846,7 +882,12 @@ __device__ __forceinline__ void halo_bsums(const HaloBuf &Lb, uint32_t offq, flo
         if (j0 < nb) {
             F4 y[kHChunk];
             static_for<0, kHChunk>([&](auto J) {
-                if (j0 + J.value < nb) y[J.value] = lds_row(Lb, row_bcast<j0 + J.value>(offq) + q16);
+                if (j0 + J.value < nb) {
+                    const F4 xv = lds_row(Lb, row_bcast<j0 + J.value>(koffq) + q16);
+                    const F4 yv = lds_row(Lb, row_bcast<j0 + J.value>(boffq) + q16);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) y[J.value][i] = bdiff(xv[i], yv[i], only_prev);
+                }
             });
             static_for<0, kHChunk>([&](auto J) {
                 if (j0 + J.value < nb) bacc = vfma(row_bcast<j0 + J.value>(bwq), y[J.value], bacc);
@@ -854,8 +895,13 @@ __device__ __forceinline__ void halo_bsums(const HaloBuf &Lb, uint32_t offq, flo
         }
     });
     for (int k = x0; k < x0 + nb - 16; ++k) {
-        const F4 yv = *reinterpret_cast<const F4 *>(Yc + (uint32_t(xcol[k]) * RS + coff + q16));
-        bacc = vfma(bslot[bo + 16 + (k - x0)], yv, bacc);
+        const uint32_t off = uint32_t(xcol[k]) * RS + coff + q16;
+        const F4 xv = *reinterpret_cast<const F4 *>(Xc + off);
+        const F4 yv = *reinterpret_cast<const F4 *>(Yc + off);
+        F4 dv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dv[i] = bdiff(xv[i], yv[i], only_prev);
+        bacc = vfma(bslot[bo + 16 + (k - x0)], dv, bacc);
     }
 }
 
@@ -908,9 +954,11 @@ __device__ __forceinline__ void halo_loop(const HWork &wk, const int32_t *hdesc,
     fn_store();
 }
 
-template <typename OT, int RB, bool NT>
-__global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
-k_fwd_h(const VFwdArgs<float> a) {
+// One halo-tile step (forward: FWD, no sources; transposed: sources and the closing
+// launch).  The K part of a tile's halo holds rows of S, the B part rows of Sp;
+// each row's own Sp comes from memory one item ahead.
+template <bool FWD, int RB, bool NT, typename Args, typename Src>
+__device__ __forceinline__ void halo_step(const Args &a, bool only_prev, Src fn_src) {
     constexpr int NC = RB / 64;
     constexpr uint32_t RS = uint32_t(RB) * 4u;
     __shared__ HaloBuf B0, B1;
@@ -918,105 +966,24 @@ k_fwd_h(const VFwdArgs<float> a) {
     const int tid = int(threadIdx.x), wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, g = tid >> 4,
               q = tid & 15;
     const HWork wk(a.n_ht, NC);
-    const bool with_b = !a.first;
-    const char *Pc = reinterpret_cast<const char *>(a.P);
-    const char *Vc = reinterpret_cast<const char *>(a.V);
-    F4 v_cur = {}, v_nxt = {}, out_v = {}, out_p = {};
+    const char *Sc = reinterpret_cast<const char *>(a.S);
+    const char *Spc = reinterpret_cast<const char *>(a.Sp);
+    F4 prev_cur = {}, prev_nxt = {}, out = {};
     uint32_t out_id = kNoRow;  // byte offset of the pending result, kNoRow: none
     auto fn_list = [&](const HDesc &d, int32_t *list) {
-        halo_list_issue(a.hrow, d, d.nk4 + (with_b ? d.nb4 : 0), list, wave, lane);
+        halo_list_issue(a.hrow, d, d.nk4 + d.nb4, list, wave, lane);
     };
     auto fn_issue = [&](int it, const HDesc &d, const int32_t *list, HaloBuf &Bn) {
-        halo_issue<RS>(Pc, Vc, uint32_t(wk.chunk(it)) * 256u, a.hmeta, d, d.nk4 + (with_b ? d.nb4 : 0), list, Bn,
-                       wave, lane);
-    };
-    auto fn_pre = [&](int it, const HDesc &d) {
-        if (with_b && g < d.nr)
-            v_nxt = vload_own<NT, F4>(reinterpret_cast<const float *>(
-                Vc + (uint32_t(d.r0 + g) * RS + uint32_t(wk.chunk(it)) * 256u + uint32_t(q) * 16u)));
-    };
-    auto fn_rot = [&]() { v_cur = v_nxt; };
-    auto fn_store = [&]() {
-        if (out_id != kNoRow) {
-            vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.Vn) + out_id), out_v);
-            vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.Pn) + out_id), out_p);
-        }
-    };
-    auto fn_compute = [&](int it, const HDesc &d, const HaloBuf &Lb) {
-        out_id = kNoRow;
-        if (g >= d.nr) return;
-        const uint32_t coff = uint32_t(wk.chunk(it)) * 256u, q16 = uint32_t(q) * 16u;
-        const HLane h = halo_lane(Lb, d.nr, g, q);
-        const uint32_t hw = hl_word(h);
-        const int x0 = hl_x0(h), x1 = x0 + hw_nx(hw);
-        F4 acc = {}, bacc = {}, p0;
-        halo_ksums(Lb, h, q16, x0, x1, a.o.xval, a.o.xcol, Pc, RS, coff, acc, p0);
-        const int row = d.r0 + g;
-        if (with_b && hw_brow(hw) != 0xFF) {
-            const int nb = hw_bnum(hw), br = hw_brow(hw);
-            const int bo = nb > 16 ? a.o.bsoff[row] : 0;
-            halo_bsums(Lb, hb_offset(Lb, d.nr, d.nbr, br, q, d.nk4), hb_value(Lb, d.nr, br, q), nb, q16, a.o.bslot, bo,
-                       a.o.xcol, x0, Vc, RS, coff, bacc);
-        }
-        const float dm = hl_dm(h);
-        const F4 v0 = with_b ? v_cur : F4{};
-        F4 v, pn;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            v[i] = v0[i] - dm * (acc[i] + bacc[i]);
-            pn[i] = p0[i] + a.dt * v[i];
-        }
-        out_v = v;
-        out_p = pn;
-        out_id = uint32_t(row) * RS + coff + q16;
-    };
-    halo_loop(wk, a.hdesc, B0, B1, L0, L1, fn_list, fn_issue, fn_pre, fn_rot, fn_compute, fn_store);
-    if (a.sample) {
-        // y^n = Pi (P - dt/2 V) of the incoming state, one lane per (sensor, rhs)
-        const int64_t total = int64_t(a.n_obs) * RB;
-        OT *yo = static_cast<OT *>(a.y);
-        for (int64_t e = int64_t(blockIdx.x) * kHThreads + tid; e < total; e += int64_t(gridDim.x) * kHThreads) {
-            const int s = int(e / RB), rr = int(e % RB);
-            float y = 0.0f;
-            for (int k = 0; k < 4; ++k) {
-                const int64_t id = int64_t(a.snode[4 * s + k]) * RB + rr;
-                const float pk = a.first ? a.P[id] : a.P[id] - a.half_dt * a.V[id];
-                y = mad(a.sw[4 * s + k], pk, y);
-            }
-            yo[(int64_t(a.t) * a.n_obs + s) * RB + rr] = static_cast<OT>(static_cast<double>(y) * a.yscale);
-        }
-    }
-}
-
-template <typename YT, int RB, bool NT>
-__global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
-k_adj_h(const VAdjArgs<float> a) {
-    constexpr int NC = RB / 64;
-    constexpr uint32_t RS = uint32_t(RB) * 4u;
-    __shared__ HaloBuf B0, B1;
-    __shared__ HaloList L0, L1;
-    const int tid = int(threadIdx.x), wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, g = tid >> 4,
-              q = tid & 15;
-    const HWork wk(a.n_ht, NC);
-    const char *Qc = reinterpret_cast<const char *>(a.Q);
-    F4 ph_cur = {}, ph_nxt = {}, out_ph = {}, out_q = {};
-    uint32_t out_id = kNoRow;  // byte offset of the pending result, kNoRow: none
-    auto fn_list = [&](const HDesc &d, int32_t *list) { halo_list_issue(a.hrow, d, d.nk4, list, wave, lane); };
-    auto fn_issue = [&](int it, const HDesc &d, const int32_t *list, HaloBuf &Bn) {
-        halo_issue<RS>(Qc, Qc, uint32_t(wk.chunk(it)) * 256u, a.hmeta, d, d.nk4, list, Bn, wave, lane);
+        halo_issue<RS>(Sc, Spc, uint32_t(wk.chunk(it)) * 256u, a.hmeta, d, d.nk4 + d.nb4, list, Bn, wave, lane);
     };
     auto fn_pre = [&](int it, const HDesc &d) {
         if (g < d.nr)
-            ph_nxt = vload_own<NT, F4>(reinterpret_cast<const float *>(
-                reinterpret_cast<const char *>(a.PH) + (uint32_t(d.r0 + g) * RS + uint32_t(wk.chunk(it)) * 256u +
-                                                        uint32_t(q) * 16u)));
+            prev_nxt = vload_own<NT, F4>(reinterpret_cast<const float *>(
+                Spc + (uint32_t(d.r0 + g) * RS + uint32_t(wk.chunk(it)) * 256u + uint32_t(q) * 16u)));
     };
-    auto fn_rot = [&]() { ph_cur = ph_nxt; };
+    auto fn_rot = [&]() { prev_cur = prev_nxt; };
     auto fn_store = [&]() {
-        if (out_id != kNoRow) {
-            if (!a.last) vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.Qn) + out_id), out_q);
-            vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.PH) + out_id), out_ph);
-        }
+        if (out_id != kNoRow) vstore<NT, F4>(reinterpret_cast<float *>(reinterpret_cast<char *>(a.Sn) + out_id), out);
     };
     auto fn_compute = [&](int it, const HDesc &d, const HaloBuf &Lb) {
         out_id = kNoRow;
@@ -1026,53 +993,70 @@ k_adj_h(const VAdjArgs<float> a) {
         const HLane h = halo_lane(Lb, d.nr, g, q);
         const uint32_t hw = hl_word(h);
         const int x0 = hl_x0(h), x1 = x0 + hw_nx(hw);
-        F4 kq = {}, bq = {}, q0;
-        halo_ksums(Lb, h, q16, x0, x1, a.o.xval, a.o.xcol, Qc, RS, coff, kq, q0);
+        F4 acc = {}, bacc = {}, cur;
+        halo_ksums(Lb, h, q16, x0, x1, a.o.xval, a.o.xcol, Sc, RS, coff, acc, cur);
         const int row = d.r0 + g;
-        if (!a.last && hw_brow(hw) != 0xFF) {
+        if (hw_brow(hw) != 0xFF) {
             const int nb = hw_bnum(hw), br = hw_brow(hw);
             const int bo = nb > 16 ? a.o.bsoff[row] : 0;
-            // B multiplies the same vector as K: the B slots read the K part of the halo
-            halo_bsums(Lb, h.koff, hb_value(Lb, d.nr, br, q), nb, q16, a.o.bslot, bo, a.o.xcol, x0, Qc, RS, coff, bq);
+            halo_bsums(Lb, h.koff, hb_offset(Lb, d.nr, d.nbr, br, q, d.nk4), hb_value(Lb, d.nr, br, q), nb, q16,
+                       a.o.bslot, bo, a.o.xcol, x0, Sc, Spc, RS, coff, only_prev, bacc);
         }
-        F4 ph;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ph[i] = ph_cur[i] - a.dt * kq[i];
-        if (!a.last) {
-            const float dm = hl_dm(h);
-            F4 inj = {};
-            const YT *yh = static_cast<const YT *>(a.yh);
+        const float dm = hl_dm(h);
+        F4 inj = {};
+        if constexpr (!FWD) {
             const int e0 = hl_inj0(h), e1 = e0 + hw_ninj(hw);
-            for (int e = e0; e < e1; ++e) {
-                const int64_t src = (int64_t(a.tm1) * a.n_obs + a.injs[e]) * RB + c * 64 + q * 4;
-                const float w = a.injw[e];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    inj[i] = mad(w, static_cast<float>(static_cast<double>(yh[src + i]) * a.yscale), inj[i]);
-            }
-            F4 qn;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                qn[i] = q0[i] - dm * bq[i] + dm * (ph[i] + 0.5f * inj[i]);
-                ph[i] += inj[i];
-            }
-            out_q = qn;
+            if (e1 > e0) inj = fn_src(e0, e1, c * 64 + q * 4);
         }
-        out_ph = ph;
+        F4 res;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float src = 0.5f * inj[i];
+            res[i] = only_prev ? adj_result(cur[i], prev_cur[i], acc[i], bacc[i], src, dm, a.dt)
+                               : step_update(cur[i], prev_cur[i], acc[i], bacc[i], src, dm, a.dt);
+        }
+        out = res;
         out_id = uint32_t(row) * RS + coff + q16;
     };
     halo_loop(wk, a.hdesc, B0, B1, L0, L1, fn_list, fn_issue, fn_pre, fn_rot, fn_compute, fn_store);
 }
 
-// p_hat = Pi^T yhat^{N_T}, q = (dt/2m) p_hat
+template <typename OT, int RB, bool NT>
+__global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_fwd_h(const VFwdArgs<float> a) {
+    halo_step<true, RB, NT>(a, false, [](int, int, int) { return F4{}; });
+    if (a.sample) {
+        // y = Pi (S^n + S^{n-1})/2 of the incoming state, one lane per (sensor, rhs)
+        const int64_t total = int64_t(a.n_obs) * RB;
+        OT *yo = static_cast<OT *>(a.y);
+        for (int64_t e = int64_t(blockIdx.x) * kHThreads + threadIdx.x; e < total;
+             e += int64_t(gridDim.x) * kHThreads) {
+            const int s = int(e / RB), rr = int(e % RB);
+            float y = 0.0f;
+            for (int k = 0; k < 4; ++k) {
+                const int64_t id = int64_t(a.snode[4 * s + k]) * RB + rr;
+                y = mad(a.sw[4 * s + k], 0.5f * (a.S[id] + a.Sp[id]), y);
+            }
+            yo[(int64_t(a.t) * a.n_obs + s) * RB + rr] = static_cast<OT>(static_cast<double>(y) * a.yscale);
+        }
+    }
+}
+
+template <typename YT, int RB, bool NT>
+__global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_adj_h(const VAdjArgs<float> a) {
+    halo_step<false, RB, NT>(a, a.last != 0,
+                             [&](int e0, int e1, int rhs0) { return vinject<float, YT, RB, F4>(a, e0, e1, rhs0); });
+}
+
+// q_{-1} = 0 and q_0 = (dt/2m) Pi^T yhat^{tb} (tb = N_T - 1, the last sample)
 template <typename T, typename YT, int RB>
-__global__ void __launch_bounds__(256) k_adj_init(const AdjArgs<T> a) {
+__global__ void __launch_bounds__(256) k_adj_init(const AdjArgs<T> a, T *q0, T *qm1) {
     const int64_t total = int64_t(a.n) * RB;
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
         const int row = int(e / RB), r = int(e % RB);
-        const T inj = inject<T, YT, RB>(a, row, r, a.tm1);
-        a.PH[e] = inj;
-        a.Qn[e] = T(0.5) * a.o.dtm[row] * inj;
+        q0[e] = T(0.5) * a.o.dtm[row] * inject<T, YT, RB>(a, row, r);
+        qm1[e] = T(0);
     }
 }
 
@@ -1642,24 +1626,23 @@ const double *injw_of<double>(const DevOps &op) { return op.injw64; }
 template <>
 const float *injw_of<float>(const DevOps &op) { return op.injw32; }
 
-// bytes of a step's state (two vectors read, two written) for one RHS block
-inline double state_bytes(const DevOps &op, int RB, size_t tsize) { return 4.0 * op.n * RB * double(tsize); }
+// bytes of a step's state (two vectors read, one written) for one RHS block
+inline double state_bytes(const DevOps &op, int RB, size_t tsize) { return 3.0 * op.n * RB * double(tsize); }
 
 template <typename T, int RB>
-VFwdArgs<T> fwd_args_v(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first,
-                       bool sample, int t, void *y, double yscale, int *blocks) {
+VFwdArgs<T> fwd_args_v(const DevOps &op, const void *S, const void *Sp, void *Sn, bool rows, bool sample, int t,
+                       void *y, double yscale, int *blocks) {
     using G = VGeo<T, RB>;
     VFwdArgs<T> a;
     a.o = row_ops<T>(op);
     a.snode = op.snode;
     a.sw = sw_of<T>(op);
-    a.P = static_cast<const T *>(P); a.V = static_cast<const T *>(V);
-    a.Pn = static_cast<T *>(Pn); a.Vn = static_cast<T *>(Vn);
+    a.S = static_cast<const T *>(S); a.Sp = static_cast<const T *>(Sp); a.Sn = static_cast<T *>(Sn);
     a.y = y; a.yscale = yscale;
     a.n = op.n; a.n_obs = op.n_obs;
     a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
-    a.first = first; a.sample = sample; a.t = t;
-    a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
+    a.sample = sample; a.t = t;
+    a.dt = T(op.dt);
     a.n_samp = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
     a.stream = state_bytes(op, RB, sizeof(T)) > kInfinityCacheBytes;
     a.hdesc = op.ht_desc; a.hrow = op.ht_hrow; a.hmeta = op.ht_meta; a.n_ht = op.n_ht;
@@ -1678,10 +1661,10 @@ bool use_halo(const DevOps &op, bool rows) {
 }
 
 template <typename T, typename OT, int RB>
-void fwd_impl_v(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
-                int t, void *y, double yscale, hipStream_t s) {
+void fwd_impl_v(const DevOps &op, const void *S, const void *Sp, void *Sn, bool rows, bool sample, int t, void *y,
+                double yscale, hipStream_t s) {
     int grid = 0;
-    const VFwdArgs<T> a = fwd_args_v<T, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, &grid);
+    const VFwdArgs<T> a = fwd_args_v<T, RB>(op, S, Sp, Sn, rows, sample, t, y, yscale, &grid);
     if (grid <= 0) return;
     if constexpr (std::is_same<T, float>::value && RB >= 64 && RB <= 256) {
         if (use_halo<T, RB>(op, rows)) {
@@ -1698,8 +1681,8 @@ template <typename T, typename OT, int RB>
 void fwd_impl_vm(const FwdStep *st, int n, hipStream_t s) {
     Multi<VFwdArgs<T>> mm{};
     for (int m = 0; m < n; ++m)
-        mm.a[m] = fwd_args_v<T, RB>(*st[m].op, st[m].P, st[m].V, st[m].Pn, st[m].Vn, st[m].rows, st[m].first,
-                                    st[m].sample, st[m].t, st[m].y, st[m].yscale, &mm.tiles[m]);
+        mm.a[m] = fwd_args_v<T, RB>(*st[m].op, st[m].S, st[m].Sp, st[m].Sn, st[m].rows, st[m].sample, st[m].t,
+                                    st[m].y, st[m].yscale, &mm.tiles[m]);
     mm.n = n;
     double sb = 0.0;
     for (int m = 0; m < n; ++m) sb += state_bytes(*st[m].op, RB, sizeof(T));
@@ -1710,16 +1693,17 @@ void fwd_impl_vm(const FwdStep *st, int n, hipStream_t s) {
 }
 
 template <typename T, int RB>
-VAdjArgs<T> adj_args_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
+VAdjArgs<T> adj_args_v(const DevOps &op, const void *S, const void *Sp, void *Sn, bool last, int tb, const void *yh,
                        double yscale) {
     using G = VGeo<T, RB>;
     VAdjArgs<T> a;
     a.o = row_ops<T>(op);
     a.injptr = op.injptr; a.injs = op.injs;
     a.injw = injw_of<T>(op);
-    a.PH = static_cast<T *>(PH); a.Q = static_cast<const T *>(Q); a.Qn = static_cast<T *>(Qn);
+    a.S = static_cast<const T *>(S); a.Sp = static_cast<const T *>(Sp); a.Sn = static_cast<T *>(Sn);
     a.yh = yh; a.yscale = yscale;
-    a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
+    a.n = op.n; a.n_obs = op.n_obs; a.last = last;
+    a.tb = tb; a.ta = last ? -1 : tb + 1;
     a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
     a.dt = T(op.dt);
     a.stream = state_bytes(op, RB, sizeof(T)) > kInfinityCacheBytes;
@@ -1728,9 +1712,9 @@ VAdjArgs<T> adj_args_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool
 }
 
 template <typename T, typename YT, int RB>
-void adj_impl_v(const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1, const void *yh,
+void adj_impl_v(const DevOps &op, const void *S, const void *Sp, void *Sn, bool last, int tb, const void *yh,
                 double yscale, hipStream_t s) {
-    const VAdjArgs<T> a = adj_args_v<T, RB>(op, PH, Q, Qn, last, tm1, yh, yscale);
+    const VAdjArgs<T> a = adj_args_v<T, RB>(op, S, Sp, Sn, last, tb, yh, yscale);
     if constexpr (std::is_same<T, float>::value && RB >= 64 && RB <= 256) {
         if (use_halo<T, RB>(op, true)) {
             if (a.stream) hipLaunchKernelGGL((k_adj_h<YT, RB, true>), dim3(halo_grid(op)), dim3(kHThreads), 0, s, a);
@@ -1746,7 +1730,7 @@ template <typename T, typename YT, int RB>
 void adj_impl_vm(const AdjStep *st, int n, hipStream_t s) {
     Multi<VAdjArgs<T>> mm{};
     for (int m = 0; m < n; ++m) {
-        mm.a[m] = adj_args_v<T, RB>(*st[m].op, st[m].PH, st[m].Q, st[m].Qn, st[m].last, st[m].tm1, st[m].yh,
+        mm.a[m] = adj_args_v<T, RB>(*st[m].op, st[m].S, st[m].Sp, st[m].Sn, st[m].last, st[m].tb, st[m].yh,
                                     st[m].yscale);
         mm.tiles[m] = mm.a[m].n_tiles;
     }
@@ -1760,24 +1744,23 @@ void adj_impl_vm(const AdjStep *st, int n, hipStream_t s) {
 }
 
 template <typename T, typename OT, int RB>
-void fwd_impl(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows, bool first, bool sample,
-              int t, void *y, double yscale, hipStream_t s) {
+void fwd_impl(const DevOps &op, const void *S, const void *Sp, void *Sn, bool rows, bool sample, int t, void *y,
+              double yscale, hipStream_t s) {
     if constexpr (RB * sizeof(T) >= 16) {
         // a row of the RHS block fits one wave (64 lanes x 16 bytes): up to 256 float / 128 double
-        if constexpr (RB * sizeof(T) <= 1024) fwd_impl_v<T, OT, RB>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s);
+        if constexpr (RB * sizeof(T) <= 1024) fwd_impl_v<T, OT, RB>(op, S, Sp, Sn, rows, sample, t, y, yscale, s);
     } else {
         using G = Geo<RB>;
         FwdArgs<T> a;
         a.o = row_ops<T>(op);
         a.snode = op.snode;
         a.sw = sw_of<T>(op);
-        a.P = static_cast<const T *>(P); a.V = static_cast<const T *>(V);
-        a.Pn = static_cast<T *>(Pn); a.Vn = static_cast<T *>(Vn);
+        a.S = static_cast<const T *>(S); a.Sp = static_cast<const T *>(Sp); a.Sn = static_cast<T *>(Sn);
         a.y = y; a.yscale = yscale;
         a.n = op.n; a.n_obs = op.n_obs;
         a.n_tiles = rows ? (op.n + G::RPB - 1) / G::RPB : 0;
-        a.first = first; a.sample = sample; a.t = t;
-        a.dt = T(op.dt); a.half_dt = T(0.5 * op.dt);
+        a.sample = sample; a.t = t;
+        a.dt = T(op.dt);
         a.n_samp = sample ? int((int64_t(op.n_obs) * RB + 255) / 256) : 0;
         const int grid = a.n_tiles + a.n_samp;
         if (grid > 0) hipLaunchKernelGGL((k_fwd<T, OT, RB>), dim3(grid), dim3(256), 0, s, a);
@@ -1785,26 +1768,37 @@ void fwd_impl(const DevOps &op, const void *P, const void *V, void *Pn, void *Vn
 }
 
 template <typename T, typename YT, int RB>
-void adj_impl(const DevOps &op, void *PH, const void *Q, void *Qn, bool init, bool last, int tm1, const void *yh,
-              double yscale, hipStream_t s) {
-    constexpr bool vec = RB * sizeof(T) >= 16;
-    using G = Geo<vec ? 1 : RB>;  // the scalar-lane geometry, used only below 16 bytes per row
+AdjArgs<T> adj_args(const DevOps &op, const void *S, const void *Sp, void *Sn, bool last, int ta, int tb,
+                    const void *yh, double yscale) {
+    using G = Geo<RB * sizeof(T) >= 16 ? 1 : RB>;  // the scalar-lane geometry, used only below 16 bytes per row
     AdjArgs<T> a;
     a.o = row_ops<T>(op);
     a.injptr = op.injptr; a.injs = op.injs;
     a.injw = injw_of<T>(op);
-    a.PH = static_cast<T *>(PH); a.Q = static_cast<const T *>(Q); a.Qn = static_cast<T *>(Qn);
+    a.S = static_cast<const T *>(S); a.Sp = static_cast<const T *>(Sp); a.Sn = static_cast<T *>(Sn);
     a.yh = yh; a.yscale = yscale;
-    a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.tm1 = tm1;
+    a.n = op.n; a.n_obs = op.n_obs; a.last = last; a.ta = ta; a.tb = tb;
     a.n_tiles = (op.n + G::RPB - 1) / G::RPB;
     a.dt = T(op.dt);
-    if (init) {
-        hipLaunchKernelGGL((k_adj_init<T, YT, RB>), dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, a);
-    } else if constexpr (vec) {
-        if constexpr (RB * sizeof(T) <= 1024) adj_impl_v<T, YT, RB>(op, PH, Q, Qn, last, tm1, yh, yscale, s);
+    return a;
+}
+
+template <typename T, typename YT, int RB>
+void adj_impl(const DevOps &op, const void *S, const void *Sp, void *Sn, bool last, int tb, const void *yh,
+              double yscale, hipStream_t s) {
+    if constexpr (RB * sizeof(T) >= 16) {
+        if constexpr (RB * sizeof(T) <= 1024) adj_impl_v<T, YT, RB>(op, S, Sp, Sn, last, tb, yh, yscale, s);
     } else {
+        const AdjArgs<T> a = adj_args<T, YT, RB>(op, S, Sp, Sn, last, last ? -1 : tb + 1, tb, yh, yscale);
         hipLaunchKernelGGL((k_adj<T, YT, RB>), dim3(a.n_tiles), dim3(256), 0, s, a);
     }
+}
+
+template <typename T, typename YT, int RB>
+void adj_init(const DevOps &op, void *q0, void *qm1, const void *yh, double yscale, hipStream_t s) {
+    const AdjArgs<T> a = adj_args<T, YT, RB>(op, nullptr, nullptr, nullptr, false, -1, op.n_steps - 1, yh, yscale);
+    hipLaunchKernelGGL((k_adj_init<T, YT, RB>), dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, a,
+                       static_cast<T *>(q0), static_cast<T *>(qm1));
 }
 
 template <typename T, typename OT, int RB>
@@ -1832,37 +1826,36 @@ void adj_multi(const AdjStep *st, int n, hipStream_t s) {
 
 }  // namespace
 
-void launch_fwd_step(Prec prec, int RB, const DevOps &op, const void *P, const void *V, void *Pn, void *Vn, bool rows,
-                     bool first, bool sample, int t, void *y, bool y_is_f64, double yscale, hipStream_t s) {
+void launch_fwd_step(Prec prec, int RB, const DevOps &op, const void *S, const void *Sp, void *Sn, bool rows,
+                     bool sample, int t, void *y, bool y_is_f64, double yscale, hipStream_t s) {
     if (prec == Prec::F64) {
-        PAT_RB_SWITCH(RB, (fwd_impl<double, double, RB_>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s)));
+        PAT_RB_SWITCH(RB, (fwd_impl<double, double, RB_>(op, S, Sp, Sn, rows, sample, t, y, yscale, s)));
     } else if (y_is_f64) {
-        PAT_RB_SWITCH(RB, (fwd_impl<float, double, RB_>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s)));
+        PAT_RB_SWITCH(RB, (fwd_impl<float, double, RB_>(op, S, Sp, Sn, rows, sample, t, y, yscale, s)));
     } else {
-        PAT_RB_SWITCH(RB, (fwd_impl<float, float, RB_>(op, P, V, Pn, Vn, rows, first, sample, t, y, yscale, s)));
+        PAT_RB_SWITCH(RB, (fwd_impl<float, float, RB_>(op, S, Sp, Sn, rows, sample, t, y, yscale, s)));
     }
 }
 
-void launch_adj_init(Prec prec, int RB, const DevOps &op, void *PH, void *Q, const void *yhat, bool y_is_f64,
+void launch_adj_init(Prec prec, int RB, const DevOps &op, void *q0, void *qm1, const void *yhat, bool y_is_f64,
                      double yscale, hipStream_t s) {
-    const int t = op.n_steps - 1;
     if (prec == Prec::F64) {
-        PAT_RB_SWITCH(RB, (adj_impl<double, double, RB_>(op, PH, nullptr, Q, true, false, t, yhat, yscale, s)));
+        PAT_RB_SWITCH(RB, (adj_init<double, double, RB_>(op, q0, qm1, yhat, yscale, s)));
     } else if (y_is_f64) {
-        PAT_RB_SWITCH(RB, (adj_impl<float, double, RB_>(op, PH, nullptr, Q, true, false, t, yhat, yscale, s)));
+        PAT_RB_SWITCH(RB, (adj_init<float, double, RB_>(op, q0, qm1, yhat, yscale, s)));
     } else {
-        PAT_RB_SWITCH(RB, (adj_impl<float, float, RB_>(op, PH, nullptr, Q, true, false, t, yhat, yscale, s)));
+        PAT_RB_SWITCH(RB, (adj_init<float, float, RB_>(op, q0, qm1, yhat, yscale, s)));
     }
 }
 
-void launch_adj_step(Prec prec, int RB, const DevOps &op, void *PH, const void *Q, void *Qn, bool last, int tm1,
+void launch_adj_step(Prec prec, int RB, const DevOps &op, const void *S, const void *Sp, void *Sn, bool last, int tb,
                      const void *yhat, bool y_is_f64, double yscale, hipStream_t s) {
     if (prec == Prec::F64) {
-        PAT_RB_SWITCH(RB, (adj_impl<double, double, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
+        PAT_RB_SWITCH(RB, (adj_impl<double, double, RB_>(op, S, Sp, Sn, last, tb, yhat, yscale, s)));
     } else if (y_is_f64) {
-        PAT_RB_SWITCH(RB, (adj_impl<float, double, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
+        PAT_RB_SWITCH(RB, (adj_impl<float, double, RB_>(op, S, Sp, Sn, last, tb, yhat, yscale, s)));
     } else {
-        PAT_RB_SWITCH(RB, (adj_impl<float, float, RB_>(op, PH, Q, Qn, false, last, tm1, yhat, yscale, s)));
+        PAT_RB_SWITCH(RB, (adj_impl<float, float, RB_>(op, S, Sp, Sn, last, tb, yhat, yscale, s)));
     }
 }
 
