@@ -121,11 +121,12 @@ def test_latent_rto_krylov_and_converged():
 
 
 def test_float32_floor_of_the_latent_std():
-    """The rounding floor behind the 40-iteration float32 latent-RTO test: on ball16 (16^3 grid,
-    ell = 0.2, 64 samples) float32 staggered sweeps (oracle/float32_floor.py, numpy float32)
-    give a posterior std 1.0e-4 away from the float64 oracle after 20 iterations while samples and
-    mean stay near 4e-6, and the oracle's float32 literal three-substep sweeps give 4e-5 there."""
-    from oracle.float32_floor import StaggeredFloat32
+    """The rounding floor behind the float32 latent-RTO test: on ball16 (16^3 grid, ell = 0.2,
+    64 samples) float32 sweeps in the velocity form (oracle/float32_floor.py, numpy float32) give a
+    posterior std 1.0e-4 away from the float64 oracle after 20 iterations while samples and mean
+    stay near 4e-6; the one-vector (three-level) form that the GPU sweeps use gives 4e-5 there, and
+    the oracle's float32 literal three-substep sweeps 4e-5."""
+    from oracle.float32_floor import StaggeredFloat32, ThreeLevel
     w = W.make_workload("ball16")
     O = oracle.Problem.from_workload(w)
     pr = SpectralPrior(16, -1.25, 2.5, 0.2, 3.0)
@@ -139,8 +140,10 @@ def test_float32_floor_of_the_latent_std():
     m0, s0 = oracle.stats(ref)
     rl = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     stag, _, _ = latent_rto(StaggeredFloat32(O), pr, I, yobs, sigma, n_iter, eta, xi)
+    three, _, _ = latent_rto(ThreeLevel(O), pr, I, yobs, sigma, n_iter, eta, xi)
     lit, _, _ = latent_rto(O, pr, I, yobs, sigma, n_iter, eta, xi, sweeps="f32")
-    (ms, ss), (ml, sl) = oracle.stats(stag), oracle.stats(lit)
+    (ms, ss), (m3, s3), (ml, sl) = oracle.stats(stag), oracle.stats(three), oracle.stats(lit)
     assert rl(stag, ref) < 1e-5 and rl(ms, m0) < 1e-5
     assert 7e-5 < rl(ss, s0) < 1.5e-4
+    assert rl(three, ref) < 1e-5 and rl(m3, m0) < 1e-5 and rl(s3, s0) < 7e-5
     assert rl(sl, s0) < 7e-5
