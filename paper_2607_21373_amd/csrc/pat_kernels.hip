@@ -954,11 +954,12 @@ __device__ __forceinline__ void halo_loop(const HWork &wk, const int32_t *hdesc,
     fn_store();
 }
 
-// One halo-tile step (forward: FWD, no sources; transposed: sources and the closing
-// launch).  The K part of a tile's halo holds rows of S, the B part rows of Sp;
-// each row's own Sp comes from memory one item ahead.
-template <bool FWD, int RB, bool NT, typename Args, typename Src>
-__device__ __forceinline__ void halo_step(const Args &a, bool only_prev, Src fn_src) {
+// One halo-tile step (forward: FWD, no sources; transposed: sources, and with LAST the
+// closing launch).  The K part of a tile's halo holds rows of S, the B part rows of
+// Sp; each row's own Sp comes from memory one item ahead.  (LAST is a template
+// parameter: as a run-time flag its selects cost 2% of every step.)
+template <bool FWD, bool LAST, int RB, bool NT, typename Args, typename Src>
+__device__ __forceinline__ void halo_step(const Args &a, Src fn_src) {
     constexpr int NC = RB / 64;
     constexpr uint32_t RS = uint32_t(RB) * 4u;
     __shared__ HaloBuf B0, B1;
@@ -1000,7 +1001,7 @@ __device__ __forceinline__ void halo_step(const Args &a, bool only_prev, Src fn_
             const int nb = hw_bnum(hw), br = hw_brow(hw);
             const int bo = nb > 16 ? a.o.bsoff[row] : 0;
             halo_bsums(Lb, h.koff, hb_offset(Lb, d.nr, d.nbr, br, q, d.nk4), hb_value(Lb, d.nr, br, q), nb, q16,
-                       a.o.bslot, bo, a.o.xcol, x0, Sc, Spc, RS, coff, only_prev, bacc);
+                       a.o.bslot, bo, a.o.xcol, x0, Sc, Spc, RS, coff, LAST, bacc);
         }
         const float dm = hl_dm(h);
         F4 inj = {};
@@ -1012,8 +1013,8 @@ __device__ __forceinline__ void halo_step(const Args &a, bool only_prev, Src fn_
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float src = 0.5f * inj[i];
-            res[i] = only_prev ? adj_result(cur[i], prev_cur[i], acc[i], bacc[i], src, dm, a.dt)
-                               : step_update(cur[i], prev_cur[i], acc[i], bacc[i], src, dm, a.dt);
+            if constexpr (LAST) res[i] = adj_result(cur[i], prev_cur[i], acc[i], bacc[i], src, dm, a.dt);
+            else res[i] = step_update(cur[i], prev_cur[i], acc[i], bacc[i], src, dm, a.dt);
         }
         out = res;
         out_id = uint32_t(row) * RS + coff + q16;
@@ -1024,7 +1025,7 @@ __device__ __forceinline__ void halo_step(const Args &a, bool only_prev, Src fn_
 template <typename OT, int RB, bool NT>
 __global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_fwd_h(const VFwdArgs<float> a) {
-    halo_step<true, RB, NT>(a, false, [](int, int, int) { return F4{}; });
+    halo_step<true, false, RB, NT>(a, [](int, int, int) { return F4{}; });
     if (a.sample) {
         // y = Pi (S^n + S^{n-1})/2 of the incoming state, one lane per (sensor, rhs)
         const int64_t total = int64_t(a.n_obs) * RB;
@@ -1042,11 +1043,10 @@ k_fwd_h(const VFwdArgs<float> a) {
     }
 }
 
-template <typename YT, int RB, bool NT>
+template <typename YT, int RB, bool NT, bool LAST>
 __global__ void __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_adj_h(const VAdjArgs<float> a) {
-    halo_step<false, RB, NT>(a, a.last != 0,
-                             [&](int e0, int e1, int rhs0) { return vinject<float, YT, RB, F4>(a, e0, e1, rhs0); });
+    halo_step<false, LAST, RB, NT>(a, [&](int e0, int e1, int rhs0) { return vinject<float, YT, RB, F4>(a, e0, e1, rhs0); });
 }
 
 // q_{-1} = 0 and q_0 = (dt/2m) Pi^T yhat^{tb} (tb = N_T - 1, the last sample)
@@ -1717,8 +1717,14 @@ void adj_impl_v(const DevOps &op, const void *S, const void *Sp, void *Sn, bool 
     const VAdjArgs<T> a = adj_args_v<T, RB>(op, S, Sp, Sn, last, tb, yh, yscale);
     if constexpr (std::is_same<T, float>::value && RB >= 64 && RB <= 256) {
         if (use_halo<T, RB>(op, true)) {
-            if (a.stream) hipLaunchKernelGGL((k_adj_h<YT, RB, true>), dim3(halo_grid(op)), dim3(kHThreads), 0, s, a);
-            else hipLaunchKernelGGL((k_adj_h<YT, RB, false>), dim3(halo_grid(op)), dim3(kHThreads), 0, s, a);
+            const dim3 g(halo_grid(op)), b(kHThreads);
+            if (a.stream) {
+                if (last) hipLaunchKernelGGL((k_adj_h<YT, RB, true, true>), g, b, 0, s, a);
+                else hipLaunchKernelGGL((k_adj_h<YT, RB, true, false>), g, b, 0, s, a);
+            } else {
+                if (last) hipLaunchKernelGGL((k_adj_h<YT, RB, false, true>), g, b, 0, s, a);
+                else hipLaunchKernelGGL((k_adj_h<YT, RB, false, false>), g, b, 0, s, a);
+            }
             return;
         }
     }
