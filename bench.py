@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -53,12 +54,15 @@ def step_bytes(info, RB, tsize, kind):
 
 
 def kernel_source_sha():
-    """Hash of what decides the step kernels' memory traffic: their source and the host setup that
-    lays out and orders the rows."""
+    """Hash of what decides the step kernels' memory traffic: their code and the host setup that
+    lays out and orders the rows (comments and layout whitespace left out)."""
     h = hashlib.sha256()
     for name in ("pat_kernels.hip", "pat_setup.cpp"):
-        with open(os.path.join(ROOT, "paper_2607_21373_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2607_21373_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -690,8 +690,9 @@ __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdj
 // flight, and the stores of the previous one drain.  Work item = (row chunk,
 // tile); XCD x takes the x-th eighth of the tiles, its workgroups interleaved
 // over them, so the tiles in flight on one XCD are neighbours and share their
-// halo rows in that XCD's L2.  The forward step also copies the rows of V
-// that its boundary slots refer to (the B part of the halo).  Each lane of a
+// halo rows in that XCD's L2.  The halo holds rows of the state S (the K part)
+// and, at the rows that its boundary slots refer to, rows of the previous state
+// S_prev (the B part).  Each lane of a
 // row's 16 reads one slot's operands from the LDS image and hands them to the
 // others by DPP row broadcast.  Sums run in the slot order of the vector-lane
 // kernels, with the same operations, so both give the same bits.
