@@ -20,7 +20,9 @@
  *    work is enqueued and leave outputs untouched.  pat_last_error() returns a
  *    thread-local message for the last failing call on the calling thread.
  *    Asynchronous device faults surface at a later call or at pat_sync().
- *  - A handle is not thread-safe; distinct handles are independent.
+ *  - A handle is not thread-safe; distinct handles are independent.  Device work
+ *    enqueued through one handle must not overlap in time on different streams:
+ *    it shares the handle's sweep buffers.
  */
 #ifndef PAT_H
 #define PAT_H
@@ -104,7 +106,7 @@ pat_status pat_forward(pat_problem *p, int64_t R, const void *p0, void *y, pat_p
  * (held from the library's first use on a device until the process ends).  No
  * hipMalloc, hipFree or other allocating call is made.  Right-hand sides run in
  * blocks of the largest power of two <= pat_forward's block whose state and
- * staging, (4 N + N_T N_obs) x block x element size, fit the scratch; a problem
+ * staging, (3 N + N_T N_obs) x block x element size, fit the scratch; a problem
  * for which one right-hand side does not fit is PAT_ERR_INVALID_ARG.  All calls
  * on one device share its scratch: calls that overlap in time on one device (on
  * different streams or threads) race and give undefined results.  Nothing in the

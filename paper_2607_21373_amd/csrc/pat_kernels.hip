@@ -734,20 +734,43 @@ __device__ __forceinline__ HDesc desc_uniform(const int4 u) {
     return {r0, nr, h0, nk4, nb4, moff, nr * 96 + nbr * 80, nbr};
 }
 
-// Work items of this workgroup: (chunk c, tile t), t = t_lo + k + j * G8.
+// Work items of this workgroup: (chunk c, tile t).  XCD x (workgroups b with
+// b % 8 == x) owns the x-th eighth of the tiles, [t_lo, t_lo + ntx), seen as rows
+// of G8 consecutive tiles (one per workgroup of the XCD: neighbouring tiles are in
+// flight together and share halo rows in its L2).  Two workgroups share a CU, and
+// the one dispatched first (k = b / 8 < G8 / 2) runs about a fifth faster than
+// the other; so every kRowPeriod-th row goes to the first half only, two tiles
+// each, and they take 10 tiles for every 8 of the others.  A workgroup walks its
+// tiles in row order, once per 256-byte chunk.
+constexpr int kRowPeriod = 9;
 struct HWork {
-    int t_lo, k, G8, per_c, n;
+    int t_lo, ntx, k, G8, per_c, n;
+    bool weighted, first_half;
+    // local index (tile - t_lo) of this workgroup's j-th tile; increasing in j
+    __device__ int local(int j) const {
+        if (!weighted) return j * G8 + k;
+        if (first_half) {
+            const int b = j / (kRowPeriod + 1), e = j % (kRowPeriod + 1);
+            return e < kRowPeriod - 1 ? (b * kRowPeriod + e) * G8 + k
+                                      : (b * kRowPeriod + kRowPeriod - 1) * G8 + 2 * k + (e - (kRowPeriod - 1));
+        }
+        const int b = j / (kRowPeriod - 1), e = j % (kRowPeriod - 1);
+        return (b * kRowPeriod + e) * G8 + k;
+    }
     __device__ HWork(int n_ht, int NC) {
         G8 = int(gridDim.x >> 3);
         const int x = int(blockIdx.x & 7);
         k = int(blockIdx.x >> 3);
         t_lo = int(int64_t(n_ht) * x / 8);
-        const int t_hi = int(int64_t(n_ht) * (x + 1) / 8);
-        per_c = t_hi - t_lo > k ? (t_hi - t_lo - k + G8 - 1) / G8 : 0;
+        ntx = int(int64_t(n_ht) * (x + 1) / 8) - t_lo;
+        weighted = G8 % 2 == 0;
+        first_half = 2 * k < G8;
+        per_c = 0;
+        while (local(per_c) < ntx) ++per_c;
         n = per_c * NC;
     }
     __device__ int chunk(int it) const { return it / per_c; }
-    __device__ int tile(int it) const { return t_lo + k + (it - chunk(it) * per_c) * G8; }
+    __device__ int tile(int it) const { return t_lo + local(it - chunk(it) * per_c); }
 };
 
 __device__ __forceinline__ void lds_copy16(const void *src, void *lds) {
