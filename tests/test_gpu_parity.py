@@ -2,7 +2,7 @@
 
 Small problems, where the oracle runs in seconds, spanning several tiles, ragged
 RHS counts and both precisions.  Tolerances:
-  * float64 sweeps: the kernels evaluate the staggered form of the step with FMA
+  * float64 sweeps: the kernels evaluate the three-level form of the step with FMA
     contraction, the oracle the literal three substeps without; both are exact
     in exact arithmetic, so differences are rounding only (bound 1e-11 relative
     to the largest output over <= 1000 steps).

@@ -3,7 +3,7 @@
 Balls of 2, 3 and 5 cells per axis (27, 64 and 216 nodes) give fewer row tiles
 than there are XCDs, partial tiles and partial waves; 3 sensors leave most waves
 without an injected row, 40 sensors put one in nearly every wave.  The forward
-and transpose maps (staggered Stormer-Verlet, Sec. 3; its transpose, Sec. 5.1)
+and transpose maps (Stormer-Verlet, Sec. 3; its transpose, Sec. 5.1)
 are checked against the oracle at 1, 2, 5 and 64 RHS in float64 (1e-11 of the
 largest output, rounding only) and float32 (2e-5), and the two GPU maps against
 each other through the discrete transpose identity.
