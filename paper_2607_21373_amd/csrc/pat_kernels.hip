@@ -365,7 +365,8 @@ struct TileOps {
     int bo[G::RPB], bn[G::RPB], x0[G::RPB], x1[G::RPB];
 };
 
-// Stage the operands of rows [row0, row0 + RPB) (rows >= n get zero weights).
+// Stage the operands of rows [row0, row0 + RPB) (rows >= n get zero weights); the
+// B values when need_b (every step of the three-level form needs them).
 // Contains __syncthreads(); every thread of the workgroup must call it.
 template <typename T, int RB>
 __device__ __forceinline__ void stage_tile(const RowOps<T> &o, int n, int row0, bool need_b, TileOps<T, RB> &L) {
@@ -1262,31 +1263,43 @@ __global__ void k_cast(const double *x, T *y, int64_t n) {
 __global__ void __launch_bounds__(256) k_prior(const int32_t *rowptr, const int32_t *col, const double *k1,
                                                const double *sqrtm, const double *isqrtm, int n, int RB, double a,
                                                const double *x, double *y) {
-    const int64_t total = int64_t(n) * RB;
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
-        const int i = int(e / RB), r = int(e % RB);
+    // 256 / RB rows per block and pass, thread (row lr, RHS r); with RB >= 64 a wave
+    // holds one row, whose operands are then wave-uniform (scalar loads)
+    const int rpb = 256 / RB, r = int(threadIdx.x) % RB, lr = int(threadIdx.x) / RB;
+    auto row = [&](int i) {
         double acc = 0.0;
 #pragma unroll 4
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc = __builtin_fma(k1[k], x[int64_t(col[k]) * RB + r], acc);
+        const int64_t e = int64_t(i) * RB + r;
         y[e] = sqrtm[i] * x[e] + a * isqrtm[i] * acc;
+    };
+    for (int64_t i = int64_t(blockIdx.x) * rpb + lr; i < n; i += int64_t(gridDim.x) * rpb) {
+        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)));
+        else row(int(i));
     }
 }
 
-// out = isig * PH + L^T rp,  L^T rp = M_L^{1/2} rp + a K1 (M_L^{-1/2} rp)
+// out = isig * PH + L^T rp,  L^T rp = M_L^{1/2} rp + a K1 (M_L^{-1/2} rp); PH is the
+// transpose sweep's result G^T r_d
 template <typename T>
 __global__ void __launch_bounds__(256) k_gext_t(const int32_t *rowptr, const int32_t *col, const double *k1,
                                                 const double *sqrtm, const double *isqrtm, int n, int RB, double a,
                                                 double isig, const T *PH, const double *rp, double *out) {
-    const int64_t total = int64_t(n) * RB;
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
-        const int i = int(e / RB), r = int(e % RB);
+    // as k_prior: 256 / RB rows per block and pass; wave-uniform rows for RB >= 64
+    const int rpb = 256 / RB, r = int(threadIdx.x) % RB, lr = int(threadIdx.x) / RB;
+    auto row = [&](int i) {
         double acc = 0.0;
 #pragma unroll 4
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
             const int j = col[k];
             acc = __builtin_fma(k1[k], isqrtm[j] * rp[int64_t(j) * RB + r], acc);
         }
+        const int64_t e = int64_t(i) * RB + r;
         out[e] = isig * static_cast<double>(PH[e]) + (sqrtm[i] * rp[e] + a * acc);
+    };
+    for (int64_t i = int64_t(blockIdx.x) * rpb + lr; i < n; i += int64_t(gridDim.x) * rpb) {
+        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)));
+        else row(int(i));
     }
 }
 
@@ -1294,16 +1307,21 @@ __global__ void __launch_bounds__(256) k_gext_t(const int32_t *rowptr, const int
 __global__ void __launch_bounds__(256) k_prior_t(const int32_t *rowptr, const int32_t *col, const double *k1,
                                                  const double *sqrtm, const double *isqrtm, int n, int RB, double a,
                                                  const double *x, double *y) {
-    const int64_t total = int64_t(n) * RB;
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
-        const int i = int(e / RB), r = int(e % RB);
+    // as k_prior: 256 / RB rows per block and pass; wave-uniform rows for RB >= 64
+    const int rpb = 256 / RB, r = int(threadIdx.x) % RB, lr = int(threadIdx.x) / RB;
+    auto row = [&](int i) {
         double acc = 0.0;
 #pragma unroll 4
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
             const int j = col[k];
             acc = __builtin_fma(k1[k], isqrtm[j] * x[int64_t(j) * RB + r], acc);
         }
+        const int64_t e = int64_t(i) * RB + r;
         y[e] = sqrtm[i] * x[e] + a * acc;
+    };
+    for (int64_t i = int64_t(blockIdx.x) * rpb + lr; i < n; i += int64_t(gridDim.x) * rpb) {
+        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)));
+        else row(int(i));
     }
 }
 
@@ -1403,24 +1421,42 @@ __global__ void k_resid(const double *a, const double *b, double *hist, double *
     }
 }
 
+// Grid-stride loops over [rows][RB] arrays: the RHS index of a thread's elements,
+// fixed when the stride is a multiple of RB (RB a power of two <= the block size),
+// so that no element pays a 64-bit division.
+struct RhsIndex {
+    int64_t stride;
+    int r0, RB;
+    bool fixed;
+    __device__ RhsIndex(int rb) : RB(rb) {
+        stride = int64_t(gridDim.x) * blockDim.x;
+        r0 = int((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) % rb);
+        fixed = stride % rb == 0;
+    }
+    __device__ int operator()(int64_t e) const { return fixed ? r0 : int(e % RB); }
+};
+
 __global__ void k_update_xr(double *x, const double *d, double *rp, const double *qp, const double *alpha,
                             int64_t total, int RB) {
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-        const double al = alpha[e % RB];
+    const RhsIndex rix(RB);
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += rix.stride) {
+        const double al = alpha[rix(e)];
         x[e] += al * d[e];
         rp[e] -= al * qp[e];
     }
 }
 
 __global__ void k_axpy_neg(double *y, const double *x, const double *alpha, int64_t total, int RB) {
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x)
-        y[e] -= alpha[e % RB] * x[e];
+    const RhsIndex rix(RB);
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += rix.stride)
+        y[e] -= alpha[rix(e)] * x[e];
 }
 
 __global__ void k_append(const double *sv, double *Qk, double *d, const double *invn, const double *beta, int first,
                          int64_t total, int RB) {
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-        const int r = int(e % RB);
+    const RhsIndex rix(RB);
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += rix.stride) {
+        const int r = rix(e);
         const double s = sv[e];
         if (Qk) Qk[e] = s * invn[r];
         d[e] = first ? s : s + beta[r] * d[e];
@@ -1476,8 +1512,9 @@ __global__ void k_lsqr_scalar(LsqrStage st, LsqrScalars c, const double *n1, con
 // out = (sa * ca[r]) a + (sb * cb[r]) b; a null coefficient pointer means 1, b may be null.
 __global__ void k_lincomb(double *out, const double *a, const double *ca, double sa, const double *b, const double *cb,
                           double sb, int64_t total, int RB) {
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-        const int r = int(e % RB);
+    const RhsIndex rix(RB);
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += rix.stride) {
+        const int r = rix(e);
         double v = sa * (ca ? ca[r] : 1.0) * a[e];
         if (b) v += sb * (cb ? cb[r] : 1.0) * b[e];
         out[e] = v;
@@ -1577,8 +1614,9 @@ __global__ void __launch_bounds__(256) k_multidot_final(const double *part, int 
 // s[row][r] -= coef[j][r] * Q[j][row][r], j = 0..k-1 in order
 __global__ void k_project(const double *Q, double *sv, const double *coef, int k, int64_t rows, int RB) {
     const int64_t total = rows * RB;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-        const int r = int(e % RB);
+    const RhsIndex rix(RB);
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += rix.stride) {
+        const int r = rix(e);
         double s = sv[e];
         for (int j = 0; j < k; ++j) s -= coef[int64_t(j) * RB + r] * Q[int64_t(j) * total + e];
         sv[e] = s;
@@ -1967,6 +2005,7 @@ void launch_build_rhs(const double *yobs, const double *eta, int64_t S, int64_t 
     hipLaunchKernelGGL(k_build_rhs, dim3(unsigned((M + 63) / 64)), dim3(256), 0, s, yobs, eta, S, rb0, RB, M, isig, bd);
 }
 
+// (the prior kernels take RB a power of two <= 256, as every RHS block is)
 void launch_prior(const DevOps &op, int RB, double a, const double *x, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_prior, dim3(grid_for(int64_t(op.n) * RB)), dim3(256), 0, s, op.rowptr, op.col, op.k1val64,
                        op.sqrtm, op.isqrtm, op.n, RB, a, x, y);
