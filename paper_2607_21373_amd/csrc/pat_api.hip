@@ -95,8 +95,9 @@ pat_status check_block(int64_t n, pat::Prec pr, int rb) {
 }  // namespace
 
 // Device scratch of pat_forward_noalloc, for callers that cannot allocate: one RHS
-// block's sweep state (P, V ping-pong) and its data staging.  Each device holds its
-// own copy from the library's first use on it until the process ends.  Host code
+// block's sweep state (three rotating state vectors) and its data staging.  Each
+// device holds its own copy from the library's first use on it until the process
+// ends.  Host code
 // never passes `scratch` itself to a kernel (on the host it only names the
 // symbol): pat_problem_create looks up each device's copy with
 // hipGetSymbolAddress and the entry point uses that address.
