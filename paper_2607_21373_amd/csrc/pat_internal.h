@@ -77,10 +77,12 @@ struct HaloTiles {
     static constexpr int kRows = 32;
     static constexpr int kMax = 132;
     static constexpr int kMetaBytes = kRows * (16 + 16 + 64 + 64 + 16);
+    static constexpr int kNrBits = 7;  // descriptor field of the rows and of the boundary rows
+    static_assert(kRows < (1 << kNrBits) && kMax < 256 && kMax % 4 == 0, "descriptor fields");
     int32_t n_tiles = 0;
     // [n_tiles][4]: first row, first halo entry, metadata offset (16-byte units),
-    // rows | K rows << 6 | B rows << 14 | boundary rows << 22 (metadata bytes:
-    // 96 per row + 80 per boundary row)
+    // rows | K rows << kNrBits | B rows << (kNrBits + 8) | boundary rows << (kNrBits + 16)
+    // (metadata bytes: 96 per row + 80 per boundary row)
     std::vector<int32_t> desc;
     std::vector<int32_t> hrow;
     std::vector<uint32_t> meta;

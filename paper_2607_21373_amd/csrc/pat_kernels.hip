@@ -708,7 +708,7 @@ constexpr int kHWaves = kHThreads / 64;
 constexpr int kHPerWave = (kHMax / 4 + kHWaves - 1) / kHWaves;  // halo copy instructions per wave at most
 constexpr int kHChunk = 4;  // LDS reads in flight per lane before they are consumed
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
-static_assert(kHThreads == 512 && (kHMetaWords + 255) / 256 <= kHWaves, "halo tile geometry");
+static_assert(kHThreads % 64 == 0 && kHThreads <= 1024 && (kHMetaWords + 255) / 256 <= kHWaves, "halo tile geometry");
 
 // LDS image of one tile
 struct alignas(16) HaloBuf {
@@ -721,7 +721,9 @@ struct alignas(16) HaloBuf {
 struct alignas(16) HaloList {  // copied into 16 bytes per lane
     int32_t r[kHMax];
 };
-static_assert(2 * (sizeof(HaloBuf) + sizeof(HaloList)) <= 81920, "two workgroups per CU");
+// workgroups per CU that the LDS of two tile images and two lists allows (160 KiB per CU)
+constexpr int kHPerCU = int(163840 / (2 * (sizeof(HaloBuf) + sizeof(HaloList))));
+static_assert(kHPerCU >= 1, "one workgroup per CU at least");
 
 struct HDesc {
     int r0, nr, h0, nk4, nb4, moff, mbytes, nbr;
@@ -731,7 +733,8 @@ struct HDesc {
 __device__ __forceinline__ HDesc desc_uniform(const int4 u) {
     const int r0 = __builtin_amdgcn_readfirstlane(u.x), h0 = __builtin_amdgcn_readfirstlane(u.y);
     const int moff = __builtin_amdgcn_readfirstlane(u.z), f = __builtin_amdgcn_readfirstlane(u.w);
-    const int nr = f & 63, nk4 = (f >> 6) & 255, nb4 = (f >> 14) & 255, nbr = (f >> 22) & 63;
+    constexpr int B = HaloTiles::kNrBits, M = (1 << B) - 1;
+    const int nr = f & M, nk4 = (f >> B) & 255, nb4 = (f >> (B + 8)) & 255, nbr = (f >> (B + 16)) & M;
     return {r0, nr, h0, nk4, nb4, moff, nr * 96 + nbr * 80, nbr};
 }
 
@@ -764,7 +767,7 @@ struct HWork {
         k = int(blockIdx.x >> 3);
         t_lo = int(int64_t(n_ht) * x / 8);
         ntx = int(int64_t(n_ht) * (x + 1) / 8) - t_lo;
-        weighted = G8 % 2 == 0;
+        weighted = kHPerCU == 2 && G8 % 2 == 0;
         first_half = 2 * k < G8;
         per_c = 0;
         while (local(per_c) < ntx) ++per_c;
@@ -1712,8 +1715,8 @@ VFwdArgs<T> fwd_args_v(const DevOps &op, const void *S, const void *Sp, void *Sn
     return a;
 }
 
-// workgroups of a halo kernel launch: two per CU, a multiple of the 8 XCDs
-inline int halo_grid(const DevOps &op) { return (2 * op.n_cu + 7) / 8 * 8; }
+// workgroups of a halo kernel launch: as many per CU as the LDS allows, a multiple of the 8 XCDs
+inline int halo_grid(const DevOps &op) { return (kHPerCU * op.n_cu + 7) / 8 * 8; }
 
 // the halo kernels take float32 blocks of 256-byte row chunks (rows == false:
 // a sampling-only launch stays with the vector-lane kernel)

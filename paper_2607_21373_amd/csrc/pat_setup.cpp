@@ -583,7 +583,6 @@ void build_halo_tiles(const HostProblem &hp, HaloTiles &ht) {
             ++r1;
         }
         const int32_t nr = r1 - r0, nk4 = pad4(kc.size()), nb4 = pad4(bc.size());
-        static_assert(HaloTiles::kRows < 64 && HaloTiles::kMax < 256, "descriptor fields");
         const int32_t h0 = int32_t(ht.hrow.size());
         for (int32_t k = 0; k < nk4; ++k) ht.hrow.push_back(kc[size_t(std::min<int32_t>(k, int32_t(kc.size()) - 1))]);
         for (int32_t k = 0; k < nb4; ++k) ht.hrow.push_back(bc[size_t(std::min<int32_t>(k, int32_t(bc.size()) - 1))]);
@@ -631,7 +630,8 @@ void build_halo_tiles(const HostProblem &hp, HaloTiles &ht) {
                 ++br;
             }
         }
-        const int32_t d[4] = {r0, h0, int32_t(m0 / 4), nr | (nk4 << 6) | (nb4 << 14) | (nbr << 22)};
+        constexpr int B = HaloTiles::kNrBits;
+        const int32_t d[4] = {r0, h0, int32_t(m0 / 4), nr | (nk4 << B) | (nb4 << (B + 8)) | (nbr << (B + 16))};
         ht.desc.insert(ht.desc.end(), d, d + 4);
         r0 = r1;
     }

@@ -61,7 +61,8 @@ int main(int argc, char **argv) {
     for (int32_t t = 0; t < ht.n_tiles; ++t) {
         const int32_t *D = &ht.desc[size_t(t) * 4];
         const int32_t r0 = D[0], h0 = D[1], moff = D[2], fl = D[3];
-        const int32_t nr = fl & 63, nk4 = (fl >> 6) & 255, nb4 = (fl >> 14) & 255, nbr = (fl >> 22) & 63;
+        constexpr int FB = pat::HaloTiles::kNrBits, FM = (1 << FB) - 1;
+        const int32_t nr = fl & FM, nk4 = (fl >> FB) & 255, nb4 = (fl >> (FB + 8)) & 255, nbr = (fl >> (FB + 16)) & FM;
         const std::string at = "tile " + std::to_string(t);
         if (r0 != next_row || nr < 1 || nr > pat::HaloTiles::kRows) return fail(at + ": rows");
         if (h0 != next_h || moff != next_m / 16) return fail(at + ": offsets");
