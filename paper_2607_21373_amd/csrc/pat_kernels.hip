@@ -155,6 +155,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
 }
 
+// xcd_tile with each XCD's range walked from its end, for the transposed steps.
+// The node order puts the rows with sensor weights at the front of each XCD's
+// range, and their tiles wait on the injection chain (range, then entries, then
+// data).  Dispatched last instead of first they cost the step less: on the
+// 195,112-node ball 11.2 -> 10.6 us per single-RHS float64 step and 3-4% per
+// float32 step of 16 or 32 RHS; the forward steps are unchanged.
+__device__ __forceinline__ int xcd_tile_rev(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    const int len = q + (x < rem ? 1 : 0);
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + len - 1 - k;
+}
+
 // The logical tiles [0, T), T = n_rows + n_samp, of a forward step come in
 // eight contiguous shares, one per XCD (share x: floor(T/8) tiles, one more
 // for x < T % 8).  Each share starts with its part of the sensor-sampling
@@ -269,21 +282,15 @@ __device__ __forceinline__ T inject(const AdjArgs<T> &a, int row, int r) {
 // Transposed step q_{k+1} = q_k + (q_k - q_{k-1}) - (dt/m)(dt K q_k + B (q_k - q_{k-1})
 // - inj/2), inj = Pi^T (yhat^{ta} + yhat^{tb}); with `last`, the result
 // (q_k - q_{k-1}) m/dt - (dt K q_k - B q_{k-1} - inj/2), inj = Pi^T yhat^{tb}.
-// One tile of RPB rows per workgroup.  Each XCD walks its contiguous range of
-// tiles from the end: the node order puts the rows with sensor weights at the
-// front of each XCD's range, and their tiles, which wait on the longer injection
-// chain, cost the step less when dispatched last than first (10.6 against 11.2 us
-// per single-RHS float64 step on the 195,112-node ball).  The injection range is
-// loaded with the row operands, a round trip earlier than after the sums.
+// One tile of RPB rows per workgroup, each XCD's range walked from its end
+// (xcd_tile_rev).  The injection range is loaded with the row operands, a round
+// trip earlier than after the sums.
 template <typename T, typename YT, int RB>
 __global__ void __launch_bounds__(256) k_adj(const AdjArgs<T> a) {
     using G = Geo<RB>;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int part = (lane / RB) % G::SPLIT, r = lane % RB;
-    const int nb = int(gridDim.x), b = int(blockIdx.x);
-    const int q8 = nb >> 3, rem = nb & 7, x = b & 7;
-    const int len = q8 + (x < rem ? 1 : 0), start = x < rem ? x * (q8 + 1) : rem * (q8 + 1) + (x - rem) * q8;
-    const int wrow0 = (start + len - 1 - (b >> 3)) * G::RPB + wave * G::RPW;
+    const int wrow0 = xcd_tile_rev(blockIdx.x, gridDim.x) * G::RPB + wave * G::RPW;
     const bool winj = wave_injects(a.injptr, wrow0, G::RPW, a.n);
     const int row = wrow0 + lane / G::LPR;
     if (row >= a.n) return;
@@ -578,7 +585,7 @@ struct Multi {
     int n;
 };
 
-__device__ __forceinline__ bool mesh_tile(const int *tiles, int n, int b, int *mesh, int *local) {
+__device__ __forceinline__ bool mesh_tile(const int *tiles, int n, int b, int *mesh, int *local, bool rev = false) {
     const int x = b & 7;
     int k = b >> 3;
     for (int m = 0; m < n; ++m) {
@@ -586,7 +593,7 @@ __device__ __forceinline__ bool mesh_tile(const int *tiles, int n, int b, int *m
         const int cnt = q + (x < r ? 1 : 0);
         if (k < cnt) {
             *mesh = m;
-            *local = x * q + (x < r ? x : r) + k;
+            *local = x * q + (x < r ? x : r) + (rev ? cnt - 1 - k : k);  // rev: as xcd_tile_rev
             return true;
         }
         k -= cnt;
@@ -682,14 +689,14 @@ __device__ __forceinline__ void adj_tile(const VAdjArgs<T> &a, int tile, TileOps
 template <typename T, typename YT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_v(const VAdjArgs<T> a) {
     __shared__ TileOps<T, RB> L;
-    adj_tile<T, YT, RB, NT>(a, xcd_tile(blockIdx.x, gridDim.x), L);
+    adj_tile<T, YT, RB, NT>(a, xcd_tile_rev(blockIdx.x, gridDim.x), L);
 }
 
 template <typename T, typename YT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_adj_vm(const Multi<VAdjArgs<T>> mm) {
     __shared__ TileOps<T, RB> L;
     int m, local;
-    if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
+    if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local, true)) return;
     adj_tile<T, YT, RB, NT>(mm.a[m], local, L);
 }
 
