@@ -1288,22 +1288,73 @@ __global__ void k_cast(const double *x, T *y, int64_t n) {
 }
 
 // y = L x = M_L^{1/2} x + a M_L^{-1/2} (K1 x)
+// float64 value of lane l of v (l wave-uniform)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b), l));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), l));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// sum over the entries k of row i of the K1 pattern, in ascending order, of
+// fma(K1[k], f_j x[j RB + r], acc) with j = col[k] and f_j = isqrtm[j] (SCALE) or
+// the plain x value, for a wave-uniform row i (RB >= 64, one row per wave): lane l
+// holds entry k0 + l's column, value and scale, read back by readlane, and the
+// gathers go in groups of 16, all issued before the first is used (the same sums
+// as entry by entry, in the same order, with a few dependent round trips per row
+// instead of one per entry)
+template <bool SCALE>
+__device__ __forceinline__ double k1_row_wave(const int32_t *rowptr, const int32_t *col, const double *k1,
+                                             const double *isqrtm, int i, int RB, int r, const double *x) {
+    constexpr int G = 16;
+    const int lane = int(threadIdx.x) & 63;
+    const int k0 = rowptr[i], ke = rowptr[i + 1];
+    double acc = 0.0;
+    for (int kb = k0; kb < ke; kb += 64) {
+        const int nk = min(64, ke - kb);
+        int cl = 0;
+        double wl = 0.0, sl = 1.0;
+        if (lane < nk) {
+            cl = col[kb + lane];
+            wl = k1[kb + lane];
+            if (SCALE) sl = isqrtm[cl];
+        }
+        for (int g = 0; g < nk; g += G) {
+            double xv[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j)  // past the end: the last entry again, loaded but not summed
+                xv[j] = x[int64_t(__builtin_amdgcn_readlane(cl, min(g + j, nk - 1))) * RB + r];
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (g + j < nk) {
+                    const double w = readlane_f64(wl, g + j);
+                    acc = SCALE ? __builtin_fma(w, readlane_f64(sl, g + j) * xv[j], acc) : __builtin_fma(w, xv[j], acc);
+                }
+        }
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(256) k_prior(const int32_t *rowptr, const int32_t *col, const double *k1,
                                                const double *sqrtm, const double *isqrtm, int n, int RB, double a,
                                                const double *x, double *y) {
     // 256 / RB rows per block and pass, thread (row lr, RHS r); with RB >= 64 a wave
     // holds one row, whose operands are then wave-uniform (scalar loads)
     const int rpb = 256 / RB, r = int(threadIdx.x) % RB, lr = int(threadIdx.x) / RB;
-    auto row = [&](int i) {
+    auto row = [&](int i, bool wave_row) {
         double acc = 0.0;
+        if (wave_row) {
+            acc = k1_row_wave<false>(rowptr, col, k1, isqrtm, i, RB, r, x);
+        } else {
 #pragma unroll 4
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc = __builtin_fma(k1[k], x[int64_t(col[k]) * RB + r], acc);
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc = __builtin_fma(k1[k], x[int64_t(col[k]) * RB + r], acc);
+        }
         const int64_t e = int64_t(i) * RB + r;
         y[e] = sqrtm[i] * x[e] + a * isqrtm[i] * acc;
     };
     for (int64_t i = int64_t(blockIdx.x) * rpb + lr; i < n; i += int64_t(gridDim.x) * rpb) {
-        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)));
-        else row(int(i));
+        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)), true);
+        else row(int(i), false);
     }
 }
 
@@ -1315,19 +1366,23 @@ __global__ void __launch_bounds__(256) k_gext_t(const int32_t *rowptr, const int
                                                 double isig, const T *PH, const double *rp, double *out) {
     // as k_prior: 256 / RB rows per block and pass; wave-uniform rows for RB >= 64
     const int rpb = 256 / RB, r = int(threadIdx.x) % RB, lr = int(threadIdx.x) / RB;
-    auto row = [&](int i) {
+    auto row = [&](int i, bool wave_row) {
         double acc = 0.0;
+        if (wave_row) {
+            acc = k1_row_wave<true>(rowptr, col, k1, isqrtm, i, RB, r, rp);
+        } else {
 #pragma unroll 4
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int j = col[k];
-            acc = __builtin_fma(k1[k], isqrtm[j] * rp[int64_t(j) * RB + r], acc);
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int j = col[k];
+                acc = __builtin_fma(k1[k], isqrtm[j] * rp[int64_t(j) * RB + r], acc);
+            }
         }
         const int64_t e = int64_t(i) * RB + r;
         out[e] = isig * static_cast<double>(PH[e]) + (sqrtm[i] * rp[e] + a * acc);
     };
     for (int64_t i = int64_t(blockIdx.x) * rpb + lr; i < n; i += int64_t(gridDim.x) * rpb) {
-        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)));
-        else row(int(i));
+        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)), true);
+        else row(int(i), false);
     }
 }
 
@@ -1337,19 +1392,23 @@ __global__ void __launch_bounds__(256) k_prior_t(const int32_t *rowptr, const in
                                                  const double *x, double *y) {
     // as k_prior: 256 / RB rows per block and pass; wave-uniform rows for RB >= 64
     const int rpb = 256 / RB, r = int(threadIdx.x) % RB, lr = int(threadIdx.x) / RB;
-    auto row = [&](int i) {
+    auto row = [&](int i, bool wave_row) {
         double acc = 0.0;
+        if (wave_row) {
+            acc = k1_row_wave<true>(rowptr, col, k1, isqrtm, i, RB, r, x);
+        } else {
 #pragma unroll 4
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int j = col[k];
-            acc = __builtin_fma(k1[k], isqrtm[j] * x[int64_t(j) * RB + r], acc);
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int j = col[k];
+                acc = __builtin_fma(k1[k], isqrtm[j] * x[int64_t(j) * RB + r], acc);
+            }
         }
         const int64_t e = int64_t(i) * RB + r;
         y[e] = sqrtm[i] * x[e] + a * acc;
     };
     for (int64_t i = int64_t(blockIdx.x) * rpb + lr; i < n; i += int64_t(gridDim.x) * rpb) {
-        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)));
-        else row(int(i));
+        if (RB >= 64) row(__builtin_amdgcn_readfirstlane(int(i)), true);
+        else row(int(i), false);
     }
 }
 
