@@ -1420,12 +1420,34 @@ __global__ void __launch_bounds__(256) k_dot_partial(const double *x, const doub
     const int r = threadIdx.x % RB, g = threadIdx.x / RB;
     const int64_t chunk = (rows + gridDim.x - 1) / gridDim.x;
     const int64_t a0 = int64_t(blockIdx.x) * chunk, a1 = a0 + chunk < rows ? a0 + chunk : rows;
-    double acc = 0.0;
-    for (int64_t row = a0 + g; row < a1; row += G) {
-        const int64_t e = row * RB + r;
-        acc = __builtin_fma(x[e], y[e], acc);
+    // four rows per pass into four partial sums, so that each lane keeps four loads
+    // in flight; a norm (x == y) loads each element once
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int64_t row = a0 + g;
+    if (x == y) {
+        for (; row + 3 * G < a1; row += 4 * G) {
+            const double v0 = x[row * RB + r], v1 = x[(row + G) * RB + r], v2 = x[(row + 2 * G) * RB + r],
+                         v3 = x[(row + 3 * G) * RB + r];
+            acc0 = __builtin_fma(v0, v0, acc0);
+            acc1 = __builtin_fma(v1, v1, acc1);
+            acc2 = __builtin_fma(v2, v2, acc2);
+            acc3 = __builtin_fma(v3, v3, acc3);
+        }
+    } else {
+        for (; row + 3 * G < a1; row += 4 * G) {
+            const int64_t e0 = row * RB + r, e1 = e0 + int64_t(G) * RB, e2 = e1 + int64_t(G) * RB,
+                          e3 = e2 + int64_t(G) * RB;
+            acc0 = __builtin_fma(x[e0], y[e0], acc0);
+            acc1 = __builtin_fma(x[e1], y[e1], acc1);
+            acc2 = __builtin_fma(x[e2], y[e2], acc2);
+            acc3 = __builtin_fma(x[e3], y[e3], acc3);
+        }
     }
-    red[threadIdx.x] = acc;
+    for (; row < a1; row += G) {
+        const int64_t e = row * RB + r;
+        acc0 = __builtin_fma(x[e], y[e], acc0);
+    }
+    red[threadIdx.x] = (acc0 + acc1) + (acc2 + acc3);
     __syncthreads();
     for (int s = 128; s >= RB; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
