@@ -54,10 +54,10 @@ def step_bytes(info, RB, tsize, kind):
 
 
 def kernel_source_sha():
-    """Hash of what decides the step kernels' memory traffic: their code and the host setup that
-    lays out and orders the rows (comments and layout whitespace left out)."""
+    """Hash of what decides the step kernels' memory traffic: their code, their work mappings and
+    the host setup that lays out and orders the rows (comments and layout whitespace left out)."""
     h = hashlib.sha256()
-    for name in ("pat_kernels.hip", "pat_setup.cpp"):
+    for name in ("pat_kernels.hip", "pat_tiles.h", "pat_setup.cpp"):
         with open(os.path.join(ROOT, "paper_2607_21373_amd", "csrc", name)) as f:
             src = f.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)

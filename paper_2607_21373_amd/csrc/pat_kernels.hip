@@ -32,6 +32,7 @@
 
 #include "pat_internal.h"
 #include "pat_kernels.h"
+#include "pat_tiles.h"
 
 namespace pat {
 namespace {
@@ -147,45 +148,8 @@ __device__ __forceinline__ void row_sums(const RowOps<T> &o, const RowMeta<T, RB
     }
 }
 
-// Workgroup b is dispatched to XCD (b % 8); map it to a logical tile so that
-// each XCD walks one contiguous range of rows.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int q = nb >> 3, rem = nb & 7;
-    const int x = b & 7, k = b >> 3;
-    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
-}
 
-// xcd_tile with each XCD's range walked from its end, for the transposed steps.
-// The node order puts the rows with sensor weights at the front of each XCD's
-// range, and their tiles wait on the injection chain (range, then entries, then
-// data).  Dispatched last instead of first they cost the step less: on the
-// 195,112-node ball 11.2 -> 10.6 us per single-RHS float64 step and 3-4% per
-// float32 step of 16 or 32 RHS; the forward steps are unchanged.
-__device__ __forceinline__ int xcd_tile_rev(int b, int nb) {
-    const int q = nb >> 3, rem = nb & 7;
-    const int x = b & 7, k = b >> 3;
-    const int len = q + (x < rem ? 1 : 0);
-    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + len - 1 - k;
-}
 
-// The logical tiles [0, T), T = n_rows + n_samp, of a forward step come in
-// eight contiguous shares, one per XCD (share x: floor(T/8) tiles, one more
-// for x < T % 8).  Each share starts with its part of the sensor-sampling
-// blocks (floor(n_samp/8), one more for x < n_samp % 8), which are short and
-// so are dispatched first, then its row tiles in order.  Returns the row tile,
-// or n_rows + j for sampling block j.
-__device__ __forceinline__ int fwd_work(int l, int n_rows, int n_samp) {
-    if (n_samp == 0) return l;
-    const int T = n_rows + n_samp;
-    const int q = T >> 3, r = T & 7;
-    const int x = l < r * (q + 1) ? l / (q + 1) : r + (l - r * (q + 1)) / q;
-    const int k = l - (x * q + (x < r ? x : r));
-    const int sq = n_samp >> 3, sr = n_samp & 7;
-    const int before = x * sq + (x < sr ? x : sr);  // sampling blocks of the shares before x
-    const int mine = sq + (x < sr ? 1 : 0);
-    if (k < mine) return n_rows + before + k;
-    return l - before - mine;
-}
 
 template <typename T>
 struct FwdArgs {
@@ -585,34 +549,13 @@ struct Multi {
     int n;
 };
 
-__device__ __forceinline__ bool mesh_tile(const int *tiles, int n, int b, int *mesh, int *local, bool rev = false) {
-    const int x = b & 7;
-    int k = b >> 3;
-    for (int m = 0; m < n; ++m) {
-        const int q = tiles[m] >> 3, r = tiles[m] & 7;
-        const int cnt = q + (x < r ? 1 : 0);
-        if (k < cnt) {
-            *mesh = m;
-            *local = x * q + (x < r ? x : r) + (rev ? cnt - 1 - k : k);  // rev: as xcd_tile_rev
-            return true;
-        }
-        k -= cnt;
-    }
-    return false;
-}
 
-// grid size of a merged launch (see Multi)
-inline int multi_grid(const int *tiles, int n) {
-    int c = 0;
-    for (int m = 0; m < n; ++m) c += (tiles[m] >> 3) + ((tiles[m] & 7) ? 1 : 0);
-    return 8 * c;
-}
 
 template <typename T, typename OT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_vm(const Multi<VFwdArgs<T>> mm) {
     __shared__ TileOps<T, RB> L;
     int m, local;
-    if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local)) return;
+    if (!mesh_tile(mm.tiles, mm.n, blockIdx.x, &m, &local, false)) return;
     fwd_tile<T, OT, RB, NT>(mm.a[m], fwd_work(local, mm.a[m].n_tiles, mm.a[m].n_samp), L);
 }
 
@@ -771,21 +714,11 @@ __device__ __forceinline__ HDesc desc_uniform(const int4 u) {
 // the other; so every kRowPeriod-th row goes to the first half only, two tiles
 // each, and they take 10 tiles for every 8 of the others.  A workgroup walks its
 // tiles in row order, once per 256-byte chunk.
-constexpr int kRowPeriod = 9;
 struct HWork {
     int t_lo, ntx, k, G8, per_c, n;
     bool weighted, first_half;
     // local index (tile - t_lo) of this workgroup's j-th tile; increasing in j
-    __device__ int local(int j) const {
-        if (!weighted) return j * G8 + k;
-        if (first_half) {
-            const int b = j / (kRowPeriod + 1), e = j % (kRowPeriod + 1);
-            return e < kRowPeriod - 1 ? (b * kRowPeriod + e) * G8 + k
-                                      : (b * kRowPeriod + kRowPeriod - 1) * G8 + 2 * k + (e - (kRowPeriod - 1));
-        }
-        const int b = j / (kRowPeriod - 1), e = j % (kRowPeriod - 1);
-        return (b * kRowPeriod + e) * G8 + k;
-    }
+    __device__ int local(int j) const { return hwork_local(j, G8, k, weighted, first_half); }
     __device__ HWork(int n_ht, int NC) {
         G8 = int(gridDim.x >> 3);
         const int x = int(blockIdx.x & 7);
