@@ -549,8 +549,9 @@ def main():
     ab = step_bytes(info, 64, 4, "adj")
     fwd_gbs = fb / fwd_avg_s / 1e9
     adj_gbs = ab / adj_avg_s / 1e9
-    # the estimate of the method's bytes per sweep-step of either direction, from the survey of the
-    # path (ball58, 64 float32 RHS: matrix 22.8 + rowptr 0.8 + B 1.1 + dt/m 0.8 + state 199.8 + sensors 0.26 MB)
+    # the a-priori estimate of the method's bytes per sweep-step of either direction, made before the
+    # kernels were written (ball58, 64 float32 RHS, four state vectors: matrix 22.8 + rowptr 0.8 + B 1.1 +
+    # dt/m 0.8 + state 199.8 + sensors 0.26 MB)
     survey_step_bytes = 225.5e6 if w.n_nodes == 195112 and R == 64 else None
     sweep_share = (prof["fwd_ms"] + prof["adj_ms"]) / (el * 1e3)
     log(f"forward step: {fwd_avg_s * 1e6:.2f} us, {fb / 1e6:.1f} MB -> {fwd_gbs:.0f} GB/s; transpose step: "
