@@ -148,9 +148,6 @@ __device__ __forceinline__ void row_sums(const RowOps<T> &o, const RowMeta<T, RB
     }
 }
 
-
-
-
 template <typename T>
 struct FwdArgs {
     RowOps<T> o;
@@ -548,8 +545,6 @@ struct Multi {
     int tiles[kMaxMeshes];
     int n;
 };
-
-
 
 template <typename T, typename OT, int RB, bool NT>
 __global__ void __launch_bounds__(256) PAT_VOCC(T, RB) k_fwd_vm(const Multi<VFwdArgs<T>> mm) {
